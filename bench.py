@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""CoFEM throughput on one MI355X.
+
+One step = one whole fit (Algorithm 1) on the large dense Gaussian workload:
+N = 16384, D = 65536, K = 32 probes, T = 30 EM iterations, PCG tol 1e-5, at
+most 400 CG steps; the dictionary is held in bfloat16 (FP32 accumulation,
+FP64 CG scalars) and the last 3 EM iterations use the FP32 dictionary.  A step
+includes loading the dictionary into the library's layouts.  Inputs are
+synthetic (seeded), already resident in HBM when the timed region starts.
+
+Prints one JSON line.  `value` is EM iterations per second.  Beside it:
+  roofline      the operator's matrix kernel (bf16), algorithmic bytes per
+                launch / average launch time from HIP events on the library's
+                stream over the timed steps, against 8 TB/s;
+  fp32          the same fit with the FP32 dictionary throughout;
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "CoFEM EM-iters/s + HBM GB/s at D=65536 (BF16 vs FP32); serving p50/p99"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "small"])
+    ap.add_argument("--no-fp32", action="store_true", help="skip the all-FP32 comparison fit")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="CG steps in the oracle sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2105_10439_amd as lib
+    import workloads
+
+    lib.load()
+    torch.cuda.set_device(0)
+    w = dict(workloads.WORKLOADS[args.workload])
+    refine = 3 if args.workload == "large" else 0
+    t0 = time.time()
+    prob = workloads.make_workload(args.workload)
+    log(f"generated {args.workload} N={prob.N} D={prob.D} in {time.time() - t0:.1f}s")
+    phi_d = torch.from_numpy(prob.phi).cuda()
+    y_d = torch.from_numpy(prob.y).cuda()
+    torch.cuda.synchronize()
+
+    def run(phi_dtype, refine_last, steps, warmup, timing):
+        m = lib.CoFEM(prob.N, prob.D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024,
+                      phi_dtype=phi_dtype, refine_last=refine_last)
+        for i in range(warmup):
+            m.set_dictionary(phi_d)
+            m.fit(y_d)
+            log(f"warmup {i + 1}/{warmup} done")
+        if timing:
+            m.set_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(steps):
+            m.set_dictionary(phi_d)
+            m.fit(y_d)
+            log(f"step {i + 1}/{steps} done")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        mu, s, alpha, st = m.posterior()
+        tim = {k: m.get_timing(k) for k in ("bf16", "fp32")} if timing else None
+        m.close()
+        return el, st, tim, mu
+
+    el, st, tim, mu = run("bf16" if args.workload == "large" else "fp32", refine, args.steps, args.warmup, True)
+    em_iters = w["T"] * args.steps
+    value = em_iters / el
+    nbytes_launch = {"bf16": prob.N * prob.D * 2, "fp32": prob.N * prob.D * 4}
+    ops = {}
+    for k, (ms, n) in tim.items():
+        if n:
+            avg_ms = ms / n
+            ops[k] = dict(launches=n, avg_ms=avg_ms, gbps=nbytes_launch[k] / (avg_ms * 1e-3) / 1e9)
+    dom = "bf16" if "bf16" in ops else "fp32"
+    roof = dict(bound="hbm", achieved=round(ops[dom]["gbps"], 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                frac=round(ops[dom]["gbps"] / HBM_PEAK_GBPS, 4), traffic=None,
+                kernel=f"k_gemm_{dom}", bytes_per_launch=nbytes_launch[dom], avg_launch_ms=ops[dom]["avg_ms"])
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "EM-iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if refine else "fp32", "data": "synthetic",
+        "config": {"workload": f"dense Gaussian {args.workload}: N={prob.N} D={prob.D} K={w['K']} T={w['T']} "
+                               f"tol={w['tol']} U={w['U']}" + (f" bf16 dictionary, last {refine} EM iterations FP32"
+                                                               if refine else " FP32"),
+                   "N": prob.N, "D": prob.D, "K": w["K"], "T": w["T"]},
+        "roofline": roof,
+        "operator": ops,
+        "cg_steps_per_fit": st["total_cg_steps"],
+        "cg_steps_per_em_iter": st["cg_steps"],
+    }
+    if not args.no_fp32 and args.workload == "large":
+        el32, st32, tim32, mu32 = run("fp32", 0, 1, 0, True)
+        ms, n = tim32["fp32"]
+        out["fp32"] = dict(em_iters_per_s=round(w["T"] / el32, 3), ms_per_fit=round(1e3 * el32, 1),
+                           cg_steps=st32["total_cg_steps"],
+                           operator_gbps=round(nbytes_launch["fp32"] / (ms / n * 1e-3) / 1e9, 1) if n else None,
+                           mu_rel_diff_bf16_refined_vs_fp32=float(
+                               (torch.linalg.vector_norm(mu.double() - mu32.double()) /
+                                torch.linalg.vector_norm(mu32.double())).item()))
+        log(f"fp32 comparison fit: {out['fp32']}")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, w, st, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(prob, w, st, cg_steps):
+    """The FP64 oracle on a bounded sample: one E-step capped at `cg_steps` CG
+    steps (tol = 0 so it runs them all), scaled to EM iterations/s with the
+    mean CG steps per EM iteration of the GPU fit on the same workload."""
+    import numpy as np
+
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    op = oracle.DenseOperator(prob.phi)
+    t_conv = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.cofem(op, prob.y, prob.beta, T=1, K=w["K"], U=cg_steps, tol=0.0, seed=2024)
+    el = time.perf_counter() - t1
+    per_step = el / cg_steps
+    mean_steps = st["total_cg_steps"] / max(st["T"], 1)
+    v = 1.0 / (per_step * mean_steps)
+    log(f"cpu baseline: {cg_steps} CG steps in {el:.1f}s ({per_step:.3f}s/step), widening {t_conv:.1f}s")
+    return dict(value=round(v, 5), unit="EM-iters/s", cores=threads, kind="oracle",
+                sample=f"one E-step of the same workload capped at {cg_steps} CG steps ({el:.1f}s), scaled by the "
+                       f"GPU fit's mean {mean_steps:.1f} CG steps per EM iteration; NumPy FP64 with {threads} BLAS "
+                       f"threads")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * cofem.h -- C ABI of the covariance-free EM (CoFEM) hot path for AMD gfx950.
+ *
+ * The problem (Eq. sparse-coding, Sec. I): y = Phi z + eps with y in R^N,
+ * z in R^D, Phi in R^{N x D}.  The model (Eq. model, Sec. II-A) puts
+ * z ~ N(0, diag(alpha)^-1) and y | z ~ N(Phi z, beta^-1 I) with the noise
+ * precision beta fixed.  A fit runs Algorithm 1 (CovarianceFreeEM(y, Phi,
+ * beta, T, K)): T EM iterations, each solving A X = B with
+ * A = beta Phi^T Phi + diag(alpha) and B = [beta Phi^T y | p_1 .. p_K]
+ * (Eq. mat-eq) by the multi-RHS preconditioned CG of Algorithm 2 with the
+ * diagonal preconditioner M = diag(beta theta + alpha) (Sec. III-C), then
+ * forming mu, the diagonal estimate s_j = (1/K) sum_k p_kj x_kj
+ * (Eq. diag-estimate) and, for t < T, alpha_j = 1 / (mu_j^2 + s_j)
+ * (Eq. mstep with Sigma_jj replaced by s_j).  It returns alpha^(T), mu, s.
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is DEVICE memory on the device that was current
+ *     when the context was created, unless a comment says "host".
+ *   - Matrices are row-major and contiguous.  A "block of Q columns of length
+ *     L" is Q contiguous vectors of L floats each (column q starts at q * L).
+ *   - The caller owns every buffer it passes; the library never frees or
+ *     retains caller pointers beyond the call, reads inputs only and writes
+ *     outputs only.  The library owns its workspace (copies of the
+ *     dictionary in its own layouts, CG blocks, reduction scratch).
+ *   - All work is enqueued on the HIP stream given at creation (NULL = the
+ *     default stream).  Calls that return results block until the stream has
+ *     finished them.
+ *   - Functions return COFEM_OK or a negative status; the thread-local
+ *     cofem_last_error() then holds a message.  Arguments are validated
+ *     before any device work; no C++ exception crosses this boundary.
+ *   - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef COFEM_H
+#define COFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COFEM_ABI_VERSION 1
+#define COFEM_MAX_T 512 /* longest EM run recorded in cofem_stats */
+#define COFEM_MAX_K 63  /* probes per EM iteration (one 64-bit hash word per coordinate) */
+
+typedef struct cofem_ctx cofem_ctx;
+
+typedef enum {
+  COFEM_OK = 0,
+  COFEM_EINVAL = -1,     /* bad argument or parameter combination */
+  COFEM_ENOMEM = -2,     /* device allocation failed */
+  COFEM_EDEVICE = -3,    /* a HIP runtime call failed */
+  COFEM_ESTATE = -4,     /* call out of order (e.g. fit before set_dictionary) */
+  COFEM_EBREAKDOWN = -5, /* CG breakdown (pi_q <= 0) in the mu column */
+  COFEM_EBUDGET = -6     /* serving: request larger than the whole memory budget */
+} cofem_status;
+
+typedef enum { COFEM_THETA_ONES = 0, COFEM_THETA_JACOBI = 1 } cofem_theta_mode;
+typedef enum { COFEM_STOP_JOINT = 0, COFEM_STOP_COLUMN = 1 } cofem_stop_mode;
+typedef enum { COFEM_OP_DENSE = 0, COFEM_OP_CONV = 1 } cofem_op_kind;
+typedef enum { COFEM_PHI_FP32 = 0, COFEM_PHI_BF16 = 1 } cofem_phi_dtype;
+
+/*
+ * Fit parameters.  Names follow Algorithms 1 and 2.
+ *   N, D        sizes of y and z (Eq. sparse-coding); for COFEM_OP_CONV N must equal D.
+ *   beta        noise precision, > 0 (Eq. model).
+ *   K           Rademacher probes per EM iteration, 1..COFEM_MAX_K (Alg. 1).
+ *   T           EM iterations, 1..COFEM_MAX_T (Alg. 1); T E-steps and T-1 M-steps.
+ *   U           maximum CG steps per E-step, >= 1 (Alg. 2).
+ *   tol         epsilon_max of the CG stop test (Alg. 2), >= 0.
+ *   theta_mode  preconditioner M = diag(beta theta + alpha) with theta = 1
+ *               (COFEM_THETA_ONES) or theta_j = sum_i Phi_ij^2 (Jacobi), Sec. III-C.
+ *   stop_mode   COFEM_STOP_JOINT: stop when ||R||_F / ||B||_F <= tol (the printed
+ *               test); COFEM_STOP_COLUMN: freeze column q once ||R_q||/||B_q|| <= tol.
+ *   op_kind     COFEM_OP_DENSE: Phi is a dense N x D matrix.  COFEM_OP_CONV: Phi is
+ *               the D x D causal convolution Phi_ij = h[i - j], 0 <= i - j < conv_taps
+ *               (the convolutional dictionary of Sec. V-A.2).
+ *   phi_dtype   arithmetic of the operator: COFEM_PHI_FP32, or COFEM_PHI_BF16 (Phi
+ *               rounded to bfloat16 once, products accumulated in FP32).
+ *   refine_last with COFEM_PHI_BF16: the last refine_last E-steps use the FP32 operator.
+ *   conv_taps   FIR length for COFEM_OP_CONV (1..4096); ignored otherwise.
+ *   seed        probe seed.  Probe entry p_{k,j} at EM iteration t is +1 if bit k of
+ *               w(t, j) is 0 and -1 otherwise, where w(t, j) is output j+1 of the
+ *               SplitMix64 stream started at key_t, and key_t is output t of the
+ *               SplitMix64 stream started at seed (Steele, Lea & Flood 2014).
+ *   alpha_floor M-step denominators mu_j^2 + s_j below it are raised to it (> 0).
+ */
+typedef struct cofem_params {
+  int64_t N, D;
+  double beta;
+  int32_t K, T, U;
+  double tol;
+  int32_t theta_mode;
+  int32_t stop_mode;
+  int32_t op_kind;
+  int32_t phi_dtype;
+  int32_t refine_last;
+  int32_t conv_taps;
+  uint64_t seed;
+  double alpha_floor;
+} cofem_params;
+
+/* Per-fit record (host struct, filled by cofem_posterior). */
+typedef struct cofem_stats {
+  int32_t T;                       /* EM iterations run */
+  int32_t cg_steps[COFEM_MAX_T];   /* operator applications in E-step t (index t-1) */
+  double rel_resid[COFEM_MAX_T];   /* ||R||_F / ||B||_F at the end of E-step t */
+  int32_t used_bf16[COFEM_MAX_T];  /* 1 if E-step t used the bfloat16 operator */
+  int64_t clamped;                 /* M-step denominators raised to alpha_floor */
+  int32_t breakdown;               /* columns that hit pi_q <= 0 */
+  int32_t total_cg_steps;          /* sum of cg_steps */
+  double ms_setup;                 /* host wall time of cofem_set_dictionary */
+  double ms_fit;                   /* host wall time of cofem_fit */
+} cofem_stats;
+
+/* Library ABI version (COFEM_ABI_VERSION). */
+int32_t cofem_abi_version(void);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* cofem_last_error(void);
+
+/*
+ * Validate *p, allocate the workspace for problems of that shape on the current
+ * device and bind the context to `stream` (a hipStream_t, NULL = default).
+ * On success *out owns the context; release it with cofem_destroy.
+ * Errors: COFEM_EINVAL (bad parameters), COFEM_ENOMEM, COFEM_EDEVICE.
+ */
+cofem_status cofem_create(const cofem_params* p, void* stream, cofem_ctx** out);
+
+/* Free the context and its workspace (NULL is a no-op). */
+void cofem_destroy(cofem_ctx* c);
+
+/*
+ * Load the dictionary: for COFEM_OP_DENSE `phi` is the N x D row-major FP32 matrix;
+ * for COFEM_OP_CONV it is the conv_taps FIR taps h[0..taps-1].  The library copies
+ * it into its own layouts (row-major and transposed, FP32 and/or bfloat16, padded)
+ * and computes theta (Sec. III-C); `phi` may be freed when the call returns.
+ * Errors: COFEM_EINVAL (NULL), COFEM_EDEVICE.
+ */
+cofem_status cofem_set_dictionary(cofem_ctx* c, const float* phi);
+
+/*
+ * Run Algorithm 1 on observation y (N floats, device) with the loaded dictionary.
+ * Results stay on the device until cofem_posterior.  Non-convergence of CG within
+ * U steps is not an error (Alg. 2 returns X after U steps); it shows in the stats.
+ * Errors: COFEM_ESTATE (no dictionary), COFEM_EINVAL, COFEM_EDEVICE,
+ * COFEM_EBREAKDOWN (the mu column broke down; results are still written).
+ */
+cofem_status cofem_fit(cofem_ctx* c, const float* y);
+
+/*
+ * Copy the fit's results into caller buffers of D floats each (device; any may be
+ * NULL): mu and s from the E-step of iteration T, alpha = alpha^(T).  If st is
+ * non-NULL (host) it receives the fit record.  Errors: COFEM_ESTATE (no fit yet).
+ */
+cofem_status cofem_posterior(cofem_ctx* c, float* mu, float* s, float* alpha, cofem_stats* st);
+
+/*
+ * One application of the operator of Alg. 2 (its line "Psi <- A P"):
+ * Psi = beta Phi^T (Phi P) + diag(alpha) P for a block of ncols (1..COFEM_MAX_K+1)
+ * columns of length D, with the loaded dictionary, alpha (D floats) and the
+ * FP32 (use_bf16 = 0) or bfloat16 (use_bf16 = 1, needs phi_dtype = BF16) operator.
+ * If pi is non-NULL (device, ncols doubles) it receives pi_q = sum_j P_jq Psi_jq.
+ * Errors: COFEM_ESTATE (no dictionary), COFEM_EINVAL.
+ */
+cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const float* P, float* Psi,
+                           int32_t ncols, int32_t use_bf16, double* pi);
+
+/*
+ * Accumulated device time of the operator's matrix kernels (the two passes of
+ * Phi P and Phi^T V) since the last reset, timed with HIP events recorded on the
+ * context's stream around each launch when timing is enabled.
+ *   cofem_set_timing(c, 1) enables and resets; (c, 0) disables.
+ *   cofem_get_timing returns total milliseconds and the number of timed launches
+ *   for the bfloat16 (which = 1) or FP32 (which = 0) operator.
+ */
+cofem_status cofem_set_timing(cofem_ctx* c, int32_t enable);
+cofem_status cofem_get_timing(cofem_ctx* c, int32_t which, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COFEM_H */

@@ -1,0 +1,190 @@
+"""Python binding of the gfx950 CoFEM library (include/cofem.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libcofem.so.  PyTorch supplies device memory and the current stream.  There is
+no CPU fallback: if the shared library is missing, `load()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcofem.so")
+
+COFEM_MAX_T = 512
+COFEM_MAX_K = 63
+
+STATUS = {0: "COFEM_OK", -1: "COFEM_EINVAL", -2: "COFEM_ENOMEM", -3: "COFEM_EDEVICE", -4: "COFEM_ESTATE",
+          -5: "COFEM_EBREAKDOWN", -6: "COFEM_EBUDGET"}
+THETA = {"ones": 0, "jacobi": 1}
+STOP = {"joint": 0, "column": 1}
+OPS = {"dense": 0, "conv": 1}
+DTYPES = {"fp32": 0, "bf16": 1}
+
+# every symbol include/cofem.h declares
+EXPORTS = [
+    "cofem_abi_version", "cofem_last_error", "cofem_create", "cofem_destroy", "cofem_set_dictionary",
+    "cofem_fit", "cofem_posterior", "cofem_apply_A", "cofem_set_timing", "cofem_get_timing",
+]
+
+
+class CofemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("D", ctypes.c_int64), ("beta", ctypes.c_double),
+        ("K", ctypes.c_int32), ("T", ctypes.c_int32), ("U", ctypes.c_int32), ("tol", ctypes.c_double),
+        ("theta_mode", ctypes.c_int32), ("stop_mode", ctypes.c_int32), ("op_kind", ctypes.c_int32),
+        ("phi_dtype", ctypes.c_int32), ("refine_last", ctypes.c_int32), ("conv_taps", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("alpha_floor", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("T", ctypes.c_int32),
+        ("cg_steps", ctypes.c_int32 * COFEM_MAX_T),
+        ("rel_resid", ctypes.c_double * COFEM_MAX_T),
+        ("used_bf16", ctypes.c_int32 * COFEM_MAX_T),
+        ("clamped", ctypes.c_int64),
+        ("breakdown", ctypes.c_int32),
+        ("total_cg_steps", ctypes.c_int32),
+        ("ms_setup", ctypes.c_double),
+        ("ms_fit", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        T = self.T
+        return dict(T=T, cg_steps=list(self.cg_steps[:T]), rel_resid=list(self.rel_resid[:T]),
+                    used_bf16=list(self.used_bf16[:T]), clamped=int(self.clamped), breakdown=int(self.breakdown),
+                    total_cg_steps=int(self.total_cg_steps), ms_setup=float(self.ms_setup),
+                    ms_fit=float(self.ms_fit))
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libcofem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2105_10439_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "cofem_abi_version": (i32, []),
+        "cofem_last_error": (ctypes.c_char_p, []),
+        "cofem_create": (i32, [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]),
+        "cofem_destroy": (None, [vp]),
+        "cofem_set_dictionary": (i32, [vp, vp]),
+        "cofem_fit": (i32, [vp, vp]),
+        "cofem_posterior": (i32, [vp, vp, vp, vp, ctypes.POINTER(Stats)]),
+        "cofem_apply_A": (i32, [vp, vp, vp, vp, i32, i32, vp]),
+        "cofem_set_timing": (i32, [vp, i32]),
+        "cofem_get_timing": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise CofemError(rc, load().cofem_last_error().decode())
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def make_params(N, D, beta, K, T, U, tol, theta="ones", stop="joint", op="dense", phi_dtype="fp32",
+                refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30) -> Params:
+    return Params(N=int(N), D=int(D), beta=float(beta), K=int(K), T=int(T), U=int(U), tol=float(tol),
+                  theta_mode=THETA[theta], stop_mode=STOP[stop], op_kind=OPS[op], phi_dtype=DTYPES[phi_dtype],
+                  refine_last=int(refine_last), conv_taps=int(conv_taps), seed=int(seed) & ((1 << 64) - 1),
+                  alpha_floor=float(alpha_floor))
+
+
+class CoFEM:
+    """One problem shape on the current device and torch stream."""
+
+    def __init__(self, N, D, beta, K, T, U, tol, theta="ones", stop="joint", op="dense", phi_dtype="fp32",
+                 refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30, stream=None):
+        import torch
+
+        lib = load()
+        self.params = make_params(N, D, beta, K, T, U, tol, theta, stop, op, phi_dtype, refine_last, conv_taps,
+                                  seed, alpha_floor)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib.cofem_create(ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(h)))
+        self._h = h
+        self.N, self.D = int(N), int(D)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().cofem_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _dev(self, t, n, name):
+        import torch
+
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+        if t.numel() != n:
+            raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_dictionary(self, phi):
+        n = self.N * self.D if self.params.op_kind == 0 else self.params.conv_taps
+        _check(load().cofem_set_dictionary(self._h, self._dev(phi, n, "phi")))
+
+    def fit(self, y):
+        _check(load().cofem_fit(self._h, self._dev(y, self.N, "y")))
+
+    def posterior(self):
+        import torch
+
+        dev = torch.device("cuda", torch.cuda.current_device())
+        mu = torch.empty(self.D, dtype=torch.float32, device=dev)
+        s = torch.empty_like(mu)
+        alpha = torch.empty_like(mu)
+        st = Stats()
+        _check(load().cofem_posterior(self._h, ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(s.data_ptr()),
+                                      ctypes.c_void_p(alpha.data_ptr()), ctypes.byref(st)))
+        return mu, s, alpha, st.as_dict()
+
+    def apply_A(self, alpha, P, use_bf16=False, want_pi=False):
+        """Psi = beta Phi^T Phi P + alpha * P for P of shape (ncols, D) (rows = columns of the block)."""
+        import torch
+
+        ncols = P.shape[0]
+        Psi = torch.empty_like(P)
+        pi = torch.empty(ncols, dtype=torch.float64, device=P.device) if want_pi else None
+        _check(load().cofem_apply_A(self._h, self._dev(alpha, self.D, "alpha"),
+                                    self._dev(P, ncols * self.D, "P"), ctypes.c_void_p(Psi.data_ptr()),
+                                    int(ncols), int(bool(use_bf16)),
+                                    ctypes.c_void_p(pi.data_ptr()) if pi is not None else None))
+        return (Psi, pi) if want_pi else Psi
+
+    def set_timing(self, enable: bool):
+        _check(load().cofem_set_timing(self._h, int(bool(enable))))
+
+    def get_timing(self, which: str):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(load().cofem_get_timing(self._h, 1 if which == "bf16" else 0, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)

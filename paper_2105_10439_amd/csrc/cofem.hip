@@ -1,0 +1,453 @@
+// Host driver of the CoFEM hot path and its C ABI (include/cofem.h).
+//
+// One context = one problem shape on one device and one stream.  The driver
+// runs Algorithm 1 on the host side of the boundary and keeps every vector,
+// every CG scalar and the stop decision on the device: the host only enqueues
+// fixed chunks of CG steps and reads back one small state record per chunk;
+// steps enqueued after the stop rule fired are no-ops on the device.
+#include "cofem.h"
+#include "kernels.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#define COFEM_API extern "C" __attribute__((visibility("default")))
+
+using namespace cofem;
+
+namespace {
+
+thread_local std::string g_err;
+
+cofem_status fail(cofem_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(COFEM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline int64_t round_up(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
+
+uint64_t mix64_host(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct TimedLaunch {
+  hipEvent_t a, b;
+  int which;      // 0 = FP32 operator, 1 = bf16 operator
+  int step;       // CG step index within the chunk
+};
+
+}  // namespace
+
+struct cofem_ctx {
+  cofem_params p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int64_t Np = 0, Dp = 0;
+  int Q = 0, Qp = 0;
+  bool need32 = false, need16 = false;
+  bool dict_loaded = false;
+  bool fitted = false;
+  // dictionary layouts
+  float* phi32 = nullptr;
+  float* phi32T = nullptr;
+  uint16_t* phi16 = nullptr;
+  uint16_t* phi16T = nullptr;
+  // D- and N-vectors
+  float *theta = nullptr, *alpha = nullptr, *alpha_hook = nullptr, *b32 = nullptr, *b16 = nullptr;
+  float* minv = nullptr;
+  float *mu = nullptr, *s = nullptr, *yv = nullptr;
+  // CG blocks
+  float *X = nullptr, *R = nullptr, *Pd = nullptr, *Psi = nullptr, *V = nullptr;
+  uint16_t *PdH = nullptr, *PdL = nullptr, *VH = nullptr, *VL = nullptr;
+  float* Ypart = nullptr;
+  double* part = nullptr;
+  CGState* st = nullptr;
+  CGState* h_st = nullptr;  // pinned host mirror
+  GemmCfg g1_16{}, g2_16{}, g1_32{}, g2_32{};
+  int chunk = 8;
+  cofem_stats stats{};
+  // operator timing
+  bool timing = false;
+  double t_ms[2] = {0, 0};
+  int64_t t_n[2] = {0, 0};
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<TimedLaunch> pending;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+template <class T>
+cofem_status dalloc(cofem_ctx* c, T** out, size_t n) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(COFEM_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed: " +
+                                  hipGetErrorString(e));
+  }
+  c->allocs.push_back(p);
+  *out = static_cast<T*>(p);
+  return COFEM_OK;
+}
+
+void free_all(cofem_ctx* c) {
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->h_st) (void)hipHostFree(c->h_st);
+  c->h_st = nullptr;
+  for (auto& t : c->pending) {
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->pending.clear();
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
+}
+
+cofem_status validate(const cofem_params* p) {
+  if (!p) return fail(COFEM_EINVAL, "params is NULL");
+  if (p->N < 1 || p->D < 1) return fail(COFEM_EINVAL, "N and D must be >= 1");
+  if (p->N > (int64_t(1) << 31) || p->D > (int64_t(1) << 31)) return fail(COFEM_EINVAL, "N or D too large");
+  if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return fail(COFEM_EINVAL, "beta must be finite and > 0");
+  if (p->K < 1 || p->K > COFEM_MAX_K) return fail(COFEM_EINVAL, "K must be in [1, COFEM_MAX_K]");
+  if (p->T < 1 || p->T > COFEM_MAX_T) return fail(COFEM_EINVAL, "T must be in [1, COFEM_MAX_T]");
+  if (p->U < 1) return fail(COFEM_EINVAL, "U must be >= 1");
+  if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return fail(COFEM_EINVAL, "tol must be finite and >= 0");
+  if (p->theta_mode != COFEM_THETA_ONES && p->theta_mode != COFEM_THETA_JACOBI)
+    return fail(COFEM_EINVAL, "bad theta_mode");
+  if (p->stop_mode != COFEM_STOP_JOINT && p->stop_mode != COFEM_STOP_COLUMN)
+    return fail(COFEM_EINVAL, "bad stop_mode");
+  if (p->phi_dtype != COFEM_PHI_FP32 && p->phi_dtype != COFEM_PHI_BF16) return fail(COFEM_EINVAL, "bad phi_dtype");
+  if (p->refine_last < 0 || p->refine_last > p->T) return fail(COFEM_EINVAL, "refine_last must be in [0, T]");
+  if (!(p->alpha_floor > 0.0) || !std::isfinite(p->alpha_floor))
+    return fail(COFEM_EINVAL, "alpha_floor must be finite and > 0");
+  if (p->op_kind == COFEM_OP_CONV) return fail(COFEM_EINVAL, "op_kind COFEM_OP_CONV is not available in this build");
+  if (p->op_kind != COFEM_OP_DENSE) return fail(COFEM_EINVAL, "bad op_kind");
+  return COFEM_OK;
+}
+
+SolveCfg solve_cfg(const cofem_ctx* c) {
+  SolveCfg s;
+  s.Q = c->Q;
+  s.Qp = c->Qp;
+  s.K = c->p.K;
+  s.U = c->p.U;
+  s.stop_mode = c->p.stop_mode;
+  s.tol = c->p.tol;
+  s.beta = c->p.beta;
+  return s;
+}
+
+cofem_status timed_begin(cofem_ctx* c, int which, int step, TimedLaunch* t) {
+  t->which = which;
+  t->step = step;
+  for (int i = 0; i < 2; ++i) {
+    hipEvent_t e;
+    if (!c->ev_pool.empty()) {
+      e = c->ev_pool.back();
+      c->ev_pool.pop_back();
+    } else {
+      HIP_TRY(hipEventCreate(&e));
+    }
+    (i == 0 ? t->a : t->b) = e;
+  }
+  HIP_TRY(hipEventRecord(t->a, c->stream));
+  return COFEM_OK;
+}
+
+cofem_status timed_end(cofem_ctx* c, TimedLaunch* t) {
+  HIP_TRY(hipEventRecord(t->b, c->stream));
+  c->pending.push_back(*t);
+  return COFEM_OK;
+}
+
+// Called after a stream sync: accumulate the launches of the first `real_steps`
+// steps of the chunk (later ones were no-ops after the stop rule fired).
+cofem_status harvest(cofem_ctx* c, int real_steps) {
+  for (auto& t : c->pending) {
+    if (t.step < real_steps) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+      c->t_ms[t.which] += ms;
+      c->t_n[t.which] += 1;
+    }
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->pending.clear();
+  return COFEM_OK;
+}
+
+// Psi = A Pd into c->Psi and pi into the state, for the given alpha buffer.
+cofem_status apply_operator(cofem_ctx* c, bool use16, const float* alpha, const SolveCfg& sc, int step) {
+  TimedLaunch t;
+  cofem_status rc;
+  if (use16) {
+    if (c->timing && (rc = timed_begin(c, 1, step, &t)) != COFEM_OK) return rc;
+    launch_gemm_bf16(c->g1_16, c->phi16, c->Np, c->Dp, c->PdH, c->PdL, c->Qp, c->Ypart, c->st, c->stream);
+    if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
+    launch_finish_pass1(c->Ypart, c->g1_16.splits, c->Qp, c->Np, nullptr, c->VH, c->VL, c->st, c->stream);
+    if (c->timing && (rc = timed_begin(c, 1, step, &t)) != COFEM_OK) return rc;
+    launch_gemm_bf16(c->g2_16, c->phi16T, c->Dp, c->Np, c->VH, c->VL, c->Qp, c->Ypart, c->st, c->stream);
+    if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
+    launch_finish_pass2(sc, c->Ypart, c->g2_16.splits, c->Dp, alpha, c->Pd, c->Psi, c->part, c->st, c->stream);
+  } else {
+    if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
+    launch_gemm_f32(c->g1_32, c->phi32, c->Np, c->Dp, c->Pd, c->Qp, c->Ypart, c->st, c->stream);
+    if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
+    launch_finish_pass1(c->Ypart, c->g1_32.splits, c->Qp, c->Np, c->V, nullptr, nullptr, c->st, c->stream);
+    if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
+    launch_gemm_f32(c->g2_32, c->phi32T, c->Dp, c->Np, c->V, c->Qp, c->Ypart, c->st, c->stream);
+    if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
+    launch_finish_pass2(sc, c->Ypart, c->g2_32.splits, c->Dp, alpha, c->Pd, c->Psi, c->part, c->st, c->stream);
+  }
+  return COFEM_OK;
+}
+
+cofem_status sync_state(cofem_ctx* c) {
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->h_st, c->st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return COFEM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+COFEM_API int32_t cofem_abi_version(void) { return COFEM_ABI_VERSION; }
+
+COFEM_API const char* cofem_last_error(void) { return g_err.c_str(); }
+
+COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_ctx** out) {
+  if (!out) return fail(COFEM_EINVAL, "out is NULL");
+  *out = nullptr;
+  cofem_status rc = validate(p);
+  if (rc != COFEM_OK) return rc;
+  cofem_ctx* c = new (std::nothrow) cofem_ctx();
+  if (!c) return fail(COFEM_ENOMEM, "host allocation failed");
+  c->p = *p;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(COFEM_EDEVICE, "hipGetDevice failed");
+  }
+  c->Np = round_up(p->N, 256);
+  c->Dp = round_up(p->D, 256);
+  c->Q = p->K + 1;
+  c->Qp = (int)round_up(c->Q, 16);
+  c->need16 = p->phi_dtype == COFEM_PHI_BF16;
+  c->need32 = p->phi_dtype == COFEM_PHI_FP32 || p->refine_last > 0;
+  c->g1_16 = choose_gemm(c->Np, c->Dp, 1);
+  c->g2_16 = choose_gemm(c->Dp, c->Np, 1);
+  c->g1_32 = choose_gemm(c->Np, c->Dp, 0);
+  c->g2_32 = choose_gemm(c->Dp, c->Np, 0);
+  const int64_t Np = c->Np, Dp = c->Dp, Qp = c->Qp;
+  const int64_t ysplit = std::max<int64_t>(std::max<int64_t>(c->g1_16.splits, c->g1_32.splits) * Np,
+                                           std::max<int64_t>(c->g2_16.splits, c->g2_32.splits) * Dp);
+  const size_t nd = (size_t)Np * (size_t)Dp;
+#define TRY(x)                   \
+  do {                           \
+    cofem_status r_ = (x);       \
+    if (r_ != COFEM_OK) {        \
+      free_all(c);               \
+      delete c;                  \
+      return r_;                 \
+    }                            \
+  } while (0)
+  if (c->need32) {
+    TRY(dalloc(c, &c->phi32, nd));
+    TRY(dalloc(c, &c->phi32T, nd));
+    TRY(dalloc(c, &c->V, (size_t)Qp * Np));
+  }
+  if (c->need16) {
+    TRY(dalloc(c, &c->phi16, nd));
+    TRY(dalloc(c, &c->phi16T, nd));
+    TRY(dalloc(c, &c->PdH, (size_t)Qp * Dp));
+    TRY(dalloc(c, &c->PdL, (size_t)Qp * Dp));
+    TRY(dalloc(c, &c->VH, (size_t)Qp * Np));
+    TRY(dalloc(c, &c->VL, (size_t)Qp * Np));
+  }
+  TRY(dalloc(c, &c->theta, Dp));
+  TRY(dalloc(c, &c->alpha, Dp));
+  TRY(dalloc(c, &c->alpha_hook, Dp));
+  TRY(dalloc(c, &c->b32, Dp));
+  TRY(dalloc(c, &c->b16, Dp));
+  TRY(dalloc(c, &c->minv, Dp));
+  TRY(dalloc(c, &c->mu, Dp));
+  TRY(dalloc(c, &c->s, Dp));
+  TRY(dalloc(c, &c->yv, Np));
+  TRY(dalloc(c, &c->X, (size_t)Qp * Dp));
+  TRY(dalloc(c, &c->R, (size_t)Qp * Dp));
+  TRY(dalloc(c, &c->Pd, (size_t)Qp * Dp));
+  TRY(dalloc(c, &c->Psi, (size_t)Qp * Dp));
+  TRY(dalloc(c, &c->Ypart, (size_t)Qp * (size_t)ysplit));
+  TRY(dalloc(c, &c->part, (size_t)(Dp / VSPAN + 1) * 2 * QMAX));
+  TRY(dalloc(c, &c->st, 1));
+  if (hipHostMalloc((void**)&c->h_st, sizeof(CGState), hipHostMallocDefault) != hipSuccess) {
+    c->h_st = nullptr;
+    free_all(c);
+    delete c;
+    return fail(COFEM_ENOMEM, "pinned host allocation failed");
+  }
+#undef TRY
+  launch_state_reset(c->st, c->Q, c->stream);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_all(c);
+    delete c;
+    return fail(COFEM_EDEVICE, "workspace initialisation failed");
+  }
+  *out = c;
+  return COFEM_OK;
+}
+
+COFEM_API void cofem_destroy(cofem_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+COFEM_API cofem_status cofem_set_dictionary(cofem_ctx* c, const float* phi) {
+  if (!c || !phi) return fail(COFEM_EINVAL, "NULL argument");
+  const double t0 = now_ms();
+  launch_dict_layouts(phi, c->p.N, c->p.D, c->Np, c->Dp, c->phi32, c->phi32T, c->phi16, c->phi16T, c->stream);
+  // theta from the caller's FP32 matrix (b is formed per fit from the library's copies)
+  launch_theta(phi, c->p.N, c->p.D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->theta, c->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->dict_loaded = true;
+  c->stats.ms_setup = now_ms() - t0;
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_fit(cofem_ctx* c, const float* y) {
+  if (!c || !y) return fail(COFEM_EINVAL, "NULL argument");
+  if (!c->dict_loaded) return fail(COFEM_ESTATE, "cofem_fit before cofem_set_dictionary");
+  const double t0 = now_ms();
+  const cofem_params& p = c->p;
+  const SolveCfg sc = solve_cfg(c);
+  const double ms_setup = c->stats.ms_setup;
+  std::memset(&c->stats, 0, sizeof(c->stats));
+  c->stats.ms_setup = ms_setup;
+  c->fitted = false;
+  launch_state_reset(c->st, c->Q, c->stream);
+  launch_copy_pad(y, p.N, c->Np, 0.0f, c->yv, c->stream);
+  // b = beta Phi^T y, formed with the same dictionary as the operator of each phase: the
+  // rounding residual of an FP32 b is not in the range of the bf16 Phi^T, and EM would
+  // amplify it through the directions that only diag(alpha) constrains.
+  if (c->need32) launch_rhs(c->phi32T, nullptr, c->Np, c->Dp, c->yv, p.beta, c->b32, c->stream);
+  if (c->need16) launch_rhs(nullptr, c->phi16T, c->Np, c->Dp, c->yv, p.beta, c->b16, c->stream);
+  launch_fill(c->alpha, 1.0f, c->Dp, c->stream);
+  for (int t = 1; t <= p.T; ++t) {
+    const bool use16 = c->need16 && (t <= p.T - p.refine_last);
+    const uint64_t key = mix64_host(p.seed + (uint64_t)t * GOLDEN_GAMMA);
+    launch_em_init(sc, key, p.D, c->Dp, use16 ? c->b16 : c->b32, c->theta, c->alpha, c->minv, c->X, c->R, c->Pd,
+                   use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr, c->part, c->st, c->stream);
+    int prev_steps = 0;
+    for (;;) {
+      for (int i = 0; i < c->chunk; ++i) {
+        cofem_status rc = apply_operator(c, use16, c->alpha, sc, i);
+        if (rc != COFEM_OK) return rc;
+        launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->part, c->st, c->stream);
+        launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr,
+                            c->st, c->stream);
+      }
+      cofem_status rc = sync_state(c);
+      if (rc != COFEM_OK) return rc;
+      if (c->timing && (rc = harvest(c, c->h_st->steps - prev_steps)) != COFEM_OK) return rc;
+      prev_steps = c->h_st->steps;
+      if (c->h_st->done) break;
+    }
+    c->stats.cg_steps[t - 1] = c->h_st->steps;
+    c->stats.rel_resid[t - 1] = c->h_st->delta;
+    c->stats.used_bf16[t - 1] = use16 ? 1 : 0;
+    c->stats.total_cg_steps += c->h_st->steps;
+    launch_mstep(sc, key, p.D, c->Dp, c->X, c->mu, c->s, c->alpha, p.alpha_floor, t < p.T ? 1 : 0, c->st,
+                 c->stream);
+  }
+  cofem_status rc = sync_state(c);
+  if (rc != COFEM_OK) return rc;
+  c->stats.T = p.T;
+  c->stats.clamped = c->h_st->clamped;
+  c->stats.breakdown = c->h_st->breakdown;
+  c->stats.ms_fit = now_ms() - t0;
+  c->fitted = true;
+  if (c->h_st->active[0] == 0 && c->h_st->breakdown > 0 && p.stop_mode == COFEM_STOP_JOINT) {
+    // the mu column can only be inactive in joint mode through a breakdown
+    return fail(COFEM_EBREAKDOWN, "CG breakdown in the mu column");
+  }
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_posterior(cofem_ctx* c, float* mu, float* s, float* alpha, cofem_stats* st) {
+  if (!c) return fail(COFEM_EINVAL, "NULL context");
+  if (!c->fitted) return fail(COFEM_ESTATE, "cofem_posterior before a successful cofem_fit");
+  const size_t bytes = (size_t)c->p.D * sizeof(float);
+  if (mu) HIP_TRY(hipMemcpyAsync(mu, c->mu, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (s) HIP_TRY(hipMemcpyAsync(s, c->s, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (alpha) HIP_TRY(hipMemcpyAsync(alpha, c->alpha, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (st) *st = c->stats;
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const float* P, float* Psi, int32_t ncols,
+                                     int32_t use_bf16, double* pi) {
+  if (!c || !alpha || !P || !Psi) return fail(COFEM_EINVAL, "NULL argument");
+  if (!c->dict_loaded) return fail(COFEM_ESTATE, "cofem_apply_A before cofem_set_dictionary");
+  if (ncols < 1 || ncols > c->Qp) return fail(COFEM_EINVAL, "ncols must be in [1, padded K+1]");
+  if (use_bf16 && !c->need16) return fail(COFEM_EINVAL, "bfloat16 operator needs phi_dtype = COFEM_PHI_BF16");
+  if (!use_bf16 && !c->need32) return fail(COFEM_EINVAL, "FP32 operator needs phi_dtype = FP32 or refine_last > 0");
+  SolveCfg sc = solve_cfg(c);
+  sc.Q = ncols;
+  launch_copy_pad(alpha, c->p.D, c->Dp, 1.0f, c->alpha_hook, c->stream);
+  launch_pack_block(P, ncols, c->p.D, c->Qp, c->Dp, c->Pd, use_bf16 ? c->PdH : nullptr, use_bf16 ? c->PdL : nullptr,
+                    c->stream);
+  launch_state_reset(c->st, c->Q, c->stream);
+  cofem_status rc = apply_operator(c, use_bf16 != 0, c->alpha_hook, sc, 0);
+  if (rc != COFEM_OK) return rc;
+  launch_unpack_block(c->Psi, ncols, c->p.D, c->Dp, Psi, c->stream);
+  if (pi) HIP_TRY(hipMemcpyAsync(pi, c->st->pi, sizeof(double) * ncols, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->timing && (rc = harvest(c, 1)) != COFEM_OK) return rc;
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_set_timing(cofem_ctx* c, int32_t enable) {
+  if (!c) return fail(COFEM_EINVAL, "NULL context");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  cofem_status rc = harvest(c, 0);
+  if (rc != COFEM_OK) return rc;
+  c->timing = enable != 0;
+  c->t_ms[0] = c->t_ms[1] = 0.0;
+  c->t_n[0] = c->t_n[1] = 0;
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_get_timing(cofem_ctx* c, int32_t which, double* total_ms, int64_t* launches) {
+  if (!c || which < 0 || which > 1) return fail(COFEM_EINVAL, "bad argument");
+  if (total_ms) *total_ms = c->t_ms[which];
+  if (launches) *launches = c->t_n[which];
+  return COFEM_OK;
+}

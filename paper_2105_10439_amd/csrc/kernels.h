@@ -1,0 +1,111 @@
+// Internal interface between the gfx950 kernels (kernels.hip) and the host
+// driver (cofem.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cofem {
+
+constexpr int QMAX = 64;          // padded right-hand-side columns per problem
+constexpr int VBLOCK = 256;       // threads per block of the vector kernels
+constexpr int VSPAN = 256;        // coordinates per block of the per-column vector kernels
+constexpr uint64_t GOLDEN_GAMMA = 0x9E3779B97F4A7C15ull;
+
+// Device-resident state of one multi-RHS PCG solve (Algorithm 2).  All step
+// scalars are FP64.  Written only by the single "last" block of a kernel.
+struct CGState {
+  double rho[QMAX];     // rho_q = sum_j R_jq W_jq
+  double pi[QMAX];      // pi_q = sum_j P_jq Psi_jq
+  double gamma[QMAX];   // gamma_q = rho_q / pi_q
+  double eta[QMAX];     // eta_q = rho_q / rho_q^old
+  double bn2[QMAX];     // ||B_q||^2
+  double rn2[QMAX];     // ||R_q||^2 after the last update
+  double bnorm2;        // ||B||_F^2 over the Q real columns
+  double delta;         // ||R||_F / ||B||_F after the last update
+  int active[QMAX];     // column still iterating
+  int done;             // stop rule met or U steps taken
+  int steps;            // operator applications in this solve
+  int breakdown;        // columns frozen because pi_q <= 0 with rho_q != 0
+  int clamped;          // M-step floor events (this fit)
+  unsigned cnt[8];      // last-block arrival counters (zero between kernels)
+};
+
+struct SolveCfg {
+  int Q, Qp, K, U, stop_mode;
+  double tol, beta;
+};
+
+// ---- setup -----------------------------------------------------------------
+// Copy the caller's N x D row-major FP32 dictionary into padded layouts:
+// phi32 (Np x Dp), phi32T (Dp x Np), phi16 (Np x Dp, bf16 bits), phi16T (Dp x Np).
+// Any output pointer may be null.  Padding is zero.
+void launch_dict_layouts(const float* phi, int64_t N, int64_t D, int64_t Np, int64_t Dp, float* phi32,
+                         float* phi32T, uint16_t* phi16, uint16_t* phi16T, hipStream_t s);
+
+// theta_j = sum_i Phi_ij^2 (jacobi) or 1 from the caller's N x D matrix; padding 1.
+void launch_theta(const float* phi, int64_t N, int64_t D, int64_t Dp, int jacobi, float* theta, hipStream_t s);
+
+// b_j = beta * sum_i Phi_ij y_i from the transposed layout (FP32 if phi32T is not
+// null, else bf16), FP64 sums; y is the padded observation (Np floats).
+void launch_rhs(const float* phi32T, const uint16_t* phi16T, int64_t Np, int64_t Dp, const float* y, double beta,
+                float* b, hipStream_t s);
+
+// x[0..n) = v.
+void launch_fill(float* x, float v, int64_t n, hipStream_t s);
+
+// ---- per EM iteration --------------------------------------------------------
+// Probes for iteration key `key`, B = [b | p_1..p_K | 0], minv = 1/(beta theta + alpha),
+// X = 0, R = B, Pd = W = minv R (FP32 and, if PdH != null, bf16 hi/lo), and the
+// initial rho, ||B_q||^2, active flags; resets done/steps.
+void launch_em_init(const SolveCfg& c, uint64_t key, int64_t D, int64_t Dp, const float* b,
+                    const float* theta, const float* alpha, float* minv, float* X, float* R, float* Pd,
+                    uint16_t* PdH, uint16_t* PdL, double* part, CGState* st, hipStream_t s);
+
+// mu = X_0, s = (1/K) sum_k p_k X_k (probes regenerated from `key`); if do_mstep,
+// alpha = 1 / max(mu^2 + s, floor) and clamp events are counted in st->clamped.
+void launch_mstep(const SolveCfg& c, uint64_t key, int64_t D, int64_t Dp, const float* X, float* mu,
+                  float* s_out, float* alpha, double floor, int do_mstep, CGState* st, hipStream_t s);
+
+// ---- operator A P = beta Phi^T (Phi P) + alpha P ----------------------------
+struct GemmCfg {
+  int rt;        // row tiles of 16 per wave (1, 2 or 4); a block has 4 waves
+  int splits;    // split of the reduction dimension
+  int64_t kchunk;
+};
+GemmCfg choose_gemm(int64_t rows, int64_t kdim, int bf16);
+
+// Ypart[split][q][row] = sum_{k in split} M[row, k] Z[q, k], for q < Qp.
+// bf16: M, ZH, ZL are bf16 bits, products of M with ZH and ZL accumulate in FP32.
+void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
+                      const uint16_t* ZL, int Qp, float* Ypart, const CGState* st, hipStream_t s);
+void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Qp,
+                     float* Ypart, const CGState* st, hipStream_t s);
+
+// V = sum_split Ypart (rows Np); writes V (FP32) and/or VH/VL (bf16 hi/lo).
+void launch_finish_pass1(const float* Ypart, int splits, int Qp, int64_t Np, float* V, uint16_t* VH,
+                         uint16_t* VL, const CGState* st, hipStream_t s);
+
+// Psi = beta * sum_split Ypart + alpha * Pd, pi_q = sum_j Pd_jq Psi_jq, then
+// gamma_q (and breakdown) in the last block.
+void launch_finish_pass2(const SolveCfg& c, const float* Ypart, int splits, int64_t Dp, const float* alpha,
+                         const float* Pd, float* Psi, double* part, CGState* st, hipStream_t s);
+
+// ---- CG vector updates (Algorithm 2 after the operator) -----------------------
+// X += Pd gamma, R -= Psi gamma, ||R_q||^2, rho'_q = sum R minv R; last block applies
+// the stop rule and computes eta.
+void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
+                      const float* Psi, double* part, CGState* st, hipStream_t s);
+// Pd = minv R + eta Pd (FP32, and bf16 hi/lo if PdH != null).
+void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
+                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s);
+
+// ---- test-hook helpers ---------------------------------------------------------
+// Copy ncols columns of length D (caller layout) into a Qp x Dp block (zero padding),
+// optionally also as bf16 hi/lo.
+void launch_pack_block(const float* src, int ncols, int64_t D, int Qp, int64_t Dp, float* dst, uint16_t* dH,
+                       uint16_t* dL, hipStream_t s);
+void launch_unpack_block(const float* src, int ncols, int64_t D, int64_t Dp, float* dst, hipStream_t s);
+void launch_copy_pad(const float* src, int64_t n, int64_t np, float pad, float* dst, hipStream_t s);
+void launch_state_reset(CGState* st, int Q, hipStream_t s);
+
+}  // namespace cofem

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* every function declared in include/cofem.h is exported by libcofem.so;
+* the ctypes structs match the C layout (sizes and offsets, from gcc);
+* cofem_create rejects bad parameters before touching the device.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2105_10439_amd as lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cofem.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cofem_[A-Za-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_binding_exports():
+    assert _declared_functions() == sorted(lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    so = lib.load()
+    for name in _declared_functions():
+        assert hasattr(so, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (cofem_\w+)", out))
+    assert exported == set(_declared_functions())
+
+
+def _c_layout(struct, fields):
+    prog = "#include <stdio.h>\n#include <stddef.h>\n#include \"cofem.h\"\nint main(void){\n"
+    prog += f'printf("%zu\\n", sizeof({struct}));\n'
+    for f in fields:
+        prog += f'printf("%zu\\n", offsetof({struct}, {f}));\n'
+    prog += "return 0;}\n"
+    d = os.environ.get("TMPDIR", "/tmp")
+    src = os.path.join(d, f"layout_{os.getpid()}.c")
+    exe = src[:-2]
+    open(src, "w").write(prog)
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+    vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    os.remove(src)
+    os.remove(exe)
+    return vals[0], vals[1:]
+
+
+@pytest.mark.parametrize("cls,cname", [(lib.Params, "cofem_params"), (lib.Stats, "cofem_stats")])
+def test_struct_layout_matches_c(cls, cname):
+    names = [f[0] for f in cls._fields_]
+    size, offs = _c_layout(cname, names)
+    assert ctypes.sizeof(cls) == size
+    assert [getattr(cls, n).offset for n in names] == offs
+
+
+@pytest.mark.parametrize("bad", [
+    dict(N=0), dict(D=0), dict(beta=0.0), dict(beta=float("nan")), dict(K=0), dict(K=64), dict(T=0),
+    dict(T=513), dict(U=0), dict(tol=-1.0), dict(theta_mode=7), dict(stop_mode=3), dict(phi_dtype=2),
+    dict(refine_last=9), dict(alpha_floor=0.0), dict(op_kind=5),
+])
+def test_create_rejects_bad_params_without_device_work(bad):
+    so = lib.load()
+    p = lib.make_params(N=64, D=256, beta=1e4, K=8, T=5, U=10, tol=1e-6)
+    for k, v in bad.items():
+        setattr(p, k, v)
+    h = ctypes.c_void_p()
+    rc = so.cofem_create(ctypes.byref(p), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert so.cofem_last_error().decode()
+
+
+def test_null_arguments_are_rejected():
+    so = lib.load()
+    assert so.cofem_create(None, None, None) == -1
+    assert so.cofem_fit(None, None) == -1
+    assert so.cofem_set_dictionary(None, None) == -1
+    assert so.cofem_posterior(None, None, None, None, None) == -1
+    so.cofem_destroy(None)
+    assert so.cofem_abi_version() == 1

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (stated per test) follow from the arithmetic: the FP32 operator
+accumulates N (pass 1) and D (pass 2) products in FP32 with MFMA, so its
+normwise error is a small multiple of sqrt(N + D) * 2^-24; the bfloat16
+operator applies the bf16-rounded dictionary exactly (integer-like products,
+FP32 accumulation) to right-hand sides carried as two bf16 pieces, i.e. to
+about 2^-17 relative precision.  Fits are compared at the same probes, stop
+rule and tolerance; the acceptance bar on mu is 1e-4 relative for FP32.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_rne(x):
+    """float32 -> bfloat16 (round to nearest even) -> float32, by bit manipulation."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF
+    return (r << 16).astype(np.uint32).view(np.float32)
+
+
+def _t(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ---------------------------------------------------------------------------
+# operator
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N,D,ncols", [(300, 1000, 9), (64, 256, 1), (513, 777, 21), (1024, 2048, 33),
+                                       (200, 600, 64)])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_apply_A_matches_oracle(gpu, N, D, ncols, dtype):
+    rng = np.random.default_rng(N * 7 + D)
+    phi = workloads.gaussian_dictionary(N, D, seed=N + D)
+    beta = 1e4
+    alpha = np.exp(rng.uniform(-3, 12, D)).astype(np.float32)
+    P = rng.standard_normal((ncols, D)).astype(np.float32)
+    m = gpu.CoFEM(N, D, beta, K=max(ncols - 1, 1), T=1, U=1, tol=0.0, phi_dtype=dtype)
+    m.set_dictionary(_t(phi))
+    Psi, pi = m.apply_A(_t(alpha), _t(P), use_bf16=(dtype == "bf16"), want_pi=True)
+    Psi = _np(Psi)
+    phi_ref = _bf16_rne(phi) if dtype == "bf16" else phi
+    op = oracle.DenseOperator(phi_ref)
+    Pt = P.T.astype(np.float64)
+    ref = (beta * op.rmatvec(op.matvec(Pt)) + alpha.astype(np.float64)[:, None] * Pt).T
+    tol = 2e-5 if dtype == "fp32" else 1e-4
+    for q in range(ncols):
+        assert _rel(Psi[q], ref[q]) < tol, (q, _rel(Psi[q], ref[q]))
+    # pi_q = sum_j P_jq Psi_jq, FP64 on the device over the device's own Psi
+    pi_ref = np.sum(P.astype(np.float64) * Psi, axis=1)
+    assert np.allclose(_np(pi), pi_ref, rtol=1e-10)
+    if dtype == "bf16":
+        # the bf16 operator is the rounded dictionary's, not the FP32 one's
+        op32 = oracle.DenseOperator(phi)
+        ref32 = (beta * op32.rmatvec(op32.matvec(Pt)) + alpha.astype(np.float64)[:, None] * Pt).T
+        assert _rel(Psi[0], ref32[0]) > 5 * _rel(Psi[0], ref[0])
+    m.close()
+
+
+# ---------------------------------------------------------------------------
+# full fits
+# ---------------------------------------------------------------------------
+def _fit(gpu, prob, w, **kw):
+    m = gpu.CoFEM(prob.N, prob.D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], **kw)
+    m.set_dictionary(_t(prob.phi))
+    m.fit(_t(prob.y))
+    mu, s, alpha, st = m.posterior()
+    m.close()
+    return _np(mu), _np(s), _np(alpha), st
+
+
+def _oracle_fit(prob, w, phi=None, **kw):
+    phi = prob.phi if phi is None else phi
+    return oracle.cofem(phi, prob.y, prob.beta, T=w["T"], K=w["K"], U=w["U"], tol=w["tol"], **kw)
+
+
+def _support(mu_ref):
+    return np.abs(mu_ref) > 1e-3 * np.abs(mu_ref).max()
+
+
+@pytest.mark.parametrize("stop", ["joint", "column"])
+def test_fit_small_workload_fp32(gpu, stop):
+    w = dict(workloads.WORKLOADS["small"])
+    prob = workloads.make_workload("small")
+    seed = 1234
+    mu, s, alpha, st = _fit(gpu, prob, w, seed=seed, stop=stop)
+    ref = _oracle_fit(prob, w, seed=seed, stop_mode=stop)
+    print("small", stop, "mu rel", _rel(mu, ref.mu), "s rel", _rel(s, ref.s),
+          "steps gpu/oracle", st["total_cg_steps"], sum(ref.cg_steps))
+    assert _rel(mu, ref.mu) <= 1e-4
+    assert _rel(s, ref.s) <= 1e-3
+    sup = _support(ref.mu)
+    assert np.max(np.abs(np.log(alpha[sup] / ref.alpha[sup]))) < 1e-3
+    # FP32 rounding of the operator and of X, R, Pd slows CG down near tol = 1e-6 (a CPU
+    # emulation of this arithmetic reproduces the GPU's step counts); bounded, not equal
+    assert 0.95 * sum(ref.cg_steps) <= st["total_cg_steps"] <= 1.35 * sum(ref.cg_steps)
+    assert st["clamped"] == ref.clamped and st["breakdown"] == 0
+    assert all(np.isfinite(x).all() for x in (mu, s, alpha))
+
+
+def test_fit_ragged_jacobi_fp32(gpu):
+    """Sizes that are not multiples of any tile, Jacobi preconditioner."""
+    prob = workloads.dense_problem(N=331, D=1234, d=40, sigma=0.01, seed=77)
+    # T = 40: EM has settled, so mu no longer moves with the CG tolerance (the oracle's own
+    # mu changes by 4e-6 between tol 1e-6 and 1e-9 here, versus 6e-4 at T = 12)
+    w = dict(K=11, T=40, U=300, tol=1e-6)
+    mu, s, alpha, st = _fit(gpu, prob, w, seed=9, theta="jacobi")
+    ref = _oracle_fit(prob, w, seed=9, theta_mode="jacobi")
+    print("ragged jacobi mu rel", _rel(mu, ref.mu), "s rel", _rel(s, ref.s))
+    assert _rel(mu, ref.mu) <= 1e-4
+    assert _rel(s, ref.s) <= 1e-3
+
+
+def test_fit_t1_estep_probe_dependent(gpu):
+    """T = 1: mu and s of one E-step at alpha = 1.  s depends on the probe
+    bits at O(1/sqrt(K)), so matching it checks the device's probe hash."""
+    prob = workloads.dense_problem(N=256, D=1024, d=20, sigma=0.01, seed=5)
+    w = dict(K=16, T=1, U=500, tol=1e-9)
+    mu, s, alpha, st = _fit(gpu, prob, w, seed=31337)
+    ref = _oracle_fit(prob, w, seed=31337)
+    other = _oracle_fit(prob, w, seed=31338)
+    assert _rel(s, ref.s) < 1e-4
+    assert _rel(other.s, ref.s) > 1e-2
+    assert np.array_equal(alpha, np.ones(prob.D))
+
+
+def test_fit_is_deterministic(gpu):
+    prob = workloads.dense_problem(N=200, D=700, d=20, sigma=0.01, seed=6)
+    w = dict(K=9, T=8, U=200, tol=1e-6)
+    a = _fit(gpu, prob, w, seed=3)
+    b = _fit(gpu, prob, w, seed=3)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert a[3]["cg_steps"] == b[3]["cg_steps"]
+
+
+def test_fit_bf16_matches_oracle_on_rounded_dictionary(gpu):
+    """BF16 without refinement solves the problem of the bf16-rounded dictionary."""
+    w = dict(workloads.WORKLOADS["small"])
+    w["T"] = 20
+    prob = workloads.make_workload("small")
+    mu, s, alpha, st = _fit(gpu, prob, w, seed=5, phi_dtype="bf16")
+    ref = _oracle_fit(prob, w, phi=_bf16_rne(prob.phi), seed=5)
+    print("bf16 vs rounded-dictionary oracle: mu rel", _rel(mu, ref.mu), "s rel", _rel(s, ref.s))
+    assert all(st["used_bf16"])
+    assert _rel(mu, ref.mu) <= 1e-3
+    assert _rel(s, ref.s) <= 1e-2
+
+
+def test_fit_bf16_refined_against_fp32_oracle(gpu):
+    w = dict(workloads.WORKLOADS["small"])
+    w["T"] = 20
+    prob = workloads.make_workload("small")
+    mu, s, alpha, st = _fit(gpu, prob, w, seed=5, phi_dtype="bf16", refine_last=3)
+    ref = _oracle_fit(prob, w, seed=5)
+    print("bf16+3 refined vs fp32 oracle: mu rel", _rel(mu, ref.mu), "s rel", _rel(s, ref.s))
+    assert st["used_bf16"] == [1] * 17 + [0] * 3
+    assert _rel(mu, ref.mu) <= 2e-2
+
+
+def test_fit_medium_workload_fp32(gpu):
+    """The N=2048, D=8192 workload against the stored oracle fit (tests/golden/make_reference.py)."""
+    import os
+
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "medium_oracle.npz"))
+    w = dict(workloads.WORKLOADS["medium"])
+    prob = workloads.make_workload("medium")
+    mu, s, alpha, st = _fit(gpu, prob, w, seed=int(ref["seed"]))
+    e_mu, e_s = _rel(mu, ref["mu"]), _rel(s, ref["s"])
+    sup = _support(ref["mu"])
+    e_sup = _rel(mu[sup], ref["mu"][sup])
+    print(f"medium: mu rel {e_mu:.2e} (support {e_sup:.2e}), s rel {e_s:.2e}, CG steps {st['total_cg_steps']} "
+          f"(oracle {int(ref['cg_steps'].sum())})")
+    assert e_mu <= 1e-4
+    assert e_s <= 1e-3
