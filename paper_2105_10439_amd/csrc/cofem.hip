@@ -77,7 +77,8 @@ struct cofem_ctx {
   float *X = nullptr, *R = nullptr, *Pd = nullptr, *Psi = nullptr, *V = nullptr;
   uint16_t *PdH = nullptr, *PdL = nullptr, *VH = nullptr, *VL = nullptr;
   float* Ypart = nullptr;
-  double* part = nullptr;
+  double* part = nullptr;    // em_init partials and CG-update partials
+  double* pipart = nullptr;  // pi partials
   CGState* st = nullptr;
   CGState* h_st = nullptr;  // pinned host mirror
   GemmCfg g1_16{}, g2_16{}, g1_32{}, g2_32{};
@@ -208,7 +209,7 @@ cofem_status apply_operator(cofem_ctx* c, bool use16, const float* alpha, const 
     if (c->timing && (rc = timed_begin(c, 1, step, &t)) != COFEM_OK) return rc;
     launch_gemm_bf16(c->g2_16, c->phi16T, c->Dp, c->Np, c->VH, c->VL, c->Qp, c->Ypart, c->st, c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
-    launch_finish_pass2(sc, c->Ypart, c->g2_16.splits, c->Dp, alpha, c->Pd, c->Psi, c->part, c->st, c->stream);
+    launch_finish_pass2(sc, c->Ypart, c->g2_16.splits, c->Dp, alpha, c->Pd, c->Psi, c->pipart, c->st, c->stream);
   } else {
     if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
     launch_gemm_f32(c->g1_32, c->phi32, c->Np, c->Dp, c->Pd, c->Qp, c->Ypart, c->st, c->stream);
@@ -217,7 +218,7 @@ cofem_status apply_operator(cofem_ctx* c, bool use16, const float* alpha, const 
     if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
     launch_gemm_f32(c->g2_32, c->phi32T, c->Dp, c->Np, c->V, c->Qp, c->Ypart, c->st, c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
-    launch_finish_pass2(sc, c->Ypart, c->g2_32.splits, c->Dp, alpha, c->Pd, c->Psi, c->part, c->st, c->stream);
+    launch_finish_pass2(sc, c->Ypart, c->g2_32.splits, c->Dp, alpha, c->Pd, c->Psi, c->pipart, c->st, c->stream);
   }
   return COFEM_OK;
 }
@@ -301,7 +302,8 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   TRY(dalloc(c, &c->Pd, (size_t)Qp * Dp));
   TRY(dalloc(c, &c->Psi, (size_t)Qp * Dp));
   TRY(dalloc(c, &c->Ypart, (size_t)Qp * (size_t)ysplit));
-  TRY(dalloc(c, &c->part, (size_t)(Dp / VSPAN + 1) * 2 * QMAX));
+  TRY(dalloc(c, &c->part, (size_t)(Dp / VPART + 1) * 2 * QMAX));
+  TRY(dalloc(c, &c->pipart, (size_t)(Dp / VPART + 1) * QMAX));
   TRY(dalloc(c, &c->st, 1));
   if (hipHostMalloc((void**)&c->h_st, sizeof(CGState), hipHostMallocDefault) != hipSuccess) {
     c->h_st = nullptr;
@@ -368,7 +370,7 @@ COFEM_API cofem_status cofem_fit(cofem_ctx* c, const float* y) {
       for (int i = 0; i < c->chunk; ++i) {
         cofem_status rc = apply_operator(c, use16, c->alpha, sc, i);
         if (rc != COFEM_OK) return rc;
-        launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->part, c->st, c->stream);
+        launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream);
         launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr,
                             c->st, c->stream);
       }
@@ -426,6 +428,7 @@ COFEM_API cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const flo
   launch_state_reset(c->st, c->Q, c->stream);
   cofem_status rc = apply_operator(c, use_bf16 != 0, c->alpha_hook, sc, 0);
   if (rc != COFEM_OK) return rc;
+  launch_reduce_pi(ncols, c->Dp, c->pipart, c->st, c->stream);
   launch_unpack_block(c->Psi, ncols, c->p.D, c->Dp, Psi, c->stream);
   if (pi) HIP_TRY(hipMemcpyAsync(pi, c->st->pi, sizeof(double) * ncols, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(hipGetLastError());

@@ -8,7 +8,7 @@ namespace cofem {
 
 constexpr int QMAX = 64;          // padded right-hand-side columns per problem
 constexpr int VBLOCK = 256;       // threads per block of the vector kernels
-constexpr int VSPAN = 256;        // coordinates per block of the per-column vector kernels
+constexpr int VPART = 256;        // coordinates per partial-sum slot (sizes the reduction scratch)
 constexpr uint64_t GOLDEN_GAMMA = 0x9E3779B97F4A7C15ull;
 
 // Device-resident state of one multi-RHS PCG solve (Algorithm 2).  All step
@@ -85,16 +85,19 @@ void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdi
 void launch_finish_pass1(const float* Ypart, int splits, int Qp, int64_t Np, float* V, uint16_t* VH,
                          uint16_t* VL, const CGState* st, hipStream_t s);
 
-// Psi = beta * sum_split Ypart + alpha * Pd, pi_q = sum_j Pd_jq Psi_jq, then
-// gamma_q (and breakdown) in the last block.
+// Psi = beta * sum_split Ypart + alpha * Pd (columns q < c.Q) and per-chunk partials of
+// pi_q = sum_j Pd_jq Psi_jq into pipart ([q][chunk], chunks of 1024 coordinates).
 void launch_finish_pass2(const SolveCfg& c, const float* Ypart, int splits, int64_t Dp, const float* alpha,
-                         const float* Pd, float* Psi, double* part, CGState* st, hipStream_t s);
+                         const float* Pd, float* Psi, double* pipart, const CGState* st, hipStream_t s);
+// st->pi[q] = sum of the pi partials (test hook only; the CG update reduces them itself).
+void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipStream_t s);
 
 // ---- CG vector updates (Algorithm 2 after the operator) -----------------------
-// X += Pd gamma, R -= Psi gamma, ||R_q||^2, rho'_q = sum R minv R; last block applies
-// the stop rule and computes eta.
+// gamma_q = rho_q / pi_q (pi reduced from pipart), X += Pd gamma, R -= Psi gamma, partials
+// of ||R_q||^2 and rho'_q = sum R minv R into part; then one block applies the stop rule
+// and computes eta (two launches).
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
-                      const float* Psi, double* part, CGState* st, hipStream_t s);
+                      const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s);
 // Pd = minv R + eta Pd (FP32, and bf16 hi/lo if PdH != null).
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
                          uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s);

@@ -66,19 +66,31 @@ __device__ __forceinline__ double ld_agent(const double* p) {
 }
 
 // Returns true in exactly one block: the last of `total` blocks to arrive.
-// Partial results stored before the call are visible to that block.
+// Only thread 0 of a block may have written the block's partial result before
+// the call; it publishes it (release) before counting in, and the last block
+// acquires before it reads the partials of the others.
 __device__ bool arrive_last(unsigned* cnt, unsigned total) {
   __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
   if (threadIdx.x == 0) {
+    __threadfence();
     unsigned prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     s_last = (prev + 1u == total) ? 1 : 0;
+    if (s_last) __threadfence();
   }
   __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __threadfence();
-  return last;
+  return s_last != 0;
+}
+
+// Sum of v over the 256 threads of a block, in a fixed order; result in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sh[4];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  __syncthreads();
+  return r;
 }
 __device__ __forceinline__ void reset_counter(unsigned* cnt) {
   __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -290,79 +302,129 @@ __global__ __launch_bounds__(VBLOCK) void k_mstep(SolveCfg c, uint64_t key, int6
 // ---------------------------------------------------------------------------
 // operator: skinny MFMA contractions
 // ---------------------------------------------------------------------------
+// Tile order of the contractions.  Workgroups of a 1-D grid are dispatched
+// round-robin over the 8 XCDs (workgroup L runs on XCD L % 8), and each XCD has
+// its own L2.  Blocks that share a split of the reduction dimension read the
+// same slice of the right-hand-side block, so they are placed on the same XCD.
+__device__ __forceinline__ void tile_of(int L, int nrb, int splits, int& rb, int& sp) {
+  const int xcd = L & 7, slot = L >> 3;
+  if ((splits & 7) == 0) {
+    const int spx = splits >> 3;
+    sp = xcd * spx + slot % spx;
+    rb = slot / spx;
+  } else if ((8 % splits) == 0 && (nrb % (8 / splits)) == 0) {
+    const int g = 8 / splits;
+    sp = xcd / g;
+    rb = slot * g + xcd % g;
+  } else {
+    rb = L % nrb;
+    sp = L / nrb;
+  }
+}
+
 // Ypart[split][q][row] = sum_{k in split} M[row, k] * (ZH[q, k] + ZL[q, k]).
-// Block = 4 waves; wave w owns rows row0 .. row0 + 16 RT - 1 and all CT*16 columns.
+//
+// Block = 5 waves.  Waves 0-3 compute: wave w owns rows row0 .. row0 + 16 RT - 1
+// and all CT*16 columns, and streams its rows of M from HBM straight into VGPRs
+// in the MFMA operand layout, one stage ahead.  Wave 4 is a producer: it copies
+// the right-hand-side fragments of the next stage (KS * CT * {hi, lo}, 1 KB each,
+// already in MFMA lane order) from L2 into a double-buffered LDS tile, so the
+// compute waves never wait on those loads (vmcnt counts in issue order per wave).
 // v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16) .. +8), B[8(l/16) .. +8)[l%16]
 // and returns D[4(l/16) .. +4)[l%16].
-template <int RT, int CT>
-__global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ M, int64_t ldm,
-                                                   const uint16_t* __restrict__ ZH,
-                                                   const uint16_t* __restrict__ ZL, int64_t ldz,
-                                                   float* __restrict__ Yp, int64_t ldy, int Qp, int64_t kchunk,
-                                                   int64_t kdim, const int* __restrict__ done) {
+template <int RT, int CT, int KS>
+__global__ __launch_bounds__(320, 2) void k_gemm_bf16(const uint16_t* __restrict__ M, int64_t ldm,
+                                                      const uint16_t* __restrict__ ZH,
+                                                      const uint16_t* __restrict__ ZL, int64_t ldz,
+                                                      float* __restrict__ Yp, int64_t ldy, int Qp, int64_t kchunk,
+                                                      int64_t kdim, int nrb, int splits,
+                                                      const int* __restrict__ done) {
   if (done && *done) return;
+  constexpr int NF = KS * CT * 2;  // fragments per stage
+  constexpr int SK = 32 * KS;      // k per stage
+  __shared__ bf16x8_t sB[2][NF][64];
+  int rb, sp;
+  tile_of(blockIdx.x, nrb, splits, rb, sp);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, g = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t kb = (int64_t)sp * kchunk;
   const int64_t ke = (kb + kchunk < kdim) ? kb + kchunk : kdim;
+  const int nst = (ke > kb) ? (int)((ke - kb) / SK) : 0;
+  if (wave == 4) {
+    const uint16_t* src[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int s = f / (CT * 2), rem = f % (CT * 2), ct = rem >> 1, hl = rem & 1;
+      src[f] = (hl ? ZL : ZH) + (int64_t)(ct * 16 + r16) * ldz + kb + s * 32 + 8 * g;
+    }
+    if (nst > 0) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sB[0][f][lane] = *reinterpret_cast<const bf16x8_t*>(src[f]);
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+      // the next stage's fragments (the last stage reloads its own into the idle buffer)
+      const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
+      bf16x8_t t[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) t[f] = *reinterpret_cast<const bf16x8_t*>(src[f] + off);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sB[(st + 1) & 1][f][lane] = t[f];
+      __syncthreads();
+    }
+    return;
+  }
+  const int64_t row0 = (int64_t)rb * (64 * RT) + (int64_t)wave * (16 * RT);
   f32x4 acc[RT][CT];
 #pragma unroll
   for (int a = 0; a < RT; ++a)
 #pragma unroll
     for (int b = 0; b < CT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (kb < ke) {
-    const uint16_t* ap[RT];
-    const uint16_t* hp[CT];
-    const uint16_t* lp[CT];
+  const uint16_t* ap[RT];
 #pragma unroll
-    for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 8 * g;
+  for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 8 * g;
+  bf16x8_t acur[RT][KS];
+  if (nst > 0) {
 #pragma unroll
-    for (int b = 0; b < CT; ++b) {
-      hp[b] = ZH + (int64_t)(b * 16 + r16) * ldz + kb + 8 * g;
-      lp[b] = ZL + (int64_t)(b * 16 + r16) * ldz + kb + 8 * g;
-    }
-    bf16x8_t a0[RT], h0[CT], l0[CT];
+    for (int a = 0; a < RT; ++a)
 #pragma unroll
-    for (int a = 0; a < RT; ++a) a0[a] = *reinterpret_cast<const bf16x8_t*>(ap[a]);
+      for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + s * 32);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    // prefetch the next stage (the last stage re-reads its own rows: always in bounds);
+    // no branch here, so the prefetch stays in flight across the stage
+    const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
+    bf16x8_t anxt[RT][KS];
 #pragma unroll
-    for (int b = 0; b < CT; ++b) {
-      h0[b] = *reinterpret_cast<const bf16x8_t*>(hp[b]);
-      l0[b] = *reinterpret_cast<const bf16x8_t*>(lp[b]);
-    }
-    for (int64_t k = kb; k < ke; k += 32) {
-      // prefetch the next k-step (clamped to the last one: always in bounds)
-      const int64_t dk = (k + 32 < ke) ? 32 : 0;
-      bf16x8_t a1[RT], h1[CT], l1[CT];
+    for (int a = 0; a < RT; ++a)
 #pragma unroll
-      for (int a = 0; a < RT; ++a) {
-        ap[a] += dk;
-        a1[a] = *reinterpret_cast<const bf16x8_t*>(ap[a]);
-      }
+      for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + off + s * 32);
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this stage's MFMAs
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      bf16x8_t bh[CT], bl[CT];
 #pragma unroll
       for (int b = 0; b < CT; ++b) {
-        hp[b] += dk;
-        lp[b] += dk;
-        h1[b] = *reinterpret_cast<const bf16x8_t*>(hp[b]);
-        l1[b] = *reinterpret_cast<const bf16x8_t*>(lp[b]);
+        bh[b] = sB[buf][(s * CT + b) * 2 + 0][lane];
+        bl[b] = sB[buf][(s * CT + b) * 2 + 1][lane];
       }
 #pragma unroll
       for (int a = 0; a < RT; ++a)
 #pragma unroll
         for (int b = 0; b < CT; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[a], h0[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[a], l0[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[a][s], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[a][s], bl[b], acc[a][b], 0, 0, 0);
         }
-#pragma unroll
-      for (int a = 0; a < RT; ++a) a0[a] = a1[a];
-#pragma unroll
-      for (int b = 0; b < CT; ++b) {
-        h0[b] = h1[b];
-        l0[b] = l1[b];
-      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acur[a][s] = anxt[a][s];
   }
-  float* yb = Yp + (int64_t)blockIdx.y * Qp * ldy;
+  float* yb = Yp + (int64_t)sp * Qp * ldy;
 #pragma unroll
   for (int a = 0; a < RT; ++a)
 #pragma unroll
@@ -373,64 +435,96 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ 
     }
 }
 
-// FP32 version with v_mfma_f32_16x16x4_f32: each lane loads 4 consecutive k of
+// FP32 version with v_mfma_f32_16x16x4_f32.  Each lane holds 4 consecutive k of
 // its row (and of its column of Z) and feeds element e to the e-th MFMA, so the
-// four MFMAs cover 16 consecutive k with the same k order in both operands.
-template <int RT, int CT>
-__global__ __launch_bounds__(256) void k_gemm_f32(const float* __restrict__ M, int64_t ldm,
-                                                  const float* __restrict__ Z, int64_t ldz,
-                                                  float* __restrict__ Yp, int64_t ldy, int Qp, int64_t kchunk,
-                                                  int64_t kdim, const int* __restrict__ done) {
+// four MFMAs of a 16-k step see the same k order in both operands.  Same wave
+// roles and staging as above (1 KB fragment per 16-k step and column tile).
+template <int RT, int CT, int KS>
+__global__ __launch_bounds__(320, 2) void k_gemm_f32(const float* __restrict__ M, int64_t ldm,
+                                                     const float* __restrict__ Z, int64_t ldz,
+                                                     float* __restrict__ Yp, int64_t ldy, int Qp, int64_t kchunk,
+                                                     int64_t kdim, int nrb, int splits,
+                                                     const int* __restrict__ done) {
   if (done && *done) return;
+  constexpr int NF = KS * CT;
+  constexpr int SK = 16 * KS;
+  __shared__ f32x4 sB[2][NF][64];
+  int rb, sp;
+  tile_of(blockIdx.x, nrb, splits, rb, sp);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, g = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t kb = (int64_t)sp * kchunk;
   const int64_t ke = (kb + kchunk < kdim) ? kb + kchunk : kdim;
+  const int nst = (ke > kb) ? (int)((ke - kb) / SK) : 0;
+  if (wave == 4) {
+    const float* src[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int s = f / CT, ct = f % CT;
+      src[f] = Z + (int64_t)(ct * 16 + r16) * ldz + kb + s * 16 + 4 * g;
+    }
+    if (nst > 0) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sB[0][f][lane] = *reinterpret_cast<const f32x4*>(src[f]);
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+      const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
+      f32x4 t[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) t[f] = *reinterpret_cast<const f32x4*>(src[f] + off);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sB[(st + 1) & 1][f][lane] = t[f];
+      __syncthreads();
+    }
+    return;
+  }
+  const int64_t row0 = (int64_t)rb * (64 * RT) + (int64_t)wave * (16 * RT);
   f32x4 acc[RT][CT];
 #pragma unroll
   for (int a = 0; a < RT; ++a)
 #pragma unroll
     for (int b = 0; b < CT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (kb < ke) {
-    const float* ap[RT];
-    const float* zp[CT];
+  const float* ap[RT];
 #pragma unroll
-    for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 4 * g;
+  for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 4 * g;
+  f32x4 acur[RT][KS];
+  if (nst > 0) {
 #pragma unroll
-    for (int b = 0; b < CT; ++b) zp[b] = Z + (int64_t)(b * 16 + r16) * ldz + kb + 4 * g;
-    f32x4 a0[RT], z0[CT];
+    for (int a = 0; a < RT; ++a)
 #pragma unroll
-    for (int a = 0; a < RT; ++a) a0[a] = *reinterpret_cast<const f32x4*>(ap[a]);
+      for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + s * 16);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
+    f32x4 anxt[RT][KS];
 #pragma unroll
-    for (int b = 0; b < CT; ++b) z0[b] = *reinterpret_cast<const f32x4*>(zp[b]);
-    for (int64_t k = kb; k < ke; k += 16) {
-      const int64_t dk = (k + 16 < ke) ? 16 : 0;
-      f32x4 a1[RT], z1[CT];
+    for (int a = 0; a < RT; ++a)
 #pragma unroll
-      for (int a = 0; a < RT; ++a) {
-        ap[a] += dk;
-        a1[a] = *reinterpret_cast<const f32x4*>(ap[a]);
-      }
+      for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + off + s * 16);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int b = 0; b < CT; ++b) {
-        zp[b] += dk;
-        z1[b] = *reinterpret_cast<const f32x4*>(zp[b]);
-      }
+    for (int s = 0; s < KS; ++s) {
+      f32x4 bz[CT];
+#pragma unroll
+      for (int b = 0; b < CT; ++b) bz[b] = sB[buf][s * CT + b][lane];
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int a = 0; a < RT; ++a)
 #pragma unroll
           for (int b = 0; b < CT; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[a][e], z0[b][e], acc[a][b], 0, 0, 0);
-#pragma unroll
-      for (int a = 0; a < RT; ++a) a0[a] = a1[a];
-#pragma unroll
-      for (int b = 0; b < CT; ++b) z0[b] = z1[b];
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[a][s][e], bz[b][e], acc[a][b], 0, 0, 0);
     }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acur[a][s] = anxt[a][s];
   }
-  float* yb = Yp + (int64_t)blockIdx.y * Qp * ldy;
+  float* yb = Yp + (int64_t)sp * Qp * ldy;
 #pragma unroll
   for (int a = 0; a < RT; ++a)
 #pragma unroll
@@ -465,76 +559,82 @@ __global__ __launch_bounds__(256) void k_finish_pass1(const float* __restrict__ 
   }
 }
 
-// Psi = beta * sum_split Ypart + alpha Pd; pi partials; last block: pi, gamma.
-// Block = 4 waves over VSPAN coordinates (float4 per lane); wave w owns columns w, w+4, ...
+// The per-column vector kernels run one block per (chunk of VCHUNK coordinates,
+// column q): each thread owns 4 consecutive coordinates of one column, and a
+// block contributes one partial per reduced quantity, stored at [q][chunk].
+constexpr int VCHUNK = 1024;
+
+// Psi = beta * sum_split Ypart + alpha Pd, and the block's partial of
+// pi_q = sum_j Pd_jq Psi_jq, stored at pipart[q * nbx + chunk].
 __global__ __launch_bounds__(VBLOCK) void k_finish_pass2(SolveCfg c, const float* __restrict__ Yp, int splits,
                                                          int64_t Dp, const float* __restrict__ alpha,
                                                          const float* __restrict__ Pd, float* __restrict__ Psi,
-                                                         double* __restrict__ part, CGState* __restrict__ st) {
+                                                         double* __restrict__ pipart, const CGState* __restrict__ st) {
   if (st->done) return;
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * VSPAN + 4 * ln;
-  const f32x4 al = *reinterpret_cast<const f32x4*>(alpha + j);
-  for (int q = wv; q < c.Qp; q += 4) {
+  const int q = blockIdx.y, nbx = gridDim.x;
+  const int64_t j = (int64_t)blockIdx.x * VCHUNK + 4 * threadIdx.x;
+  double acc = 0.0;
+  if (j < Dp) {
     const int64_t o = (int64_t)q * Dp + j;
     f32x4 y = *reinterpret_cast<const f32x4*>(Yp + o);
     for (int sp = 1; sp < splits; ++sp) y += *reinterpret_cast<const f32x4*>(Yp + (int64_t)sp * c.Qp * Dp + o);
+    const f32x4 al = *reinterpret_cast<const f32x4*>(alpha + j);
     const f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
     f32x4 ps;
-    double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       ps[e] = (float)(c.beta * (double)y[e] + (double)al[e] * (double)p[e]);
       acc += (double)p[e] * (double)ps[e];
     }
     *reinterpret_cast<f32x4*>(Psi + o) = ps;
-    acc = wave_sum(acc);
-    if (ln == 0) part[(int64_t)blockIdx.x * QMAX + q] = acc;
   }
-  if (!arrive_last(&st->cnt[1], gridDim.x)) return;
-  __shared__ double s_pi[QMAX];
-  for (int q = wv; q < c.Qp; q += 4) {
-    const double pi = wave_sum_parts(part, gridDim.x, QMAX, q);
-    if (ln == 0) s_pi[q] = pi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < c.Qp; ++q) {
-      const double pi = s_pi[q];
-      const double rho = st->rho[q];
-      double gam = 0.0;
-      if (st->active[q]) {
-        if (pi > 0.0) {
-          gam = rho / pi;
-        } else if (rho != 0.0) {
-          st->active[q] = 0;
-          st->breakdown += 1;
-        }
-      }
-      st->pi[q] = pi;
-      st->gamma[q] = gam;
-    }
-    reset_counter(&st->cnt[1]);
-  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) pipart[(int64_t)q * nbx + blockIdx.x] = acc;
 }
 
-// X += gamma Pd, R -= gamma Psi; ||R_q||^2 and rho'_q = sum R (M^-1 R); stop rule, eta.
+// pi_q from its nbx partials (fixed order), the same value in every block that asks.
+__device__ __forceinline__ double column_pi(const double* pipart, int q, int nbx) {
+  __shared__ double s_pi;
+  if (threadIdx.x < 64) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nbx; b += 64) a += pipart[(int64_t)q * nbx + b];
+    a = wave_sum(a);
+    if (threadIdx.x == 0) s_pi = a;
+  }
+  __syncthreads();
+  return s_pi;
+}
+
+// gamma_q = rho_q / pi_q; X += gamma Pd, R -= gamma Psi; partials of ||R_q||^2 and
+// rho'_q = sum R (M^-1 R) at part[(q * nbx + chunk) * 2 + {0, 1}].
 __global__ __launch_bounds__(VBLOCK) void k_cg_update(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                       float* __restrict__ X, float* __restrict__ R,
                                                       const float* __restrict__ Pd, const float* __restrict__ Psi,
-                                                      double* __restrict__ part, CGState* __restrict__ st) {
+                                                      const double* __restrict__ pipart, double* __restrict__ part,
+                                                      CGState* __restrict__ st) {
   if (st->done) return;
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * VSPAN + 4 * ln;
-  const f32x4 mi = *reinterpret_cast<const f32x4*>(minv + j);
-  for (int q = wv; q < c.Qp; q += 4) {
-    const double gam = st->gamma[q];
+  const int q = blockIdx.y, nbx = gridDim.x;
+  const double pi = column_pi(pipart, q, nbx);
+  const double rho = st->rho[q];
+  const int act = st->active[q];
+  const double gam = (act && pi > 0.0) ? rho / pi : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->pi[q] = pi;
+    st->gamma[q] = gam;
+    if (act && !(pi > 0.0) && rho != 0.0) {  // breakdown: freeze the column
+      st->active[q] = 0;
+      atomicAdd(&st->breakdown, 1);
+    }
+  }
+  const int64_t j = (int64_t)blockIdx.x * VCHUNK + 4 * threadIdx.x;
+  double rr = 0.0, rw = 0.0;
+  if (j < Dp) {
     const int64_t o = (int64_t)q * Dp + j;
+    const f32x4 mi = *reinterpret_cast<const f32x4*>(minv + j);
     f32x4 x = *reinterpret_cast<const f32x4*>(X + o);
     f32x4 r = *reinterpret_cast<const f32x4*>(R + o);
     const f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
     const f32x4 ps = *reinterpret_cast<const f32x4*>(Psi + o);
-    double rr = 0.0, rw = 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       x[e] = (float)((double)x[e] + gam * (double)p[e]);
@@ -545,51 +645,73 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_update(SolveCfg c, int64_t Dp, co
     }
     *reinterpret_cast<f32x4*>(X + o) = x;
     *reinterpret_cast<f32x4*>(R + o) = r;
-    rr = wave_sum(rr);
-    rw = wave_sum(rw);
-    if (ln == 0) {
-      part[((int64_t)blockIdx.x * QMAX + q) * 2 + 0] = rr;
-      part[((int64_t)blockIdx.x * QMAX + q) * 2 + 1] = rw;
-    }
   }
-  if (!arrive_last(&st->cnt[2], gridDim.x)) return;
+  rr = block_sum(rr);
+  rw = block_sum(rw);
+  if (threadIdx.x == 0) {
+    part[((int64_t)q * nbx + blockIdx.x) * 2 + 0] = rr;
+    part[((int64_t)q * nbx + blockIdx.x) * 2 + 1] = rw;
+  }
+}
+
+// One block: ||R_q||^2 and rho'_q from the partials (fixed order), the stop rule of
+// Algorithm 2 (joint Frobenius ratio, or per-column freezing), eta_q = rho'_q / rho_q.
+__global__ __launch_bounds__(VBLOCK) void k_cg_scalars(SolveCfg c, int nbx, const double* __restrict__ part,
+                                                       CGState* __restrict__ st) {
+  if (st->done) return;
   __shared__ double s_rr[QMAX], s_rw[QMAX];
-  for (int q = wv; q < c.Qp; q += 4) {
-    const double rr = wave_sum_parts(part, gridDim.x, 2 * QMAX, 2 * q);
-    const double rw = wave_sum_parts(part, gridDim.x, 2 * QMAX, 2 * q + 1);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int q = wv; q < c.Q; q += 4) {
+    double a = 0.0, b = 0.0;
+    for (int i = ln; i < nbx; i += 64) {
+      a += part[((int64_t)q * nbx + i) * 2 + 0];
+      b += part[((int64_t)q * nbx + i) * 2 + 1];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
     if (ln == 0) {
-      s_rr[q] = rr;
-      s_rw[q] = rw;
+      s_rr[q] = a;
+      s_rw[q] = b;
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double rsum = 0.0;
-    for (int q = 0; q < c.Q; ++q) rsum += s_rr[q];
-    const double delta = sqrt(rsum / st->bnorm2);
-    st->delta = delta;
-    const int steps = st->steps + 1;
-    st->steps = steps;
-    int done = 0;
-    if (c.stop_mode == 0) {
-      if (delta <= c.tol) done = 1;
-    } else {
-      int nact = 0;
-      for (int q = 0; q < c.Q; ++q) {
-        if (st->active[q] && sqrt(s_rr[q] / st->bn2[q]) <= c.tol) st->active[q] = 0;
-        nact += st->active[q];
-      }
-      if (nact == 0) done = 1;
+  if (threadIdx.x != 0) return;
+  double rsum = 0.0;
+  for (int q = 0; q < c.Q; ++q) rsum += s_rr[q];
+  const double delta = sqrt(rsum / st->bnorm2);
+  st->delta = delta;
+  const int steps = st->steps + 1;
+  st->steps = steps;
+  int done = 0;
+  if (c.stop_mode == 0) {
+    if (delta <= c.tol) done = 1;
+  } else {
+    int nact = 0;
+    for (int q = 0; q < c.Q; ++q) {
+      if (st->active[q] && sqrt(s_rr[q] / st->bn2[q]) <= c.tol) st->active[q] = 0;
+      nact += st->active[q];
     }
-    if (steps >= c.U) done = 1;
-    for (int q = 0; q < c.Qp; ++q) {
-      st->rn2[q] = s_rr[q];
-      const double old = st->rho[q];
-      st->eta[q] = (old != 0.0) ? s_rw[q] / old : 0.0;
-      st->rho[q] = s_rw[q];
-    }
-    st->done = done;
-    reset_counter(&st->cnt[2]);
+    if (nact == 0) done = 1;
+  }
+  if (steps >= c.U) done = 1;
+  for (int q = 0; q < c.Q; ++q) {
+    st->rn2[q] = s_rr[q];
+    const double old = st->rho[q];
+    st->eta[q] = (old != 0.0) ? s_rw[q] / old : 0.0;
+    st->rho[q] = s_rw[q];
+  }
+  st->done = done;
+}
+
+// One block: pi_q into the state (used by the single-application test hook).
+__global__ __launch_bounds__(VBLOCK) void k_reduce_pi(int Q, int nbx, const double* __restrict__ pipart,
+                                                      CGState* __restrict__ st) {
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int q = wv; q < Q; q += 4) {
+    double a = 0.0;
+    for (int i = ln; i < nbx; i += 64) a += pipart[(int64_t)q * nbx + i];
+    a = wave_sum(a);
+    if (ln == 0) st->pi[q] = a;
   }
 }
 
@@ -599,26 +721,25 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction(SolveCfg c, int64_t Dp,
                                                          uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
                                                          const CGState* __restrict__ st) {
   if (st->done) return;
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * VSPAN + 4 * ln;
+  const int q = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * VCHUNK + 4 * threadIdx.x;
+  if (j >= Dp) return;
+  const double eta = st->eta[q];
+  const int64_t o = (int64_t)q * Dp + j;
   const f32x4 mi = *reinterpret_cast<const f32x4*>(minv + j);
-  for (int q = wv; q < c.Q; q += 4) {
-    const double eta = st->eta[q];
-    const int64_t o = (int64_t)q * Dp + j;
-    const f32x4 r = *reinterpret_cast<const f32x4*>(R + o);
-    f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
+  const f32x4 r = *reinterpret_cast<const f32x4*>(R + o);
+  f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) p[e] = (float)((double)mi[e] * (double)r[e] + eta * (double)p[e]);
-    *reinterpret_cast<f32x4*>(Pd + o) = p;
-    if (PdH) {
-      uint16_t h[4], l[4];
+  for (int e = 0; e < 4; ++e) p[e] = (float)((double)mi[e] * (double)r[e] + eta * (double)p[e]);
+  *reinterpret_cast<f32x4*>(Pd + o) = p;
+  if (PdH) {
+    uint16_t h[4], l[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) split_bf16(p[e], h[e], l[e]);
-      *reinterpret_cast<uint2*>(PdH + o) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
-                                                      (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-      *reinterpret_cast<uint2*>(PdL + o) = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16),
-                                                      (uint32_t)l[2] | ((uint32_t)l[3] << 16));
-    }
+    for (int e = 0; e < 4; ++e) split_bf16(p[e], h[e], l[e]);
+    *reinterpret_cast<uint2*>(PdH + o) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                                    (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+    *reinterpret_cast<uint2*>(PdL + o) = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16),
+                                                    (uint32_t)l[2] | ((uint32_t)l[3] << 16));
   }
 }
 
@@ -711,15 +832,19 @@ GemmCfg choose_gemm(int64_t rows, int64_t kdim, int bf16) {
   return g;
 }
 
+constexpr int KS_BF16 = 2;  // 32-k steps per stage (64 k)
+constexpr int KS_F32 = 4;   // 16-k steps per stage (64 k)
+
 template <int RT>
 static void gemm_bf16_rt(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
                          const uint16_t* ZL, int Qp, float* Yp, const int* done, hipStream_t s) {
-  dim3 grid((unsigned)(rows / (64 * RT)), (unsigned)g.splits);
+  const int nrb = (int)(rows / (64 * RT));
+  dim3 grid((unsigned)(nrb * g.splits));
   switch (Qp / 16) {
-    case 1: hipLaunchKernelGGL((k_gemm_bf16<RT, 1>), grid, dim3(256), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, done); break;
-    case 2: hipLaunchKernelGGL((k_gemm_bf16<RT, 2>), grid, dim3(256), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, done); break;
-    case 3: hipLaunchKernelGGL((k_gemm_bf16<RT, 3>), grid, dim3(256), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, done); break;
-    default: hipLaunchKernelGGL((k_gemm_bf16<RT, 4>), grid, dim3(256), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, done); break;
+    case 1: hipLaunchKernelGGL((k_gemm_bf16<RT, 1, KS_BF16>), grid, dim3(320), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 2: hipLaunchKernelGGL((k_gemm_bf16<RT, 2, KS_BF16>), grid, dim3(320), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 3: hipLaunchKernelGGL((k_gemm_bf16<RT, 3, KS_BF16>), grid, dim3(320), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    default: hipLaunchKernelGGL((k_gemm_bf16<RT, 4, KS_BF16>), grid, dim3(320), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
   }
 }
 
@@ -734,12 +859,13 @@ void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t
 template <int RT>
 static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Qp,
                         float* Yp, const int* done, hipStream_t s) {
-  dim3 grid((unsigned)(rows / (64 * RT)), (unsigned)g.splits);
+  const int nrb = (int)(rows / (64 * RT));
+  dim3 grid((unsigned)(nrb * g.splits));
   switch (Qp / 16) {
-    case 1: hipLaunchKernelGGL((k_gemm_f32<RT, 1>), grid, dim3(256), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, done); break;
-    case 2: hipLaunchKernelGGL((k_gemm_f32<RT, 2>), grid, dim3(256), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, done); break;
-    case 3: hipLaunchKernelGGL((k_gemm_f32<RT, 3>), grid, dim3(256), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, done); break;
-    default: hipLaunchKernelGGL((k_gemm_f32<RT, 4>), grid, dim3(256), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, done); break;
+    case 1: hipLaunchKernelGGL((k_gemm_f32<RT, 1, KS_F32>), grid, dim3(320), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 2: hipLaunchKernelGGL((k_gemm_f32<RT, 2, KS_F32>), grid, dim3(320), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 3: hipLaunchKernelGGL((k_gemm_f32<RT, 3, KS_F32>), grid, dim3(320), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    default: hipLaunchKernelGGL((k_gemm_f32<RT, 4, KS_F32>), grid, dim3(320), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
   }
 }
 
@@ -758,21 +884,27 @@ void launch_finish_pass1(const float* Ypart, int splits, int Qp, int64_t Np, flo
 }
 
 void launch_finish_pass2(const SolveCfg& c, const float* Ypart, int splits, int64_t Dp, const float* alpha,
-                         const float* Pd, float* Psi, double* part, CGState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_pass2, dim3((unsigned)(Dp / VSPAN)), dim3(VBLOCK), 0, s, c, Ypart, splits, Dp,
-                     alpha, Pd, Psi, part, st);
+                         const float* Pd, float* Psi, double* pipart, const CGState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_pass2, dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Ypart, splits,
+                     Dp, alpha, Pd, Psi, pipart, st);
 }
 
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
-                      const float* Psi, double* part, CGState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update, dim3((unsigned)(Dp / VSPAN)), dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi,
+                      const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s) {
+  const unsigned nbx = cdiv(Dp, VCHUNK);
+  hipLaunchKernelGGL(k_cg_update, dim3(nbx, (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi, pipart,
                      part, st);
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(VBLOCK), 0, s, c, (int)nbx, (const double*)part, st);
+}
+
+void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_pi, dim3(1), dim3(VBLOCK), 0, s, Q, (int)cdiv(Dp, VCHUNK), pipart, st);
 }
 
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
                          uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_direction, dim3((unsigned)(Dp / VSPAN)), dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd, PdH,
-                     PdL, st);
+  hipLaunchKernelGGL(k_cg_direction, dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd,
+                     PdH, PdL, st);
 }
 
 void launch_pack_block(const float* src, int ncols, int64_t D, int Qp, int64_t Dp, float* dst, uint16_t* dH,
