@@ -178,6 +178,94 @@ cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const float* P, flo
 cofem_status cofem_set_timing(cofem_ctx* c, int32_t enable);
 cofem_status cofem_get_timing(cofem_ctx* c, int32_t which, double* total_ms, int64_t* launches);
 
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent fits.
+ *
+ * A server owns one device arena of `hbm_budget` bytes and up to `max_slots`
+ * concurrent fits.  Requests are admitted first-in first-out whenever a slot is
+ * free and the request's workspace fits in the arena; admitted fits advance
+ * together: every tick runs `steps_per_tick` CG steps of every running fit in one
+ * graph-captured sequence of persistent kernels (each kernel strides over a tile
+ * table that covers all running fits), and each fit moves through its own EM
+ * iterations on the device (E-step initialisation, PCG, M-step, Algorithm 1).
+ * Fits are independent and their reductions run in a fixed order, so a result
+ * does not depend on which other requests share the device.
+ *
+ * Serving requests: op_kind COFEM_OP_DENSE, phi_dtype COFEM_PHI_FP32,
+ * refine_last 0, K <= 31.
+ * ------------------------------------------------------------------------- */
+typedef struct cofem_server cofem_server;
+
+typedef enum {
+  COFEM_REQ_PENDING = 0, /* submitted, waiting for a slot and memory */
+  COFEM_REQ_RUNNING = 1, /* admitted; the caller's phi and y are no longer read */
+  COFEM_REQ_DONE = 2,    /* results available through cofem_server_poll */
+  COFEM_REQ_UNKNOWN = -1
+} cofem_request_state;
+
+typedef struct cofem_request_info {
+  int32_t state;           /* cofem_request_state */
+  int32_t T;               /* EM iterations */
+  int32_t total_cg_steps;  /* CG steps over the fit */
+  int32_t pad_;
+  double t_submit_ms;      /* host clock, ms since the server was created */
+  double t_admit_ms;
+  double t_finish_ms;
+  int64_t bytes;           /* device workspace of the request */
+} cofem_request_info;
+
+typedef struct cofem_server_stats {
+  int64_t submitted, admitted, completed, rejected;
+  int64_t ticks;
+  int32_t active;        /* running fits now */
+  int32_t max_active;    /* most fits running at once */
+  int64_t bytes_in_use;  /* arena bytes held by running fits */
+  int64_t bytes_peak;    /* never above budget */
+  int64_t budget;
+} cofem_server_stats;
+
+/*
+ * Create a server on the current device.  hbm_budget: arena size in bytes (allocated
+ * here, once).  max_slots: 1..128 concurrent fits.  steps_per_tick: CG steps per
+ * tick (>= 1).  stream: hipStream_t to run on, or NULL for a server-owned stream
+ * (stream capture needs a non-default stream).  Errors: COFEM_EINVAL, COFEM_ENOMEM,
+ * COFEM_EDEVICE.
+ */
+cofem_status cofem_server_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_tick, void* stream,
+                                 cofem_server** out);
+void cofem_server_destroy(cofem_server* s);
+
+/*
+ * Queue one fit.  p as for cofem_create (serving restrictions above).  phi: HOST
+ * pointer to the N x D row-major FP32 dictionary; y: HOST pointer to N floats.  The
+ * caller keeps phi and y alive and unchanged until cofem_server_poll reports the
+ * request RUNNING or DONE (they are copied to the device at admission).
+ * *id receives the request id.  Errors: COFEM_EINVAL (bad parameters or
+ * arguments), COFEM_EBUDGET (the request's workspace exceeds the whole budget).
+ */
+cofem_status cofem_server_submit(cofem_server* s, const cofem_params* p, const float* phi, const float* y,
+                                 int64_t* id);
+
+/*
+ * One scheduling tick: admit what fits, run one tick of every running fit, collect
+ * finished fits.  Blocks until the tick's device work is done.  n_running and
+ * n_pending (may be NULL) receive the counts after the tick.
+ */
+cofem_status cofem_server_step(cofem_server* s, int32_t* n_running, int32_t* n_pending);
+
+/*
+ * State of request `id`; when DONE, copies mu, s, alpha (HOST buffers of D floats,
+ * any may be NULL) and releases the request's record on the first call that passes
+ * a non-NULL mu.  info (host, may be NULL) receives the state and time stamps.
+ * Errors: COFEM_EINVAL (unknown id).
+ */
+cofem_status cofem_server_poll(cofem_server* s, int64_t id, float* mu, float* s_out, float* alpha,
+                               cofem_request_info* info);
+
+/* Counters of the server (host struct). */
+cofem_status cofem_server_get_stats(cofem_server* s, cofem_server_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

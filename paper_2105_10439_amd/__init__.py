@@ -26,7 +26,10 @@ DTYPES = {"fp32": 0, "bf16": 1}
 EXPORTS = [
     "cofem_abi_version", "cofem_last_error", "cofem_create", "cofem_destroy", "cofem_set_dictionary",
     "cofem_fit", "cofem_posterior", "cofem_apply_A", "cofem_set_timing", "cofem_get_timing",
+    "cofem_server_create", "cofem_server_destroy", "cofem_server_submit", "cofem_server_step",
+    "cofem_server_poll", "cofem_server_get_stats",
 ]
+REQ_STATE = {0: "pending", 1: "running", 2: "done", -1: "unknown"}
 
 
 class CofemError(RuntimeError):
@@ -66,6 +69,23 @@ class Stats(ctypes.Structure):
                     ms_fit=float(self.ms_fit))
 
 
+class RequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int32), ("T", ctypes.c_int32), ("total_cg_steps", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double), ("t_finish_ms", ctypes.c_double),
+        ("bytes", ctypes.c_int64),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+        ("rejected", ctypes.c_int64), ("ticks", ctypes.c_int64), ("active", ctypes.c_int32),
+        ("max_active", ctypes.c_int32), ("bytes_in_use", ctypes.c_int64), ("bytes_peak", ctypes.c_int64),
+        ("budget", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 
@@ -89,6 +109,12 @@ def load() -> ctypes.CDLL:
         "cofem_apply_A": (i32, [vp, vp, vp, vp, i32, i32, vp]),
         "cofem_set_timing": (i32, [vp, i32]),
         "cofem_get_timing": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+        "cofem_server_create": (i32, [ctypes.c_size_t, i32, i32, vp, ctypes.POINTER(vp)]),
+        "cofem_server_destroy": (None, [vp]),
+        "cofem_server_submit": (i32, [vp, ctypes.POINTER(Params), vp, vp, ctypes.POINTER(i64)]),
+        "cofem_server_step": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "cofem_server_poll": (i32, [vp, i64, vp, vp, vp, ctypes.POINTER(RequestInfo)]),
+        "cofem_server_get_stats": (i32, [vp, ctypes.POINTER(ServerStats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -188,3 +214,78 @@ class CoFEM:
         n = ctypes.c_int64()
         _check(load().cofem_get_timing(self._h, 1 if which == "bf16" else 0, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+
+class Server:
+    """Continuous-batching server (cofem_server_*).  Dictionaries and observations are
+    host float32 arrays; they are kept referenced here until the request is admitted."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, steps_per_tick: int = 4, stream=None):
+        lib = load()
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(lib.cofem_server_create(ctypes.c_size_t(int(budget_bytes)), int(max_slots), int(steps_per_tick), st,
+                                       ctypes.byref(h)))
+        self._h = h
+        self._held = {}   # request id -> (phi, y) kept alive until admission
+        self._D = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().cofem_server_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def submit(self, phi, y, *, beta, K, T, U, tol, theta="ones", stop="joint", seed=0, alpha_floor=1e-30) -> int:
+        import numpy as np
+
+        phi = np.ascontiguousarray(phi, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        N, D = phi.shape
+        if y.shape != (N,):
+            raise ValueError("y must have N elements")
+        p = make_params(N, D, beta, K, T, U, tol, theta, stop, "dense", "fp32", 0, 0, seed, alpha_floor)
+        rid = ctypes.c_int64()
+        _check(load().cofem_server_submit(self._h, ctypes.byref(p), phi.ctypes.data_as(ctypes.c_void_p),
+                                          y.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rid)))
+        self._held[rid.value] = (phi, y)
+        self._D[rid.value] = D
+        return rid.value
+
+    def step(self):
+        run = ctypes.c_int32()
+        pend = ctypes.c_int32()
+        _check(load().cofem_server_step(self._h, ctypes.byref(run), ctypes.byref(pend)))
+        for rid in list(self._held):
+            if self.info(rid)["state"] != "pending":
+                del self._held[rid]
+        return run.value, pend.value
+
+    def info(self, rid: int) -> dict:
+        inf = RequestInfo()
+        _check(load().cofem_server_poll(self._h, int(rid), None, None, None, ctypes.byref(inf)))
+        return dict(state=REQ_STATE[inf.state], T=inf.T, total_cg_steps=inf.total_cg_steps,
+                    t_submit_ms=inf.t_submit_ms, t_admit_ms=inf.t_admit_ms, t_finish_ms=inf.t_finish_ms,
+                    bytes=inf.bytes)
+
+    def result(self, rid: int):
+        """(mu, s, alpha, info) of a finished request (releases its record), or None if not done."""
+        import numpy as np
+
+        inf = self.info(rid)
+        if inf["state"] != "done":
+            return None
+        D = self._D.pop(rid)
+        mu = np.empty(D, np.float32)
+        s = np.empty(D, np.float32)
+        alpha = np.empty(D, np.float32)
+        _check(load().cofem_server_poll(self._h, int(rid), mu.ctypes.data_as(ctypes.c_void_p),
+                                        s.ctypes.data_as(ctypes.c_void_p), alpha.ctypes.data_as(ctypes.c_void_p),
+                                        None))
+        return mu, s, alpha, inf
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().cofem_server_get_stats(self._h, ctypes.byref(st)))
+        return {f[0]: getattr(st, f[0]) for f in ServerStats._fields_}

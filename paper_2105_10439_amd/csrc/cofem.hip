@@ -28,6 +28,12 @@ cofem_status fail(cofem_status s, const std::string& msg) {
   return s;
 }
 
+}  // namespace
+
+void cofem::set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                         \
   do {                                                                                        \
     hipError_t e_ = (expr);                                                                   \

@@ -4,15 +4,21 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace cofem {
+
+// Thread-local message of the last failing C-ABI call (shared by all entry points).
+void set_error(const std::string& msg);
 
 constexpr int QMAX = 64;          // padded right-hand-side columns per problem
 constexpr int VBLOCK = 256;       // threads per block of the vector kernels
 constexpr int VPART = 256;        // coordinates per partial-sum slot (sizes the reduction scratch)
 constexpr uint64_t GOLDEN_GAMMA = 0x9E3779B97F4A7C15ull;
 
-// Device-resident state of one multi-RHS PCG solve (Algorithm 2).  All step
-// scalars are FP64.  Written only by the single "last" block of a kernel.
+// Device-resident state of one multi-RHS PCG solve (Algorithm 2) and of the EM
+// iteration around it.  All step scalars are FP64.  Scalars are written by
+// single-block kernels; per-column flags by the first tile of the column.
 struct CGState {
   double rho[QMAX];     // rho_q = sum_j R_jq W_jq
   double pi[QMAX];      // pi_q = sum_j P_jq Psi_jq
@@ -27,7 +33,10 @@ struct CGState {
   int steps;            // operator applications in this solve
   int breakdown;        // columns frozen because pi_q <= 0 with rho_q != 0
   int clamped;          // M-step floor events (this fit)
-  unsigned cnt[8];      // last-block arrival counters (zero between kernels)
+  int phase;            // serving: 0 idle, 1 needs E-step init, 2 in CG, 3 finished
+  int t;                // serving: current EM iteration (1-based)
+  int total_steps;      // serving: CG steps over the fit
+  int pad_;
 };
 
 struct SolveCfg {
@@ -55,8 +64,8 @@ void launch_fill(float* x, float v, int64_t n, hipStream_t s);
 
 // ---- per EM iteration --------------------------------------------------------
 // Probes for iteration key `key`, B = [b | p_1..p_K | 0], minv = 1/(beta theta + alpha),
-// X = 0, R = B, Pd = W = minv R (FP32 and, if PdH != null, bf16 hi/lo), and the
-// initial rho, ||B_q||^2, active flags; resets done/steps.
+// X = 0, R = B, Pd = W = minv R (FP32 and, if PdH != null, bf16 hi/lo); then one
+// block sets the initial rho, ||B_q||^2, active flags and resets done/steps (two launches).
 void launch_em_init(const SolveCfg& c, uint64_t key, int64_t D, int64_t Dp, const float* b,
                     const float* theta, const float* alpha, float* minv, float* X, float* R, float* Pd,
                     uint16_t* PdH, uint16_t* PdL, double* part, CGState* st, hipStream_t s);

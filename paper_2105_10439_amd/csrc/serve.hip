@@ -1,0 +1,756 @@
+// Serving: continuous batching of independent CoFEM fits (include/cofem.h).
+//
+// Every admitted request owns a slot: a region of one device arena holding its
+// dictionary (row-major and transposed, FP32), its CG blocks and its state.  A
+// tick is a fixed sequence of persistent kernels, captured once as a hipGraph:
+// E-step initialisation, steps_per_tick CG steps, M-step and EM advance.  Each
+// kernel has a fixed grid that strides over a tile table covering all running
+// slots (rebuilt by the host only when slots are admitted or retired), and each
+// slot moves through its own EM iterations on the device.  The per-tile work is
+// the same code as the single-problem path (tiles.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "cofem.h"
+#include "kernels.h"
+#include "tiles.h"
+
+#define COFEM_API extern "C" __attribute__((visibility("default")))
+
+namespace cofem {
+
+constexpr int SRV_MAXSLOTS = 128;
+constexpr int SRV_QP = 32;              // padded right-hand sides of a serving fit (K <= 31)
+constexpr int SRV_RT = 2;               // row tiles of 16 per wave in the serving contractions
+constexpr int64_t SRV_KCHUNK = 2048;    // reduction length per split
+constexpr int SRV_GEMM_GRID = 512;      // persistent grids (multiples of 8: tile L stays on XCD L % 8)
+constexpr int SRV_VEC_GRID = 1024;
+
+enum { PH_IDLE = 0, PH_INIT = 1, PH_CG = 2, PH_DONE = 3 };
+
+// Immutable description of one running fit (device copy in the slot array).
+struct SlotDev {
+  SolveCfg c;
+  int64_t N, D, Np, Dp;
+  int T;
+  uint64_t seed;
+  double floor;
+  int nrb1, splits1, nrb2, splits2;
+  int64_t kchunk1, kchunk2;
+  int nbx, nbn;  // vector tiles per column over Dp and Np
+  const float* phi;
+  const float* phiT;
+  float *V, *Ypart, *X, *R, *Pd, *Psi, *minv, *alpha, *b, *theta, *mu, *s;
+  double *part, *pipart;
+  CGState* st;
+  int* steps_log;  // CG steps of each E-step (T ints)
+};
+
+// Tile table of the running slots: for every kind of tile, a prefix sum of the
+// per-slot tile counts, each slot's range starting at a multiple of 8.
+struct SrvTable {
+  int n;
+  int slot[SRV_MAXSLOTS];
+  int em[SRV_MAXSLOTS + 1];   // E-step init / M-step blocks: Dp / 256
+  int g1[SRV_MAXSLOTS + 1];   // pass-1 contraction tiles: nrb1 * splits1
+  int g2[SRV_MAXSLOTS + 1];   // pass-2 contraction tiles: nrb2 * splits2
+  int f1[SRV_MAXSLOTS + 1];   // pass-1 finish tiles: nbn * Qp
+  int vq[SRV_MAXSLOTS + 1];   // per-column vector tiles: nbx * Q
+};
+
+__device__ __forceinline__ int find_slot(const int* start, int n, int t) {
+  int lo = 0, hi = n - 1;  // largest i with start[i] <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---- tick kernels -----------------------------------------------------------
+__global__ __launch_bounds__(VBLOCK) void ks_em_init(const SlotDev* __restrict__ slots,
+                                                     const SrvTable* __restrict__ tab) {
+  const int n = tab->n, total = tab->em[n];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_slot(tab->em, n, t);
+    const SlotDev& sd = slots[tab->slot[i]];
+    const int local = t - tab->em[i];
+    if (sd.st->phase != PH_INIT || local >= (int)(sd.Dp / VBLOCK)) continue;
+    em_init_block(sd.c, iteration_key(sd.seed, sd.st->t), sd.D, sd.Dp, local, sd.b, sd.theta, sd.alpha, sd.minv,
+                  sd.X, sd.R, sd.Pd, nullptr, nullptr, sd.part);
+  }
+}
+
+__global__ __launch_bounds__(VBLOCK) void ks_em_scalars(const SlotDev* __restrict__ slots,
+                                                        const SrvTable* __restrict__ tab) {
+  for (int i = blockIdx.x; i < tab->n; i += gridDim.x) {
+    const SlotDev& sd = slots[tab->slot[i]];
+    if (sd.st->phase != PH_INIT) continue;
+    em_scalars_block(sd.c, sd.D, (int)(sd.Dp / VBLOCK), sd.part, sd.st);
+    if (threadIdx.x == 0) sd.st->phase = PH_CG;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ bool in_cg(const SlotDev& sd) { return sd.st->phase == PH_CG && !sd.st->done; }
+
+__global__ __launch_bounds__(320, 2) void ks_gemm(const SlotDev* __restrict__ slots, const SrvTable* __restrict__ tab,
+                                                  int pass) {
+  const int n = tab->n;
+  const int* start = pass == 1 ? tab->g1 : tab->g2;
+  const int total = start[n];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_slot(start, n, t);
+    const SlotDev& sd = slots[tab->slot[i]];
+    const int local = t - start[i];
+    const int ntile = pass == 1 ? sd.nrb1 * sd.splits1 : sd.nrb2 * sd.splits2;
+    if (!in_cg(sd) || local >= ntile) continue;
+    if (pass == 1)
+      gemm_f32_tile<SRV_RT, SRV_QP / 16, 4>(local, sd.phi, sd.Dp, sd.Pd, sd.Dp, sd.Ypart, sd.Np, SRV_QP, sd.kchunk1,
+                                            sd.Dp, sd.nrb1, sd.splits1);
+    else
+      gemm_f32_tile<SRV_RT, SRV_QP / 16, 4>(local, sd.phiT, sd.Np, sd.V, sd.Np, sd.Ypart, sd.Dp, SRV_QP,
+                                            sd.kchunk2, sd.Np, sd.nrb2, sd.splits2);
+    __syncthreads();  // the next tile reuses the LDS staging buffers
+  }
+}
+
+__global__ __launch_bounds__(VBLOCK) void ks_finish1(const SlotDev* __restrict__ slots,
+                                                     const SrvTable* __restrict__ tab) {
+  const int n = tab->n, total = tab->f1[n];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_slot(tab->f1, n, t);
+    const SlotDev& sd = slots[tab->slot[i]];
+    const int local = t - tab->f1[i];
+    if (!in_cg(sd) || local >= sd.nbn * SRV_QP) continue;
+    finish1_tile(local % sd.nbn, local / sd.nbn, sd.Ypart, sd.splits1, sd.Np, sd.V, nullptr, nullptr, SRV_QP);
+  }
+}
+
+__global__ __launch_bounds__(VBLOCK) void ks_finish2(const SlotDev* __restrict__ slots,
+                                                     const SrvTable* __restrict__ tab) {
+  const int n = tab->n, total = tab->vq[n];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_slot(tab->vq, n, t);
+    const SlotDev& sd = slots[tab->slot[i]];
+    const int local = t - tab->vq[i];
+    if (!in_cg(sd) || local >= sd.nbx * sd.c.Q) continue;
+    finish2_tile(sd.c, local % sd.nbx, local / sd.nbx, sd.nbx, sd.Ypart, sd.splits2, sd.Dp, sd.alpha, sd.Pd, sd.Psi,
+                 sd.pipart);
+  }
+}
+
+__global__ __launch_bounds__(VBLOCK) void ks_update(const SlotDev* __restrict__ slots,
+                                                    const SrvTable* __restrict__ tab) {
+  const int n = tab->n, total = tab->vq[n];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_slot(tab->vq, n, t);
+    const SlotDev& sd = slots[tab->slot[i]];
+    const int local = t - tab->vq[i];
+    if (!in_cg(sd) || local >= sd.nbx * sd.c.Q) continue;
+    cg_update_tile(sd.c, local % sd.nbx, local / sd.nbx, sd.nbx, sd.Dp, sd.minv, sd.X, sd.R, sd.Pd, sd.Psi,
+                   sd.pipart, sd.part, sd.st);
+  }
+}
+
+__global__ __launch_bounds__(VBLOCK) void ks_scalars(const SlotDev* __restrict__ slots,
+                                                     const SrvTable* __restrict__ tab) {
+  for (int i = blockIdx.x; i < tab->n; i += gridDim.x) {
+    const SlotDev& sd = slots[tab->slot[i]];
+    if (!in_cg(sd)) continue;
+    cg_scalars_block(sd.c, sd.nbx, sd.part, sd.st);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(VBLOCK) void ks_direction(const SlotDev* __restrict__ slots,
+                                                       const SrvTable* __restrict__ tab) {
+  const int n = tab->n, total = tab->vq[n];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_slot(tab->vq, n, t);
+    const SlotDev& sd = slots[tab->slot[i]];
+    const int local = t - tab->vq[i];
+    if (!in_cg(sd) || local >= sd.nbx * sd.c.Q) continue;
+    cg_direction_tile(local % sd.nbx, local / sd.nbx, sd.Dp, sd.minv, sd.R, sd.Pd, nullptr, nullptr, sd.st);
+  }
+}
+
+__global__ __launch_bounds__(VBLOCK) void ks_mstep(const SlotDev* __restrict__ slots, const SrvTable* __restrict__ tab) {
+  const int n = tab->n, total = tab->em[n];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_slot(tab->em, n, t);
+    const SlotDev& sd = slots[tab->slot[i]];
+    const int local = t - tab->em[i];
+    if (sd.st->phase != PH_CG || !sd.st->done || local >= (int)((sd.D + VBLOCK - 1) / VBLOCK)) continue;
+    const int tt = sd.st->t;
+    mstep_block(sd.c, iteration_key(sd.seed, tt), sd.D, sd.Dp, local, sd.X, sd.mu, sd.s, sd.alpha, sd.floor,
+                tt < sd.T ? 1 : 0, sd.st);
+  }
+}
+
+// One thread per slot: record the finished E-step and move to the next EM
+// iteration or to DONE; publish every listed slot's phase.
+__global__ void ks_advance(const SlotDev* __restrict__ slots, const SrvTable* __restrict__ tab,
+                           int* __restrict__ phase_out) {
+  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < tab->n; i += blockDim.x * gridDim.x) {
+    const SlotDev& sd = slots[tab->slot[i]];
+    CGState* st = sd.st;
+    if (st->phase == PH_CG && st->done) {
+      sd.steps_log[st->t - 1] = st->steps;
+      st->total_steps += st->steps;
+      if (st->t < sd.T) {
+        st->t += 1;
+        st->phase = PH_INIT;
+      } else {
+        st->phase = PH_DONE;
+      }
+    }
+    phase_out[i] = st->phase;
+  }
+}
+
+// ---- admission kernels ---------------------------------------------------------
+__global__ void ks_zero(float* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+// phiT (Dp x Np) from phi (Np x Dp), 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void ks_transpose(const float* __restrict__ phi, int64_t Np, int64_t Dp,
+                                                    float* __restrict__ phiT) {
+  __shared__ float tile[64][65];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t j0 = (int64_t)blockIdx.x * 64, i0 = (int64_t)blockIdx.y * 64;
+  for (int r = ty; r < 64; r += 4) tile[r][tx] = phi[(i0 + r) * Dp + j0 + tx];
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) phiT[(j0 + r) * Np + i0 + tx] = tile[tx][r];
+}
+
+// theta_j = sum_i Phi_ij^2 (Jacobi) or 1 over the padded row-major copy; padding 1.
+__global__ void ks_theta(const float* __restrict__ phi, int64_t Np, int64_t D, int64_t Dp, int jacobi,
+                         float* __restrict__ theta) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Dp) return;
+  if (!jacobi || j >= D) {
+    theta[j] = 1.0f;
+    return;
+  }
+  double sq = 0.0;
+  for (int64_t i = 0; i < Np; ++i) {
+    const double v = (double)phi[i * Dp + j];
+    sq += v * v;
+  }
+  theta[j] = (float)sq;
+}
+
+__global__ void ks_slot_start(CGState* st, float* alpha, int64_t Dp) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < Dp; j += (int64_t)gridDim.x * blockDim.x)
+    alpha[j] = 1.0f;
+  if (blockIdx.x == 0) {
+    int* w = reinterpret_cast<int*>(st);
+    for (int i = threadIdx.x; i < (int)(sizeof(CGState) / sizeof(int)); i += blockDim.x) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      st->t = 1;
+      st->phase = PH_INIT;
+    }
+  }
+}
+
+}  // namespace cofem
+
+using namespace cofem;
+
+namespace {
+
+cofem_status sfail(cofem_status s, const std::string& m) {
+  set_error(m);
+  return s;
+}
+#define SRV_TRY(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return sfail(COFEM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline int64_t rup(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
+inline int cdivi(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+double wall_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Byte layout of one slot's workspace inside the arena.
+struct SlotLayout {
+  int64_t Np, Dp;
+  int nrb1, splits1, nrb2, splits2;
+  int64_t kchunk1, kchunk2;
+  size_t off_phi, off_phiT, off_V, off_Yp, off_X, off_R, off_Pd, off_Psi, off_vec, off_y, off_part, off_pipart,
+      off_st, off_log, total;
+};
+
+SlotLayout layout_of(const cofem_params& p) {
+  SlotLayout L{};
+  L.Np = rup(p.N, 256);
+  L.Dp = rup(p.D, 256);
+  L.nrb1 = (int)(L.Np / (64 * SRV_RT));
+  L.kchunk1 = std::min<int64_t>(SRV_KCHUNK, L.Dp);
+  L.splits1 = cdivi(L.Dp, L.kchunk1);
+  L.nrb2 = (int)(L.Dp / (64 * SRV_RT));
+  L.kchunk2 = std::min<int64_t>(SRV_KCHUNK, L.Np);
+  L.splits2 = cdivi(L.Np, L.kchunk2);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += (size_t)rup((int64_t)bytes, 256);
+    return at;
+  };
+  const size_t nd = (size_t)L.Np * (size_t)L.Dp * sizeof(float);
+  L.off_phi = take(nd);
+  L.off_phiT = take(nd);
+  L.off_V = take((size_t)SRV_QP * L.Np * sizeof(float));
+  L.off_Yp = take((size_t)SRV_QP * std::max<int64_t>(L.splits1 * L.Np, L.splits2 * L.Dp) * sizeof(float));
+  L.off_X = take((size_t)SRV_QP * L.Dp * sizeof(float));
+  L.off_R = take((size_t)SRV_QP * L.Dp * sizeof(float));
+  L.off_Pd = take((size_t)SRV_QP * L.Dp * sizeof(float));
+  L.off_Psi = take((size_t)SRV_QP * L.Dp * sizeof(float));
+  L.off_vec = take((size_t)6 * L.Dp * sizeof(float));  // minv, alpha, b, theta, mu, s
+  L.off_y = take((size_t)L.Np * sizeof(float));
+  L.off_part = take((size_t)(L.Dp / VPART + 1) * 2 * QMAX * sizeof(double));
+  L.off_pipart = take((size_t)(L.Dp / VPART + 1) * QMAX * sizeof(double));
+  L.off_st = take(sizeof(CGState));
+  L.off_log = take((size_t)p.T * sizeof(int));
+  L.total = o;
+  return L;
+}
+
+// First-fit allocator over [0, size) with coalescing.
+struct Arena {
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  void init(size_t n) {
+    size = n;
+    free_.clear();
+    free_[0] = n;
+  }
+  bool alloc(size_t n, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n, at = it->first + n;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Request {
+  cofem_params p;
+  const float* phi = nullptr;
+  const float* y = nullptr;
+  int state = COFEM_REQ_PENDING;
+  double t_submit = 0, t_admit = 0, t_finish = 0;
+  size_t bytes = 0, off = 0;
+  int slot = -1;
+  int total_steps = 0;
+  std::vector<float> mu, s, alpha;
+};
+
+}  // namespace
+
+struct cofem_server {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int max_slots = 0, steps = 1;
+  char* arena_base = nullptr;
+  Arena arena;
+  SlotDev* d_slots = nullptr;
+  SrvTable* d_table = nullptr;
+  int* d_phase = nullptr;
+  int* h_phase = nullptr;  // pinned
+  SrvTable h_table{};
+  std::vector<SlotDev> slot_dev;
+  std::vector<int64_t> slot_req;  // request id per slot, -1 = free
+  std::deque<int64_t> pending;
+  std::unordered_map<int64_t, Request> reqs;
+  int64_t next_id = 1;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  bool table_dirty = true;
+  double t0 = 0;
+  cofem_server_stats stats{};
+};
+
+namespace {
+
+cofem_status validate_request(const cofem_params* p) {
+  if (!p) return sfail(COFEM_EINVAL, "params is NULL");
+  if (p->N < 1 || p->D < 1 || p->N > (int64_t(1) << 28) || p->D > (int64_t(1) << 28))
+    return sfail(COFEM_EINVAL, "bad N or D");
+  if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return sfail(COFEM_EINVAL, "beta must be finite and > 0");
+  if (p->K < 1 || p->K > SRV_QP - 1) return sfail(COFEM_EINVAL, "serving requests need 1 <= K <= 31");
+  if (p->T < 1 || p->T > COFEM_MAX_T) return sfail(COFEM_EINVAL, "T must be in [1, COFEM_MAX_T]");
+  if (p->U < 1) return sfail(COFEM_EINVAL, "U must be >= 1");
+  if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return sfail(COFEM_EINVAL, "tol must be finite and >= 0");
+  if (p->theta_mode != COFEM_THETA_ONES && p->theta_mode != COFEM_THETA_JACOBI)
+    return sfail(COFEM_EINVAL, "bad theta_mode");
+  if (p->stop_mode != COFEM_STOP_JOINT && p->stop_mode != COFEM_STOP_COLUMN) return sfail(COFEM_EINVAL, "bad stop_mode");
+  if (p->op_kind != COFEM_OP_DENSE || p->phi_dtype != COFEM_PHI_FP32 || p->refine_last != 0)
+    return sfail(COFEM_EINVAL, "serving requests are dense FP32 without refinement");
+  if (!(p->alpha_floor > 0.0) || !std::isfinite(p->alpha_floor))
+    return sfail(COFEM_EINVAL, "alpha_floor must be finite and > 0");
+  return COFEM_OK;
+}
+
+cofem_status capture_tick(cofem_server* s) {
+  SRV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(ks_em_init, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
+  hipLaunchKernelGGL(ks_em_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
+  for (int k = 0; k < s->steps; ++k) {
+    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(320), 0, s->stream, s->d_slots, s->d_table, 1);
+    hipLaunchKernelGGL(ks_finish1, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
+    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(320), 0, s->stream, s->d_slots, s->d_table, 2);
+    hipLaunchKernelGGL(ks_finish2, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
+    hipLaunchKernelGGL(ks_update, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
+    hipLaunchKernelGGL(ks_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
+    hipLaunchKernelGGL(ks_direction, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
+  }
+  hipLaunchKernelGGL(ks_mstep, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
+  hipLaunchKernelGGL(ks_advance, dim3(1), dim3(SRV_MAXSLOTS), 0, s->stream, s->d_slots, s->d_table, s->d_phase);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s->stream, &g);
+  if (e != hipSuccess) return sfail(COFEM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  s->graph = g;
+  SRV_TRY(hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0));
+  return COFEM_OK;
+}
+
+void destroy_server(cofem_server* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->arena_base) (void)hipFree(s->arena_base);
+  if (s->d_slots) (void)hipFree(s->d_slots);
+  if (s->d_table) (void)hipFree(s->d_table);
+  if (s->d_phase) (void)hipFree(s->d_phase);
+  if (s->h_phase) (void)hipHostFree(s->h_phase);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+// Copy the request's inputs into its slot and prepare its first E-step.
+cofem_status admit(cofem_server* s, int slot, Request& r) {
+  const cofem_params& p = r.p;
+  const SlotLayout L = layout_of(p);
+  char* base = s->arena_base + r.off;
+  SlotDev sd{};
+  sd.c.Q = p.K + 1;
+  sd.c.Qp = SRV_QP;
+  sd.c.K = p.K;
+  sd.c.U = p.U;
+  sd.c.stop_mode = p.stop_mode;
+  sd.c.tol = p.tol;
+  sd.c.beta = p.beta;
+  sd.N = p.N;
+  sd.D = p.D;
+  sd.Np = L.Np;
+  sd.Dp = L.Dp;
+  sd.T = p.T;
+  sd.seed = p.seed;
+  sd.floor = p.alpha_floor;
+  sd.nrb1 = L.nrb1;
+  sd.splits1 = L.splits1;
+  sd.kchunk1 = L.kchunk1;
+  sd.nrb2 = L.nrb2;
+  sd.splits2 = L.splits2;
+  sd.kchunk2 = L.kchunk2;
+  sd.nbx = cdivi(L.Dp, VCHUNK);
+  sd.nbn = cdivi(L.Np, VCHUNK);
+  float* phi = reinterpret_cast<float*>(base + L.off_phi);
+  float* phiT = reinterpret_cast<float*>(base + L.off_phiT);
+  sd.phi = phi;
+  sd.phiT = phiT;
+  sd.V = reinterpret_cast<float*>(base + L.off_V);
+  sd.Ypart = reinterpret_cast<float*>(base + L.off_Yp);
+  sd.X = reinterpret_cast<float*>(base + L.off_X);
+  sd.R = reinterpret_cast<float*>(base + L.off_R);
+  sd.Pd = reinterpret_cast<float*>(base + L.off_Pd);
+  sd.Psi = reinterpret_cast<float*>(base + L.off_Psi);
+  float* vec = reinterpret_cast<float*>(base + L.off_vec);
+  sd.minv = vec;
+  sd.alpha = vec + L.Dp;
+  sd.b = vec + 2 * L.Dp;
+  sd.theta = vec + 3 * L.Dp;
+  sd.mu = vec + 4 * L.Dp;
+  sd.s = vec + 5 * L.Dp;
+  float* yv = reinterpret_cast<float*>(base + L.off_y);
+  sd.part = reinterpret_cast<double*>(base + L.off_part);
+  sd.pipart = reinterpret_cast<double*>(base + L.off_pipart);
+  sd.st = reinterpret_cast<CGState*>(base + L.off_st);
+  sd.steps_log = reinterpret_cast<int*>(base + L.off_log);
+  const int64_t nd = L.Np * L.Dp;
+  // zero the padded buffers the copies do not cover (V's padded rows and columns stay zero)
+  hipLaunchKernelGGL(ks_zero, dim3(1024), dim3(256), 0, s->stream, phi, nd);
+  hipLaunchKernelGGL(ks_zero, dim3(64), dim3(256), 0, s->stream, yv, L.Np);
+  hipLaunchKernelGGL(ks_zero, dim3(256), dim3(256), 0, s->stream, sd.V, (int64_t)SRV_QP * L.Np);
+  SRV_TRY(hipMemcpy2DAsync(phi, (size_t)L.Dp * sizeof(float), r.phi, (size_t)p.D * sizeof(float),
+                           (size_t)p.D * sizeof(float), (size_t)p.N, hipMemcpyHostToDevice, s->stream));
+  SRV_TRY(hipMemcpyAsync(yv, r.y, (size_t)p.N * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  hipLaunchKernelGGL(ks_transpose, dim3((unsigned)(L.Dp / 64), (unsigned)(L.Np / 64)), dim3(256), 0, s->stream, phi,
+                     L.Np, L.Dp, phiT);
+  hipLaunchKernelGGL(ks_theta, dim3((unsigned)cdivi(L.Dp, 256)), dim3(256), 0, s->stream, phi, L.Np, p.D, L.Dp,
+                     p.theta_mode == COFEM_THETA_JACOBI ? 1 : 0, sd.theta);
+  launch_rhs(phiT, nullptr, L.Np, L.Dp, yv, p.beta, sd.b, s->stream);
+  hipLaunchKernelGGL(ks_slot_start, dim3(64), dim3(256), 0, s->stream, sd.st, sd.alpha, L.Dp);
+  SRV_TRY(hipGetLastError());
+  // the caller's host buffers have been consumed once the copies above are done
+  SRV_TRY(hipStreamSynchronize(s->stream));
+  s->slot_dev[slot] = sd;
+  SRV_TRY(hipMemcpyAsync(s->d_slots + slot, &s->slot_dev[slot], sizeof(SlotDev), hipMemcpyHostToDevice, s->stream));
+  return COFEM_OK;
+}
+
+void rebuild_table(cofem_server* s) {
+  SrvTable& t = s->h_table;
+  t.n = 0;
+  t.em[0] = t.g1[0] = t.g2[0] = t.f1[0] = t.vq[0] = 0;
+  auto pad8 = [](int x) { return (x + 7) & ~7; };
+  for (int i = 0; i < s->max_slots; ++i) {
+    if (s->slot_req[i] < 0) continue;
+    const SlotDev& sd = s->slot_dev[i];
+    const int k = t.n++;
+    t.slot[k] = i;
+    t.em[k + 1] = t.em[k] + pad8((int)(sd.Dp / VBLOCK));
+    t.g1[k + 1] = t.g1[k] + pad8(sd.nrb1 * sd.splits1);
+    t.g2[k + 1] = t.g2[k] + pad8(sd.nrb2 * sd.splits2);
+    t.f1[k + 1] = t.f1[k] + pad8(sd.nbn * SRV_QP);
+    t.vq[k + 1] = t.vq[k] + pad8(sd.nbx * sd.c.Q);
+  }
+}
+
+}  // namespace
+
+COFEM_API cofem_status cofem_server_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_tick, void* stream,
+                                           cofem_server** out) {
+  if (!out) return sfail(COFEM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (hbm_budget < (size_t(1) << 20)) return sfail(COFEM_EINVAL, "hbm_budget must be at least 1 MiB");
+  if (max_slots < 1 || max_slots > SRV_MAXSLOTS) return sfail(COFEM_EINVAL, "max_slots must be in [1, 128]");
+  if (steps_per_tick < 1 || steps_per_tick > 64) return sfail(COFEM_EINVAL, "steps_per_tick must be in [1, 64]");
+  cofem_server* s = new (std::nothrow) cofem_server();
+  if (!s) return sfail(COFEM_ENOMEM, "host allocation failed");
+  s->max_slots = max_slots;
+  s->steps = steps_per_tick;
+  s->slot_dev.assign(SRV_MAXSLOTS, SlotDev{});
+  s->slot_req.assign(SRV_MAXSLOTS, -1);
+  s->t0 = wall_ms();
+  auto bail = [&](cofem_status st, const char* what) {
+    (void)hipGetLastError();
+    destroy_server(s);
+    return sfail(st, what);
+  };
+  if (stream) {
+    s->stream = static_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(COFEM_EDEVICE, "hipStreamCreate failed");
+    s->own_stream = true;
+  }
+  if (hipMalloc((void**)&s->arena_base, hbm_budget) != hipSuccess) return bail(COFEM_ENOMEM, "arena allocation failed");
+  s->arena.init(hbm_budget);
+  if (hipMalloc((void**)&s->d_slots, sizeof(SlotDev) * SRV_MAXSLOTS) != hipSuccess ||
+      hipMalloc((void**)&s->d_table, sizeof(SrvTable)) != hipSuccess ||
+      hipMalloc((void**)&s->d_phase, sizeof(int) * SRV_MAXSLOTS) != hipSuccess)
+    return bail(COFEM_ENOMEM, "server tables allocation failed");
+  if (hipHostMalloc((void**)&s->h_phase, sizeof(int) * SRV_MAXSLOTS, hipHostMallocDefault) != hipSuccess) {
+    s->h_phase = nullptr;
+    return bail(COFEM_ENOMEM, "pinned allocation failed");
+  }
+  rebuild_table(s);
+  if (hipMemcpyAsync(s->d_table, &s->h_table, sizeof(SrvTable), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    return bail(COFEM_EDEVICE, "server table upload failed");
+  s->table_dirty = false;
+  cofem_status rc = capture_tick(s);
+  if (rc != COFEM_OK) {
+    destroy_server(s);
+    return rc;
+  }
+  s->stats.budget = (int64_t)hbm_budget;
+  *out = s;
+  return COFEM_OK;
+}
+
+COFEM_API void cofem_server_destroy(cofem_server* s) { destroy_server(s); }
+
+COFEM_API cofem_status cofem_server_submit(cofem_server* s, const cofem_params* p, const float* phi, const float* y,
+                                           int64_t* id) {
+  if (!s || !phi || !y || !id) return sfail(COFEM_EINVAL, "NULL argument");
+  cofem_status rc = validate_request(p);
+  if (rc != COFEM_OK) {
+    s->stats.rejected++;
+    return rc;
+  }
+  const SlotLayout L = layout_of(*p);
+  if (L.total > s->arena.size) {
+    s->stats.rejected++;
+    return sfail(COFEM_EBUDGET, "request workspace (" + std::to_string(L.total) + " bytes) exceeds the budget");
+  }
+  Request r;
+  r.p = *p;
+  r.phi = phi;
+  r.y = y;
+  r.bytes = L.total;
+  r.t_submit = wall_ms() - s->t0;
+  const int64_t rid = s->next_id++;
+  s->reqs.emplace(rid, std::move(r));
+  s->pending.push_back(rid);
+  s->stats.submitted++;
+  *id = rid;
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_server_step(cofem_server* s, int32_t* n_running, int32_t* n_pending) {
+  if (!s) return sfail(COFEM_EINVAL, "NULL server");
+  // admission, first in first out
+  while (!s->pending.empty()) {
+    int slot = -1;
+    for (int i = 0; i < s->max_slots; ++i)
+      if (s->slot_req[i] < 0) {
+        slot = i;
+        break;
+      }
+    if (slot < 0) break;
+    const int64_t rid = s->pending.front();
+    Request& r = s->reqs[rid];
+    size_t off = 0;
+    if (!s->arena.alloc(r.bytes, &off)) break;
+    r.off = off;
+    cofem_status rc = admit(s, slot, r);
+    if (rc != COFEM_OK) return rc;
+    s->slot_req[slot] = rid;
+    r.slot = slot;
+    r.state = COFEM_REQ_RUNNING;
+    r.phi = nullptr;
+    r.y = nullptr;
+    r.t_admit = wall_ms() - s->t0;
+    s->pending.pop_front();
+    s->stats.admitted++;
+    s->stats.bytes_in_use += (int64_t)r.bytes;
+    s->stats.bytes_peak = std::max(s->stats.bytes_peak, s->stats.bytes_in_use);
+    s->table_dirty = true;
+  }
+  if (s->table_dirty) {
+    rebuild_table(s);
+    SRV_TRY(hipMemcpyAsync(s->d_table, &s->h_table, sizeof(SrvTable), hipMemcpyHostToDevice, s->stream));
+    s->table_dirty = false;
+  }
+  const int n = s->h_table.n;
+  s->stats.active = n;
+  s->stats.max_active = std::max(s->stats.max_active, n);
+  if (n > 0) {
+    SRV_TRY(hipGraphLaunch(s->exec, s->stream));
+    SRV_TRY(hipMemcpyAsync(s->h_phase, s->d_phase, sizeof(int) * n, hipMemcpyDeviceToHost, s->stream));
+    SRV_TRY(hipStreamSynchronize(s->stream));
+    s->stats.ticks++;
+    for (int k = 0; k < n; ++k) {
+      if (s->h_phase[k] != PH_DONE) continue;
+      const int slot = s->h_table.slot[k];
+      const int64_t rid = s->slot_req[slot];
+      Request& r = s->reqs[rid];
+      const SlotDev& sd = s->slot_dev[slot];
+      r.mu.resize((size_t)r.p.D);
+      r.s.resize((size_t)r.p.D);
+      r.alpha.resize((size_t)r.p.D);
+      const size_t bytes = (size_t)r.p.D * sizeof(float);
+      CGState st;
+      SRV_TRY(hipMemcpyAsync(r.mu.data(), sd.mu, bytes, hipMemcpyDeviceToHost, s->stream));
+      SRV_TRY(hipMemcpyAsync(r.s.data(), sd.s, bytes, hipMemcpyDeviceToHost, s->stream));
+      SRV_TRY(hipMemcpyAsync(r.alpha.data(), sd.alpha, bytes, hipMemcpyDeviceToHost, s->stream));
+      SRV_TRY(hipMemcpyAsync(&st, sd.st, sizeof(CGState), hipMemcpyDeviceToHost, s->stream));
+      SRV_TRY(hipStreamSynchronize(s->stream));
+      r.total_steps = st.total_steps;
+      r.state = COFEM_REQ_DONE;
+      r.t_finish = wall_ms() - s->t0;
+      s->arena.release(r.off, r.bytes);
+      s->stats.bytes_in_use -= (int64_t)r.bytes;
+      s->slot_req[slot] = -1;
+      s->stats.completed++;
+      s->table_dirty = true;
+    }
+  }
+  int running = 0;
+  for (int i = 0; i < s->max_slots; ++i) running += s->slot_req[i] >= 0;
+  s->stats.active = running;
+  if (n_running) *n_running = running;
+  if (n_pending) *n_pending = (int32_t)s->pending.size();
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_server_poll(cofem_server* s, int64_t id, float* mu, float* s_out, float* alpha,
+                                         cofem_request_info* info) {
+  if (!s) return sfail(COFEM_EINVAL, "NULL server");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) {
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->state = COFEM_REQ_UNKNOWN;
+    }
+    return sfail(COFEM_EINVAL, "unknown request id");
+  }
+  Request& r = it->second;
+  if (info) {
+    info->state = r.state;
+    info->T = r.p.T;
+    info->total_cg_steps = r.total_steps;
+    info->pad_ = 0;
+    info->t_submit_ms = r.t_submit;
+    info->t_admit_ms = r.t_admit;
+    info->t_finish_ms = r.t_finish;
+    info->bytes = (int64_t)r.bytes;
+  }
+  if (r.state == COFEM_REQ_DONE) {
+    const size_t bytes = (size_t)r.p.D * sizeof(float);
+    if (mu) std::memcpy(mu, r.mu.data(), bytes);
+    if (s_out) std::memcpy(s_out, r.s.data(), bytes);
+    if (alpha) std::memcpy(alpha, r.alpha.data(), bytes);
+    if (mu) s->reqs.erase(it);
+  }
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_server_get_stats(cofem_server* s, cofem_server_stats* out) {
+  if (!s || !out) return sfail(COFEM_EINVAL, "NULL argument");
+  *out = s->stats;
+  return COFEM_OK;
+}

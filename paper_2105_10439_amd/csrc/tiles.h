@@ -1,0 +1,489 @@
+// Block-level building blocks of one CoFEM E-step (Algorithm 1 around Algorithm 2).
+// Each function is the work of one thread block on one tile, with the tile's
+// coordinates passed explicitly, so that the single-problem kernels (one problem
+// per launch, tile = block index) and the serving kernels (many problems per
+// launch, tiles taken from a table) run the same code and produce bitwise the
+// same results for a problem.
+#pragma once
+#include "device_common.h"
+
+namespace cofem {
+
+// ---------------------------------------------------------------------------
+// E-step initialisation: B = [b | p_1..p_K | 0], X = 0, R = B, W = M^-1 R, P = W,
+// M^-1 = 1 / (beta theta + alpha).  Block blk covers coordinates [256 blk, +256).
+// Partial sums for rho and ||B_q||^2 go to part[blk * 3 + {0,1,2}].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void em_init_block(const SolveCfg& c, uint64_t key, int64_t D, int64_t Dp, int blk,
+                                              const float* __restrict__ b, const float* __restrict__ theta,
+                                              const float* __restrict__ alpha, float* __restrict__ minv,
+                                              float* __restrict__ X, float* __restrict__ R, float* __restrict__ Pd,
+                                              uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
+                                              double* __restrict__ part) {
+  const int64_t j = (int64_t)blk * VBLOCK + threadIdx.x;  // Dp is a multiple of VBLOCK
+  const bool real = j < D;
+  const float mi = (float)(1.0 / (c.beta * (double)theta[j] + (double)alpha[j]));
+  minv[j] = mi;
+  const double mid = (double)mi;
+  const uint64_t w = real ? probe_word(key, j) : 0ull;
+  const float bj = real ? b[j] : 0.0f;
+  for (int q = 0; q < c.Qp; ++q) {
+    float bq = 0.0f;
+    if (real) bq = (q == 0) ? bj : (q <= c.K ? probe_sign(w, q - 1) : 0.0f);
+    const int64_t o = (int64_t)q * Dp + j;
+    X[o] = 0.0f;
+    R[o] = bq;
+    const float p = (float)(mid * (double)bq);
+    Pd[o] = p;
+    if (PdH) {
+      uint16_t h, l;
+      split_bf16(p, h, l);
+      PdH[o] = h;
+      PdL[o] = l;
+    }
+  }
+  // rho_0 = sum_j b_j (minv_j b_j); rho_q = sum_j minv_j for probes (entries square to 1); ||b||^2
+  const double s_minv = block_sum(real ? mid : 0.0);
+  const double s_bw = block_sum(real ? (double)bj * (mid * (double)bj) : 0.0);
+  const double s_bb = block_sum(real ? (double)bj * (double)bj : 0.0);
+  if (threadIdx.x == 0) {
+    part[(int64_t)blk * 3 + 0] = s_minv;
+    part[(int64_t)blk * 3 + 1] = s_bw;
+    part[(int64_t)blk * 3 + 2] = s_bb;
+  }
+}
+
+// One block: rho_q, ||B_q||^2, ||B||_F^2, active flags, done = 0 (or 1 when the
+// per-column rule has nothing to solve), steps = 0.
+__device__ __forceinline__ void em_scalars_block(const SolveCfg& c, int64_t D, int nblk, const double* __restrict__ part,
+                                                 CGState* __restrict__ st) {
+  if (threadIdx.x >= 64) return;
+  const double t_minv = wave_sum_strided(part + 0, nblk, 3);
+  const double t_bw = wave_sum_strided(part + 1, nblk, 3);
+  const double t_bb = wave_sum_strided(part + 2, nblk, 3);
+  if (threadIdx.x != 0) return;
+  int nact = 0;
+  for (int q = 0; q < QMAX; ++q) {
+    double rho = 0.0, bn2 = 0.0;
+    if (q == 0) {
+      rho = t_bw;
+      bn2 = t_bb;
+    } else if (q <= c.K) {
+      rho = t_minv;
+      bn2 = (double)D;
+    }
+    st->rho[q] = rho;
+    st->bn2[q] = bn2;
+    st->pi[q] = 0.0;
+    st->gamma[q] = 0.0;
+    st->eta[q] = 0.0;
+    st->rn2[q] = bn2;
+    int act = (q < c.Q) ? 1 : 0;
+    if (c.stop_mode == 1 && bn2 <= 0.0) act = 0;
+    st->active[q] = act;
+    nact += act;
+  }
+  st->bnorm2 = t_bb + (double)c.K * (double)D;
+  st->delta = 1.0;
+  st->steps = 0;
+  st->done = (c.stop_mode == 1 && nact == 0) ? 1 : 0;
+}
+
+// mu = X_0, s_j = (1/K) sum_k p_kj X_kj (Eq. diag-estimate; probes regenerated from
+// the key), and for do_mstep: alpha_j = 1 / max(mu_j^2 + s_j, floor) (Eq. mstep),
+// counting floor events.  Block blk covers coordinates [256 blk, +256).
+__device__ __forceinline__ void mstep_block(const SolveCfg& c, uint64_t key, int64_t D, int64_t Dp, int blk,
+                                            const float* __restrict__ X, float* __restrict__ mu,
+                                            float* __restrict__ s_out, float* __restrict__ alpha, double floor,
+                                            int do_mstep, CGState* __restrict__ st) {
+  const int64_t j = (int64_t)blk * VBLOCK + threadIdx.x;
+  int clamped = 0;
+  if (j < D) {
+    const float m = X[j];
+    const uint64_t w = probe_word(key, j);
+    double acc = 0.0;
+    for (int k = 0; k < c.K; ++k) acc += (double)probe_sign(w, k) * (double)X[(int64_t)(k + 1) * Dp + j];
+    const double s = acc / (double)c.K;
+    mu[j] = m;
+    s_out[j] = (float)s;
+    if (do_mstep) {
+      double den = (double)m * (double)m + s;
+      if (den < floor) {
+        den = floor;
+        clamped = 1;
+      }
+      alpha[j] = (float)(1.0 / den);
+    }
+  }
+  clamped = wave_sum_int(clamped);
+  if ((threadIdx.x & 63) == 0 && clamped) atomicAdd(&st->clamped, clamped);
+}
+
+// ---------------------------------------------------------------------------
+// The operator's contractions: Ypart[split][q][row] = sum_{k in split} M[row, k] Z[q, k].
+//
+// Block = 5 waves.  Waves 0-3 compute: wave w owns rows row0 .. row0 + 16 RT - 1
+// and all CT*16 columns, and streams its rows of M from HBM straight into VGPRs
+// in the MFMA operand layout, one stage ahead.  Wave 4 is a producer: it copies
+// the right-hand-side fragments of the next stage (already in MFMA lane order)
+// from L2 into a double-buffered LDS tile, so the compute waves never wait on
+// those loads (vmcnt counts in issue order per wave).  The prefetch is issued
+// without a branch and pinned ahead of the MFMAs with sched_barrier, so it stays
+// in flight across the stage.  L is the tile index (split and row block via tile_of).
+// ---------------------------------------------------------------------------
+// bf16: v_mfma_f32_16x16x32_bf16, lane l holds A[l%16][8(l/16) .. +8), B[8(l/16) .. +8)[l%16]
+// and returns D[4(l/16) .. +4)[l%16].  ZH + ZL carries each right-hand side to ~2^-17.
+template <int RT, int CT, int KS>
+__device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict__ M, int64_t ldm,
+                                               const uint16_t* __restrict__ ZH, const uint16_t* __restrict__ ZL,
+                                               int64_t ldz, float* __restrict__ Yp, int64_t ldy, int Qp,
+                                               int64_t kchunk, int64_t kdim, int nrb, int splits) {
+  constexpr int NF = KS * CT * 2;  // fragments per stage
+  constexpr int SK = 32 * KS;      // k per stage
+  __shared__ bf16x8_t sB[2][NF][64];
+  int rb, sp;
+  tile_of(L, nrb, splits, rb, sp);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int64_t kb = (int64_t)sp * kchunk;
+  const int64_t ke = (kb + kchunk < kdim) ? kb + kchunk : kdim;
+  const int nst = (ke > kb) ? (int)((ke - kb) / SK) : 0;
+  if (wave == 4) {
+    const uint16_t* src[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int s = f / (CT * 2), rem = f % (CT * 2), ct = rem >> 1, hl = rem & 1;
+      src[f] = (hl ? ZL : ZH) + (int64_t)(ct * 16 + r16) * ldz + kb + s * 32 + 8 * g;
+    }
+    if (nst > 0) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sB[0][f][lane] = *reinterpret_cast<const bf16x8_t*>(src[f]);
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+      // the next stage's fragments (the last stage reloads its own into the idle buffer)
+      const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
+      bf16x8_t t[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) t[f] = *reinterpret_cast<const bf16x8_t*>(src[f] + off);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sB[(st + 1) & 1][f][lane] = t[f];
+      __syncthreads();
+    }
+    return;
+  }
+  const int64_t row0 = (int64_t)rb * (64 * RT) + (int64_t)wave * (16 * RT);
+  f32x4 acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* ap[RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 8 * g;
+  bf16x8_t acur[RT][KS];
+  if (nst > 0) {
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + s * 32);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;  // always in bounds
+    bf16x8_t anxt[RT][KS];
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + off + s * 32);
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this stage's MFMAs
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      bf16x8_t bh[CT], bl[CT];
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        bh[b] = sB[buf][(s * CT + b) * 2 + 0][lane];
+        bl[b] = sB[buf][(s * CT + b) * 2 + 1][lane];
+      }
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int b = 0; b < CT; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[a][s], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[a][s], bl[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acur[a][s] = anxt[a][s];
+  }
+  float* yb = Yp + (int64_t)sp * Qp * ldy;
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int64_t q = b * 16 + r16;
+      const int64_t row = row0 + a * 16 + 4 * g;
+      *reinterpret_cast<f32x4*>(yb + q * ldy + row) = acc[a][b];
+    }
+}
+
+// FP32: v_mfma_f32_16x16x4_f32.  Each lane holds 4 consecutive k of its row (and of its
+// column of Z) and feeds element e to the e-th MFMA, so the four MFMAs of a 16-k step
+// see the same k order in both operands.  1 KB fragment per 16-k step and column tile.
+template <int RT, int CT, int KS>
+__device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M, int64_t ldm,
+                                              const float* __restrict__ Z, int64_t ldz, float* __restrict__ Yp,
+                                              int64_t ldy, int Qp, int64_t kchunk, int64_t kdim, int nrb,
+                                              int splits) {
+  constexpr int NF = KS * CT;
+  constexpr int SK = 16 * KS;
+  __shared__ f32x4 sB[2][NF][64];
+  int rb, sp;
+  tile_of(L, nrb, splits, rb, sp);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int64_t kb = (int64_t)sp * kchunk;
+  const int64_t ke = (kb + kchunk < kdim) ? kb + kchunk : kdim;
+  const int nst = (ke > kb) ? (int)((ke - kb) / SK) : 0;
+  if (wave == 4) {
+    const float* src[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int s = f / CT, ct = f % CT;
+      src[f] = Z + (int64_t)(ct * 16 + r16) * ldz + kb + s * 16 + 4 * g;
+    }
+    if (nst > 0) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sB[0][f][lane] = *reinterpret_cast<const f32x4*>(src[f]);
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+      const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
+      f32x4 t[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) t[f] = *reinterpret_cast<const f32x4*>(src[f] + off);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sB[(st + 1) & 1][f][lane] = t[f];
+      __syncthreads();
+    }
+    return;
+  }
+  const int64_t row0 = (int64_t)rb * (64 * RT) + (int64_t)wave * (16 * RT);
+  f32x4 acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const float* ap[RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 4 * g;
+  f32x4 acur[RT][KS];
+  if (nst > 0) {
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + s * 16);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
+    f32x4 anxt[RT][KS];
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + off + s * 16);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      f32x4 bz[CT];
+#pragma unroll
+      for (int b = 0; b < CT; ++b) bz[b] = sB[buf][s * CT + b][lane];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int a = 0; a < RT; ++a)
+#pragma unroll
+          for (int b = 0; b < CT; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[a][s][e], bz[b][e], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acur[a][s] = anxt[a][s];
+  }
+  float* yb = Yp + (int64_t)sp * Qp * ldy;
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int64_t q = b * 16 + r16;
+      const int64_t row = row0 + a * 16 + 4 * g;
+      *reinterpret_cast<f32x4*>(yb + q * ldy + row) = acc[a][b];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Split-K finishes and the CG vector updates.  Vector tiles: (chunk bx of VCHUNK
+// coordinates, column q); each thread owns 4 consecutive coordinates.
+// ---------------------------------------------------------------------------
+// V[q][i] = sum_split Ypart[split][q][i] (fixed split order); V (FP32) and/or VH/VL.
+__device__ __forceinline__ void finish1_tile(int bx, int q, const float* __restrict__ Yp, int splits, int64_t Np,
+                                             float* __restrict__ V, uint16_t* __restrict__ VH,
+                                             uint16_t* __restrict__ VL, int Qp) {
+  const int64_t i = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
+  if (i >= Np) return;
+  const int64_t o = (int64_t)q * Np + i;
+  f32x4 v = *reinterpret_cast<const f32x4*>(Yp + o);
+  for (int sp = 1; sp < splits; ++sp) v += *reinterpret_cast<const f32x4*>(Yp + (int64_t)sp * Qp * Np + o);
+  if (V) *reinterpret_cast<f32x4*>(V + o) = v;
+  if (VH) store_split4(VH, VL, o, v);
+}
+
+// Psi = beta * sum_split Ypart + alpha Pd and the tile's partial of pi_q = sum_j Pd_jq Psi_jq
+// at pipart[q * nbx + bx].
+__device__ __forceinline__ void finish2_tile(const SolveCfg& c, int bx, int q, int nbx, const float* __restrict__ Yp,
+                                             int splits, int64_t Dp, const float* __restrict__ alpha,
+                                             const float* __restrict__ Pd, float* __restrict__ Psi,
+                                             double* __restrict__ pipart) {
+  const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
+  double acc = 0.0;
+  if (j < Dp) {
+    const int64_t o = (int64_t)q * Dp + j;
+    f32x4 y = *reinterpret_cast<const f32x4*>(Yp + o);
+    for (int sp = 1; sp < splits; ++sp) y += *reinterpret_cast<const f32x4*>(Yp + (int64_t)sp * c.Qp * Dp + o);
+    const f32x4 al = *reinterpret_cast<const f32x4*>(alpha + j);
+    const f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
+    f32x4 ps;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ps[e] = (float)(c.beta * (double)y[e] + (double)al[e] * (double)p[e]);
+      acc += (double)p[e] * (double)ps[e];
+    }
+    *reinterpret_cast<f32x4*>(Psi + o) = ps;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) pipart[(int64_t)q * nbx + bx] = acc;
+}
+
+// gamma_q = rho_q / pi_q (pi_q reduced here from its nbx partials in a fixed order, so
+// every tile of the column gets the same value); X += gamma Pd, R -= gamma Psi; partials
+// of ||R_q||^2 and rho'_q = sum R (M^-1 R) at part[(q * nbx + bx) * 2 + {0, 1}].
+__device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q, int nbx, int64_t Dp,
+                                               const float* __restrict__ minv, float* __restrict__ X,
+                                               float* __restrict__ R, const float* __restrict__ Pd,
+                                               const float* __restrict__ Psi, const double* __restrict__ pipart,
+                                               double* __restrict__ part, CGState* __restrict__ st) {
+  __shared__ double s_pi;
+  if (threadIdx.x < 64) {
+    const double a = wave_sum_strided(pipart + (int64_t)q * nbx, nbx, 1);
+    if (threadIdx.x == 0) s_pi = a;
+  }
+  __syncthreads();
+  const double pi = s_pi;
+  const double rho = st->rho[q];
+  const int act = st->active[q];
+  const double gam = (act && pi > 0.0) ? rho / pi : 0.0;
+  if (bx == 0 && threadIdx.x == 0) {
+    st->pi[q] = pi;
+    st->gamma[q] = gam;
+    if (act && !(pi > 0.0) && rho != 0.0) {  // breakdown: freeze the column
+      st->active[q] = 0;
+      atomicAdd(&st->breakdown, 1);
+    }
+  }
+  const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
+  double rr = 0.0, rw = 0.0;
+  if (j < Dp) {
+    const int64_t o = (int64_t)q * Dp + j;
+    const f32x4 mi = *reinterpret_cast<const f32x4*>(minv + j);
+    f32x4 x = *reinterpret_cast<const f32x4*>(X + o);
+    f32x4 r = *reinterpret_cast<const f32x4*>(R + o);
+    const f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
+    const f32x4 ps = *reinterpret_cast<const f32x4*>(Psi + o);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      x[e] = (float)((double)x[e] + gam * (double)p[e]);
+      r[e] = (float)((double)r[e] - gam * (double)ps[e]);
+      const double rd = (double)r[e];
+      rr += rd * rd;
+      rw += rd * ((double)mi[e] * rd);
+    }
+    *reinterpret_cast<f32x4*>(X + o) = x;
+    *reinterpret_cast<f32x4*>(R + o) = r;
+  }
+  rr = block_sum(rr);
+  rw = block_sum(rw);
+  if (threadIdx.x == 0) {
+    part[((int64_t)q * nbx + bx) * 2 + 0] = rr;
+    part[((int64_t)q * nbx + bx) * 2 + 1] = rw;
+  }
+}
+
+// One block: ||R_q||^2 and rho'_q from the partials, the stop rule of Algorithm 2
+// (joint Frobenius ratio, or per-column freezing), steps, eta_q = rho'_q / rho_q.
+__device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, const double* __restrict__ part,
+                                                 CGState* __restrict__ st) {
+  __shared__ double s_rr[QMAX], s_rw[QMAX];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int q = wv; q < c.Q; q += 4) {
+    const double a = wave_sum_strided(part + (int64_t)q * nbx * 2 + 0, nbx, 2);
+    const double b = wave_sum_strided(part + (int64_t)q * nbx * 2 + 1, nbx, 2);
+    if (ln == 0) {
+      s_rr[q] = a;
+      s_rw[q] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double rsum = 0.0;
+  for (int q = 0; q < c.Q; ++q) rsum += s_rr[q];
+  const double delta = sqrt(rsum / st->bnorm2);
+  st->delta = delta;
+  const int steps = st->steps + 1;
+  st->steps = steps;
+  int done = 0;
+  if (c.stop_mode == 0) {
+    if (delta <= c.tol) done = 1;
+  } else {
+    int nact = 0;
+    for (int q = 0; q < c.Q; ++q) {
+      if (st->active[q] && sqrt(s_rr[q] / st->bn2[q]) <= c.tol) st->active[q] = 0;
+      nact += st->active[q];
+    }
+    if (nact == 0) done = 1;
+  }
+  if (steps >= c.U) done = 1;
+  for (int q = 0; q < c.Q; ++q) {
+    st->rn2[q] = s_rr[q];
+    const double old = st->rho[q];
+    st->eta[q] = (old != 0.0) ? s_rw[q] / old : 0.0;
+    st->rho[q] = s_rw[q];
+  }
+  st->done = done;
+}
+
+// P = M^-1 R + eta P (FP32, and bf16 hi/lo when PdH is not null).
+__device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, const float* __restrict__ minv,
+                                                  const float* __restrict__ R, float* __restrict__ Pd,
+                                                  uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
+                                                  const CGState* __restrict__ st) {
+  const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
+  if (j >= Dp) return;
+  const double eta = st->eta[q];
+  const int64_t o = (int64_t)q * Dp + j;
+  const f32x4 mi = *reinterpret_cast<const f32x4*>(minv + j);
+  const f32x4 r = *reinterpret_cast<const f32x4*>(R + o);
+  f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) p[e] = (float)((double)mi[e] * (double)r[e] + eta * (double)p[e]);
+  *reinterpret_cast<f32x4*>(Pd + o) = p;
+  if (PdH) store_split4(PdH, PdL, o, p);
+}
+
+}  // namespace cofem

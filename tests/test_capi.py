@@ -53,7 +53,9 @@ def _c_layout(struct, fields):
     return vals[0], vals[1:]
 
 
-@pytest.mark.parametrize("cls,cname", [(lib.Params, "cofem_params"), (lib.Stats, "cofem_stats")])
+@pytest.mark.parametrize("cls,cname", [(lib.Params, "cofem_params"), (lib.Stats, "cofem_stats"),
+                                       (lib.RequestInfo, "cofem_request_info"),
+                                       (lib.ServerStats, "cofem_server_stats")])
 def test_struct_layout_matches_c(cls, cname):
     names = [f[0] for f in cls._fields_]
     size, offs = _c_layout(cname, names)
@@ -85,3 +87,15 @@ def test_null_arguments_are_rejected():
     assert so.cofem_posterior(None, None, None, None, None) == -1
     so.cofem_destroy(None)
     assert so.cofem_abi_version() == 1
+
+
+def test_server_rejects_bad_arguments_without_device_work():
+    so = lib.load()
+    h = ctypes.c_void_p()
+    assert so.cofem_server_create(ctypes.c_size_t(1 << 30), 0, 4, None, ctypes.byref(h)) == -1
+    assert so.cofem_server_create(ctypes.c_size_t(1 << 30), 129, 4, None, ctypes.byref(h)) == -1
+    assert so.cofem_server_create(ctypes.c_size_t(1 << 30), 8, 0, None, ctypes.byref(h)) == -1
+    assert so.cofem_server_create(ctypes.c_size_t(1000), 8, 4, None, ctypes.byref(h)) == -1
+    assert not h.value
+    assert so.cofem_server_step(None, None, None) == -1
+    so.cofem_server_destroy(None)
