@@ -13,7 +13,12 @@ Prints one JSON line.  `value` is EM iterations per second.  Beside it:
                 launch / average launch time from HIP events on the library's
                 stream over the timed steps, against 8 TB/s;
   fp32          the same fit with the FP32 dictionary throughout;
-  cpu_baseline  the FP64 oracle on a bounded sample of the same workload.
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload;
+  serving       the continuous-batching server on a stream of independent
+                requests (D uniform in [512, 16384], N = D/4, 5 % spikes, sigma in
+                {0.01, 0.05}, K = 16, T = 30, FP32): saturated request rate from a
+                pilot batch, then Poisson arrivals at 0.8x that rate; p50/p99 latency
+                from submission to completion.
 """
 from __future__ import annotations
 
@@ -43,6 +48,10 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the all-FP32 comparison fit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12, help="CG steps in the oracle sample")
+    ap.add_argument("--serve-requests", type=int, default=512, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-pilot", type=int, default=32, help="requests of the saturation pilot")
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of saturation")
     return ap.parse_args()
 
 
@@ -128,7 +137,120 @@ def main():
         log(f"fp32 comparison fit: {out['fp32']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, w, st, args.cpu_steps)
+    if args.serve_requests > 0:
+        del phi_d, y_d, prob
+        torch.cuda.empty_cache()
+        out["serving"] = serving(args)
     print(json.dumps(out), flush=True)
+
+
+SERVE_KW = dict(K=16, T=30, U=400, tol=1e-5)
+
+
+class Prepared:
+    """Generates request inputs in arrival order on a background thread, a bounded
+    number ahead (NumPy releases the GIL while it fills the arrays)."""
+
+    def __init__(self, descs, ahead=48):
+        import queue
+        import threading
+
+        import workloads
+
+        self.q = queue.Queue(maxsize=ahead)
+
+        def run():
+            for d in descs:
+                self.q.put((d, workloads.serving_request(d)))
+
+        self.t = threading.Thread(target=run, daemon=True)
+        self.t.start()
+
+    def get(self, block=True):
+        import queue
+
+        try:
+            return self.q.get(block=block)
+        except queue.Empty:
+            return None
+
+
+def serving(args):
+    import numpy as np
+
+    import paper_2105_10439_amd as lib
+    import workloads
+
+    budget = int(args.serve_budget_gib * (1 << 30))
+    descs = workloads.serving_stream(args.serve_requests, seed=4242)
+
+    def submit(srv, d, p):
+        return srv.submit(p.phi, p.y, beta=p.beta, seed=d["seed"], **SERVE_KW)
+
+    def drain(srv, ids, done):
+        for rid in ids:
+            if rid not in done:
+                r = srv.result(rid)
+                if r is not None:
+                    done[rid] = r[3]
+
+    # 1. saturated rate: a pilot batch submitted at once
+    pilot = descs[:min(args.serve_pilot, len(descs))]
+    prep = Prepared(pilot)
+    items = [prep.get() for _ in pilot]
+    srv = lib.Server(budget, max_slots=128, steps_per_tick=4)
+    t0 = time.perf_counter()
+    ids = [submit(srv, d, p) for d, p in items]
+    done = {}
+    while len(done) < len(ids):
+        srv.step()
+        drain(srv, ids, done)
+    sat_s = time.perf_counter() - t0
+    sat_rps = len(ids) / sat_s
+    srv.close()
+    del items
+    log(f"serving pilot: {len(ids)} requests in {sat_s:.2f}s = {sat_rps:.2f} req/s")
+
+    # 2. Poisson arrivals at a fraction of saturation
+    rate = args.serve_load * sat_rps
+    arrivals = workloads.poisson_arrivals(len(descs), rate, seed=777)
+    prep = Prepared(descs)
+    srv = lib.Server(budget, max_slots=128, steps_per_tick=4)
+    ids, done = [], {}
+    nxt = prep.get()
+    k = 0
+    late = 0.0
+    t0 = time.perf_counter()
+    last_log = t0
+    while len(done) < len(descs):
+        now = time.perf_counter() - t0
+        while nxt is not None and k < len(descs) and arrivals[k] <= now:
+            late = max(late, now - arrivals[k])
+            ids.append(submit(srv, *nxt))
+            k += 1
+            nxt = prep.get() if k < len(descs) else None
+        running, pending = srv.step()
+        drain(srv, ids, done)
+        if running == 0 and pending == 0 and k < len(descs):
+            time.sleep(max(0.0, min(0.002, arrivals[k] - (time.perf_counter() - t0))))
+        if time.perf_counter() - last_log > 10:
+            last_log = time.perf_counter()
+            log(f"serving: {len(done)}/{len(descs)} done, {running} running, {pending} pending")
+    el = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array([inf["t_finish_ms"] - inf["t_submit_ms"] for inf in done.values()])
+    steps = sum(inf["total_cg_steps"] for inf in done.values())
+    res = dict(requests=len(descs), workload="dense Gaussian requests, D uniform in [512, 16384], N = D/4, 5% spikes, "
+                                             "sigma in {0.01, 0.05}, K=16, T=30, tol=1e-5, FP32",
+               budget_gib=args.serve_budget_gib, saturated_rps=round(sat_rps, 3), arrival_rps=round(rate, 3),
+               throughput_rps=round(len(descs) / el, 3), em_iters_per_s=round(len(descs) * SERVE_KW["T"] / el, 2),
+               p50_ms=round(float(np.percentile(lat, 50)), 2), p99_ms=round(float(np.percentile(lat, 99)), 2),
+               mean_ms=round(float(lat.mean()), 2), max_active=st["max_active"], ticks=st["ticks"],
+               cg_steps_total=int(steps), max_submit_delay_ms=round(1e3 * late, 1),
+               bytes_peak_gib=round(st["bytes_peak"] / (1 << 30), 3))
+    log(f"serving: {res}")
+    return res
 
 
 def cpu_baseline(prob, w, st, cg_steps):
