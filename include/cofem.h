@@ -79,7 +79,7 @@ typedef enum { COFEM_PHI_FP32 = 0, COFEM_PHI_BF16 = 1 } cofem_phi_dtype;
  *   phi_dtype   arithmetic of the operator: COFEM_PHI_FP32, or COFEM_PHI_BF16 (Phi
  *               rounded to bfloat16 once, products accumulated in FP32).
  *   refine_last with COFEM_PHI_BF16: the last refine_last E-steps use the FP32 operator.
- *   conv_taps   FIR length for COFEM_OP_CONV (1..4096); ignored otherwise.
+ *   conv_taps   FIR length L for COFEM_OP_CONV (1..256); ignored otherwise.
  *   seed        probe seed.  Probe entry p_{k,j} at EM iteration t is +1 if bit k of
  *               w(t, j) is 0 and -1 otherwise, where w(t, j) is output j+1 of the
  *               SplitMix64 stream started at key_t, and key_t is output t of the

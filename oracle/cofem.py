@@ -177,6 +177,24 @@ class ConvOperator:
             Phi[idx + t, idx] = ht
         return Phi
 
+    def normal_rows(self, P: np.ndarray, alpha: np.ndarray, beta: float, rows) -> np.ndarray:
+        """Rows `rows` of beta Phi^T Phi P + alpha P (the operator of Algorithm 2) by
+        direct sums, for sizes where whole products are too slow: row j needs
+        (Phi P)_i only for j <= i < j + L, and each of those is a sum over L taps."""
+        P = np.asarray(P, dtype=np.float64)
+        if P.ndim == 1:
+            P = P[:, None]
+        L = self.h.shape[0]
+        taps = np.arange(L)
+        out = np.empty((len(rows), P.shape[1]))
+        for r, j in enumerate(rows):
+            i = np.arange(j, min(j + L, self.D))              # rows of Phi P that meet column j
+            src = i[:, None] - taps[None, :]                  # (Phi P)_i = sum_s h[s] P[i - s], i - s >= 0
+            w = np.where(src >= 0, self.h[None, :], 0.0)
+            V = np.einsum("is,isq->iq", w, P[np.clip(src, 0, None)])
+            out[r] = beta * (self.h[:i.shape[0]] @ V) + float(alpha[j]) * P[j]
+        return out
+
 
 # ---------------------------------------------------------------------------
 # Algorithm 2: parallel (multi-RHS) preconditioned conjugate gradient.

@@ -75,6 +75,9 @@ struct cofem_ctx {
   float* phi32T = nullptr;
   uint16_t* phi16 = nullptr;
   uint16_t* phi16T = nullptr;
+  // convolutional dictionary: padded taps (FP32 and bfloat16)
+  float* hp32 = nullptr;
+  uint16_t* hp16 = nullptr;
   // D- and N-vectors
   float *theta = nullptr, *alpha = nullptr, *alpha_hook = nullptr, *b32 = nullptr, *b16 = nullptr;
   float* minv = nullptr;
@@ -146,8 +149,13 @@ cofem_status validate(const cofem_params* p) {
   if (p->refine_last < 0 || p->refine_last > p->T) return fail(COFEM_EINVAL, "refine_last must be in [0, T]");
   if (!(p->alpha_floor > 0.0) || !std::isfinite(p->alpha_floor))
     return fail(COFEM_EINVAL, "alpha_floor must be finite and > 0");
-  if (p->op_kind == COFEM_OP_CONV) return fail(COFEM_EINVAL, "op_kind COFEM_OP_CONV is not available in this build");
-  if (p->op_kind != COFEM_OP_DENSE) return fail(COFEM_EINVAL, "bad op_kind");
+  if (p->op_kind == COFEM_OP_CONV) {
+    if (p->N != p->D) return fail(COFEM_EINVAL, "COFEM_OP_CONV needs N == D");
+    if (p->conv_taps < 1 || p->conv_taps > CONV_MAX_TAPS)
+      return fail(COFEM_EINVAL, "conv_taps must be in [1, " + std::to_string(CONV_MAX_TAPS) + "]");
+  } else if (p->op_kind != COFEM_OP_DENSE) {
+    return fail(COFEM_EINVAL, "bad op_kind");
+  }
   return COFEM_OK;
 }
 
@@ -204,7 +212,50 @@ cofem_status harvest(cofem_ctx* c, int real_steps) {
 }
 
 // Psi = A Pd into c->Psi and pi into the state, for the given alpha buffer.
+// The two filter passes of the convolutional dictionary (pass 2 fuses the finish).
+cofem_status apply_conv(cofem_ctx* c, bool use16, const float* alpha, const SolveCfg& sc, int step) {
+  ConvArgs a{};
+  a.hp32 = c->hp32;
+  a.hp16 = c->hp16;
+  a.L = c->p.conv_taps;
+  a.D = c->p.D;
+  a.Dp = c->Dp;
+  a.Q = sc.Q;
+  a.nct = (sc.Q + 15) / 16;
+  a.nbx = (int)((c->Dp + 1023) / 1024);
+  a.beta = sc.beta;
+  a.done = &c->st->done;
+  ConvArgs p1 = a, p2 = a;
+  if (use16) {
+    p1.inH = c->PdH;
+    p1.inL = c->PdL;
+    p1.outH = c->VH;
+    p1.outL = c->VL;
+    p2.inH = c->VH;
+    p2.inL = c->VL;
+  } else {
+    p1.in32 = c->Pd;
+    p1.out32 = c->V;
+    p2.in32 = c->V;
+  }
+  p2.out32 = c->Psi;
+  p2.alpha = alpha;
+  p2.Pd = c->Pd;
+  p2.pipart = c->pipart;
+  TimedLaunch t;
+  cofem_status rc;
+  const int which = use16 ? 1 : 0;
+  if (c->timing && (rc = timed_begin(c, which, step, &t)) != COFEM_OK) return rc;
+  launch_conv_pass(p1, 0, use16 ? 1 : 0, c->stream);
+  if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
+  if (c->timing && (rc = timed_begin(c, which, step, &t)) != COFEM_OK) return rc;
+  launch_conv_pass(p2, 1, use16 ? 1 : 0, c->stream);
+  if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
+  return COFEM_OK;
+}
+
 cofem_status apply_operator(cofem_ctx* c, bool use16, const float* alpha, const SolveCfg& sc, int step) {
+  if (c->p.op_kind == COFEM_OP_CONV) return apply_conv(c, use16, alpha, sc, step);
   TimedLaunch t;
   cofem_status rc;
   if (use16) {
@@ -258,6 +309,7 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
     delete c;
     return fail(COFEM_EDEVICE, "hipGetDevice failed");
   }
+  const bool conv = p->op_kind == COFEM_OP_CONV;
   c->Np = round_up(p->N, 256);
   c->Dp = round_up(p->D, 256);
   c->Q = p->K + 1;
@@ -269,9 +321,10 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   c->g1_32 = choose_gemm(c->Np, c->Dp, 0);
   c->g2_32 = choose_gemm(c->Dp, c->Np, 0);
   const int64_t Np = c->Np, Dp = c->Dp, Qp = c->Qp;
-  const int64_t ysplit = std::max<int64_t>(std::max<int64_t>(c->g1_16.splits, c->g1_32.splits) * Np,
-                                           std::max<int64_t>(c->g2_16.splits, c->g2_32.splits) * Dp);
-  const size_t nd = (size_t)Np * (size_t)Dp;
+  const int64_t ysplit = conv ? 0
+                              : std::max<int64_t>(std::max<int64_t>(c->g1_16.splits, c->g1_32.splits) * Np,
+                                                  std::max<int64_t>(c->g2_16.splits, c->g2_32.splits) * Dp);
+  const size_t nd = conv ? 0 : (size_t)Np * (size_t)Dp;
 #define TRY(x)                   \
   do {                           \
     cofem_status r_ = (x);       \
@@ -281,14 +334,22 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
       return r_;                 \
     }                            \
   } while (0)
+  if (conv) {
+    TRY(dalloc(c, &c->hp32, CONV_HPAD));
+    TRY(dalloc(c, &c->hp16, CONV_HPAD));
+  }
   if (c->need32) {
-    TRY(dalloc(c, &c->phi32, nd));
-    TRY(dalloc(c, &c->phi32T, nd));
+    if (!conv) {
+      TRY(dalloc(c, &c->phi32, nd));
+      TRY(dalloc(c, &c->phi32T, nd));
+    }
     TRY(dalloc(c, &c->V, (size_t)Qp * Np));
   }
   if (c->need16) {
-    TRY(dalloc(c, &c->phi16, nd));
-    TRY(dalloc(c, &c->phi16T, nd));
+    if (!conv) {
+      TRY(dalloc(c, &c->phi16, nd));
+      TRY(dalloc(c, &c->phi16T, nd));
+    }
     TRY(dalloc(c, &c->PdH, (size_t)Qp * Dp));
     TRY(dalloc(c, &c->PdL, (size_t)Qp * Dp));
     TRY(dalloc(c, &c->VH, (size_t)Qp * Np));
@@ -338,6 +399,15 @@ COFEM_API void cofem_destroy(cofem_ctx* c) {
 COFEM_API cofem_status cofem_set_dictionary(cofem_ctx* c, const float* phi) {
   if (!c || !phi) return fail(COFEM_EINVAL, "NULL argument");
   const double t0 = now_ms();
+  if (c->p.op_kind == COFEM_OP_CONV) {
+    launch_conv_setup(phi, c->p.conv_taps, c->p.D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->hp32, c->hp16,
+                      c->theta, c->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->dict_loaded = true;
+    c->stats.ms_setup = now_ms() - t0;
+    return COFEM_OK;
+  }
   launch_dict_layouts(phi, c->p.N, c->p.D, c->Np, c->Dp, c->phi32, c->phi32T, c->phi16, c->phi16T, c->stream);
   // theta from the caller's FP32 matrix (b is formed per fit from the library's copies)
   launch_theta(phi, c->p.N, c->p.D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->theta, c->stream);
@@ -363,8 +433,13 @@ COFEM_API cofem_status cofem_fit(cofem_ctx* c, const float* y) {
   // b = beta Phi^T y, formed with the same dictionary as the operator of each phase: the
   // rounding residual of an FP32 b is not in the range of the bf16 Phi^T, and EM would
   // amplify it through the directions that only diag(alpha) constrains.
-  if (c->need32) launch_rhs(c->phi32T, nullptr, c->Np, c->Dp, c->yv, p.beta, c->b32, c->stream);
-  if (c->need16) launch_rhs(nullptr, c->phi16T, c->Np, c->Dp, c->yv, p.beta, c->b16, c->stream);
+  if (p.op_kind == COFEM_OP_CONV) {
+    if (c->need32) launch_conv_rhs(c->hp32, nullptr, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b32, c->stream);
+    if (c->need16) launch_conv_rhs(c->hp32, c->hp16, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b16, c->stream);
+  } else {
+    if (c->need32) launch_rhs(c->phi32T, nullptr, c->Np, c->Dp, c->yv, p.beta, c->b32, c->stream);
+    if (c->need16) launch_rhs(nullptr, c->phi16T, c->Np, c->Dp, c->yv, p.beta, c->b16, c->stream);
+  }
   launch_fill(c->alpha, 1.0f, c->Dp, c->stream);
   for (int t = 1; t <= p.T; ++t) {
     const bool use16 = c->need16 && (t <= p.T - p.refine_last);

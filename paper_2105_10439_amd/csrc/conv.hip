@@ -1,0 +1,327 @@
+// The convolutional dictionary of Sec. V-A.2 on gfx950: N = D and
+// Phi_ij = h[i - j] for 0 <= i - j < L, a lower-triangular band Toeplitz matrix.
+// Applying it is a causal FIR filter and applying Phi^T the time-reversed one, so
+// the operator Psi = beta Phi^T (Phi Pd) + alpha Pd of Algorithm 2 costs 2 L
+// multiply-adds per coordinate and right-hand side and never forms Phi.
+//
+// Both filters run on the matrix cores.  Cut the time axis into 16-sample
+// blocks: output block a of the causal filter is sum_d T_d Pd_{a-d}, where T_d is
+// the 16 x 16 Toeplitz block T_d[r][c] = h[16 d + r - c] (zero outside [0, L)),
+// d = 0 .. NB-1 with NB = floor((L + 14) / 16) + 1 (17 for L = 256, so the
+// blocks carry 6 % more multiply-adds than the taps).  A wave owns one 16-column
+// tile of right-hand sides and a run of VCHUNK output samples: the NB Toeplitz
+// blocks sit in VGPRs in the MFMA operand layout for the whole run, and the
+// input blocks pass through a sliding window of NB VGPR slots, so each input
+// sample is loaded once per run and used NB times.  The anti-causal filter is
+// the same with T_d^T and the window running forward.  The second pass fuses
+// the rest of the line "Psi <- A P": Psi = beta (.) + alpha Pd and the FP64
+// partials of pi_q = sum_j Pd_jq Psi_jq, one per (column, VCHUNK run), in the
+// layout the CG update kernel reduces.
+//
+// FP32 form: v_mfma_f32_16x16x4_f32, taps and signals in FP32.
+// bf16 form: v_mfma_f32_16x16x32_bf16 with the taps rounded to bfloat16 once (the
+// dictionary of the precision form) and each signal carried as a hi + lo pair of
+// bfloat16 (about 2^-17 relative), over 32-sample input blocks: output block
+// a = 2 m + par is sum_d T^(par)_d Pd_{m-d} with T^(par)_d[r][c] = h[32 d + 16 par
+// + r - c], d = 0 .. NB-1, NB = floor((L + 30) / 32) + 1 (9 for L = 256).
+#include <algorithm>
+
+#include "kernels.h"
+#include "device_common.h"
+
+namespace cofem {
+
+typedef __attribute__((ext_vector_type(8))) unsigned short u16x8;
+
+// Padded taps: hp[CONV_HOFF + m] = h[m] for 0 <= m < L, zero for the rest of the
+// CONV_HPAD entries (every index the Toeplitz blocks touch stays inside).
+constexpr int CONV_HOFF = 32;
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+__global__ void k_conv_taps(const float* __restrict__ h, int L, float* __restrict__ hp32,
+                            uint16_t* __restrict__ hp16) {
+  for (int i = threadIdx.x; i < CONV_HPAD; i += blockDim.x) {
+    const int m = i - CONV_HOFF;
+    const float v = (m >= 0 && m < L) ? h[m] : 0.0f;
+    hp32[i] = v;
+    hp16[i] = bf16_rne(v);
+  }
+}
+
+// theta_j = sum_i Phi_ij^2 = sum_{t < min(L, D - j)} h[t]^2 (Jacobi, FP64) or 1; padding 1.
+__global__ __launch_bounds__(256) void k_conv_theta(const float* __restrict__ hp32, int L, int64_t D, int64_t Dp,
+                                                    int jacobi, float* __restrict__ theta) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Dp) return;
+  if (j >= D || !jacobi) {
+    theta[j] = 1.0f;
+    return;
+  }
+  const int64_t n = std::min<int64_t>(L, D - j);
+  double sq = 0.0;
+  for (int64_t t = 0; t < n; ++t) {
+    const double v = (double)hp32[CONV_HOFF + t];
+    sq += v * v;
+  }
+  theta[j] = (float)sq;
+}
+
+// b_j = beta sum_{t < L, j + t < D} h[t] y_{j+t} (the anti-causal filter of y, FP64
+// sums) with the FP32 taps, or with the bfloat16 taps for the bf16 phase.
+__global__ __launch_bounds__(256) void k_conv_rhs(const float* __restrict__ hp32, const uint16_t* __restrict__ hp16,
+                                                  int L, int64_t D, int64_t Dp, const float* __restrict__ y,
+                                                  double beta, float* __restrict__ b) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Dp) return;
+  double acc = 0.0;
+  if (j < D) {
+    const int64_t n = std::min<int64_t>(L, D - j);
+    for (int64_t t = 0; t < n; ++t) {
+      const double h = hp16 ? (double)bf16_val(hp16[CONV_HOFF + t]) : (double)hp32[CONV_HOFF + t];
+      acc += h * (double)y[j + t];
+    }
+  }
+  b[j] = (float)(beta * acc);
+}
+
+// ---------------------------------------------------------------------------
+// The two filter passes.  DIR 0: out = Phi in (causal).  DIR 1: out = beta Phi^T in +
+// alpha Pd with the pi partials (anti-causal).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void conv_epilogue(const ConvArgs& a, int dir, int64_t q, bool qv, int64_t row, f32x4 v,
+                                              const f32x4& al, const f32x4& pd, double& pacc) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (row + e >= a.D) v[e] = 0.0f;
+  const int64_t o = q * a.Dp + row;
+  if (dir == 0) {
+    if (qv) {
+      if (a.out32) *reinterpret_cast<f32x4*>(a.out32 + o) = v;
+      if (a.outH) store_split4(a.outH, a.outL, o, v);
+    }
+  } else {
+    f32x4 ps;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ps[e] = (float)(a.beta * (double)v[e] + (double)al[e] * (double)pd[e]);
+      pacc += (double)pd[e] * (double)ps[e];
+    }
+    if (qv) *reinterpret_cast<f32x4*>(a.out32 + o) = ps;
+  }
+}
+
+__device__ __forceinline__ void conv_pi_store(const ConvArgs& a, int64_t q, bool qv, int g, int bx, double pacc) {
+  pacc += __shfl_xor(pacc, 16, 64);
+  pacc += __shfl_xor(pacc, 32, 64);
+  if (g == 0 && qv) a.pipart[q * a.nbx + bx] = pacc;
+}
+
+template <int NB, int DIR>
+__global__ __launch_bounds__(256) void k_conv_f32(ConvArgs a) {
+  if (a.done && *a.done) return;
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= a.nbx * a.nct) return;
+  const int bx = wid / a.nct, ct = wid - bx * a.nct;
+  const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
+  const int64_t q = ct * 16 + r16;
+  const bool qv = q < a.Q;
+  const int64_t qld = qv ? q : 0;  // idle columns read column 0 (no extra lines) and use zeros
+  const int64_t nblk = a.Dp >> 4;
+  const int64_t a0 = (int64_t)bx * (VCHUNK / 16);
+  const int cnt = (int)std::min<int64_t>(VCHUNK / 16, nblk - a0);
+
+  // Toeplitz blocks in the operand layout of MFMA e: lane (r16, g) holds T[r16][4 g + e].
+  f32x4 A[NB];
+#pragma unroll
+  for (int d = 0; d < NB; ++d)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int m = DIR == 0 ? 16 * d + r16 - 4 * g - e : 16 * d + 4 * g + e - r16;
+      A[d][e] = a.hp32[CONV_HOFF + m];
+    }
+
+  const float* src = a.in32 + qld * a.Dp + 4 * g;
+  const float* pdp = a.Pd ? a.Pd + qld * a.Dp : nullptr;
+  const int64_t base = DIR == 0 ? a0 - (NB - 1) : a0;  // input block of window position 0
+  auto load = [&](int64_t b) -> f32x4 {
+    const bool ok = qv && b >= 0 && b < nblk;
+    f32x4 v = *reinterpret_cast<const f32x4*>(src + 16 * (ok ? b : 0));
+    return ok ? v : f32x4{0.f, 0.f, 0.f, 0.f};
+  };
+
+  f32x4 win[NB];
+#pragma unroll
+  for (int p = 0; p < NB - 1; ++p) win[p] = load(base + p);
+  f32x4 nxt = load(base + NB - 1);
+  double pacc = 0.0;
+  for (int i0 = 0; i0 < cnt; i0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int i = i0 + u;
+      if (i < cnt) {
+        const int64_t row = (a0 + i) * 16 + 4 * g;
+        f32x4 al{0.f, 0.f, 0.f, 0.f}, pd{0.f, 0.f, 0.f, 0.f};
+        if (DIR == 1) {
+          al = *reinterpret_cast<const f32x4*>(a.alpha + row);
+          pd = *reinterpret_cast<const f32x4*>(pdp + row);
+        }
+        win[(u + NB - 1) % NB] = nxt;
+        nxt = load(base + i + NB);  // the next block, in flight during this block's MFMAs
+        __builtin_amdgcn_sched_barrier(0);
+        f32x4 acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+          const f32x4 bv = win[DIR == 0 ? (u + NB - 1 - d) % NB : (u + d) % NB];
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            acc[d & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[d][e], bv[e], acc[d & 3], 0, 0, 0);
+        }
+        const f32x4 v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        conv_epilogue(a, DIR, q, qv, row, v, al, pd, pacc);
+      }
+    }
+  }
+  if (DIR == 1) conv_pi_store(a, q, qv, g, bx, pacc);
+}
+
+template <int NB, int DIR>
+__global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
+  if (a.done && *a.done) return;
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= a.nbx * a.nct) return;
+  const int bx = wid / a.nct, ct = wid - bx * a.nct;
+  const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
+  const int64_t q = ct * 16 + r16;
+  const bool qv = q < a.Q;
+  const int64_t qld = qv ? q : 0;
+  const int64_t nb32 = a.Dp >> 5;
+  const int64_t m0 = (int64_t)bx * (VCHUNK / 32);
+  const int cnt = (int)std::min<int64_t>(VCHUNK / 32, nb32 - m0);
+
+  // Toeplitz blocks: lane (r16, g) holds T^(par)_d[r16][8 g .. 8 g + 8).
+  bf16x8_t A[2][NB];
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int d = 0; d < NB; ++d) {
+      u16x8 t;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int m = DIR == 0 ? 32 * d + 16 * par + r16 - 8 * g - j : 32 * d + 8 * g + j - 16 * par - r16;
+        t[j] = a.hp16[CONV_HOFF + m];
+      }
+      A[par][d] = __builtin_bit_cast(bf16x8_t, t);
+    }
+
+  const uint16_t* sh = a.inH + qld * a.Dp + 8 * g;
+  const uint16_t* sl = a.inL + qld * a.Dp + 8 * g;
+  const float* pdp = a.Pd ? a.Pd + qld * a.Dp : nullptr;
+  const int64_t base = DIR == 0 ? m0 - (NB - 1) : m0;
+  const bf16x8_t zero = __builtin_bit_cast(bf16x8_t, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+  auto load = [&](const uint16_t* s, int64_t b) -> bf16x8_t {
+    const bool ok = qv && b >= 0 && b < nb32;
+    const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(s + 32 * (ok ? b : 0));
+    return ok ? v : zero;
+  };
+
+  bf16x8_t wh[NB], wl[NB];
+#pragma unroll
+  for (int p = 0; p < NB - 1; ++p) {
+    wh[p] = load(sh, base + p);
+    wl[p] = load(sl, base + p);
+  }
+  bf16x8_t nh = load(sh, base + NB - 1), nl = load(sl, base + NB - 1);
+  double pacc = 0.0;
+  for (int i0 = 0; i0 < cnt; i0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int i = i0 + u;
+      if (i < cnt) {
+        const int64_t rowp = (m0 + i) * 32 + 4 * g;  // row of par 0; par 1 is 16 further
+        f32x4 al[2], pd[2];
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+          al[par] = pd[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+          if (DIR == 1) {
+            al[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp + 16 * par);
+            pd[par] = *reinterpret_cast<const f32x4*>(pdp + rowp + 16 * par);
+          }
+        }
+        wh[(u + NB - 1) % NB] = nh;
+        wl[(u + NB - 1) % NB] = nl;
+        nh = load(sh, base + i + NB);
+        nl = load(sl, base + i + NB);
+        __builtin_amdgcn_sched_barrier(0);
+        f32x4 ah[2], aL[2];
+#pragma unroll
+        for (int par = 0; par < 2; ++par) ah[par] = aL[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+          const int w = DIR == 0 ? (u + NB - 1 - d) % NB : (u + d) % NB;
+#pragma unroll
+          for (int par = 0; par < 2; ++par) {
+            ah[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wh[w], ah[par], 0, 0, 0);
+            aL[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wl[w], aL[par], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int par = 0; par < 2; ++par)
+          conv_epilogue(a, DIR, q, qv, rowp + 16 * par, ah[par] + aL[par], al[par], pd[par], pacc);
+      }
+    }
+  }
+  if (DIR == 1) conv_pi_store(a, q, qv, g, bx, pacc);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned cdiv_(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+int conv_blocks_f32(int L) { return (L + 14) / 16 + 1; }
+int conv_blocks_bf16(int L) { return (L + 30) / 32 + 1; }
+
+void launch_conv_setup(const float* h, int L, int64_t D, int64_t Dp, int jacobi, float* hp32, uint16_t* hp16,
+                       float* theta, hipStream_t s) {
+  hipLaunchKernelGGL(k_conv_taps, dim3(1), dim3(256), 0, s, h, L, hp32, hp16);
+  hipLaunchKernelGGL(k_conv_theta, dim3(cdiv_(Dp, 256)), dim3(256), 0, s, (const float*)hp32, L, D, Dp, jacobi,
+                     theta);
+}
+
+void launch_conv_rhs(const float* hp32, const uint16_t* hp16, int L, int64_t D, int64_t Dp, const float* y,
+                     double beta, float* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_conv_rhs, dim3(cdiv_(Dp, 256)), dim3(256), 0, s, hp32, hp16, L, D, Dp, y, beta, b);
+}
+
+template <int DIR>
+static void conv_f32_dir(const ConvArgs& a, int nb, dim3 grid, hipStream_t s) {
+  if (nb <= 5) hipLaunchKernelGGL((k_conv_f32<5, DIR>), grid, dim3(256), 0, s, a);
+  else if (nb <= 9) hipLaunchKernelGGL((k_conv_f32<9, DIR>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_conv_f32<17, DIR>), grid, dim3(256), 0, s, a);
+}
+
+template <int DIR>
+static void conv_bf16_dir(const ConvArgs& a, int nb, dim3 grid, hipStream_t s) {
+  if (nb <= 3) hipLaunchKernelGGL((k_conv_bf16<3, DIR>), grid, dim3(256), 0, s, a);
+  else if (nb <= 5) hipLaunchKernelGGL((k_conv_bf16<5, DIR>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_conv_bf16<9, DIR>), grid, dim3(256), 0, s, a);
+}
+
+void launch_conv_pass(const ConvArgs& a, int dir, int bf16, hipStream_t s) {
+  const dim3 grid(cdiv_((int64_t)a.nbx * a.nct, 4));
+  if (bf16) {
+    const int nb = conv_blocks_bf16(a.L);
+    if (dir == 0) conv_bf16_dir<0>(a, nb, grid, s);
+    else conv_bf16_dir<1>(a, nb, grid, s);
+  } else {
+    const int nb = conv_blocks_f32(a.L);
+    if (dir == 0) conv_f32_dir<0>(a, nb, grid, s);
+    else conv_f32_dir<1>(a, nb, grid, s);
+  }
+}
+
+}  // namespace cofem

@@ -120,4 +120,40 @@ void launch_unpack_block(const float* src, int ncols, int64_t D, int64_t Dp, flo
 void launch_copy_pad(const float* src, int64_t n, int64_t np, float pad, float* dst, hipStream_t s);
 void launch_state_reset(CGState* st, int Q, hipStream_t s);
 
+// ---- convolutional dictionary (conv.hip) ----------------------------------------
+// Phi_ij = h[i - j] for 0 <= i - j < L (N = D).  The taps live padded with zeros in
+// hp32 / hp16 (CONV_HPAD entries, FP32 and bfloat16).
+constexpr int CONV_MAX_TAPS = 256;
+constexpr int CONV_HPAD = 384;
+
+// One filter pass over the Qp x Dp blocks (columns q < Q are computed; runs of 1024
+// samples per wave and 16-column tile).  dir 0: out = Phi in.  dir 1: out = beta Phi^T in
+// + alpha Pd and the pi partials into pipart[q * nbx + run].  FP32 reads in32; bf16
+// reads the hi/lo pair inH/inL.  Pass 1 writes out32 and/or outH/outL.
+struct ConvArgs {
+  const float* hp32;
+  const uint16_t* hp16;
+  int L;
+  int64_t D, Dp;
+  int Q, nct, nbx;
+  const float* in32;
+  const uint16_t *inH, *inL;
+  float* out32;
+  uint16_t *outH, *outL;
+  double beta;
+  const float* alpha;
+  const float* Pd;
+  double* pipart;
+  const int* done;
+};
+int conv_blocks_f32(int L);
+int conv_blocks_bf16(int L);
+// Pad the device taps h[0..L) into hp32/hp16 and fill theta (Jacobi: column norms).
+void launch_conv_setup(const float* h, int L, int64_t D, int64_t Dp, int jacobi, float* hp32, uint16_t* hp16,
+                       float* theta, hipStream_t s);
+// b = beta Phi^T y with the FP32 taps (hp16 null) or the bfloat16 taps.
+void launch_conv_rhs(const float* hp32, const uint16_t* hp16, int L, int64_t D, int64_t Dp, const float* y,
+                     double beta, float* b, hipStream_t s);
+void launch_conv_pass(const ConvArgs& a, int dir, int bf16, hipStream_t s);
+
 }  // namespace cofem

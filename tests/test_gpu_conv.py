@@ -1,0 +1,179 @@
+"""GPU parity of the convolutional dictionary (Sec. V-A.2): Phi_ij = h[i - j] for
+0 <= i - j < L, N = D, applied by the MFMA Toeplitz-block filters.
+
+* The operator beta Phi^T Phi P + alpha P against the oracle's direct FIR sums,
+  on random (sign-changing) taps so that a causal/anti-causal mix-up or an
+  off-by-one in the band fails, at sizes with ragged tails, L > D, L = 1.
+  Tolerances as for the dense operator: FP32 sums of 2 L products (2e-5 per
+  column), and for bf16 the rounded taps applied to signals carried as hi + lo
+  bfloat16 pairs (1e-4 against the oracle with the same rounded taps).
+* Fits against the oracle at the same probes, stop rule and tolerance.  On this
+  dictionary A is ill-conditioned (beta (sum h)^2 ~ 1e6 against alpha ~ 1), so
+  mu moves visibly with the CG tolerance itself; the bar is 1e-4 or twice the
+  oracle's own change of mu between tol and tol / 100, whichever is larger.
+* The full-size workload (D = 2^20, L = 256, K = 20): sampled operator rows, and
+  the benchmark's fit by properties (true FP64 residual of mu, recovery).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_rne(x):
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF
+    return (r << 16).astype(np.uint32).view(np.float32)
+
+
+def _t(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("D,L,ncols", [(1000, 256, 21), (3000, 256, 9), (777, 37, 5), (2048, 100, 33),
+                                       (513, 1, 3), (200, 256, 17), (4096, 256, 64)])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_conv_apply_A_matches_oracle(gpu, D, L, ncols, dtype):
+    rng = np.random.default_rng(D * 3 + L)
+    h = rng.standard_normal(L).astype(np.float32)
+    beta = 400.0
+    alpha = np.exp(rng.uniform(-3, 8, D)).astype(np.float32)
+    P = rng.standard_normal((ncols, D)).astype(np.float32)
+    m = gpu.CoFEM(D, D, beta, K=max(ncols - 1, 1), T=1, U=1, tol=0.0, op="conv", conv_taps=L, phi_dtype=dtype)
+    m.set_dictionary(_t(h))
+    Psi, pi = m.apply_A(_t(alpha), _t(P), use_bf16=(dtype == "bf16"), want_pi=True)
+    Psi = _np(Psi)
+    m.close()
+    op = oracle.ConvOperator(_bf16_rne(h) if dtype == "bf16" else h, D)
+    Pt = P.T.astype(np.float64)
+    ref = (beta * op.rmatvec(op.matvec(Pt)) + alpha.astype(np.float64)[:, None] * Pt).T
+    tol = 2e-5 if dtype == "fp32" else 1e-4
+    errs = [_rel(Psi[q], ref[q]) for q in range(ncols)]
+    print(f"conv D={D} L={L} {dtype}: max column error {max(errs):.2e}")
+    assert max(errs) < tol
+    pi_ref = np.sum(P.astype(np.float64) * Psi, axis=1)
+    assert np.allclose(_np(pi), pi_ref, rtol=1e-10)
+    if dtype == "bf16" and L > 1:
+        op32 = oracle.ConvOperator(h, D)
+        ref32 = beta * op32.rmatvec(op32.matvec(Pt[:, :1]))[:, 0] + alpha * Pt[:, 0]
+        assert _rel(Psi[0], ref32) > 5 * _rel(Psi[0], ref[0])
+
+
+def _conv_fit(gpu, prob, K, T, U, tol, seed, **kw):
+    m = gpu.CoFEM(prob.D, prob.D, prob.beta, K=K, T=T, U=U, tol=tol, seed=seed, op="conv",
+                  conv_taps=prob.h.shape[0], **kw)
+    m.set_dictionary(_t(prob.h))
+    m.fit(_t(prob.y))
+    mu, s, alpha, st = m.posterior()
+    m.close()
+    return _np(mu), _np(s), _np(alpha), st
+
+
+def _oracle_pair(prob, h, K, T, U, tol, seed, **kw):
+    op = oracle.ConvOperator(h, prob.D)
+    ref = oracle.cofem(op, prob.y, prob.beta, T=T, K=K, U=U, tol=tol, seed=seed, **kw)
+    tight = oracle.cofem(op, prob.y, prob.beta, T=T, K=K, U=U, tol=tol / 100, seed=seed, **kw)
+    return ref, _rel(ref.mu, tight.mu), _rel(ref.s, tight.s)
+
+
+@pytest.mark.parametrize("theta", ["ones", "jacobi"])
+def test_conv_fit_fp32_matches_oracle(gpu, theta):
+    prob = workloads.conv_problem(1500, 256, 50.0, 0.01, 0.05, seed=31)
+    K, T, U, tol, seed = 20, 5, 400, 1e-6, 7
+    mu, s, alpha, st = _conv_fit(gpu, prob, K, T, U, tol, seed, theta=theta)
+    ref, sens_mu, sens_s = _oracle_pair(prob, prob.h, K, T, U, tol, seed, theta_mode=theta)
+    e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
+    print(f"conv fit {theta}: mu rel {e_mu:.2e} (oracle tol sensitivity {sens_mu:.2e}), s rel {e_s:.2e} "
+          f"({sens_s:.2e}); CG steps gpu {st['cg_steps'][:T]} oracle {ref.cg_steps}")
+    assert e_mu <= max(1e-4, 2 * sens_mu)
+    assert e_s <= max(1e-3, 2 * sens_s)
+    assert st["breakdown"] == 0 and all(np.isfinite(x).all() for x in (mu, s, alpha))
+
+
+def test_conv_fit_bf16_matches_rounded_oracle_and_refines(gpu):
+    prob = workloads.conv_problem(1200, 256, 50.0, 0.01, 0.05, seed=41)
+    K, T, U, tol, seed = 20, 5, 400, 1e-6, 9
+    # bf16 throughout: the oracle with the same rounded taps
+    mu, s, _, st = _conv_fit(gpu, prob, K, T, U, tol, seed, phi_dtype="bf16")
+    assert all(st["used_bf16"][:T])
+    ref, sens_mu, _ = _oracle_pair(prob, _bf16_rne(prob.h), K, T, U, tol, seed)
+    e_mu = _rel(mu, ref.mu)
+    print(f"conv bf16 vs rounded-taps oracle: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e})")
+    assert e_mu <= max(1e-3, 2 * sens_mu)
+    # bf16 with the last 2 E-steps on the FP32 taps: against the FP32 oracle
+    mu2, _, _, st2 = _conv_fit(gpu, prob, K, T, U, tol, seed, phi_dtype="bf16", refine_last=2)
+    assert list(st2["used_bf16"][:T]) == [1, 1, 1, 0, 0]
+    ref32, sens32, _ = _oracle_pair(prob, prob.h, K, T, U, tol, seed)
+    e2 = _rel(mu2, ref32.mu)
+    print(f"conv bf16 + 2 FP32 refinements vs FP32 oracle: mu rel {e2:.2e} (sensitivity {sens32:.2e})")
+    assert e2 <= max(2e-2, 2 * sens32)
+
+
+# ---------------------------------------------------------------------------
+# full size: D = 2^20, 256 taps of exp(-t/50), K = 20
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def conv_large():
+    prob = workloads.make_workload("conv")
+    print(f"conv workload D={prob.D} taps={prob.h.shape[0]} generated", flush=True)
+    return prob
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_conv_large_operator_sampled(gpu, conv_large, dtype):
+    prob = conv_large
+    w = workloads.WORKLOADS["conv"]
+    rng = np.random.default_rng(5)
+    Q = w["K"] + 1
+    P = rng.standard_normal((Q, prob.D)).astype(np.float32)
+    alpha = np.exp(rng.uniform(-3, 12, prob.D)).astype(np.float32)
+    m = gpu.CoFEM(prob.D, prob.D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], op="conv",
+                  conv_taps=prob.h.shape[0], phi_dtype=dtype)
+    m.set_dictionary(_t(prob.h))
+    Psi = _np(m.apply_A(_t(alpha), _t(P), use_bf16=(dtype == "bf16")))
+    m.close()
+    h = _bf16_rne(prob.h) if dtype == "bf16" else prob.h
+    op = oracle.ConvOperator(h, prob.D)
+    rows = np.concatenate([[0, 1, 255, 256, prob.D - 257, prob.D - 1],
+                           np.sort(rng.choice(prob.D, 42, replace=False))])
+    ref = op.normal_rows(P.T, alpha, prob.beta, rows)                 # rows x Q
+    absop = oracle.ConvOperator(np.abs(h), prob.D)
+    scale = absop.normal_rows(np.abs(P.T), alpha, prob.beta, rows)   # size of the summed terms
+    err = np.abs(Psi[:, rows].T - ref) / scale
+    tol = 1e-5 if dtype == "fp32" else 1e-4
+    print(f"conv large {dtype}: max scaled error {err.max():.2e}")
+    assert err.max() < tol
+
+
+def test_conv_large_bench_fit_properties(gpu, conv_large):
+    """The benchmark's conv fit (bf16 taps, last 3 EM iterations FP32): the true
+    FP64 residual of its mu system and the recovery of the spikes."""
+    prob = conv_large
+    w = workloads.WORKLOADS["conv"]
+    mu, s, alpha, st = _conv_fit(gpu, prob, w["K"], w["T"], w["U"], w["tol"], 2024, phi_dtype="bf16",
+                                 refine_last=3)
+    T = w["T"]
+    assert list(st["used_bf16"][:T]) == [1] * (T - 3) + [0] * 3
+    assert all(np.isfinite(x).all() for x in (mu, s, alpha)) and st["breakdown"] == 0
+    op = oracle.ConvOperator(prob.h, prob.D)
+    b = prob.beta * op.rmatvec(prob.y.astype(np.float64))
+    # alpha^(T) is the alpha of the last E-step (no M-step follows it)
+    Amu = prob.beta * op.rmatvec(op.matvec(mu)) + alpha * mu
+    res = np.linalg.norm(b - Amu) / np.linalg.norm(b)
+    nrmse = np.linalg.norm(mu - prob.z) / np.linalg.norm(prob.z)
+    print(f"conv bench fit: {st['total_cg_steps']} CG steps, true residual {res:.2e}, NRMSE {nrmse:.3f}")
+    assert res < 100 * w["tol"]
+    assert nrmse < 0.5

@@ -359,6 +359,25 @@ def test_conv_operator_is_lower_triangular_toeplitz(D, L):
     assert np.allclose(op.dense(), Phi)
 
 
+@pytest.mark.parametrize("D,L", [(40, 7), (30, 30), (9, 20)])
+def test_conv_normal_rows_match_explicit_matrix(D, L):
+    # sampled rows of beta Phi^T Phi P + alpha P against the explicit band matrix
+    rng = np.random.default_rng(23)
+    h = rng.standard_normal(L)
+    Phi = np.zeros((D, D))
+    for i in range(D):
+        for j in range(D):
+            if 0 <= i - j < L:
+                Phi[i, j] = h[i - j]
+    P = rng.standard_normal((D, 4))
+    alpha = rng.uniform(0.5, 2.0, D)
+    beta = 3.5
+    full = beta * Phi.T @ (Phi @ P) + alpha[:, None] * P
+    rows = [0, 1, D // 2, D - 2, D - 1]
+    got = ConvOperator(h, D).normal_rows(P, alpha, beta, rows)
+    assert np.allclose(got, full[rows], atol=1e-12)
+
+
 def test_nonneg_second_moment_matches_truncated_gaussian_integral():
     from scipy.integrate import quad
 
