@@ -14,6 +14,9 @@ Prints one JSON line.  `value` is EM iterations per second.  Beside it:
                 stream over the timed steps, against 8 TB/s;
   fp32          the same fit with the FP32 dictionary throughout;
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload;
+  conv          the convolutional dictionary (D = 2^20 causal FIR, 256 taps,
+                K = 20): EM iterations/s with bf16 taps (+ 3 FP32 iterations) and
+                FP32, and the filter passes against the MFMA and HBM peaks;
   serving       the continuous-batching server on a stream of independent
                 requests (D uniform in [512, 16384], N = D/4, 5 % spikes, sigma in
                 {0.01, 0.05}, K = 16, T = 30, FP32): saturated request rate from a
@@ -86,6 +89,7 @@ def parse():
     ap.add_argument("--serve-pilot", type=int, default=32, help="requests of the saturation pilot")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--no-conv", action="store_true", help="skip the convolutional-dictionary fits")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run a 1 GiB copy and three operator applications (for rocprofv3 --pmc)")
     return ap.parse_args()
@@ -210,11 +214,67 @@ def main():
         log(f"fp32 comparison fit: {out['fp32']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, w, st, args.cpu_steps)
+    del phi_d, y_d, prob
+    torch.cuda.empty_cache()
+    if not args.no_conv:
+        out["conv"] = conv_bench()
     if args.serve_requests > 0:
-        del phi_d, y_d, prob
-        torch.cuda.empty_cache()
         out["serving"] = serving(args)
     print(json.dumps(out), flush=True)
+
+
+def conv_bench():
+    """The convolutional dictionary (D = 2^20 causal FIR, 256 taps): one warm-up and
+    one timed fit with bf16 taps and the last 3 EM iterations on FP32 taps, and one
+    timed all-FP32 fit.  Per operator application (both filter passes): algorithmic
+    flops 4 L D Q (Q = K + 1 real columns) against the MFMA peak of the dtype, and
+    algorithmic bytes (pass 1 reads Pd and writes V, pass 2 reads V, Pd, alpha and
+    writes Psi: 20 D Q + 4 D bytes, signals as FP32 or as bf16 hi/lo pairs) against 8 TB/s."""
+    import torch
+
+    import paper_2105_10439_amd as lib
+    import workloads
+
+    w = dict(workloads.WORKLOADS["conv"])
+    prob = workloads.make_workload("conv")
+    L, D, Q = prob.h.shape[0], prob.D, w["K"] + 1
+    h_d = torch.from_numpy(prob.h).cuda()
+    y_d = torch.from_numpy(prob.y).cuda()
+    flops_app = 4.0 * L * D * Q
+    bytes_app = 20.0 * D * Q + 4.0 * D
+    peak = {"bf16": 2500.0, "fp32": 157.3}
+    res = dict(workload=f"causal FIR dictionary: D=N={D}, {L} taps of exp(-t/{w['tau']:g}), Bernoulli({w['p']})*Exp(1) "
+                        f"spikes, sigma={w['sigma']}, K={w['K']} T={w['T']} tol={w['tol']} U={w['U']}")
+    for name, dt, refine in (("bf16_refined", "bf16", 3), ("fp32", "fp32", 0)):
+        m = lib.CoFEM(D, D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024, op="conv",
+                      conv_taps=L, phi_dtype=dt, refine_last=refine)
+        if dt == "bf16":
+            m.set_dictionary(h_d)
+            m.fit(y_d)
+        m.set_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        m.set_dictionary(h_d)
+        m.fit(y_d)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        _, _, _, st = m.posterior()
+        passes = {}
+        for k in ("bf16", "fp32"):
+            ms, n = m.get_timing(k)
+            if n:
+                app_s = 2 * ms / n * 1e-3
+                passes[k] = dict(launches=n, avg_pass_us=round(1e3 * ms / n, 1),
+                                 tflops=round(flops_app / app_s / 1e12, 1),
+                                 mfma_frac=round(flops_app / app_s / 1e12 / peak[k], 4),
+                                 gbps=round(bytes_app / app_s / 1e9, 1),
+                                 hbm_frac=round(bytes_app / app_s / 1e9 / HBM_PEAK_GBPS, 4))
+        m.close()
+        res[name] = dict(em_iters_per_s=round(w["T"] / el, 3), ms_per_fit=round(1e3 * el, 1),
+                         cg_steps=st["total_cg_steps"], ms_per_cg_step=round(1e3 * el / st["total_cg_steps"], 4),
+                         passes=passes)
+        log(f"conv {name}: {res[name]}")
+    return res
 
 
 SERVE_KW = dict(K=16, T=30, U=400, tol=1e-5)

@@ -118,8 +118,14 @@ __device__ __forceinline__ void conv_pi_store(const ConvArgs& a, int64_t q, bool
   if (g == 0 && qv) a.pipart[q * a.nbx + bx] = pacc;
 }
 
+// The window is a ring of S = NB + PF slots: the block for window position p sits in
+// slot p % S and is loaded PF iterations before its first use, so PF loads per wave are
+// in flight behind the MFMAs.  The loop body is unrolled over S iterations, which
+// makes every slot index a constant; loads are unconditional (clamped address, zero
+// outside the signal) and only the MFMAs and the epilogue are skipped past the run.
 template <int NB, int DIR>
 __global__ __launch_bounds__(256) void k_conv_f32(ConvArgs a) {
+  constexpr int PF = 3, S = NB + PF;
   if (a.done && *a.done) return;
   const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wid >= a.nbx * a.nct) return;
@@ -150,38 +156,42 @@ __global__ __launch_bounds__(256) void k_conv_f32(ConvArgs a) {
     f32x4 v = *reinterpret_cast<const f32x4*>(src + 16 * (ok ? b : 0));
     return ok ? v : f32x4{0.f, 0.f, 0.f, 0.f};
   };
+  // epilogue operands of output block a0 + i (clamped row; only used while i < cnt)
+  auto row_of = [&](int i) -> int64_t { return (a0 + std::min(i, cnt - 1)) * 16 + 4 * g; };
 
-  f32x4 win[NB];
+  f32x4 win[S];
 #pragma unroll
-  for (int p = 0; p < NB - 1; ++p) win[p] = load(base + p);
-  f32x4 nxt = load(base + NB - 1);
+  for (int p = 0; p < S - 1; ++p) win[p] = load(base + p);
+  f32x4 aln{0.f, 0.f, 0.f, 0.f}, pdn{0.f, 0.f, 0.f, 0.f};
+  if (DIR == 1) {
+    aln = *reinterpret_cast<const f32x4*>(a.alpha + row_of(0));
+    pdn = *reinterpret_cast<const f32x4*>(pdp + row_of(0));
+  }
   double pacc = 0.0;
-  for (int i0 = 0; i0 < cnt; i0 += NB) {
+  for (int i0 = 0; i0 < cnt; i0 += S) {
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
+    for (int u = 0; u < S; ++u) {
       const int i = i0 + u;
+      win[(u + S - 1) % S] = load(base + i + S - 1);
+      const f32x4 al = aln, pd = pdn;
+      if (DIR == 1) {
+        aln = *reinterpret_cast<const f32x4*>(a.alpha + row_of(i + 1));
+        pdn = *reinterpret_cast<const f32x4*>(pdp + row_of(i + 1));
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
       if (i < cnt) {
-        const int64_t row = (a0 + i) * 16 + 4 * g;
-        f32x4 al{0.f, 0.f, 0.f, 0.f}, pd{0.f, 0.f, 0.f, 0.f};
-        if (DIR == 1) {
-          al = *reinterpret_cast<const f32x4*>(a.alpha + row);
-          pd = *reinterpret_cast<const f32x4*>(pdp + row);
-        }
-        win[(u + NB - 1) % NB] = nxt;
-        nxt = load(base + i + NB);  // the next block, in flight during this block's MFMAs
-        __builtin_amdgcn_sched_barrier(0);
         f32x4 acc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int d = 0; d < NB; ++d) {
-          const f32x4 bv = win[DIR == 0 ? (u + NB - 1 - d) % NB : (u + d) % NB];
+          const f32x4 bv = win[DIR == 0 ? (u + NB - 1 - d) % S : (u + d) % S];
 #pragma unroll
           for (int e = 0; e < 4; ++e)
             acc[d & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[d][e], bv[e], acc[d & 3], 0, 0, 0);
         }
         const f32x4 v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        conv_epilogue(a, DIR, q, qv, row, v, al, pd, pacc);
+        conv_epilogue(a, DIR, q, qv, (a0 + i) * 16 + 4 * g, v, al, pd, pacc);
       }
     }
   }
@@ -190,6 +200,7 @@ __global__ __launch_bounds__(256) void k_conv_f32(ConvArgs a) {
 
 template <int NB, int DIR>
 __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
+  constexpr int PF = 3, S = NB + PF;
   if (a.done && *a.done) return;
   const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wid >= a.nbx * a.nct) return;
@@ -227,47 +238,46 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
     const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(s + 32 * (ok ? b : 0));
     return ok ? v : zero;
   };
+  auto rowp_of = [&](int i) -> int64_t { return (m0 + std::min(i, cnt - 1)) * 32 + 4 * g; };
 
-  bf16x8_t wh[NB], wl[NB];
+  bf16x8_t wh[S], wl[S];
 #pragma unroll
-  for (int p = 0; p < NB - 1; ++p) {
+  for (int p = 0; p < S - 1; ++p) {
     wh[p] = load(sh, base + p);
     wl[p] = load(sl, base + p);
   }
-  bf16x8_t nh = load(sh, base + NB - 1), nl = load(sl, base + NB - 1);
   double pacc = 0.0;
-  for (int i0 = 0; i0 < cnt; i0 += NB) {
+  for (int i0 = 0; i0 < cnt; i0 += S) {
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
+    for (int u = 0; u < S; ++u) {
       const int i = i0 + u;
-      if (i < cnt) {
-        const int64_t rowp = (m0 + i) * 32 + 4 * g;  // row of par 0; par 1 is 16 further
-        f32x4 al[2], pd[2];
+      wh[(u + S - 1) % S] = load(sh, base + i + S - 1);
+      wl[(u + S - 1) % S] = load(sl, base + i + S - 1);
+      // epilogue operands of this iteration (registers are too tight to fetch them earlier)
+      f32x4 al[2], pd[2];
 #pragma unroll
-        for (int par = 0; par < 2; ++par) {
-          al[par] = pd[par] = f32x4{0.f, 0.f, 0.f, 0.f};
-          if (DIR == 1) {
-            al[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp + 16 * par);
-            pd[par] = *reinterpret_cast<const f32x4*>(pdp + rowp + 16 * par);
-          }
+      for (int par = 0; par < 2; ++par) {
+        al[par] = pd[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (DIR == 1) {
+          al[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(i) + 16 * par);
+          pd[par] = *reinterpret_cast<const f32x4*>(pdp + rowp_of(i) + 16 * par);
         }
-        wh[(u + NB - 1) % NB] = nh;
-        wl[(u + NB - 1) % NB] = nl;
-        nh = load(sh, base + i + NB);
-        nl = load(sl, base + i + NB);
-        __builtin_amdgcn_sched_barrier(0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (i < cnt) {
         f32x4 ah[2], aL[2];
 #pragma unroll
         for (int par = 0; par < 2; ++par) ah[par] = aL[par] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int d = 0; d < NB; ++d) {
-          const int w = DIR == 0 ? (u + NB - 1 - d) % NB : (u + d) % NB;
+          const int w = DIR == 0 ? (u + NB - 1 - d) % S : (u + d) % S;
 #pragma unroll
           for (int par = 0; par < 2; ++par) {
             ah[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wh[w], ah[par], 0, 0, 0);
             aL[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wl[w], aL[par], 0, 0, 0);
           }
         }
+        const int64_t rowp = (m0 + i) * 32 + 4 * g;  // row of par 0; par 1 is 16 further
 #pragma unroll
         for (int par = 0; par < 2; ++par)
           conv_epilogue(a, DIR, q, qv, rowp + 16 * par, ah[par] + aL[par], al[par], pd[par], pacc);

@@ -122,15 +122,24 @@ __device__ __forceinline__ void mstep_block(const SolveCfg& c, uint64_t key, int
 // ---------------------------------------------------------------------------
 // The operator's contractions: Ypart[split][q][row] = sum_{k in split} M[row, k] Z[q, k].
 //
-// Block = 5 waves.  Waves 0-3 compute: wave w owns rows row0 .. row0 + 16 RT - 1
-// and all CT*16 columns, and streams its rows of M from HBM straight into VGPRs
-// in the MFMA operand layout, one stage ahead.  Wave 4 is a producer: it copies
-// the right-hand-side fragments of the next stage (already in MFMA lane order)
-// from L2 into a double-buffered LDS tile, so the compute waves never wait on
-// those loads (vmcnt counts in issue order per wave).  The prefetch is issued
-// without a branch and pinned ahead of the MFMAs with sched_barrier, so it stays
-// in flight across the stage.  L is the tile index (split and row block via tile_of).
+// Block = 4 waves.  Wave w owns rows row0 .. row0 + 16 RT - 1 and all CT*16
+// columns, and streams its rows of M from HBM straight into VGPRs in the MFMA
+// operand layout, one stage (KS MFMA k-steps) ahead.  The right-hand-side
+// fragments of a stage (already in MFMA lane order: lane l's 16 bytes) are copied
+// from L2 into LDS by the compute waves themselves with 16-byte LDS DMA loads
+// (global_load_lds_dwordx4: lane l's bytes land at base + 16 l), a quarter of the
+// fragments per wave, into a double buffer; they take no VGPRs while in flight.
+// Per stage: wait for this wave's loads of the stage, one barrier (every wave's
+// fragments have landed, and the other buffer is free), issue the next stage's
+// loads (branch-free: the last stage reloads itself), then the MFMAs.  The
+// sched_barrier keeps the prefetch ahead of the MFMAs.  L is the tile index
+// (split and row block via tile_of).  Every call ends with no DMA in flight.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_dma16(const void* src, void* lds_base) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
+}
+__device__ __forceinline__ void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // bf16: v_mfma_f32_16x16x32_bf16, lane l holds A[l%16][8(l/16) .. +8), B[8(l/16) .. +8)[l%16]
 // and returns D[4(l/16) .. +4)[l%16].  ZH + ZL carries each right-hand side to ~2^-17.
 template <int RT, int CT, int KS>
@@ -148,30 +157,18 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
   const int64_t kb = (int64_t)sp * kchunk;
   const int64_t ke = (kb + kchunk < kdim) ? kb + kchunk : kdim;
   const int nst = (ke > kb) ? (int)((ke - kb) / SK) : 0;
-  if (wave == 4) {
-    const uint16_t* src[NF];
+  if (nst == 0) return;
+  auto issue_B = [&](int st, int buf) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int s = f / (CT * 2), rem = f % (CT * 2), ct = rem >> 1, hl = rem & 1;
-      src[f] = (hl ? ZL : ZH) + (int64_t)(ct * 16 + r16) * ldz + kb + s * 32 + 8 * g;
+    for (int i = 0; i < (NF + 3) / 4; ++i) {
+      const int f = wave + 4 * i;
+      if (f < NF) {
+        const int s = f / (CT * 2), rem = f % (CT * 2), ct = rem >> 1, hl = rem & 1;
+        lds_dma16((hl ? ZL : ZH) + (int64_t)(ct * 16 + r16) * ldz + kb + (int64_t)st * SK + s * 32 + 8 * g,
+                  &sB[buf][f][0]);
+      }
     }
-    if (nst > 0) {
-#pragma unroll
-      for (int f = 0; f < NF; ++f) sB[0][f][lane] = *reinterpret_cast<const bf16x8_t*>(src[f]);
-    }
-    __syncthreads();
-    for (int st = 0; st < nst; ++st) {
-      // the next stage's fragments (the last stage reloads its own into the idle buffer)
-      const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
-      bf16x8_t t[NF];
-#pragma unroll
-      for (int f = 0; f < NF; ++f) t[f] = *reinterpret_cast<const bf16x8_t*>(src[f] + off);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) sB[(st + 1) & 1][f][lane] = t[f];
-      __syncthreads();
-    }
-    return;
-  }
+  };
   const int64_t row0 = (int64_t)rb * (64 * RT) + (int64_t)wave * (16 * RT);
   f32x4 acc[RT][CT];
 #pragma unroll
@@ -182,21 +179,22 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
 #pragma unroll
   for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 8 * g;
   bf16x8_t acur[RT][KS];
-  if (nst > 0) {
 #pragma unroll
-    for (int a = 0; a < RT; ++a)
+  for (int a = 0; a < RT; ++a)
 #pragma unroll
-      for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + s * 32);
-  }
-  __syncthreads();
+    for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + s * 32);
+  issue_B(0, 0);
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
-    const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;  // always in bounds
+    wait_vm_all();    // this wave's A and B pieces of stage st
+    __syncthreads();  // every wave's B pieces; buf ^ 1 is no longer read
+    const int nx = (st + 1 < nst) ? st + 1 : st;
     bf16x8_t anxt[RT][KS];
 #pragma unroll
     for (int a = 0; a < RT; ++a)
 #pragma unroll
-      for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + off + s * 32);
+      for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + (int64_t)nx * SK + s * 32);
+    issue_B(nx, buf ^ 1);
     __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this stage's MFMAs
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -214,12 +212,12 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[a][s], bl[b], acc[a][b], 0, 0, 0);
         }
     }
-    __syncthreads();
 #pragma unroll
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int s = 0; s < KS; ++s) acur[a][s] = anxt[a][s];
   }
+  wait_vm_all();  // the last (self-reloading) DMA has landed before the LDS is released
   float* yb = Yp + (int64_t)sp * Qp * ldy;
 #pragma unroll
   for (int a = 0; a < RT; ++a)
@@ -249,29 +247,17 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
   const int64_t kb = (int64_t)sp * kchunk;
   const int64_t ke = (kb + kchunk < kdim) ? kb + kchunk : kdim;
   const int nst = (ke > kb) ? (int)((ke - kb) / SK) : 0;
-  if (wave == 4) {
-    const float* src[NF];
+  if (nst == 0) return;
+  auto issue_B = [&](int st, int buf) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int s = f / CT, ct = f % CT;
-      src[f] = Z + (int64_t)(ct * 16 + r16) * ldz + kb + s * 16 + 4 * g;
+    for (int i = 0; i < (NF + 3) / 4; ++i) {
+      const int f = wave + 4 * i;
+      if (f < NF) {
+        const int s = f / CT, ct = f % CT;
+        lds_dma16(Z + (int64_t)(ct * 16 + r16) * ldz + kb + (int64_t)st * SK + s * 16 + 4 * g, &sB[buf][f][0]);
+      }
     }
-    if (nst > 0) {
-#pragma unroll
-      for (int f = 0; f < NF; ++f) sB[0][f][lane] = *reinterpret_cast<const f32x4*>(src[f]);
-    }
-    __syncthreads();
-    for (int st = 0; st < nst; ++st) {
-      const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
-      f32x4 t[NF];
-#pragma unroll
-      for (int f = 0; f < NF; ++f) t[f] = *reinterpret_cast<const f32x4*>(src[f] + off);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) sB[(st + 1) & 1][f][lane] = t[f];
-      __syncthreads();
-    }
-    return;
-  }
+  };
   const int64_t row0 = (int64_t)rb * (64 * RT) + (int64_t)wave * (16 * RT);
   f32x4 acc[RT][CT];
 #pragma unroll
@@ -282,21 +268,22 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
 #pragma unroll
   for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 4 * g;
   f32x4 acur[RT][KS];
-  if (nst > 0) {
 #pragma unroll
-    for (int a = 0; a < RT; ++a)
+  for (int a = 0; a < RT; ++a)
 #pragma unroll
-      for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + s * 16);
-  }
-  __syncthreads();
+    for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + s * 16);
+  issue_B(0, 0);
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
-    const int64_t off = (int64_t)((st + 1 < nst) ? st + 1 : st) * SK;
+    wait_vm_all();
+    __syncthreads();
+    const int nx = (st + 1 < nst) ? st + 1 : st;
     f32x4 anxt[RT][KS];
 #pragma unroll
     for (int a = 0; a < RT; ++a)
 #pragma unroll
-      for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + off + s * 16);
+      for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + (int64_t)nx * SK + s * 16);
+    issue_B(nx, buf ^ 1);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -311,12 +298,12 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
           for (int b = 0; b < CT; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[a][s][e], bz[b][e], acc[a][b], 0, 0, 0);
     }
-    __syncthreads();
 #pragma unroll
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int s = 0; s < KS; ++s) acur[a][s] = anxt[a][s];
   }
+  wait_vm_all();
   float* yb = Yp + (int64_t)sp * Qp * ldy;
 #pragma unroll
   for (int a = 0; a < RT; ++a)
@@ -327,6 +314,7 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
       *reinterpret_cast<f32x4*>(yb + q * ldy + row) = acc[a][b];
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // Split-K finishes and the CG vector updates.  Vector tiles: (chunk bx of VCHUNK
