@@ -43,8 +43,8 @@ METRIC = "CoFEM EM-iters/s + HBM GB/s at D=65536 (BF16 vs FP32); serving p50/p99
 # WRITE_SIZE; KiB per dispatch, averaged over 6 dispatches), each scaled by what the
 # same counter reads for a plain 1 GiB device copy.  It holds only for the kernel
 # source it was taken on: the hash covers the tile function and the launch shape choice.
-GEMM_TRAFFIC = dict(src_sha="dc365a0a712c4093", fetch_kib=1084194.1, write_kib=24763.6,
-                    copy_kib=1048576.0, copy_fetch_kib=524302.4, copy_write_kib=1048576.0,
+GEMM_TRAFFIC = dict(src_sha="c034a455bbdb592c", fetch_kib=1069869.8, write_kib=24693.3,
+                    copy_kib=1048576.0, copy_fetch_kib=524302.3, copy_write_kib=1048576.0,
                     profile="profiles/hbm_traffic_k_gemm_bf16_dense_N16384_D65536.md")
 
 
@@ -54,7 +54,7 @@ def gemm_source_sha() -> str:
     csrc = os.path.join(ROOT, "paper_2105_10439_amd", "csrc")
     tiles = open(os.path.join(csrc, "tiles.h")).read()
     kern = open(os.path.join(csrc, "kernels.hip")).read()
-    a = tiles.index("template <int RT, int CT, int KS>\n__device__ __forceinline__ void gemm_bf16_tile")
+    a = tiles.index("constexpr int GEMM_WAVES")
     b = tiles.index("// FP32: v_mfma_f32_16x16x4_f32.")
     c = kern.index("GemmCfg choose_gemm(")
     d = kern.index("template <int RT>\nstatic void gemm_bf16_rt(")
@@ -90,6 +90,7 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of saturation")
     ap.add_argument("--no-conv", action="store_true", help="skip the convolutional-dictionary fits")
+    ap.add_argument("--conv-only", action="store_true", help="only the convolutional-dictionary fits (for profiling)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run a 1 GiB copy and three operator applications (for rocprofv3 --pmc)")
     return ap.parse_args()
@@ -132,6 +133,12 @@ def main():
         sys.exit(2)
     if args.pmc_probe:
         pmc_probe()
+        return
+    if args.conv_only:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"conv": conv_bench()}), flush=True)
         return
     import numpy as np
     import torch
