@@ -123,7 +123,7 @@ __global__ __launch_bounds__(VBLOCK) void k_mstep(SolveCfg c, uint64_t key, int6
 }
 
 template <int RT, int CT, int KS>
-__global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict__ M, int64_t ldm,
+__global__ __launch_bounds__(64 * GEMM_WAVES, 2) void k_gemm_bf16(const uint16_t* __restrict__ M, int64_t ldm,
                                                       const uint16_t* __restrict__ ZH,
                                                       const uint16_t* __restrict__ ZL, int64_t ldz,
                                                       float* __restrict__ Yp, int64_t ldy, int Qp, int64_t kchunk,
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict
 }
 
 template <int RT, int CT, int KS>
-__global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ M, int64_t ldm,
+__global__ __launch_bounds__(64 * GEMM_WAVES, 2) void k_gemm_f32(const float* __restrict__ M, int64_t ldm,
                                                      const float* __restrict__ Z, int64_t ldz,
                                                      float* __restrict__ Yp, int64_t ldy, int Qp, int64_t kchunk,
                                                      int64_t kdim, int nrb, int splits,
@@ -292,10 +292,10 @@ static void gemm_bf16_rt(const GemmCfg& g, const uint16_t* M, int64_t rows, int6
   const int nrb = (int)(rows / (64 * RT));
   dim3 grid((unsigned)(nrb * g.splits));
   switch (Qp / 16) {
-    case 1: hipLaunchKernelGGL((k_gemm_bf16<RT, 1, KS_BF16>), grid, dim3(256), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    case 2: hipLaunchKernelGGL((k_gemm_bf16<RT, 2, KS_BF16>), grid, dim3(256), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    case 3: hipLaunchKernelGGL((k_gemm_bf16<RT, 3, KS_BF16>), grid, dim3(256), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    default: hipLaunchKernelGGL((k_gemm_bf16<RT, 4, KS_BF16>), grid, dim3(256), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 1: hipLaunchKernelGGL((k_gemm_bf16<RT, 1, KS_BF16>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 2: hipLaunchKernelGGL((k_gemm_bf16<RT, 2, KS_BF16>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 3: hipLaunchKernelGGL((k_gemm_bf16<RT, 3, KS_BF16>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    default: hipLaunchKernelGGL((k_gemm_bf16<RT, 4, KS_BF16>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
   }
 }
 
@@ -313,10 +313,10 @@ static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t rows, int64_t 
   const int nrb = (int)(rows / (64 * RT));
   dim3 grid((unsigned)(nrb * g.splits));
   switch (Qp / 16) {
-    case 1: hipLaunchKernelGGL((k_gemm_f32<RT, 1, KS_F32>), grid, dim3(256), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    case 2: hipLaunchKernelGGL((k_gemm_f32<RT, 2, KS_F32>), grid, dim3(256), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    case 3: hipLaunchKernelGGL((k_gemm_f32<RT, 3, KS_F32>), grid, dim3(256), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    default: hipLaunchKernelGGL((k_gemm_f32<RT, 4, KS_F32>), grid, dim3(256), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 1: hipLaunchKernelGGL((k_gemm_f32<RT, 1, KS_F32>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 2: hipLaunchKernelGGL((k_gemm_f32<RT, 2, KS_F32>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    case 3: hipLaunchKernelGGL((k_gemm_f32<RT, 3, KS_F32>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+    default: hipLaunchKernelGGL((k_gemm_f32<RT, 4, KS_F32>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
   }
 }
 

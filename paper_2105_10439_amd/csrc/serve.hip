@@ -104,7 +104,7 @@ __global__ __launch_bounds__(VBLOCK) void ks_em_scalars(const SlotDev* __restric
 
 __device__ __forceinline__ bool in_cg(const SlotDev& sd) { return sd.st->phase == PH_CG && !sd.st->done; }
 
-__global__ __launch_bounds__(256, 2) void ks_gemm(const SlotDev* __restrict__ slots, const SrvTable* __restrict__ tab,
+__global__ __launch_bounds__(64 * GEMM_WAVES, 2) void ks_gemm(const SlotDev* __restrict__ slots, const SrvTable* __restrict__ tab,
                                                   int pass) {
   const int n = tab->n;
   const int* start = pass == 1 ? tab->g1 : tab->g2;
@@ -436,9 +436,9 @@ cofem_status capture_tick(cofem_server* s) {
   hipLaunchKernelGGL(ks_em_init, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
   hipLaunchKernelGGL(ks_em_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
   for (int k = 0; k < s->steps; ++k) {
-    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(256), 0, s->stream, s->d_slots, s->d_table, 1);
+    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, s->stream, s->d_slots, s->d_table, 1);
     hipLaunchKernelGGL(ks_finish1, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
-    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(256), 0, s->stream, s->d_slots, s->d_table, 2);
+    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, s->stream, s->d_slots, s->d_table, 2);
     hipLaunchKernelGGL(ks_finish2, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
     hipLaunchKernelGGL(ks_update, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
     hipLaunchKernelGGL(ks_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);

@@ -135,6 +135,8 @@ __device__ __forceinline__ void mstep_block(const SolveCfg& c, uint64_t key, int
 // sched_barrier keeps the prefetch ahead of the MFMAs.  L is the tile index
 // (split and row block via tile_of).  Every call ends with no DMA in flight.
 // ---------------------------------------------------------------------------
+constexpr int GEMM_WAVES = 4;  // waves per contraction tile (launch with 64 * GEMM_WAVES threads)
+
 __device__ __forceinline__ void lds_dma16(const void* src, void* lds_base) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
 }
@@ -157,7 +159,7 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
   const int64_t kb = (int64_t)sp * kchunk;
   const int64_t ke = (kb + kchunk < kdim) ? kb + kchunk : kdim;
   const int nst = (ke > kb) ? (int)((ke - kb) / SK) : 0;
-  if (nst == 0) return;
+  if (nst == 0 || wave >= GEMM_WAVES) return;  // the tile is 64 RT rows: waves past the fourth have none
   auto issue_B = [&](int st, int buf) {
 #pragma unroll
     for (int i = 0; i < (NF + 3) / 4; ++i) {
@@ -247,7 +249,7 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
   const int64_t kb = (int64_t)sp * kchunk;
   const int64_t ke = (kb + kchunk < kdim) ? kb + kchunk : kdim;
   const int nst = (ke > kb) ? (int)((ke - kb) / SK) : 0;
-  if (nst == 0) return;
+  if (nst == 0 || wave >= GEMM_WAVES) return;  // the tile is 64 RT rows: waves past the fourth have none
   auto issue_B = [&](int st, int buf) {
 #pragma unroll
     for (int i = 0; i < (NF + 3) / 4; ++i) {
