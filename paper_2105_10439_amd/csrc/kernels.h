@@ -104,7 +104,7 @@ void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipS
 // ---- CG vector updates (Algorithm 2 after the operator) -----------------------
 // gamma_q = rho_q / pi_q (pi reduced from pipart), X += Pd gamma, R -= Psi gamma, partials
 // of ||R_q||^2 and rho'_q = sum R minv R into part; then one block applies the stop rule
-// and computes eta (two launches).
+// and computes eta (two launches; three when a first block reduces the pi partials).
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
                       const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s);
 // Pd = minv R + eta Pd (FP32, and bf16 hi/lo if PdH != null).

@@ -159,17 +159,24 @@ __global__ __launch_bounds__(VBLOCK) void k_finish_pass2(SolveCfg c, const float
   finish2_tile(c, blockIdx.x, blockIdx.y, gridDim.x, Yp, splits, Dp, alpha, Pd, Psi, pipart);
 }
 
+template <bool PRE>
 __global__ __launch_bounds__(VBLOCK) void k_cg_update(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                       float* __restrict__ X, float* __restrict__ R,
                                                       const float* __restrict__ Pd, const float* __restrict__ Psi,
                                                       const double* __restrict__ pipart, double* __restrict__ part,
                                                       CGState* __restrict__ st) {
   if (st->done) return;
-  cg_update_tile(c, blockIdx.x, blockIdx.y, gridDim.x, Dp, minv, X, R, Pd, Psi, pipart, part, st);
+  cg_update_tile<PRE>(c, blockIdx.x, blockIdx.y, gridDim.x, Dp, minv, X, R, Pd, Psi, pipart, part, st);
 }
 
-__global__ __launch_bounds__(VBLOCK) void k_cg_scalars(SolveCfg c, int nbx, const double* __restrict__ part,
-                                                       CGState* __restrict__ st) {
+__global__ __launch_bounds__(1024) void k_cg_gamma(SolveCfg c, int nbx, const double* __restrict__ pipart,
+                                                   CGState* __restrict__ st) {
+  if (st->done) return;
+  cg_gamma_block(c, nbx, pipart, st);
+}
+
+__global__ __launch_bounds__(1024) void k_cg_scalars(SolveCfg c, int nbx, const double* __restrict__ part,
+                                                     CGState* __restrict__ st) {
   if (st->done) return;
   cg_scalars_block(c, nbx, part, st);
 }
@@ -340,12 +347,22 @@ void launch_finish_pass2(const SolveCfg& c, const float* Ypart, int splits, int6
                      Dp, alpha, Pd, Psi, pipart, st);
 }
 
+// Above this many pi partials per column, one block reduces them once (k_cg_gamma)
+// instead of every update tile re-reducing them.
+constexpr int GAMMA_PRE_MIN_CHUNKS = 128;
+
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
                       const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s) {
   const unsigned nbx = cdiv(Dp, VCHUNK);
-  hipLaunchKernelGGL(k_cg_update, dim3(nbx, (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi, pipart,
-                     part, st);
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(VBLOCK), 0, s, c, (int)nbx, (const double*)part, st);
+  if (nbx > (unsigned)GAMMA_PRE_MIN_CHUNKS) {
+    hipLaunchKernelGGL(k_cg_gamma, dim3(1), dim3(1024), 0, s, c, (int)nbx, pipart, st);
+    hipLaunchKernelGGL(k_cg_update<true>, dim3(nbx, (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi,
+                       pipart, part, st);
+  } else {
+    hipLaunchKernelGGL(k_cg_update<false>, dim3(nbx, (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi,
+                       pipart, part, st);
+  }
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(1024), 0, s, c, (int)nbx, (const double*)part, st);
 }
 
 void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipStream_t s) {

@@ -158,7 +158,7 @@ __global__ __launch_bounds__(VBLOCK) void ks_update(const SlotDev* __restrict__ 
     const SlotDev& sd = slots[tab->slot[i]];
     const int local = t - tab->vq[i];
     if (!in_cg(sd) || local >= sd.nbx * sd.c.Q) continue;
-    cg_update_tile(sd.c, local % sd.nbx, local / sd.nbx, sd.nbx, sd.Dp, sd.minv, sd.X, sd.R, sd.Pd, sd.Psi,
+    cg_update_tile<false>(sd.c, local % sd.nbx, local / sd.nbx, sd.nbx, sd.Dp, sd.minv, sd.X, sd.R, sd.Pd, sd.Psi,
                    sd.pipart, sd.part, sd.st);
   }
 }

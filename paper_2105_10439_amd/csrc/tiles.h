@@ -361,31 +361,56 @@ __device__ __forceinline__ void finish2_tile(const SolveCfg& c, int bx, int q, i
   if (threadIdx.x == 0) pipart[(int64_t)q * nbx + bx] = acc;
 }
 
-// gamma_q = rho_q / pi_q (pi_q reduced here from its nbx partials in a fixed order, so
-// every tile of the column gets the same value); X += gamma Pd, R -= gamma Psi; partials
-// of ||R_q||^2 and rho'_q = sum R (M^-1 R) at part[(q * nbx + bx) * 2 + {0, 1}].
-__device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q, int nbx, int64_t Dp,
-                                               const float* __restrict__ minv, float* __restrict__ X,
-                                               float* __restrict__ R, const float* __restrict__ Pd,
-                                               const float* __restrict__ Psi, const double* __restrict__ pipart,
-                                               double* __restrict__ part, CGState* __restrict__ st) {
-  __shared__ double s_pi;
-  if (threadIdx.x < 64) {
-    const double a = wave_sum_strided(pipart + (int64_t)q * nbx, nbx, 1);
-    if (threadIdx.x == 0) s_pi = a;
-  }
-  __syncthreads();
-  const double pi = s_pi;
+// gamma_q = rho_q / pi_q from the column's nbx pi partials, summed in a fixed order; a
+// column with pi_q <= 0 and rho_q != 0 breaks down and is frozen.  Lane 0 of the calling
+// wave gets the result; with `record` it also writes pi, gamma and the breakdown flag.
+__device__ __forceinline__ double column_gamma(int q, int nbx, const double* __restrict__ pipart,
+                                               CGState* __restrict__ st, bool record) {
+  const double pi = wave_sum_strided(pipart + (int64_t)q * nbx, nbx, 1);
   const double rho = st->rho[q];
   const int act = st->active[q];
   const double gam = (act && pi > 0.0) ? rho / pi : 0.0;
-  if (bx == 0 && threadIdx.x == 0) {
+  if (record && (threadIdx.x & 63) == 0) {
     st->pi[q] = pi;
     st->gamma[q] = gam;
     if (act && !(pi > 0.0) && rho != 0.0) {  // breakdown: freeze the column
       st->active[q] = 0;
       atomicAdd(&st->breakdown, 1);
     }
+  }
+  return gam;
+}
+
+// One block, one wave per column: gamma_q for all columns into the state, for problems
+// with many pi partials per column (the update tiles then read gamma instead of each
+// re-reducing the partials).
+__device__ __forceinline__ void cg_gamma_block(const SolveCfg& c, int nbx, const double* __restrict__ pipart,
+                                               CGState* __restrict__ st) {
+  const int nw = blockDim.x >> 6;
+  for (int q = threadIdx.x >> 6; q < c.Q; q += nw) column_gamma(q, nbx, pipart, st, true);
+}
+
+// X += gamma Pd, R -= gamma Psi; partials of ||R_q||^2 and rho'_q = sum R (M^-1 R) at
+// part[(q * nbx + bx) * 2 + {0, 1}].  gamma_q comes from the state (PRE, after
+// cg_gamma_block) or is reduced here by every tile of the column, in the same order, so
+// all tiles get the same value (the tile of chunk 0 records it).
+template <bool PRE>
+__device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q, int nbx, int64_t Dp,
+                                               const float* __restrict__ minv, float* __restrict__ X,
+                                               float* __restrict__ R, const float* __restrict__ Pd,
+                                               const float* __restrict__ Psi, const double* __restrict__ pipart,
+                                               double* __restrict__ part, CGState* __restrict__ st) {
+  double gam;
+  if (PRE) {
+    gam = st->gamma[q];
+  } else {
+    __shared__ double s_gam;
+    if (threadIdx.x < 64) {
+      const double g = column_gamma(q, nbx, pipart, st, bx == 0);
+      if (threadIdx.x == 0) s_gam = g;
+    }
+    __syncthreads();
+    gam = s_gam;
   }
   const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
   double rr = 0.0, rw = 0.0;
@@ -415,15 +440,23 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
   }
 }
 
-// One block: ||R_q||^2 and rho'_q from the partials, the stop rule of Algorithm 2
-// (joint Frobenius ratio, or per-column freezing), steps, eta_q = rho'_q / rho_q.
+// One block: ||R_q||^2 and rho'_q from the partials (one wave per column, any block
+// size), the stop rule of Algorithm 2 (joint Frobenius ratio, or per-column freezing),
+// steps, eta_q = rho'_q / rho_q.
 __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, const double* __restrict__ part,
                                                  CGState* __restrict__ st) {
   __shared__ double s_rr[QMAX], s_rw[QMAX];
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  for (int q = wv; q < c.Q; q += 4) {
-    const double a = wave_sum_strided(part + (int64_t)q * nbx * 2 + 0, nbx, 2);
-    const double b = wave_sum_strided(part + (int64_t)q * nbx * 2 + 1, nbx, 2);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int q = wv; q < c.Q; q += nw) {
+    const double2* pq = reinterpret_cast<const double2*>(part + (int64_t)q * nbx * 2);
+    double a = 0.0, b = 0.0;
+    for (int i = ln; i < nbx; i += 64) {
+      const double2 v = pq[i];
+      a += v.x;
+      b += v.y;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
     if (ln == 0) {
       s_rr[q] = a;
       s_rw[q] = b;
