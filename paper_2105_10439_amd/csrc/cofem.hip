@@ -260,20 +260,20 @@ cofem_status apply_operator(cofem_ctx* c, bool use16, const float* alpha, const 
   cofem_status rc;
   if (use16) {
     if (c->timing && (rc = timed_begin(c, 1, step, &t)) != COFEM_OK) return rc;
-    launch_gemm_bf16(c->g1_16, c->phi16, c->Np, c->Dp, c->PdH, c->PdL, c->Qp, c->Ypart, c->st, c->stream);
+    launch_gemm_bf16(c->g1_16, c->phi16, c->Np, c->Dp, c->PdH, c->PdL, sc.Q, c->Qp, c->Ypart, c->st, c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
-    launch_finish_pass1(c->Ypart, c->g1_16.splits, c->Qp, c->Np, nullptr, c->VH, c->VL, c->st, c->stream);
+    launch_finish_pass1(c->Ypart, c->g1_16.splits, sc.Q, c->Qp, c->Np, nullptr, c->VH, c->VL, c->st, c->stream);
     if (c->timing && (rc = timed_begin(c, 1, step, &t)) != COFEM_OK) return rc;
-    launch_gemm_bf16(c->g2_16, c->phi16T, c->Dp, c->Np, c->VH, c->VL, c->Qp, c->Ypart, c->st, c->stream);
+    launch_gemm_bf16(c->g2_16, c->phi16T, c->Dp, c->Np, c->VH, c->VL, sc.Q, c->Qp, c->Ypart, c->st, c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
     launch_finish_pass2(sc, c->Ypart, c->g2_16.splits, c->Dp, alpha, c->Pd, c->Psi, c->pipart, c->st, c->stream);
   } else {
     if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
-    launch_gemm_f32(c->g1_32, c->phi32, c->Np, c->Dp, c->Pd, c->Qp, c->Ypart, c->st, c->stream);
+    launch_gemm_f32(c->g1_32, c->phi32, c->Np, c->Dp, c->Pd, sc.Q, c->Qp, c->Ypart, c->st, c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
-    launch_finish_pass1(c->Ypart, c->g1_32.splits, c->Qp, c->Np, c->V, nullptr, nullptr, c->st, c->stream);
+    launch_finish_pass1(c->Ypart, c->g1_32.splits, sc.Q, c->Qp, c->Np, c->V, nullptr, nullptr, c->st, c->stream);
     if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
-    launch_gemm_f32(c->g2_32, c->phi32T, c->Dp, c->Np, c->V, c->Qp, c->Ypart, c->st, c->stream);
+    launch_gemm_f32(c->g2_32, c->phi32T, c->Dp, c->Np, c->V, sc.Q, c->Qp, c->Ypart, c->st, c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
     launch_finish_pass2(sc, c->Ypart, c->g2_32.splits, c->Dp, alpha, c->Pd, c->Psi, c->pipart, c->st, c->stream);
   }
@@ -380,7 +380,12 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   }
 #undef TRY
   launch_state_reset(c->st, c->Q, c->stream);
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+  // columns of V past the real ones are never written by the passes: keep them zero
+  bool zero_ok = true;
+  if (c->V) zero_ok &= hipMemsetAsync(c->V, 0, (size_t)Qp * Np * sizeof(float), c->stream) == hipSuccess;
+  if (c->VH) zero_ok &= hipMemsetAsync(c->VH, 0, (size_t)Qp * Np * sizeof(uint16_t), c->stream) == hipSuccess;
+  if (c->VL) zero_ok &= hipMemsetAsync(c->VL, 0, (size_t)Qp * Np * sizeof(uint16_t), c->stream) == hipSuccess;
+  if (!zero_ok || hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
     free_all(c);
     delete c;
     return fail(COFEM_EDEVICE, "workspace initialisation failed");

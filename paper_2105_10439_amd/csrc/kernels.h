@@ -83,15 +83,16 @@ struct GemmCfg {
 };
 GemmCfg choose_gemm(int64_t rows, int64_t kdim, int bf16);
 
-// Ypart[split][q][row] = sum_{k in split} M[row, k] Z[q, k], for q < Qp.
+// Ypart[split][q][row] = sum_{k in split} M[row, k] Z[q, k] for the Q real columns (rows of
+// Ypart past the column tiles are not written); Qp is the padded column count of Z and Ypart.
 // bf16: M, ZH, ZL are bf16 bits, products of M with ZH and ZL accumulate in FP32.
 void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
-                      const uint16_t* ZL, int Qp, float* Ypart, const CGState* st, hipStream_t s);
-void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Qp,
+                      const uint16_t* ZL, int Q, int Qp, float* Ypart, const CGState* st, hipStream_t s);
+void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Q, int Qp,
                      float* Ypart, const CGState* st, hipStream_t s);
 
 // V = sum_split Ypart (rows Np); writes V (FP32) and/or VH/VL (bf16 hi/lo).
-void launch_finish_pass1(const float* Ypart, int splits, int Qp, int64_t Np, float* V, uint16_t* VH,
+void launch_finish_pass1(const float* Ypart, int splits, int Q, int Qp, int64_t Np, float* V, uint16_t* VH,
                          uint16_t* VL, const CGState* st, hipStream_t s);
 
 // Psi = beta * sum_split Ypart + alpha * Pd (columns q < c.Q) and per-chunk partials of

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(VBLOCK) void k_mstep(SolveCfg c, uint64_t key, int6
   mstep_block(c, key, D, Dp, blockIdx.x, X, mu, s_out, alpha, floor, do_mstep, st);
 }
 
-template <int RT, int CT, int KS>
+template <int RT, int CT, int KS, bool X1>
 __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void k_gemm_bf16(const uint16_t* __restrict__ M, int64_t ldm,
                                                       const uint16_t* __restrict__ ZH,
                                                       const uint16_t* __restrict__ ZL, int64_t ldz,
@@ -130,17 +130,17 @@ __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void k_gemm_bf16(const uint16_t
                                                       int64_t kdim, int nrb, int splits,
                                                       const int* __restrict__ done) {
   if (done && *done) return;
-  gemm_bf16_tile<RT, CT, KS>(blockIdx.x, M, ldm, ZH, ZL, ldz, Yp, ldy, Qp, kchunk, kdim, nrb, splits);
+  gemm_bf16_tile<RT, CT, KS, X1>(blockIdx.x, M, ldm, ZH, ZL, ldz, Yp, ldy, Qp, kchunk, kdim, nrb, splits);
 }
 
-template <int RT, int CT, int KS>
+template <int RT, int CT, int KS, bool X1>
 __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void k_gemm_f32(const float* __restrict__ M, int64_t ldm,
                                                      const float* __restrict__ Z, int64_t ldz,
                                                      float* __restrict__ Yp, int64_t ldy, int Qp, int64_t kchunk,
                                                      int64_t kdim, int nrb, int splits,
                                                      const int* __restrict__ done) {
   if (done && *done) return;
-  gemm_f32_tile<RT, CT, KS>(blockIdx.x, M, ldm, Z, ldz, Yp, ldy, Qp, kchunk, kdim, nrb, splits);
+  gemm_f32_tile<RT, CT, KS, X1>(blockIdx.x, M, ldm, Z, ldz, Yp, ldy, Qp, kchunk, kdim, nrb, splits);
 }
 
 __global__ __launch_bounds__(256) void k_finish_pass1(const float* __restrict__ Yp, int splits, int64_t Np,
@@ -293,51 +293,81 @@ GemmCfg choose_gemm(int64_t rows, int64_t kdim, int bf16) {
 constexpr int KS_BF16 = 2;  // 32-k steps per stage (64 k)
 constexpr int KS_F32 = 4;   // 16-k steps per stage (64 k)
 
+// Column tiles for Q right-hand sides: MFMA tiles of 16, except that a lone column past one
+// or two full tiles (Q = 17, 33) goes to the vector ALU instead of a mostly padded tile.
+static inline void gemm_cols(int Q, int& ct, bool& x1) {
+  x1 = Q == 17 || Q == 33;
+  ct = x1 ? Q / 16 : (Q + 15) / 16;
+}
+
+#define GEMM_BF16(RT, CT, X1)                                                                                      \
+  hipLaunchKernelGGL((k_gemm_bf16<RT, CT, KS_BF16, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, \
+                     Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done)
+#define GEMM_F32(RT, CT, X1)                                                                                      \
+  hipLaunchKernelGGL((k_gemm_f32<RT, CT, KS_F32, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp,   \
+                     rows, Qp, g.kchunk, kdim, nrb, g.splits, done)
+
 template <int RT>
 static void gemm_bf16_rt(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
-                         const uint16_t* ZL, int Qp, float* Yp, const int* done, hipStream_t s) {
+                         const uint16_t* ZL, int Q, int Qp, float* Yp, const int* done, hipStream_t s) {
   const int nrb = (int)(rows / (64 * RT));
   dim3 grid((unsigned)(nrb * g.splits));
-  switch (Qp / 16) {
-    case 1: hipLaunchKernelGGL((k_gemm_bf16<RT, 1, KS_BF16>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    case 2: hipLaunchKernelGGL((k_gemm_bf16<RT, 2, KS_BF16>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    case 3: hipLaunchKernelGGL((k_gemm_bf16<RT, 3, KS_BF16>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    default: hipLaunchKernelGGL((k_gemm_bf16<RT, 4, KS_BF16>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+  int ct;
+  bool x1;
+  gemm_cols(Q, ct, x1);
+  if (x1) {
+    if (ct == 1) GEMM_BF16(RT, 1, true);
+    else GEMM_BF16(RT, 2, true);
+  } else {
+    switch (ct) {
+      case 1: GEMM_BF16(RT, 1, false); break;
+      case 2: GEMM_BF16(RT, 2, false); break;
+      case 3: GEMM_BF16(RT, 3, false); break;
+      default: GEMM_BF16(RT, 4, false); break;
+    }
   }
 }
 
 void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
-                      const uint16_t* ZL, int Qp, float* Yp, const CGState* st, hipStream_t s) {
+                      const uint16_t* ZL, int Q, int Qp, float* Yp, const CGState* st, hipStream_t s) {
   const int* done = st ? &st->done : nullptr;
-  if (g.rt == 4) gemm_bf16_rt<4>(g, M, rows, kdim, ZH, ZL, Qp, Yp, done, s);
-  else if (g.rt == 2) gemm_bf16_rt<2>(g, M, rows, kdim, ZH, ZL, Qp, Yp, done, s);
-  else gemm_bf16_rt<1>(g, M, rows, kdim, ZH, ZL, Qp, Yp, done, s);
+  if (g.rt == 4) gemm_bf16_rt<4>(g, M, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
+  else if (g.rt == 2) gemm_bf16_rt<2>(g, M, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
+  else gemm_bf16_rt<1>(g, M, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
 }
 
 template <int RT>
-static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Qp,
+static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Q, int Qp,
                         float* Yp, const int* done, hipStream_t s) {
   const int nrb = (int)(rows / (64 * RT));
   dim3 grid((unsigned)(nrb * g.splits));
-  switch (Qp / 16) {
-    case 1: hipLaunchKernelGGL((k_gemm_f32<RT, 1, KS_F32>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    case 2: hipLaunchKernelGGL((k_gemm_f32<RT, 2, KS_F32>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    case 3: hipLaunchKernelGGL((k_gemm_f32<RT, 3, KS_F32>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
-    default: hipLaunchKernelGGL((k_gemm_f32<RT, 4, KS_F32>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done); break;
+  int ct;
+  bool x1;
+  gemm_cols(Q, ct, x1);
+  if (x1) {
+    if (ct == 1) GEMM_F32(RT, 1, true);
+    else GEMM_F32(RT, 2, true);
+  } else {
+    switch (ct) {
+      case 1: GEMM_F32(RT, 1, false); break;
+      case 2: GEMM_F32(RT, 2, false); break;
+      case 3: GEMM_F32(RT, 3, false); break;
+      default: GEMM_F32(RT, 4, false); break;
+    }
   }
 }
 
-void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Qp,
+void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Q, int Qp,
                      float* Yp, const CGState* st, hipStream_t s) {
   const int* done = st ? &st->done : nullptr;
-  if (g.rt == 4) gemm_f32_rt<4>(g, M, rows, kdim, Z, Qp, Yp, done, s);
-  else if (g.rt == 2) gemm_f32_rt<2>(g, M, rows, kdim, Z, Qp, Yp, done, s);
-  else gemm_f32_rt<1>(g, M, rows, kdim, Z, Qp, Yp, done, s);
+  if (g.rt == 4) gemm_f32_rt<4>(g, M, rows, kdim, Z, Q, Qp, Yp, done, s);
+  else if (g.rt == 2) gemm_f32_rt<2>(g, M, rows, kdim, Z, Q, Qp, Yp, done, s);
+  else gemm_f32_rt<1>(g, M, rows, kdim, Z, Q, Qp, Yp, done, s);
 }
 
-void launch_finish_pass1(const float* Ypart, int splits, int Qp, int64_t Np, float* V, uint16_t* VH,
+void launch_finish_pass1(const float* Ypart, int splits, int Q, int Qp, int64_t Np, float* V, uint16_t* VH,
                          uint16_t* VL, const CGState* st, hipStream_t s) {
-  dim3 grid(cdiv(Np, VCHUNK), (unsigned)Qp);
+  dim3 grid(cdiv(Np, VCHUNK), (unsigned)Q);
   hipLaunchKernelGGL(k_finish_pass1, grid, dim3(256), 0, s, Ypart, splits, Np, V, VH, VL, Qp, &st->done);
 }
 

@@ -116,10 +116,10 @@ __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void ks_gemm(const SlotDev* __r
     const int ntile = pass == 1 ? sd.nrb1 * sd.splits1 : sd.nrb2 * sd.splits2;
     if (!in_cg(sd) || local >= ntile) continue;
     if (pass == 1)
-      gemm_f32_tile<SRV_RT, SRV_QP / 16, 4>(local, sd.phi, sd.Dp, sd.Pd, sd.Dp, sd.Ypart, sd.Np, SRV_QP, sd.kchunk1,
+      gemm_f32_tile<SRV_RT, SRV_QP / 16, 4, false>(local, sd.phi, sd.Dp, sd.Pd, sd.Dp, sd.Ypart, sd.Np, SRV_QP, sd.kchunk1,
                                             sd.Dp, sd.nrb1, sd.splits1);
     else
-      gemm_f32_tile<SRV_RT, SRV_QP / 16, 4>(local, sd.phiT, sd.Np, sd.V, sd.Np, sd.Ypart, sd.Dp, SRV_QP,
+      gemm_f32_tile<SRV_RT, SRV_QP / 16, 4, false>(local, sd.phiT, sd.Np, sd.V, sd.Np, sd.Ypart, sd.Dp, SRV_QP,
                                             sd.kchunk2, sd.Np, sd.nrb2, sd.splits2);
     __syncthreads();  // the next tile reuses the LDS staging buffers
   }

@@ -137,14 +137,33 @@ __device__ __forceinline__ void mstep_block(const SolveCfg& c, uint64_t key, int
 // ---------------------------------------------------------------------------
 constexpr int GEMM_WAVES = 4;  // waves per contraction tile (launch with 64 * GEMM_WAVES threads)
 
+typedef __attribute__((ext_vector_type(8))) unsigned short u16x8v;
+
 __device__ __forceinline__ void lds_dma16(const void* src, void* lds_base) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
 }
 __device__ __forceinline__ void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// The extra column's partials: lane (r16, g) holds row r16 of each row tile summed over its
+// k-subset; the four g-lanes of a row are added in a fixed order and lane g = 0 stores.
+template <int RT>
+__device__ __forceinline__ void store_x1(float (&xacc)[RT], float* __restrict__ ycol, int64_t row0, int r16, int g) {
+#pragma unroll
+  for (int a = 0; a < RT; ++a) {
+    float v = xacc[a];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (g == 0) ycol[row0 + a * 16 + r16] = v;
+  }
+}
+
 // bf16: v_mfma_f32_16x16x32_bf16, lane l holds A[l%16][8(l/16) .. +8), B[8(l/16) .. +8)[l%16]
 // and returns D[4(l/16) .. +4)[l%16].  ZH + ZL carries each right-hand side to ~2^-17.
-template <int RT, int CT, int KS>
+// X1: one more right-hand side (column 16 CT, e.g. the 33rd of K = 32 probes) on the vector
+// ALU instead of a mostly empty MFMA column tile: lane (r16, g) accumulates its row's
+// products over its k-subset in FP32 (the column's value is hi + lo), and the four
+// g-lanes of a row are summed at the end.
+template <int RT, int CT, int KS, bool X1>
 __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict__ M, int64_t ldm,
                                                const uint16_t* __restrict__ ZH, const uint16_t* __restrict__ ZL,
                                                int64_t ldz, float* __restrict__ Yp, int64_t ldy, int Qp,
@@ -185,6 +204,20 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
   for (int a = 0; a < RT; ++a)
 #pragma unroll
     for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + s * 32);
+  // the extra column: this lane's 8 k of each sub-step, hi and lo
+  const uint16_t* xh = ZH + (int64_t)(CT * 16) * ldz + kb + 8 * g;
+  const uint16_t* xl = ZL + (int64_t)(CT * 16) * ldz + kb + 8 * g;
+  u16x8v xcur[KS][2];
+  float xacc[RT];
+  if constexpr (X1) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      xcur[s][0] = *reinterpret_cast<const u16x8v*>(xh + s * 32);
+      xcur[s][1] = *reinterpret_cast<const u16x8v*>(xl + s * 32);
+    }
+#pragma unroll
+    for (int a = 0; a < RT; ++a) xacc[a] = 0.0f;
+  }
   issue_B(0, 0);
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
@@ -196,6 +229,14 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + (int64_t)nx * SK + s * 32);
+    u16x8v xnxt[KS][2];
+    if constexpr (X1) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        xnxt[s][0] = *reinterpret_cast<const u16x8v*>(xh + (int64_t)nx * SK + s * 32);
+        xnxt[s][1] = *reinterpret_cast<const u16x8v*>(xl + (int64_t)nx * SK + s * 32);
+      }
+    }
     issue_B(nx, buf ^ 1);
     __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this stage's MFMAs
 #pragma unroll
@@ -213,11 +254,29 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[a][s], bh[b], acc[a][b], 0, 0, 0);
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[a][s], bl[b], acc[a][b], 0, 0, 0);
         }
+      if constexpr (X1) {
+        float z[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) z[j] = bf16_val(xcur[s][0][j]) + bf16_val(xcur[s][1][j]);
+#pragma unroll
+        for (int a = 0; a < RT; ++a) {
+          const u16x8v av = __builtin_bit_cast(u16x8v, acur[a][s]);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) xacc[a] = __builtin_fmaf(bf16_val(av[j]), z[j], xacc[a]);
+        }
+      }
     }
 #pragma unroll
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int s = 0; s < KS; ++s) acur[a][s] = anxt[a][s];
+    if constexpr (X1) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        xcur[s][0] = xnxt[s][0];
+        xcur[s][1] = xnxt[s][1];
+      }
+    }
   }
   wait_vm_all();  // the last (self-reloading) DMA has landed before the LDS is released
   float* yb = Yp + (int64_t)sp * Qp * ldy;
@@ -229,12 +288,14 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
       const int64_t row = row0 + a * 16 + 4 * g;
       *reinterpret_cast<f32x4*>(yb + q * ldy + row) = acc[a][b];
     }
+  if constexpr (X1) store_x1<RT>(xacc, yb + (int64_t)(CT * 16) * ldy, row0, r16, g);
 }
 
 // FP32: v_mfma_f32_16x16x4_f32.  Each lane holds 4 consecutive k of its row (and of its
 // column of Z) and feeds element e to the e-th MFMA, so the four MFMAs of a 16-k step
 // see the same k order in both operands.  1 KB fragment per 16-k step and column tile.
-template <int RT, int CT, int KS>
+// X1: one more right-hand side (column 16 CT) on the vector ALU, as in the bf16 tile.
+template <int RT, int CT, int KS, bool X1>
 __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M, int64_t ldm,
                                               const float* __restrict__ Z, int64_t ldz, float* __restrict__ Yp,
                                               int64_t ldy, int Qp, int64_t kchunk, int64_t kdim, int nrb,
@@ -274,6 +335,15 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
   for (int a = 0; a < RT; ++a)
 #pragma unroll
     for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + s * 16);
+  const float* xp = Z + (int64_t)(CT * 16) * ldz + kb + 4 * g;
+  f32x4 xcur[KS];
+  float xacc[RT];
+  if constexpr (X1) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) xcur[s] = *reinterpret_cast<const f32x4*>(xp + s * 16);
+#pragma unroll
+    for (int a = 0; a < RT; ++a) xacc[a] = 0.0f;
+  }
   issue_B(0, 0);
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
@@ -285,6 +355,11 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const f32x4*>(ap[a] + (int64_t)nx * SK + s * 16);
+    f32x4 xnxt[KS];
+    if constexpr (X1) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) xnxt[s] = *reinterpret_cast<const f32x4*>(xp + (int64_t)nx * SK + s * 16);
+    }
     issue_B(nx, buf ^ 1);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -299,11 +374,21 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
 #pragma unroll
           for (int b = 0; b < CT; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[a][s][e], bz[b][e], acc[a][b], 0, 0, 0);
+      if constexpr (X1) {
+#pragma unroll
+        for (int a = 0; a < RT; ++a)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) xacc[a] = __builtin_fmaf(acur[a][s][e], xcur[s][e], xacc[a]);
+      }
     }
 #pragma unroll
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int s = 0; s < KS; ++s) acur[a][s] = anxt[a][s];
+    if constexpr (X1) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) xcur[s] = xnxt[s];
+    }
   }
   wait_vm_all();
   float* yb = Yp + (int64_t)sp * Qp * ldy;
@@ -315,6 +400,7 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
       const int64_t row = row0 + a * 16 + 4 * g;
       *reinterpret_cast<f32x4*>(yb + q * ldy + row) = acc[a][b];
     }
+  if constexpr (X1) store_x1<RT>(xacc, yb + (int64_t)(CT * 16) * ldy, row0, r16, g);
 }
 
 

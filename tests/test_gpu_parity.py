@@ -42,7 +42,7 @@ def _rel(a, b):
 # operator
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("N,D,ncols", [(300, 1000, 9), (64, 256, 1), (513, 777, 21), (1024, 2048, 33),
-                                       (200, 600, 64)])
+                                       (200, 600, 64), (260, 700, 17), (256, 512, 49)])
 @pytest.mark.parametrize("dtype", ["fp32", "bf16"])
 def test_apply_A_matches_oracle(gpu, N, D, ncols, dtype):
     rng = np.random.default_rng(N * 7 + D)
