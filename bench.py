@@ -91,6 +91,7 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of saturation")
     ap.add_argument("--no-conv", action="store_true", help="skip the convolutional-dictionary fits")
     ap.add_argument("--conv-only", action="store_true", help="only the convolutional-dictionary fits (for profiling)")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving phase (for profiling)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run a 1 GiB copy and three operator applications (for rocprofv3 --pmc)")
     return ap.parse_args()
@@ -133,6 +134,12 @@ def main():
         sys.exit(2)
     if args.pmc_probe:
         pmc_probe()
+        return
+    if args.serve_only:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving": serving(args)}), flush=True)
         return
     if args.conv_only:
         import torch

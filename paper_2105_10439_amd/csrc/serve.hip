@@ -47,6 +47,7 @@ struct SlotDev {
   int nrb1, splits1, nrb2, splits2;
   int64_t kchunk1, kchunk2;
   int nbx, nbn;  // vector tiles per column over Dp and Np
+  int x1;        // Q = 17: one MFMA column tile plus the 17th column on the vector ALU
   const float* phi;
   const float* phiT;
   float *V, *Ypart, *X, *R, *Pd, *Psi, *minv, *alpha, *b, *theta, *mu, *s;
@@ -115,12 +116,16 @@ __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void ks_gemm(const SlotDev* __r
     const int local = t - start[i];
     const int ntile = pass == 1 ? sd.nrb1 * sd.splits1 : sd.nrb2 * sd.splits2;
     if (!in_cg(sd) || local >= ntile) continue;
-    if (pass == 1)
-      gemm_f32_tile<SRV_RT, SRV_QP / 16, 4, false>(local, sd.phi, sd.Dp, sd.Pd, sd.Dp, sd.Ypart, sd.Np, SRV_QP, sd.kchunk1,
-                                            sd.Dp, sd.nrb1, sd.splits1);
+    const float* M = pass == 1 ? sd.phi : sd.phiT;
+    const float* Z = pass == 1 ? sd.Pd : sd.V;
+    const int64_t kdim = pass == 1 ? sd.Dp : sd.Np, rows = pass == 1 ? sd.Np : sd.Dp;
+    const int64_t kchunk = pass == 1 ? sd.kchunk1 : sd.kchunk2;
+    const int nrb = pass == 1 ? sd.nrb1 : sd.nrb2, splits = pass == 1 ? sd.splits1 : sd.splits2;
+    if (sd.x1)
+      gemm_f32_tile<SRV_RT, 1, 4, true>(local, M, kdim, Z, kdim, sd.Ypart, rows, SRV_QP, kchunk, kdim, nrb, splits);
     else
-      gemm_f32_tile<SRV_RT, SRV_QP / 16, 4, false>(local, sd.phiT, sd.Np, sd.V, sd.Np, sd.Ypart, sd.Dp, SRV_QP,
-                                            sd.kchunk2, sd.Np, sd.nrb2, sd.splits2);
+      gemm_f32_tile<SRV_RT, SRV_QP / 16, 4, false>(local, M, kdim, Z, kdim, sd.Ypart, rows, SRV_QP, kchunk, kdim, nrb,
+                                                   splits);
     __syncthreads();  // the next tile reuses the LDS staging buffers
   }
 }
@@ -132,7 +137,7 @@ __global__ __launch_bounds__(VBLOCK) void ks_finish1(const SlotDev* __restrict__
     const int i = find_slot(tab->f1, n, t);
     const SlotDev& sd = slots[tab->slot[i]];
     const int local = t - tab->f1[i];
-    if (!in_cg(sd) || local >= sd.nbn * SRV_QP) continue;
+    if (!in_cg(sd) || local >= sd.nbn * (sd.x1 ? sd.c.Q : SRV_QP)) continue;  // X1 leaves columns > Q unwritten
     finish1_tile(local % sd.nbn, local / sd.nbn, sd.Ypart, sd.splits1, sd.Np, sd.V, nullptr, nullptr, SRV_QP);
   }
 }
@@ -476,6 +481,7 @@ cofem_status admit(cofem_server* s, int slot, Request& r) {
   SlotDev sd{};
   sd.c.Q = p.K + 1;
   sd.c.Qp = SRV_QP;
+  sd.x1 = sd.c.Q == 17 ? 1 : 0;
   sd.c.K = p.K;
   sd.c.U = p.U;
   sd.c.stop_mode = p.stop_mode;

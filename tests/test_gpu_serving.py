@@ -63,8 +63,10 @@ def test_alone_equals_mix_bitwise(gpu):
         assert alone[0][3]["total_cg_steps"] == mixed[i][3]["total_cg_steps"]
 
 
-def test_served_fit_matches_oracle(gpu):
-    w = dict(workloads.WORKLOADS["small"])
+@pytest.mark.parametrize("K", [8, 16])
+def test_served_fit_matches_oracle(gpu, K):
+    # K = 16 runs the 17th column on the vector ALU
+    w = dict(workloads.WORKLOADS["small"], K=K)
     prob = workloads.make_workload("small")
     kw = dict(K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=1234)
     (res,), _ = _run(gpu, [prob], kw)
@@ -72,7 +74,7 @@ def test_served_fit_matches_oracle(gpu):
     ref = oracle.cofem(prob.phi, prob.y, prob.beta, T=w["T"], K=w["K"], U=w["U"], tol=w["tol"], seed=1234)
     e_mu = np.linalg.norm(mu - ref.mu) / np.linalg.norm(ref.mu)
     e_s = np.linalg.norm(s - ref.s) / np.linalg.norm(ref.s)
-    print(f"served small workload: mu rel {e_mu:.2e}, s rel {e_s:.2e}")
+    print(f"served small workload K={K}: mu rel {e_mu:.2e}, s rel {e_s:.2e}")
     assert e_mu <= 1e-4
     assert e_s <= 1e-3
 
