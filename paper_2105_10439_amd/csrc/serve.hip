@@ -105,12 +105,22 @@ __global__ __launch_bounds__(VBLOCK) void ks_em_scalars(const SlotDev* __restric
 
 __device__ __forceinline__ bool in_cg(const SlotDev& sd) { return sd.st->phase == PH_CG && !sd.st->done; }
 
+// Contraction tiles of all running slots, claimed one at a time from a counter (tiles of
+// different requests differ in length, so a static stride leaves blocks idle at the end).
+// Each tile writes its own partial, so the result does not depend on which block ran it.
+// Every block leaves once the counter has passed the last tile.
 __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void ks_gemm(const SlotDev* __restrict__ slots, const SrvTable* __restrict__ tab,
-                                                  int pass) {
+                                                  int pass, int* __restrict__ ctr) {
   const int n = tab->n;
   const int* start = pass == 1 ? tab->g1 : tab->g2;
   const int total = start[n];
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+  __shared__ int s_t;
+  for (;;) {
+    if (threadIdx.x == 0) s_t = atomicAdd(ctr, 1);
+    __syncthreads();
+    const int t = s_t;
+    __syncthreads();  // every wave has read s_t before the next claim overwrites it
+    if (t >= total) break;
     const int i = find_slot(start, n, t);
     const SlotDev& sd = slots[tab->slot[i]];
     const int local = t - start[i];
@@ -128,6 +138,11 @@ __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void ks_gemm(const SlotDev* __r
                                                    splits);
     __syncthreads();  // the next tile reuses the LDS staging buffers
   }
+}
+
+// Zero the tile counters of one tick (a kernel, not a memset node, inside the captured graph).
+__global__ void ks_reset_ctr(int* __restrict__ ctr, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0;
 }
 
 __global__ __launch_bounds__(VBLOCK) void ks_finish1(const SlotDev* __restrict__ slots,
@@ -401,6 +416,7 @@ struct cofem_server {
   SlotDev* d_slots = nullptr;
   SrvTable* d_table = nullptr;
   int* d_phase = nullptr;
+  int* d_ctr = nullptr;  // tile counters: two per CG step of a tick
   int* h_phase = nullptr;  // pinned
   SrvTable h_table{};
   std::vector<SlotDev> slot_dev;
@@ -438,12 +454,15 @@ cofem_status validate_request(const cofem_params* p) {
 
 cofem_status capture_tick(cofem_server* s) {
   SRV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(ks_reset_ctr, dim3(1), dim3(128), 0, s->stream, s->d_ctr, 2 * s->steps);
   hipLaunchKernelGGL(ks_em_init, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
   hipLaunchKernelGGL(ks_em_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
   for (int k = 0; k < s->steps; ++k) {
-    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, s->stream, s->d_slots, s->d_table, 1);
+    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, s->stream, s->d_slots, s->d_table, 1,
+                       s->d_ctr + 2 * k);
     hipLaunchKernelGGL(ks_finish1, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
-    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, s->stream, s->d_slots, s->d_table, 2);
+    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, s->stream, s->d_slots, s->d_table, 2,
+                       s->d_ctr + 2 * k + 1);
     hipLaunchKernelGGL(ks_finish2, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
     hipLaunchKernelGGL(ks_update, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
     hipLaunchKernelGGL(ks_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
@@ -468,6 +487,7 @@ void destroy_server(cofem_server* s) {
   if (s->d_slots) (void)hipFree(s->d_slots);
   if (s->d_table) (void)hipFree(s->d_table);
   if (s->d_phase) (void)hipFree(s->d_phase);
+  if (s->d_ctr) (void)hipFree(s->d_ctr);
   if (s->h_phase) (void)hipHostFree(s->h_phase);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
@@ -596,7 +616,8 @@ COFEM_API cofem_status cofem_server_create(size_t hbm_budget, int32_t max_slots,
   s->arena.init(hbm_budget);
   if (hipMalloc((void**)&s->d_slots, sizeof(SlotDev) * SRV_MAXSLOTS) != hipSuccess ||
       hipMalloc((void**)&s->d_table, sizeof(SrvTable)) != hipSuccess ||
-      hipMalloc((void**)&s->d_phase, sizeof(int) * SRV_MAXSLOTS) != hipSuccess)
+      hipMalloc((void**)&s->d_phase, sizeof(int) * SRV_MAXSLOTS) != hipSuccess ||
+      hipMalloc((void**)&s->d_ctr, sizeof(int) * 2 * 64) != hipSuccess)  // steps_per_tick <= 64
     return bail(COFEM_ENOMEM, "server tables allocation failed");
   if (hipHostMalloc((void**)&s->h_phase, sizeof(int) * SRV_MAXSLOTS, hipHostMallocDefault) != hipSuccess) {
     s->h_phase = nullptr;
