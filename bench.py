@@ -38,13 +38,13 @@ HBM_PEAK_GBPS = 8000.0
 METRIC = "CoFEM EM-iters/s + HBM GB/s at D=65536 (BF16 vs FP32); serving p50/p99"
 
 
-# HBM traffic of the bf16 operator kernel (k_gemm_bf16<4,3,2>) at N=16384, D=65536,
+# HBM traffic of the bf16 operator kernel (k_gemm_bf16<4,2,2,true>) at N=16384, D=65536,
 # from two rocprofv3 --pmc passes over `bench.py --pmc-probe` (FETCH_SIZE, then
 # WRITE_SIZE; KiB per dispatch, averaged over 6 dispatches), each scaled by what the
 # same counter reads for a plain 1 GiB device copy.  It holds only for the kernel
 # source it was taken on: the hash covers the tile function and the launch shape choice.
-GEMM_TRAFFIC = dict(src_sha="c034a455bbdb592c", fetch_kib=1069869.8, write_kib=24693.3,
-                    copy_kib=1048576.0, copy_fetch_kib=524302.3, copy_write_kib=1048576.0,
+GEMM_TRAFFIC = dict(src_sha="0c80e7a9af4a815c", fetch_kib=1065091.1, write_kib=16963.5,
+                    copy_kib=1048576.0, copy_fetch_kib=524304.6, copy_write_kib=1048576.0,
                     profile="profiles/hbm_traffic_k_gemm_bf16_dense_N16384_D65536.md")
 
 
