@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define COFEM_ABI_VERSION 1
+#define COFEM_ABI_VERSION 2
 #define COFEM_MAX_T 512 /* longest EM run recorded in cofem_stats */
 #define COFEM_MAX_K 63  /* probes per EM iteration (one 64-bit hash word per coordinate) */
 
@@ -60,6 +60,7 @@ typedef enum { COFEM_THETA_ONES = 0, COFEM_THETA_JACOBI = 1 } cofem_theta_mode;
 typedef enum { COFEM_STOP_JOINT = 0, COFEM_STOP_COLUMN = 1 } cofem_stop_mode;
 typedef enum { COFEM_OP_DENSE = 0, COFEM_OP_CONV = 1 } cofem_op_kind;
 typedef enum { COFEM_PHI_FP32 = 0, COFEM_PHI_BF16 = 1 } cofem_phi_dtype;
+typedef enum { COFEM_MSTEP_GAUSSIAN = 0, COFEM_MSTEP_NONNEG = 1 } cofem_mstep_mode;
 
 /*
  * Fit parameters.  Names follow Algorithms 1 and 2.
@@ -84,7 +85,14 @@ typedef enum { COFEM_PHI_FP32 = 0, COFEM_PHI_BF16 = 1 } cofem_phi_dtype;
  *               w(t, j) is 0 and -1 otherwise, where w(t, j) is output j+1 of the
  *               SplitMix64 stream started at key_t, and key_t is output t of the
  *               SplitMix64 stream started at seed (Steele, Lea & Flood 2014).
- *   alpha_floor M-step denominators mu_j^2 + s_j below it are raised to it (> 0).
+ *   alpha_floor M-step denominators below it are raised to it (> 0); with the
+ *               non-negative M-step it also floors s_j used as the posterior variance.
+ *   mstep_mode  COFEM_MSTEP_GAUSSIAN: alpha_j = 1 / (mu_j^2 + s_j) (Eq. mstep).
+ *               COFEM_MSTEP_NONNEG: the rectified-Gaussian prior of Sec. III-E.2;
+ *               alpha_j = 1 / E[z_j^2] with the second moment of Eq. (nonneg-sbl),
+ *               s_j in place of Sigma_jj (the truncated-Gaussian moment carries
+ *               sqrt(2 s_j / pi)).  mu and s are the Gaussian E-step's in both modes.
+ *   reserved_   set to 0.
  */
 typedef struct cofem_params {
   int64_t N, D;
@@ -99,6 +107,8 @@ typedef struct cofem_params {
   int32_t conv_taps;
   uint64_t seed;
   double alpha_floor;
+  int32_t mstep_mode;
+  int32_t reserved_;
 } cofem_params;
 
 /* Per-fit record (host struct, filled by cofem_posterior). */

@@ -333,7 +333,7 @@ def _as_operator(op):
 
 def cofem(op, y: np.ndarray, beta: float, T: int, K: int, U: int, tol: float, seed: int = 0,
           theta_mode: str = "ones", stop_mode: str = "joint", probes=None,
-          alpha_floor: float = 1e-30, alpha0=None, record: bool = False) -> CoFEMResult:
+          alpha_floor: float = 1e-30, alpha0=None, record: bool = False, mstep: str = "gaussian") -> CoFEMResult:
     """Algorithm 1, CovarianceFreeEM(y, Phi, beta, T, K).
 
     alpha starts at 1.  Each iteration t = 1..T draws K Rademacher probes
@@ -349,7 +349,14 @@ def cofem(op, y: np.ndarray, beta: float, T: int, K: int, U: int, tol: float, se
     draw (used for Hadamard probes in tests).  mu_j^2 + s_j may come out <= 0
     because s is only unbiased; such denominators are raised to alpha_floor
     and counted.
+
+    mstep="nonneg" is the M-step of the non-negative model (Sec. III-E.2): the
+    denominator is the second moment of the rectified Gaussian posterior,
+    `nonneg_second_moment(mu, s)` with s in place of Sigma_jj (the paper's own
+    substitution), its variance floor being alpha_floor.
     """
+    if mstep not in ("gaussian", "nonneg"):
+        raise ValueError("mstep must be 'gaussian' or 'nonneg'")
     op = _as_operator(op)
     D = op.D
     y = np.asarray(y, dtype=np.float64).reshape(-1, 1)
@@ -383,7 +390,7 @@ def cofem(op, y: np.ndarray, beta: float, T: int, K: int, U: int, tol: float, se
         mu = res.X[:, 0].copy()
         s = diag_estimate(Pr, res.X[:, 1:])
         if t < T:
-            denom = mu ** 2 + s
+            denom = mu ** 2 + s if mstep == "gaussian" else nonneg_second_moment(mu, s, alpha_floor)
             low = denom < alpha_floor
             clamped += int(low.sum())
             alpha = 1.0 / np.maximum(denom, alpha_floor)
@@ -394,12 +401,15 @@ def cofem(op, y: np.ndarray, beta: float, T: int, K: int, U: int, tol: float, se
 # ---------------------------------------------------------------------------
 # Covariance-based EM (Sec. II-B) and the quantities used to pin it.
 # ---------------------------------------------------------------------------
-def exact_em(phi: np.ndarray, y: np.ndarray, beta: float, T: int, alpha0=None, record: bool = False):
+def exact_em(phi: np.ndarray, y: np.ndarray, beta: float, T: int, alpha0=None, record: bool = False,
+             mstep: str = "gaussian", alpha_floor: float = 1e-30):
     """EM with the explicit posterior covariance.
 
     E-step, Eq. (estep-params): Sigma = (beta Phi^T Phi + diag(alpha))^{-1},
     mu = beta Sigma Phi^T y.  M-step, Eq. (mstep): alpha_j = 1 / (mu_j^2 +
     Sigma_jj), done for t < T to match the iteration count of Algorithm 1.
+    mstep="nonneg": alpha_j = 1 / max(E[z_j^2], alpha_floor) with the second moment
+    of the rectified Gaussian posterior, Eq. (nonneg-sbl), from the exact Sigma_jj.
     Returns (alpha^(T), mu, diag(Sigma), list of alpha^(t)).
     """
     phi = np.asarray(phi, dtype=np.float64)
@@ -419,7 +429,10 @@ def exact_em(phi: np.ndarray, y: np.ndarray, beta: float, T: int, alpha0=None, r
         mu = beta * Sigma @ c
         dSig = np.diag(Sigma).copy()
         if t < T:
-            alpha = 1.0 / (mu ** 2 + dSig)
+            if mstep == "gaussian":
+                alpha = 1.0 / (mu ** 2 + dSig)
+            else:
+                alpha = 1.0 / np.maximum(nonneg_second_moment(mu, dSig, alpha_floor), alpha_floor)
     return alpha, mu, dSig, alphas
 
 

@@ -21,6 +21,8 @@ THETA = {"ones": 0, "jacobi": 1}
 STOP = {"joint": 0, "column": 1}
 OPS = {"dense": 0, "conv": 1}
 DTYPES = {"fp32": 0, "bf16": 1}
+MSTEP = {"gaussian": 0, "nonneg": 1}
+ABI_VERSION = 2  # COFEM_ABI_VERSION of include/cofem.h
 
 # every symbol include/cofem.h declares
 EXPORTS = [
@@ -45,6 +47,7 @@ class Params(ctypes.Structure):
         ("theta_mode", ctypes.c_int32), ("stop_mode", ctypes.c_int32), ("op_kind", ctypes.c_int32),
         ("phi_dtype", ctypes.c_int32), ("refine_last", ctypes.c_int32), ("conv_taps", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("alpha_floor", ctypes.c_double),
+        ("mstep_mode", ctypes.c_int32), ("reserved_", ctypes.c_int32),
     ]
 
 
@@ -120,6 +123,9 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.cofem_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {lib.cofem_abi_version()}, the binding expects "
+                           f"{ABI_VERSION}: rebuild it with `python -m paper_2105_10439_amd.build`")
     _lib = lib
     return lib
 
@@ -134,23 +140,23 @@ def _ptr(t) -> int:
 
 
 def make_params(N, D, beta, K, T, U, tol, theta="ones", stop="joint", op="dense", phi_dtype="fp32",
-                refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30) -> Params:
+                refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30, mstep="gaussian") -> Params:
     return Params(N=int(N), D=int(D), beta=float(beta), K=int(K), T=int(T), U=int(U), tol=float(tol),
                   theta_mode=THETA[theta], stop_mode=STOP[stop], op_kind=OPS[op], phi_dtype=DTYPES[phi_dtype],
                   refine_last=int(refine_last), conv_taps=int(conv_taps), seed=int(seed) & ((1 << 64) - 1),
-                  alpha_floor=float(alpha_floor))
+                  alpha_floor=float(alpha_floor), mstep_mode=MSTEP[mstep], reserved_=0)
 
 
 class CoFEM:
     """One problem shape on the current device and torch stream."""
 
     def __init__(self, N, D, beta, K, T, U, tol, theta="ones", stop="joint", op="dense", phi_dtype="fp32",
-                 refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30, stream=None):
+                 refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30, mstep="gaussian", stream=None):
         import torch
 
         lib = load()
         self.params = make_params(N, D, beta, K, T, U, tol, theta, stop, op, phi_dtype, refine_last, conv_taps,
-                                  seed, alpha_floor)
+                                  seed, alpha_floor, mstep)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
         _check(lib.cofem_create(ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
@@ -237,7 +243,8 @@ class Server:
 
     __del__ = close
 
-    def submit(self, phi, y, *, beta, K, T, U, tol, theta="ones", stop="joint", seed=0, alpha_floor=1e-30) -> int:
+    def submit(self, phi, y, *, beta, K, T, U, tol, theta="ones", stop="joint", seed=0, alpha_floor=1e-30,
+               mstep="gaussian") -> int:
         import numpy as np
 
         phi = np.ascontiguousarray(phi, dtype=np.float32)
@@ -245,7 +252,7 @@ class Server:
         N, D = phi.shape
         if y.shape != (N,):
             raise ValueError("y must have N elements")
-        p = make_params(N, D, beta, K, T, U, tol, theta, stop, "dense", "fp32", 0, 0, seed, alpha_floor)
+        p = make_params(N, D, beta, K, T, U, tol, theta, stop, "dense", "fp32", 0, 0, seed, alpha_floor, mstep)
         rid = ctypes.c_int64()
         _check(load().cofem_server_submit(self._h, ctypes.byref(p), phi.ctypes.data_as(ctypes.c_void_p),
                                           y.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rid)))

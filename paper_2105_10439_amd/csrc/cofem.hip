@@ -149,6 +149,8 @@ cofem_status validate(const cofem_params* p) {
   if (p->refine_last < 0 || p->refine_last > p->T) return fail(COFEM_EINVAL, "refine_last must be in [0, T]");
   if (!(p->alpha_floor > 0.0) || !std::isfinite(p->alpha_floor))
     return fail(COFEM_EINVAL, "alpha_floor must be finite and > 0");
+  if (p->mstep_mode != COFEM_MSTEP_GAUSSIAN && p->mstep_mode != COFEM_MSTEP_NONNEG)
+    return fail(COFEM_EINVAL, "bad mstep_mode");
   if (p->op_kind == COFEM_OP_CONV) {
     if (p->N != p->D) return fail(COFEM_EINVAL, "COFEM_OP_CONV needs N == D");
     if (p->conv_taps < 1 || p->conv_taps > CONV_MAX_TAPS)
@@ -166,6 +168,7 @@ SolveCfg solve_cfg(const cofem_ctx* c) {
   s.K = c->p.K;
   s.U = c->p.U;
   s.stop_mode = c->p.stop_mode;
+  s.nonneg = c->p.mstep_mode == COFEM_MSTEP_NONNEG ? 1 : 0;
   s.tol = c->p.tol;
   s.beta = c->p.beta;
   return s;

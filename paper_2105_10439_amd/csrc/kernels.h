@@ -41,6 +41,7 @@ struct CGState {
 
 struct SolveCfg {
   int Q, Qp, K, U, stop_mode;
+  int nonneg;  // M-step of the non-negative model (Sec. III-E.2)
   double tol, beta;
 };
 

@@ -449,6 +449,8 @@ cofem_status validate_request(const cofem_params* p) {
     return sfail(COFEM_EINVAL, "serving requests are dense FP32 without refinement");
   if (!(p->alpha_floor > 0.0) || !std::isfinite(p->alpha_floor))
     return sfail(COFEM_EINVAL, "alpha_floor must be finite and > 0");
+  if (p->mstep_mode != COFEM_MSTEP_GAUSSIAN && p->mstep_mode != COFEM_MSTEP_NONNEG)
+    return sfail(COFEM_EINVAL, "bad mstep_mode");
   return COFEM_OK;
 }
 
@@ -502,6 +504,7 @@ cofem_status admit(cofem_server* s, int slot, Request& r) {
   sd.c.Q = p.K + 1;
   sd.c.Qp = SRV_QP;
   sd.x1 = sd.c.Q == 17 ? 1 : 0;
+  sd.c.nonneg = p.mstep_mode == COFEM_MSTEP_NONNEG ? 1 : 0;
   sd.c.K = p.K;
   sd.c.U = p.U;
   sd.c.stop_mode = p.stop_mode;

@@ -90,8 +90,13 @@ __device__ __forceinline__ void em_scalars_block(const SolveCfg& c, int64_t D, i
 }
 
 // mu = X_0, s_j = (1/K) sum_k p_kj X_kj (Eq. diag-estimate; probes regenerated from
-// the key), and for do_mstep: alpha_j = 1 / max(mu_j^2 + s_j, floor) (Eq. mstep),
-// counting floor events.  Block blk covers coordinates [256 blk, +256).
+// the key), and for do_mstep: alpha_j = 1 / max(E_j, floor), counting floor events, with
+// E_j = mu_j^2 + s_j (Eq. mstep) or, for the non-negative model, the second moment of
+// the rectified Gaussian posterior (Eq. nonneg-sbl) with s_j in place of Sigma_jj:
+// E_j = mu^2 + v + mu sqrt(2 v / pi) / erfcx(-xi), v = max(s_j, floor), xi = mu / sqrt(2 v)
+// (the sqrt(2 v / pi) factor is the truncated-Gaussian moment; exp(-xi^2) / erfc(-xi) is
+// evaluated as 1 / erfcx(-xi), ROCm's scaled complementary error function).
+// Block blk covers coordinates [256 blk, +256).
 __device__ __forceinline__ void mstep_block(const SolveCfg& c, uint64_t key, int64_t D, int64_t Dp, int blk,
                                             const float* __restrict__ X, float* __restrict__ mu,
                                             float* __restrict__ s_out, float* __restrict__ alpha, double floor,
@@ -107,7 +112,15 @@ __device__ __forceinline__ void mstep_block(const SolveCfg& c, uint64_t key, int
     mu[j] = m;
     s_out[j] = (float)s;
     if (do_mstep) {
-      double den = (double)m * (double)m + s;
+      const double md = (double)m;
+      double den;
+      if (c.nonneg) {
+        const double v = s > floor ? s : floor;
+        const double xi = md / sqrt(2.0 * v);
+        den = md * md + v + md * sqrt(2.0 * v / M_PI) / erfcx(-xi);
+      } else {
+        den = md * md + s;
+      }
       if (den < floor) {
         den = floor;
         clamped = 1;

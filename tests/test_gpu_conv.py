@@ -103,6 +103,18 @@ def test_conv_fit_fp32_matches_oracle(gpu, theta):
     assert st["breakdown"] == 0 and all(np.isfinite(x).all() for x in (mu, s, alpha))
 
 
+def test_conv_fit_nonneg_mstep_matches_oracle(gpu):
+    """Calcium-like use: non-negative spikes, the rectified-Gaussian M-step (Sec. III-E.2)."""
+    prob = workloads.conv_problem(1500, 256, 50.0, 0.01, 0.05, seed=37)
+    K, T, U, tol, seed = 20, 5, 400, 1e-6, 11
+    mu, s, alpha, st = _conv_fit(gpu, prob, K, T, U, tol, seed, mstep="nonneg")
+    ref, sens_mu, sens_s = _oracle_pair(prob, prob.h, K, T, U, tol, seed, mstep="nonneg")
+    e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
+    print(f"conv nonneg fit: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e}), s rel {e_s:.2e} ({sens_s:.2e})")
+    assert e_mu <= max(1e-4, 2 * sens_mu)
+    assert e_s <= max(1e-3, 2 * sens_s)
+
+
 def test_conv_fit_bf16_matches_rounded_oracle_and_refines(gpu):
     prob = workloads.conv_problem(1200, 256, 50.0, 0.01, 0.05, seed=41)
     K, T, U, tol, seed = 20, 5, 400, 1e-6, 9

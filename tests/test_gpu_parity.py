@@ -188,3 +188,21 @@ def test_fit_medium_workload_fp32(gpu):
           f"(oracle {int(ref['cg_steps'].sum())})")
     assert e_mu <= 1e-4
     assert e_s <= 1e-3
+
+
+def test_fit_nonneg_mstep_matches_oracle(gpu):
+    """The non-negative M-step (Sec. III-E.2) on non-negative spikes: the same E-steps,
+    alpha_j = 1 / E[z_j^2] of the rectified Gaussian posterior."""
+    prob = workloads.dense_problem(N=200, D=600, d=30, sigma=0.01, seed=91, law="exp1")
+    w = dict(K=16, T=30, U=300, tol=1e-6)
+    mu, s, alpha, st = _fit(gpu, prob, w, seed=5, mstep="nonneg")
+    ref = _oracle_fit(prob, w, seed=5, mstep="nonneg")
+    gauss = _oracle_fit(prob, w, seed=5)
+    e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
+    sup = _support(ref.mu)
+    print(f"nonneg fit: mu rel {e_mu:.2e}, s rel {e_s:.2e}; the Gaussian M-step's mu differs by "
+          f"{_rel(gauss.mu, ref.mu):.2e}")
+    assert e_mu <= 1e-4
+    assert e_s <= 1e-3
+    assert np.max(np.abs(np.log(alpha[sup] / ref.alpha[sup]))) < 1e-3
+    assert _rel(gauss.mu, ref.mu) > 10 * e_mu   # the M-step really changed the fit

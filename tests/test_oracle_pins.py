@@ -252,6 +252,34 @@ def test_cofem_hadamard_probes_reproduce_exact_em():
     assert np.allclose(r.s, dS_em, rtol=1e-6)
 
 
+def test_cofem_nonneg_hadamard_probes_reproduce_exact_nonneg_em():
+    """The non-negative M-step (Sec. III-E.2) on top of the covariance-free E-step: with
+    K = D Hadamard probes s equals diag(Sigma), so CoFEM equals the explicit-covariance
+    EM with the same M-step."""
+    phi, y, beta = _small_dense(N=16, D=32, d=3, seed=17)
+    H = hadamard_probes(32)
+    r = cofem(phi, y, beta, T=10, K=32, U=400, tol=1e-13, probes=lambda t: H, record=True, mstep="nonneg")
+    a_em, mu_em, dS_em, alphas_em = exact_em(phi, y, beta, T=10, record=True, mstep="nonneg")
+    for a, b in zip(r.alphas, alphas_em):
+        # compare the second moments 1/alpha (alpha can be huge where E[z^2] is tiny)
+        assert np.allclose(1.0 / a, 1.0 / b, rtol=1e-6, atol=1e-9 * np.max(1.0 / b))
+    assert np.linalg.norm(r.mu - mu_em) <= 1e-8 * np.linalg.norm(mu_em)
+
+
+def test_nonneg_mstep_moves_alpha_by_the_sign_of_mu():
+    """One EM step from alpha = 1: the rectified second moment exceeds mu^2 + Sigma_jj where
+    mu_j > 0 and falls below it where mu_j < 0, so the non-negative alpha is smaller,
+    resp. larger, than the Gaussian one."""
+    phi, y, beta = _small_dense(N=24, D=48, d=5, seed=18)
+    _, mu, _, _ = exact_em(phi, y, beta, T=1)             # the E-step at alpha = 1
+    a_g = exact_em(phi, y, beta, T=2)[0]                  # alpha after one M-step of each kind
+    a_n = exact_em(phi, y, beta, T=2, mstep="nonneg")[0]
+    pos, neg = mu > 1e-6, mu < -1e-6
+    assert pos.any() and neg.any()
+    assert np.all(a_n[pos] < a_g[pos])
+    assert np.all(a_n[neg] > a_g[neg])
+
+
 def test_cofem_t1_is_one_estep_at_alpha_one():
     phi, y, beta = _small_dense(seed=13)
     r = cofem(phi, y, beta, T=1, K=8, U=500, tol=1e-13, seed=3)

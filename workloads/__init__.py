@@ -135,12 +135,13 @@ class Problem:
     meta: dict = field(default_factory=dict)
 
 
-def dense_problem(N: int, D: int, d: int, sigma: float, seed: int, name: str = "dense") -> Problem:
+def dense_problem(N: int, D: int, d: int, sigma: float, seed: int, name: str = "dense",
+                  law: str = "normal") -> Problem:
     phi = gaussian_dictionary(N, D, seed)
-    z = sparse_code(D, d, seed)
+    z = sparse_code(D, d, seed, law)
     y = dense_observation(phi, z, sigma, seed)
     return Problem(name=name, N=N, D=D, beta=1.0 / sigma ** 2, sigma=sigma, y=y, z=z, phi=phi,
-                   meta={"d": int(d), "seed": int(seed), "law": "normal"})
+                   meta={"d": int(d), "seed": int(seed), "law": law})
 
 
 def conv_problem(D: int, taps: int, tau: float, p_spike: float, sigma: float, seed: int,
