@@ -188,6 +188,46 @@ cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const float* P, flo
 cofem_status cofem_set_timing(cofem_ctx* c, int32_t enable);
 cofem_status cofem_get_timing(cofem_ctx* c, int32_t which, double* total_ms, int64_t* launches);
 
+/* ---------------------------------------------------------------------------
+ * Multi-task CoFEM (Sec. III-E.1): L sparse-coding problems y_l = Phi_l z_l + eps_l
+ * whose codes share one sparsity profile alpha.  Every EM iteration runs the
+ * covariance-free E-step of each task at the shared alpha (task l draws its probes
+ * with seed + l), then the joint M-step alpha_j = L / sum_l (mu_lj^2 + s_lj),
+ * raised to 1 / alpha_floor like the single-task M-step.
+ * ------------------------------------------------------------------------- */
+typedef struct cofem_mt cofem_mt;
+
+#define COFEM_MAX_TASKS 64
+
+/*
+ * Validate *p (the shape N x D and the settings every task shares; mstep_mode must
+ * be COFEM_MSTEP_GAUSSIAN), allocate L task workspaces on the current device and
+ * bind them to `stream`.  1 <= L <= COFEM_MAX_TASKS.
+ * Errors: COFEM_EINVAL, COFEM_ENOMEM, COFEM_EDEVICE.
+ */
+cofem_status cofem_mt_create(const cofem_params* p, int32_t L, void* stream, cofem_mt** out);
+
+/* Free the tasks and their workspaces (NULL is a no-op). */
+void cofem_mt_destroy(cofem_mt* m);
+
+/* Load task `task`'s dictionary (as cofem_set_dictionary).  Errors: COFEM_EINVAL, COFEM_EDEVICE. */
+cofem_status cofem_mt_set_dictionary(cofem_mt* m, int32_t task, const float* phi);
+
+/*
+ * Run the multi-task EM: `ys` is a host array of L device pointers, ys[l] holding
+ * task l's N observations.  Errors: COFEM_ESTATE (a dictionary missing), COFEM_EINVAL,
+ * COFEM_EDEVICE, COFEM_EBREAKDOWN (some task's mu column broke down).
+ */
+cofem_status cofem_mt_fit(cofem_mt* m, const float* const* ys);
+
+/*
+ * Task `task`'s mu and s from its last E-step, and the shared alpha^(T), into caller
+ * device buffers of D floats (any may be NULL); st (host) receives the task's record
+ * (the clamp count of the joint M-step is reported with task 0).
+ * Errors: COFEM_EINVAL, COFEM_ESTATE (no fit yet).
+ */
+cofem_status cofem_mt_posterior(cofem_mt* m, int32_t task, float* mu, float* s, float* alpha, cofem_stats* st);
+
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent fits.

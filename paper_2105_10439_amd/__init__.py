@@ -30,6 +30,7 @@ EXPORTS = [
     "cofem_fit", "cofem_posterior", "cofem_apply_A", "cofem_set_timing", "cofem_get_timing",
     "cofem_server_create", "cofem_server_destroy", "cofem_server_submit", "cofem_server_step",
     "cofem_server_poll", "cofem_server_get_stats",
+    "cofem_mt_create", "cofem_mt_destroy", "cofem_mt_set_dictionary", "cofem_mt_fit", "cofem_mt_posterior",
 ]
 REQ_STATE = {0: "pending", 1: "running", 2: "done", -1: "unknown"}
 
@@ -118,6 +119,11 @@ def load() -> ctypes.CDLL:
         "cofem_server_step": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cofem_server_poll": (i32, [vp, i64, vp, vp, vp, ctypes.POINTER(RequestInfo)]),
         "cofem_server_get_stats": (i32, [vp, ctypes.POINTER(ServerStats)]),
+        "cofem_mt_create": (i32, [ctypes.POINTER(Params), i32, vp, ctypes.POINTER(vp)]),
+        "cofem_mt_destroy": (None, [vp]),
+        "cofem_mt_set_dictionary": (i32, [vp, i32, vp]),
+        "cofem_mt_fit": (i32, [vp, ctypes.POINTER(vp)]),
+        "cofem_mt_posterior": (i32, [vp, i32, vp, vp, vp, ctypes.POINTER(Stats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -220,6 +226,62 @@ class CoFEM:
         n = ctypes.c_int64()
         _check(load().cofem_get_timing(self._h, 1 if which == "bf16" else 0, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+
+class MultiTask(CoFEM):
+    """Multi-task CoFEM (cofem_mt_*): L problems of one shape sharing alpha."""
+
+    def __init__(self, L, N, D, beta, K, T, U, tol, theta="ones", stop="joint", op="dense", phi_dtype="fp32",
+                 refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30, stream=None):
+        import torch
+
+        lib = load()
+        self.params = make_params(N, D, beta, K, T, U, tol, theta, stop, op, phi_dtype, refine_last, conv_taps,
+                                  seed, alpha_floor)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib.cofem_mt_create(ctypes.byref(self.params), int(L), ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h)))
+        self._h = h
+        self.L, self.N, self.D = int(L), int(N), int(D)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().cofem_mt_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_dictionary(self, task, phi):
+        n = self.N * self.D if self.params.op_kind == 0 else self.params.conv_taps
+        _check(load().cofem_mt_set_dictionary(self._h, int(task), self._dev(phi, n, "phi")))
+
+    def fit(self, ys):
+        if len(ys) != self.L:
+            raise ValueError(f"need {self.L} observation vectors")
+        arr = (ctypes.c_void_p * self.L)(*[self._dev(y, self.N, f"ys[{l}]") for l, y in enumerate(ys)])
+        _check(load().cofem_mt_fit(self._h, arr))
+
+    def posterior(self, task):
+        import torch
+
+        dev = torch.device("cuda", torch.cuda.current_device())
+        mu = torch.empty(self.D, dtype=torch.float32, device=dev)
+        s = torch.empty_like(mu)
+        alpha = torch.empty_like(mu)
+        st = Stats()
+        _check(load().cofem_mt_posterior(self._h, int(task), ctypes.c_void_p(mu.data_ptr()),
+                                         ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(alpha.data_ptr()),
+                                         ctypes.byref(st)))
+        return mu, s, alpha, st.as_dict()
+
+    def apply_A(self, *a, **k):
+        raise NotImplementedError("apply_A is a single-problem test hook")
+
+    def set_timing(self, enable: bool):
+        raise NotImplementedError("operator timing is per single-problem context")
+
+    get_timing = set_timing
 
 
 class Server:

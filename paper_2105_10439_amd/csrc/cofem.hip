@@ -290,6 +290,75 @@ cofem_status sync_state(cofem_ctx* c) {
   return COFEM_OK;
 }
 
+uint64_t estep_key(const cofem_ctx* c, int t) { return mix64_host(c->p.seed + (uint64_t)t * GOLDEN_GAMMA); }
+
+// Start of a fit: stats, CG state, y padded, and b = beta Phi^T y for each phase's operator.
+void begin_fit(cofem_ctx* c, const float* y) {
+  const cofem_params& p = c->p;
+  const double ms_setup = c->stats.ms_setup;
+  std::memset(&c->stats, 0, sizeof(c->stats));
+  c->stats.ms_setup = ms_setup;
+  c->fitted = false;
+  launch_state_reset(c->st, c->Q, c->stream);
+  launch_copy_pad(y, p.N, c->Np, 0.0f, c->yv, c->stream);
+  // b = beta Phi^T y, formed with the same dictionary as the operator of each phase: the
+  // rounding residual of an FP32 b is not in the range of the bf16 Phi^T, and EM would
+  // amplify it through the directions that only diag(alpha) constrains.
+  if (p.op_kind == COFEM_OP_CONV) {
+    if (c->need32) launch_conv_rhs(c->hp32, nullptr, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b32, c->stream);
+    if (c->need16) launch_conv_rhs(c->hp32, c->hp16, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b16, c->stream);
+  } else {
+    if (c->need32) launch_rhs(c->phi32T, nullptr, c->Np, c->Dp, c->yv, p.beta, c->b32, c->stream);
+    if (c->need16) launch_rhs(nullptr, c->phi16T, c->Np, c->Dp, c->yv, p.beta, c->b16, c->stream);
+  }
+}
+
+// The E-step of EM iteration t (Algorithm 1) at the given alpha: probes and B, then the
+// PCG of Algorithm 2 in chunks of steps until the device-side stop rule has fired.
+cofem_status run_estep(cofem_ctx* c, int t, const float* alpha) {
+  const cofem_params& p = c->p;
+  const SolveCfg sc = solve_cfg(c);
+  const bool use16 = c->need16 && (t <= p.T - p.refine_last);
+  launch_em_init(sc, estep_key(c, t), p.D, c->Dp, use16 ? c->b16 : c->b32, c->theta, alpha, c->minv, c->X, c->R,
+                 c->Pd, use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr, c->part, c->st, c->stream);
+  int prev_steps = 0;
+  for (;;) {
+    for (int i = 0; i < c->chunk; ++i) {
+      cofem_status rc = apply_operator(c, use16, alpha, sc, i);
+      if (rc != COFEM_OK) return rc;
+      launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream);
+      launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr,
+                          c->st, c->stream);
+    }
+    cofem_status rc = sync_state(c);
+    if (rc != COFEM_OK) return rc;
+    if (c->timing && (rc = harvest(c, c->h_st->steps - prev_steps)) != COFEM_OK) return rc;
+    prev_steps = c->h_st->steps;
+    if (c->h_st->done) break;
+  }
+  c->stats.cg_steps[t - 1] = c->h_st->steps;
+  c->stats.rel_resid[t - 1] = c->h_st->delta;
+  c->stats.used_bf16[t - 1] = use16 ? 1 : 0;
+  c->stats.total_cg_steps += c->h_st->steps;
+  return COFEM_OK;
+}
+
+// End of a fit: the record, and the breakdown error if the mu column broke down.
+cofem_status end_fit(cofem_ctx* c, double t0) {
+  cofem_status rc = sync_state(c);
+  if (rc != COFEM_OK) return rc;
+  c->stats.T = c->p.T;
+  c->stats.clamped = c->h_st->clamped;
+  c->stats.breakdown = c->h_st->breakdown;
+  c->stats.ms_fit = now_ms() - t0;
+  c->fitted = true;
+  if (c->h_st->active[0] == 0 && c->h_st->breakdown > 0 && c->p.stop_mode == COFEM_STOP_JOINT) {
+    // the mu column can only be inactive in joint mode through a breakdown
+    return fail(COFEM_EBREAKDOWN, "CG breakdown in the mu column");
+  }
+  return COFEM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -431,63 +500,15 @@ COFEM_API cofem_status cofem_fit(cofem_ctx* c, const float* y) {
   if (!c->dict_loaded) return fail(COFEM_ESTATE, "cofem_fit before cofem_set_dictionary");
   const double t0 = now_ms();
   const cofem_params& p = c->p;
-  const SolveCfg sc = solve_cfg(c);
-  const double ms_setup = c->stats.ms_setup;
-  std::memset(&c->stats, 0, sizeof(c->stats));
-  c->stats.ms_setup = ms_setup;
-  c->fitted = false;
-  launch_state_reset(c->st, c->Q, c->stream);
-  launch_copy_pad(y, p.N, c->Np, 0.0f, c->yv, c->stream);
-  // b = beta Phi^T y, formed with the same dictionary as the operator of each phase: the
-  // rounding residual of an FP32 b is not in the range of the bf16 Phi^T, and EM would
-  // amplify it through the directions that only diag(alpha) constrains.
-  if (p.op_kind == COFEM_OP_CONV) {
-    if (c->need32) launch_conv_rhs(c->hp32, nullptr, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b32, c->stream);
-    if (c->need16) launch_conv_rhs(c->hp32, c->hp16, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b16, c->stream);
-  } else {
-    if (c->need32) launch_rhs(c->phi32T, nullptr, c->Np, c->Dp, c->yv, p.beta, c->b32, c->stream);
-    if (c->need16) launch_rhs(nullptr, c->phi16T, c->Np, c->Dp, c->yv, p.beta, c->b16, c->stream);
-  }
+  begin_fit(c, y);
   launch_fill(c->alpha, 1.0f, c->Dp, c->stream);
   for (int t = 1; t <= p.T; ++t) {
-    const bool use16 = c->need16 && (t <= p.T - p.refine_last);
-    const uint64_t key = mix64_host(p.seed + (uint64_t)t * GOLDEN_GAMMA);
-    launch_em_init(sc, key, p.D, c->Dp, use16 ? c->b16 : c->b32, c->theta, c->alpha, c->minv, c->X, c->R, c->Pd,
-                   use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr, c->part, c->st, c->stream);
-    int prev_steps = 0;
-    for (;;) {
-      for (int i = 0; i < c->chunk; ++i) {
-        cofem_status rc = apply_operator(c, use16, c->alpha, sc, i);
-        if (rc != COFEM_OK) return rc;
-        launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream);
-        launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr,
-                            c->st, c->stream);
-      }
-      cofem_status rc = sync_state(c);
-      if (rc != COFEM_OK) return rc;
-      if (c->timing && (rc = harvest(c, c->h_st->steps - prev_steps)) != COFEM_OK) return rc;
-      prev_steps = c->h_st->steps;
-      if (c->h_st->done) break;
-    }
-    c->stats.cg_steps[t - 1] = c->h_st->steps;
-    c->stats.rel_resid[t - 1] = c->h_st->delta;
-    c->stats.used_bf16[t - 1] = use16 ? 1 : 0;
-    c->stats.total_cg_steps += c->h_st->steps;
-    launch_mstep(sc, key, p.D, c->Dp, c->X, c->mu, c->s, c->alpha, p.alpha_floor, t < p.T ? 1 : 0, c->st,
-                 c->stream);
+    cofem_status rc = run_estep(c, t, c->alpha);
+    if (rc != COFEM_OK) return rc;
+    launch_mstep(solve_cfg(c), estep_key(c, t), p.D, c->Dp, c->X, c->mu, c->s, c->alpha, p.alpha_floor,
+                 t < p.T ? 1 : 0, c->st, c->stream);
   }
-  cofem_status rc = sync_state(c);
-  if (rc != COFEM_OK) return rc;
-  c->stats.T = p.T;
-  c->stats.clamped = c->h_st->clamped;
-  c->stats.breakdown = c->h_st->breakdown;
-  c->stats.ms_fit = now_ms() - t0;
-  c->fitted = true;
-  if (c->h_st->active[0] == 0 && c->h_st->breakdown > 0 && p.stop_mode == COFEM_STOP_JOINT) {
-    // the mu column can only be inactive in joint mode through a breakdown
-    return fail(COFEM_EBREAKDOWN, "CG breakdown in the mu column");
-  }
-  return COFEM_OK;
+  return end_fit(c, t0);
 }
 
 COFEM_API cofem_status cofem_posterior(cofem_ctx* c, float* mu, float* s, float* alpha, cofem_stats* st) {
@@ -543,3 +564,126 @@ COFEM_API cofem_status cofem_get_timing(cofem_ctx* c, int32_t which, double* tot
   if (launches) *launches = c->t_n[which];
   return COFEM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Multi-task CoFEM: one context per task, alpha shared (the buffer of task 0).
+// ---------------------------------------------------------------------------
+struct cofem_mt {
+  std::vector<cofem_ctx*> tasks;
+  const float** d_mus = nullptr;  // device arrays of the tasks' mu and s pointers
+  const float** d_ss = nullptr;
+  bool fitted = false;
+};
+
+namespace {
+
+void mt_free(cofem_mt* m) {
+  for (cofem_ctx* c : m->tasks) cofem_destroy(c);
+  m->tasks.clear();
+  if (m->d_mus) (void)hipFree(m->d_mus);
+  if (m->d_ss) (void)hipFree(m->d_ss);
+  m->d_mus = m->d_ss = nullptr;
+}
+
+}  // namespace
+
+COFEM_API cofem_status cofem_mt_create(const cofem_params* p, int32_t L, void* stream, cofem_mt** out) {
+  if (!out) return fail(COFEM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (L < 1 || L > COFEM_MAX_TASKS) return fail(COFEM_EINVAL, "L must be in [1, COFEM_MAX_TASKS]");
+  cofem_status rc = validate(p);
+  if (rc != COFEM_OK) return rc;
+  if (p->mstep_mode != COFEM_MSTEP_GAUSSIAN) return fail(COFEM_EINVAL, "multi-task fits use the Gaussian M-step");
+  cofem_mt* m = new (std::nothrow) cofem_mt();
+  if (!m) return fail(COFEM_ENOMEM, "host allocation failed");
+  std::vector<const float*> mus(L), ss(L);
+  for (int l = 0; l < L; ++l) {
+    cofem_params q = *p;
+    q.seed = p->seed + (uint64_t)l;  // task l's probes
+    cofem_ctx* c = nullptr;
+    rc = cofem_create(&q, stream, &c);
+    if (rc != COFEM_OK) {
+      mt_free(m);
+      delete m;
+      return rc;
+    }
+    m->tasks.push_back(c);
+    mus[l] = c->mu;
+    ss[l] = c->s;
+  }
+  hipStream_t st = m->tasks[0]->stream;
+  if (hipMalloc((void**)&m->d_mus, sizeof(float*) * L) != hipSuccess ||
+      hipMalloc((void**)&m->d_ss, sizeof(float*) * L) != hipSuccess ||
+      hipMemcpyAsync(m->d_mus, mus.data(), sizeof(float*) * L, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(m->d_ss, ss.data(), sizeof(float*) * L, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipGetLastError();
+    mt_free(m);
+    delete m;
+    return fail(COFEM_ENOMEM, "task table allocation failed");
+  }
+  *out = m;
+  return COFEM_OK;
+}
+
+COFEM_API void cofem_mt_destroy(cofem_mt* m) {
+  if (!m) return;
+  mt_free(m);
+  delete m;
+}
+
+COFEM_API cofem_status cofem_mt_set_dictionary(cofem_mt* m, int32_t task, const float* phi) {
+  if (!m || task < 0 || task >= (int32_t)m->tasks.size()) return fail(COFEM_EINVAL, "bad task");
+  return cofem_set_dictionary(m->tasks[task], phi);
+}
+
+COFEM_API cofem_status cofem_mt_fit(cofem_mt* m, const float* const* ys) {
+  if (!m || !ys) return fail(COFEM_EINVAL, "NULL argument");
+  const int L = (int)m->tasks.size();
+  for (int l = 0; l < L; ++l) {
+    if (!ys[l]) return fail(COFEM_EINVAL, "NULL observation");
+    if (!m->tasks[l]->dict_loaded) return fail(COFEM_ESTATE, "cofem_mt_fit before every task has a dictionary");
+  }
+  const double t0 = now_ms();
+  m->fitted = false;
+  cofem_ctx* c0 = m->tasks[0];
+  const cofem_params& p = c0->p;
+  float* alpha = c0->alpha;  // the shared alpha
+  for (int l = 0; l < L; ++l) begin_fit(m->tasks[l], ys[l]);
+  launch_fill(alpha, 1.0f, c0->Dp, c0->stream);
+  for (int t = 1; t <= p.T; ++t) {
+    for (int l = 0; l < L; ++l) {
+      cofem_ctx* c = m->tasks[l];
+      cofem_status rc = run_estep(c, t, alpha);
+      if (rc != COFEM_OK) return rc;
+      // mu_l and s_l only; the joint M-step follows
+      launch_mstep(solve_cfg(c), estep_key(c, t), p.D, c->Dp, c->X, c->mu, c->s, nullptr, p.alpha_floor, 0, c->st,
+                   c->stream);
+    }
+    if (t < p.T) launch_mt_mstep(m->d_mus, m->d_ss, L, p.D, alpha, p.alpha_floor, &c0->st->clamped, c0->stream);
+  }
+  cofem_status worst = COFEM_OK;
+  for (int l = 0; l < L; ++l) {
+    cofem_status rc = end_fit(m->tasks[l], t0);
+    if (rc == COFEM_EBREAKDOWN) worst = rc;
+    else if (rc != COFEM_OK) return rc;
+  }
+  m->fitted = true;
+  return worst;
+}
+
+COFEM_API cofem_status cofem_mt_posterior(cofem_mt* m, int32_t task, float* mu, float* s, float* alpha,
+                                          cofem_stats* st) {
+  if (!m || task < 0 || task >= (int32_t)m->tasks.size()) return fail(COFEM_EINVAL, "bad task");
+  if (!m->fitted) return fail(COFEM_ESTATE, "cofem_mt_posterior before a successful cofem_mt_fit");
+  cofem_ctx* c = m->tasks[task];
+  cofem_status rc = cofem_posterior(c, mu, s, nullptr, st);
+  if (rc != COFEM_OK) return rc;
+  if (alpha) {
+    cofem_ctx* c0 = m->tasks[0];
+    HIP_TRY(hipMemcpyAsync(alpha, c0->alpha, (size_t)c0->p.D * sizeof(float), hipMemcpyDeviceToDevice, c0->stream));
+    HIP_TRY(hipStreamSynchronize(c0->stream));
+  }
+  return COFEM_OK;
+}
+

@@ -113,6 +113,10 @@ void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
                          uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s);
 
+// Multi-task M-step over L tasks' mu and s (device arrays of L device pointers).
+void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int64_t D, float* alpha, double floor,
+                     int* clamped, hipStream_t s);
+
 // ---- test-hook helpers ---------------------------------------------------------
 // Copy ncols columns of length D (caller layout) into a Qp x Dp block (zero padding),
 // optionally also as bf16 hi/lo.

@@ -199,6 +199,30 @@ __global__ __launch_bounds__(VBLOCK) void k_reduce_pi(int Q, int nbx, const doub
   }
 }
 
+// Multi-task M-step (Sec. III-E.1): alpha_j = 1 / max(sum_l (mu_lj^2 + s_lj) / L, floor),
+// summed over the tasks in order; floor events are counted into *clamped.
+__global__ __launch_bounds__(VBLOCK) void k_mt_mstep(const float* const* __restrict__ mus,
+                                                     const float* const* __restrict__ ss, int L, int64_t D,
+                                                     float* __restrict__ alpha, double floor, int* __restrict__ clamped) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int low = 0;
+  if (j < D) {
+    double acc = 0.0;
+    for (int l = 0; l < L; ++l) {
+      const double m = (double)mus[l][j];
+      acc += m * m + (double)ss[l][j];
+    }
+    double den = acc / (double)L;
+    if (den < floor) {
+      den = floor;
+      low = 1;
+    }
+    alpha[j] = (float)(1.0 / den);
+  }
+  low = wave_sum_int(low);
+  if ((threadIdx.x & 63) == 0 && low) atomicAdd(clamped, low);
+}
+
 // ---------------------------------------------------------------------------
 // test-hook helpers
 // ---------------------------------------------------------------------------
@@ -403,6 +427,11 @@ void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const
                          uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_direction, dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd,
                      PdH, PdL, st);
+}
+
+void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int64_t D, float* alpha, double floor,
+                     int* clamped, hipStream_t s) {
+  hipLaunchKernelGGL(k_mt_mstep, dim3(cdiv(D, VBLOCK)), dim3(VBLOCK), 0, s, mus, ss, L, D, alpha, floor, clamped);
 }
 
 void launch_pack_block(const float* src, int ncols, int64_t D, int Qp, int64_t Dp, float* dst, uint16_t* dH,

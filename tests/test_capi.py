@@ -66,7 +66,8 @@ def test_struct_layout_matches_c(cls, cname):
 @pytest.mark.parametrize("bad", [
     dict(N=0), dict(D=0), dict(beta=0.0), dict(beta=float("nan")), dict(K=0), dict(K=64), dict(T=0),
     dict(T=513), dict(U=0), dict(tol=-1.0), dict(theta_mode=7), dict(stop_mode=3), dict(phi_dtype=2),
-    dict(refine_last=9), dict(alpha_floor=0.0), dict(op_kind=5),
+    dict(refine_last=9), dict(alpha_floor=0.0), dict(op_kind=5), dict(mstep_mode=2),
+    dict(op_kind=1, conv_taps=0), dict(op_kind=1, conv_taps=257), dict(op_kind=1, N=100, D=200),
 ])
 def test_create_rejects_bad_params_without_device_work(bad):
     so = lib.load()
@@ -75,6 +76,18 @@ def test_create_rejects_bad_params_without_device_work(bad):
         setattr(p, k, v)
     h = ctypes.c_void_p()
     rc = so.cofem_create(ctypes.byref(p), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert so.cofem_last_error().decode()
+
+
+@pytest.mark.parametrize("L,bad", [(0, {}), (65, {}), (2, dict(mstep_mode=1)), (2, dict(K=0))])
+def test_multitask_create_rejects_bad_arguments_without_device_work(L, bad):
+    so = lib.load()
+    p = lib.make_params(N=64, D=256, beta=1e4, K=8, T=5, U=10, tol=1e-6)
+    for k, v in bad.items():
+        setattr(p, k, v)
+    h = ctypes.c_void_p()
+    rc = so.cofem_mt_create(ctypes.byref(p), L, None, ctypes.byref(h))
     assert rc == -1 and not h.value
     assert so.cofem_last_error().decode()
 

@@ -1,0 +1,79 @@
+"""GPU parity of multi-task CoFEM (Sec. III-E.1, cofem_mt_*): L problems sharing one
+alpha, each task's E-step covariance-free with its own dictionary and probes (seed + l),
+the joint M-step alpha_j = L / sum_l (mu_lj^2 + s_lj), against the oracle's
+`cofem_multitask` at the same probes, stop rule and tolerance (FP32 bar as for single
+fits: mu within 1e-4, s within 1e-3, alpha on the support within 1e-3 in log)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("L", [1, 3])
+def test_multitask_matches_oracle(gpu, L):
+    probs = workloads.multitask_problems(L, N=120, D=400, d=12, sigma=0.01, seed=61)
+    K, T, U, tol, seed = 8, 30, 300, 1e-6, 21
+    m = gpu.MultiTask(L, 120, 400, probs[0].beta, K=K, T=T, U=U, tol=tol, seed=seed)
+    for l, p in enumerate(probs):
+        m.set_dictionary(l, _t(p.phi))
+    m.fit([_t(p.y) for p in probs])
+    out = [m.posterior(l) for l in range(L)]
+    m.close()
+    a_ref, mus_ref, ss_ref, steps_ref = oracle.cofem_multitask([p.phi for p in probs], [p.y for p in probs],
+                                                               probs[0].beta, T=T, K=K, U=U, tol=tol, seed=seed)
+    alpha = _np(out[0][2])
+    sup = np.abs(mus_ref[0]) > 1e-3 * np.abs(mus_ref[0]).max()
+    for l in range(L):
+        mu, s, a, st = out[l]
+        e_mu, e_s = _rel(_np(mu), mus_ref[l]), _rel(_np(s), ss_ref[l])
+        print(f"L={L} task {l}: mu rel {e_mu:.2e}, s rel {e_s:.2e}, CG steps {st['total_cg_steps']} "
+              f"(oracle {sum(r[l] for r in steps_ref)})")
+        assert e_mu <= 1e-4
+        assert e_s <= 1e-3
+        assert np.array_equal(_np(a), alpha)        # every task reports the shared alpha
+    assert np.max(np.abs(np.log(alpha[sup] / a_ref[sup]))) < 1e-3
+    if L == 1:
+        # one task is plain CoFEM
+        ref1 = oracle.cofem(probs[0].phi, probs[0].y, probs[0].beta, T=T, K=K, U=U, tol=tol, seed=seed)
+        assert _rel(_np(out[0][0]), ref1.mu) <= 1e-4
+
+
+def test_multitask_shares_support_better_than_single_tasks(gpu):
+    """The point of sharing alpha: with few measurements per task, the joint fit recovers
+    the common support better than the tasks fitted one by one."""
+    L, N, D, d = 4, 60, 400, 20
+    probs = workloads.multitask_problems(L, N=N, D=D, d=d, sigma=0.01, seed=62)
+    kw = dict(K=8, T=30, U=300, tol=1e-5, seed=3)
+    m = gpu.MultiTask(L, N, D, probs[0].beta, **kw)
+    for l, p in enumerate(probs):
+        m.set_dictionary(l, _t(p.phi))
+    m.fit([_t(p.y) for p in probs])
+    joint = [_np(m.posterior(l)[0]) for l in range(L)]
+    m.close()
+    single = []
+    for p in probs:
+        c = gpu.CoFEM(N, D, p.beta, **kw)
+        c.set_dictionary(_t(p.phi))
+        c.fit(_t(p.y))
+        single.append(_np(c.posterior()[0]))
+        c.close()
+    err = lambda mus: np.mean([np.linalg.norm(mu - p.z) / np.linalg.norm(p.z) for mu, p in zip(mus, probs)])
+    print(f"NRMSE joint {err(joint):.3f}, single {err(single):.3f}")
+    assert err(joint) < err(single)

@@ -144,6 +144,22 @@ def dense_problem(N: int, D: int, d: int, sigma: float, seed: int, name: str = "
                    meta={"d": int(d), "seed": int(seed), "law": law})
 
 
+def multitask_problems(L: int, N: int, D: int, d: int, sigma: float, seed: int) -> list:
+    """L dense problems whose codes share one support of d positions (Sec. III-E.1's
+    setting): task l has its own dictionary and values, drawn with seed * 1009 + l."""
+    pos = _stream(seed, 0x3A5C).choice(int(D), size=int(d), replace=False)
+    out = []
+    for l in range(int(L)):
+        s = int(seed) * 1009 + l
+        phi = gaussian_dictionary(N, D, s)
+        z = np.zeros(int(D), dtype=np.float64)
+        z[pos] = _stream(s, 0x5A11).standard_normal(int(d))
+        y = dense_observation(phi, z, sigma, s)
+        out.append(Problem(name=f"task{l}", N=N, D=D, beta=1.0 / sigma ** 2, sigma=sigma, y=y, z=z, phi=phi,
+                           meta={"d": int(d), "seed": s, "law": "normal", "shared_support": True}))
+    return out
+
+
 def conv_problem(D: int, taps: int, tau: float, p_spike: float, sigma: float, seed: int,
                  name: str = "conv") -> Problem:
     h = exp_filter(taps, tau)
