@@ -19,6 +19,8 @@ from .cofem import (  # noqa: F401
     hadamard_probes,
     DenseOperator,
     ConvOperator,
+    DctOperator,
+    dct_matrix,
     PCGResult,
     pcg,
     diag_estimate,

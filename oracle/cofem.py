@@ -18,7 +18,9 @@ Contents, each restating one passage of the paper (Lin, Song, Bilgic, Ba,
   (mstep), used as the reference that CoFEM approximates;
 * `log_evidence`, `woodbury_sigma`: the objective of Eq. (mle2) and the
   Woodbury form of Eq. (woodbury), used only to pin `exact_em`;
-* `cofem_multitask`, `nonneg_second_moment`: the extensions of Sec. III-E.
+* `cofem_multitask`, `nonneg_second_moment`: the extensions of Sec. III-E;
+* `DenseOperator`, `ConvOperator`, `DctOperator` (with `dct_matrix`): the three
+  dictionaries of Sec. V-A.
 
 Parity status: every function here is pinned by a test against something
 other than itself (closed forms, exact EM, library solvers, invariants,
@@ -196,6 +198,64 @@ class ConvOperator:
         return out
 
 
+def dct_matrix(D: int) -> np.ndarray:
+    """The orthonormal DCT-II matrix Omega of size D, entry by entry from its
+    definition: Omega_kn = s_k cos(pi (2n + 1) k / (2D)), s_0 = sqrt(1/D) and
+    s_k = sqrt(2/D) for k >= 1 (rows are frequencies, columns are samples)."""
+    k = np.arange(D, dtype=np.float64)[:, None]
+    n = np.arange(D, dtype=np.float64)[None, :]
+    s = np.full((D, 1), np.sqrt(2.0 / D))
+    s[0, 0] = np.sqrt(1.0 / D)
+    return s * np.cos(np.pi * (2.0 * n + 1.0) * k / (2.0 * D))
+
+
+class DctOperator:
+    """Subsampled DCT dictionary of Sec. V-A.1: Phi = M Omega^{-1}.
+
+    Omega is the orthonormal 1-D DCT-II of size D (so Omega^{-1} = Omega^T, the
+    DCT-III), and M keeps the N samples listed in `rows` (distinct indices in
+    [0, D), in the order of the entries of y).  Phi v is the inverse DCT of v read
+    at those samples; Phi^T u scatters u into a zero signal of length D and takes
+    its DCT.  Both use scipy's orthonormal type-II DCT as the library step.
+    """
+
+    def __init__(self, D: int, rows):
+        import scipy.fft  # local: only the DCT dictionary needs it
+
+        self._fft = scipy.fft
+        self.D = int(D)
+        self.rows = np.asarray(rows, dtype=np.int64).reshape(-1)
+        self.N = int(self.rows.shape[0])
+        if self.N < 1 or self.rows.min() < 0 or self.rows.max() >= self.D:
+            raise ValueError("rows must be indices in [0, D)")
+        if np.unique(self.rows).shape[0] != self.N:
+            raise ValueError("rows must be distinct")
+
+    def matvec(self, V: np.ndarray) -> np.ndarray:
+        V = np.asarray(V, dtype=np.float64)
+        return self._fft.idct(V, type=2, norm="ortho", axis=0)[self.rows]
+
+    def rmatvec(self, Uu: np.ndarray) -> np.ndarray:
+        Uu = np.asarray(Uu, dtype=np.float64)
+        full = np.zeros((self.D,) + Uu.shape[1:])
+        full[self.rows] = Uu
+        return self._fft.dct(full, type=2, norm="ortho", axis=0)
+
+    def col_sq_norms(self) -> np.ndarray:
+        """theta_j = sum_i Omega_{j, rows_i}^2, summed over the kept samples in row blocks."""
+        out = np.empty(self.D)
+        n = self.rows.astype(np.float64)[None, :]
+        for j0 in range(0, self.D, 256):
+            k = np.arange(j0, min(j0 + 256, self.D), dtype=np.float64)[:, None]
+            c = np.cos(np.pi * (2.0 * n + 1.0) * k / (2.0 * self.D))
+            sk2 = np.where(k[:, 0] == 0, 1.0 / self.D, 2.0 / self.D)
+            out[j0:j0 + k.shape[0]] = sk2 * np.sum(c * c, axis=1)
+        return out
+
+    def dense(self) -> np.ndarray:
+        return dct_matrix(self.D)[:, self.rows].T
+
+
 # ---------------------------------------------------------------------------
 # Algorithm 2: parallel (multi-RHS) preconditioned conjugate gradient.
 # ---------------------------------------------------------------------------
@@ -326,7 +386,7 @@ class CoFEMResult:
 
 
 def _as_operator(op):
-    if isinstance(op, (DenseOperator, ConvOperator)):
+    if isinstance(op, (DenseOperator, ConvOperator, DctOperator)):
         return op
     return DenseOperator(op)
 

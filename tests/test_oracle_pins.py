@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import (ConvOperator, DenseOperator, cofem, cofem_multitask, diag_estimate,
+from oracle import (ConvOperator, DctOperator, DenseOperator, cofem, cofem_multitask, dct_matrix, diag_estimate,
                     diag_estimate_general, exact_em, hadamard_probes, log_evidence,
                     nonneg_second_moment, pcg, probe_words, rademacher_probes,
                     splitmix64_outputs, woodbury_sigma)
@@ -404,6 +404,72 @@ def test_conv_normal_rows_match_explicit_matrix(D, L):
     rows = [0, 1, D // 2, D - 2, D - 1]
     got = ConvOperator(h, D).normal_rows(P, alpha, beta, rows)
     assert np.allclose(got, full[rows], atol=1e-12)
+
+
+def _dct_by_cosine_sums(D):
+    """Omega_kn = s_k cos(pi (2n+1) k / 2D), one math.cos per entry."""
+    Om = np.zeros((D, D))
+    for k in range(D):
+        sk = math.sqrt((1.0 if k == 0 else 2.0) / D)
+        for n in range(D):
+            Om[k, n] = sk * math.cos(math.pi * (2 * n + 1) * k / (2 * D))
+    return Om
+
+
+@pytest.mark.parametrize("D,N", [(16, 5), (24, 24), (64, 21)])
+def test_dct_operator_matches_cosine_definition(D, N):
+    """Phi = M Omega^{-1} (Sec. V-A.1): the library-DCT matvec / rmatvec, the column
+    norms and the explicit matrix against the DCT-II written as cosine sums."""
+    rng = np.random.default_rng(D + N)
+    rows = rng.permutation(D)[:N]
+    Om = _dct_by_cosine_sums(D)
+    Phi = Om.T[rows]                                    # rows of Omega^{-1} = Omega^T
+    op = DctOperator(D, rows)
+    V = rng.standard_normal((D, 3))
+    Uu = rng.standard_normal((N, 3))
+    assert np.allclose(op.matvec(V), Phi @ V, atol=1e-12)
+    assert np.allclose(op.rmatvec(Uu), Phi.T @ Uu, atol=1e-12)
+    assert np.allclose(op.col_sq_norms(), np.sum(Phi ** 2, axis=0), atol=1e-12)
+    assert np.allclose(op.dense(), Phi, atol=1e-12)
+    assert np.allclose(dct_matrix(D), Om, atol=1e-12)
+
+
+def test_dct_orthonormality_and_cosine_closed_form():
+    """Omega is orthogonal, so Phi Phi^T = I_N for distinct samples; and the DCT of the
+    sampled cosine x_n = cos(pi (2n+1) k0 / 2D) is s_k0 D / 2 at k0 (D s_0 at k0 = 0)."""
+    D = 48
+    Om = dct_matrix(D)
+    assert np.allclose(Om @ Om.T, np.eye(D), atol=1e-12)
+    rng = np.random.default_rng(3)
+    rows = rng.permutation(D)[:16]
+    Phi = DctOperator(D, rows).dense()
+    assert np.allclose(Phi @ Phi.T, np.eye(16), atol=1e-12)
+    full = DctOperator(D, np.arange(D))
+    n = np.arange(D)
+    for k0 in (0, 1, 7, D - 1):
+        x = np.cos(np.pi * (2 * n + 1) * k0 / (2 * D))
+        want = np.zeros(D)
+        want[k0] = math.sqrt(D) if k0 == 0 else math.sqrt(2.0 / D) * D / 2
+        assert np.allclose(full.rmatvec(x), want, atol=1e-12)
+        assert np.allclose(full.matvec(want), x, atol=1e-12)
+
+
+def test_cofem_dct_hadamard_probes_reproduce_exact_em():
+    """On the DCT dictionary with N = D/3 samples, K = D Hadamard probes make CoFEM's
+    E-step exact, so it follows covariance-based EM on the explicit matrix."""
+    D, N, beta = 32, 10, 1e4
+    rng = np.random.default_rng(29)
+    op = DctOperator(D, np.sort(rng.permutation(D)[:N]))
+    z = np.zeros(D)
+    z[rng.permutation(D)[:3]] = rng.normal(0.0, math.sqrt(5.0), 3)
+    y = op.matvec(z) + 0.01 * rng.standard_normal(N)
+    H = hadamard_probes(D)
+    r = cofem(op, y, beta, T=12, K=D, U=400, tol=1e-13, probes=lambda t: H, record=True)
+    a_em, mu_em, dS_em, alphas_em = exact_em(op.dense(), y, beta, T=12, record=True)
+    for a, b in zip(r.alphas, alphas_em):
+        assert np.allclose(a, b, rtol=1e-6)
+    assert np.linalg.norm(r.mu - mu_em) <= 1e-8 * np.linalg.norm(mu_em)
+    assert np.allclose(r.s, dS_em, rtol=1e-6)
 
 
 def test_nonneg_second_moment_matches_truncated_gaussian_integral():

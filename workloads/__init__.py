@@ -62,13 +62,16 @@ def gaussian_dictionary(N: int, D: int, seed: int) -> np.ndarray:
 def sparse_code(D: int, d: int, seed: int, law: str = "normal") -> np.ndarray:
     """Ground-truth code z in R^D with d nonzeros at uniformly random positions.
 
-    law = "normal": values N(0, 1); "exp1": values Exp(1) (non-negative spikes).
+    law = "normal": values N(0, 1); "normal5": values N(0, 5), read as variance 5 (the
+    DCT setting of Sec. V-A.2); "exp1": values Exp(1) (non-negative spikes).
     """
     rng = _stream(seed, 0x5A11)
     z = np.zeros(int(D), dtype=np.float64)
     pos = rng.choice(int(D), size=int(d), replace=False)
     if law == "normal":
         z[pos] = rng.standard_normal(int(d))
+    elif law == "normal5":
+        z[pos] = math.sqrt(5.0) * rng.standard_normal(int(d))
     elif law == "exp1":
         z[pos] = rng.exponential(1.0, int(d))
     else:
@@ -120,6 +123,24 @@ def conv_observation(h: np.ndarray, z: np.ndarray, sigma: float, seed: int) -> n
     return y.astype(np.float32)
 
 
+def dct_rows(D: int, N: int, seed: int) -> np.ndarray:
+    """The N of D sample positions kept by the undersampling operator M of the DCT
+    dictionary (Sec. V-A.2): distinct, uniformly random, sorted, int32."""
+    rng = _stream(seed, 0xDC7)
+    return np.sort(rng.choice(int(D), size=int(N), replace=False)).astype(np.int32)
+
+
+def dct_observation(rows: np.ndarray, z: np.ndarray, sigma: float, seed: int) -> np.ndarray:
+    """y = M Omega^{-1} z + sigma * N(0, I) with Omega the orthonormal DCT-II of size D
+    (inverse DCT by scipy in float64, then the kept samples), rounded to float32."""
+    import scipy.fft
+
+    x = scipy.fft.idct(np.asarray(z, dtype=np.float64), type=2, norm="ortho")
+    y = x[np.asarray(rows, dtype=np.int64)]
+    y += float(sigma) * _stream(seed, 0x0B5E).standard_normal(y.shape[0])
+    return y.astype(np.float32)
+
+
 @dataclass
 class Problem:
     """One sparse-coding problem y = Phi z + eps with its generation recipe."""
@@ -132,6 +153,7 @@ class Problem:
     z: np.ndarray
     phi: np.ndarray | None = None     # dense dictionary (N x D float32), or None
     h: np.ndarray | None = None       # FIR taps for a convolutional dictionary
+    rows: np.ndarray | None = None    # kept sample positions of a subsampled DCT dictionary
     meta: dict = field(default_factory=dict)
 
 
@@ -169,18 +191,32 @@ def conv_problem(D: int, taps: int, tau: float, p_spike: float, sigma: float, se
                    meta={"taps": int(taps), "tau": float(tau), "p": float(p_spike), "seed": int(seed)})
 
 
+def dct_problem(D: int, N: int, d: int, sigma: float, seed: int, name: str = "dct") -> Problem:
+    """Subsampled DCT dictionary Phi = M Omega^{-1} with N of D samples kept, d spikes
+    N(0, 5) at uniformly random positions, noise std sigma."""
+    rows = dct_rows(D, N, seed)
+    z = sparse_code(D, d, seed, "normal5")
+    y = dct_observation(rows, z, sigma, seed)
+    return Problem(name=name, N=int(N), D=int(D), beta=1.0 / sigma ** 2, sigma=sigma, y=y, z=z, rows=rows,
+                   meta={"d": int(d), "seed": int(seed), "law": "normal5"})
+
+
 # ---------------------------------------------------------------------------
 # Named workloads.  "small": N=64, D=256, 10 spikes, sigma=0.01, K=8, T=50,
 # tol=1e-6, U=256.  "medium": N=2048, D=8192, 5% spikes, K=20, T=50, tol=1e-5,
 # U=400.  "large": N=16384, D=65536, 2% spikes, K=32, T=30, tol=1e-5, U=400.
 # "conv": D=2^20 causal FIR with 256 taps of exp(-t/50), Bernoulli(0.01)*Exp(1)
-# spikes, sigma=0.05, K=20, T=30.
+# spikes, sigma=0.05, K=20, T=30.  "dct": the DCT scalability setting of Sec. V-C at
+# its largest size, D=2^15, N=floor(D/3), d=floor(0.12 D) spikes N(0, 5), sigma=0.01,
+# K=20, T=30, U=400, tol=1e-4.
 # ---------------------------------------------------------------------------
 WORKLOADS = {
     "small": dict(N=64, D=256, d=10, sigma=0.01, K=8, T=50, tol=1e-6, U=256, seed=1001),
     "medium": dict(N=2048, D=8192, d=409, sigma=0.01, K=20, T=50, tol=1e-5, U=400, seed=1002),
     "large": dict(N=16384, D=65536, d=1310, sigma=0.01, K=32, T=30, tol=1e-5, U=400, seed=1003),
     "conv": dict(D=1 << 20, taps=256, tau=50.0, p=0.01, sigma=0.05, K=20, T=30, tol=1e-5, U=400, seed=1005),
+    "dct": dict(D=1 << 15, N=(1 << 15) // 3, d=int(0.12 * (1 << 15)), sigma=0.01, K=20, T=30, tol=1e-4, U=400,
+                seed=1006, dictionary="dct"),
 }
 
 
@@ -189,6 +225,8 @@ def make_workload(name: str, **override) -> Problem:
     w.update(override)
     if name == "conv" or "taps" in w:
         return conv_problem(w["D"], w["taps"], w["tau"], w["p"], w["sigma"], w["seed"], name=name)
+    if w.get("dictionary") == "dct":
+        return dct_problem(w["D"], w["N"], w["d"], w["sigma"], w["seed"], name=name)
     return dense_problem(w["N"], w["D"], w["d"], w["sigma"], w["seed"], name=name)
 
 
