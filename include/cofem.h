@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define COFEM_ABI_VERSION 2
+#define COFEM_ABI_VERSION 3
 #define COFEM_MAX_T 512 /* longest EM run recorded in cofem_stats */
 #define COFEM_MAX_K 63  /* probes per EM iteration (one 64-bit hash word per coordinate) */
 
@@ -58,13 +58,14 @@ typedef enum {
 
 typedef enum { COFEM_THETA_ONES = 0, COFEM_THETA_JACOBI = 1 } cofem_theta_mode;
 typedef enum { COFEM_STOP_JOINT = 0, COFEM_STOP_COLUMN = 1 } cofem_stop_mode;
-typedef enum { COFEM_OP_DENSE = 0, COFEM_OP_CONV = 1 } cofem_op_kind;
+typedef enum { COFEM_OP_DENSE = 0, COFEM_OP_CONV = 1, COFEM_OP_DCT = 2 } cofem_op_kind;
 typedef enum { COFEM_PHI_FP32 = 0, COFEM_PHI_BF16 = 1 } cofem_phi_dtype;
 typedef enum { COFEM_MSTEP_GAUSSIAN = 0, COFEM_MSTEP_NONNEG = 1 } cofem_mstep_mode;
 
 /*
  * Fit parameters.  Names follow Algorithms 1 and 2.
- *   N, D        sizes of y and z (Eq. sparse-coding); for COFEM_OP_CONV N must equal D.
+ *   N, D        sizes of y and z (Eq. sparse-coding); for COFEM_OP_CONV N must equal D;
+ *               for COFEM_OP_DCT D is a power of two in [16, 32768] and N <= D.
  *   beta        noise precision, > 0 (Eq. model).
  *   K           Rademacher probes per EM iteration, 1..COFEM_MAX_K (Alg. 1).
  *   T           EM iterations, 1..COFEM_MAX_T (Alg. 1); T E-steps and T-1 M-steps.
@@ -76,7 +77,9 @@ typedef enum { COFEM_MSTEP_GAUSSIAN = 0, COFEM_MSTEP_NONNEG = 1 } cofem_mstep_mo
  *               test); COFEM_STOP_COLUMN: freeze column q once ||R_q||/||B_q|| <= tol.
  *   op_kind     COFEM_OP_DENSE: Phi is a dense N x D matrix.  COFEM_OP_CONV: Phi is
  *               the D x D causal convolution Phi_ij = h[i - j], 0 <= i - j < conv_taps
- *               (the convolutional dictionary of Sec. V-A.2).
+ *               (the convolutional dictionary of Sec. V-A.2).  COFEM_OP_DCT: Phi =
+ *               M Omega^{-1}, Omega the orthonormal DCT-II of size D and M keeping N
+ *               of the D samples (the DCT dictionary of Sec. V-A.2); FP32 only.
  *   phi_dtype   arithmetic of the operator: COFEM_PHI_FP32, or COFEM_PHI_BF16 (Phi
  *               rounded to bfloat16 once, products accumulated in FP32).
  *   refine_last with COFEM_PHI_BF16: the last refine_last E-steps use the FP32 operator.
@@ -146,9 +149,20 @@ void cofem_destroy(cofem_ctx* c);
  * for COFEM_OP_CONV it is the conv_taps FIR taps h[0..taps-1].  The library copies
  * it into its own layouts (row-major and transposed, FP32 and/or bfloat16, padded)
  * and computes theta (Sec. III-C); `phi` may be freed when the call returns.
- * Errors: COFEM_EINVAL (NULL), COFEM_EDEVICE.
+ * Errors: COFEM_EINVAL (NULL, or a COFEM_OP_DCT context), COFEM_EDEVICE.
  */
 cofem_status cofem_set_dictionary(cofem_ctx* c, const float* phi);
+
+/*
+ * Load a COFEM_OP_DCT dictionary Phi = M Omega^{-1} (Sec. V-A.2): `rows` holds N
+ * int32 sample indices on the device, distinct and in [0, D); entry i of y is
+ * sample rows[i] of the inverse DCT of z.  The library copies them, builds its
+ * transform tables and the sample mask, and computes theta (Jacobi: theta_j =
+ * sum_i Omega_{j, rows_i}^2); `rows` may be freed when the call returns.
+ * Errors: COFEM_EINVAL (NULL, not a DCT context, an index out of range or
+ * repeated), COFEM_EDEVICE.
+ */
+cofem_status cofem_set_dct_samples(cofem_ctx* c, const int32_t* rows);
 
 /*
  * Run Algorithm 1 on observation y (N floats, device) with the loaded dictionary.

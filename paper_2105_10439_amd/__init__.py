@@ -19,14 +19,15 @@ STATUS = {0: "COFEM_OK", -1: "COFEM_EINVAL", -2: "COFEM_ENOMEM", -3: "COFEM_EDEV
           -5: "COFEM_EBREAKDOWN", -6: "COFEM_EBUDGET"}
 THETA = {"ones": 0, "jacobi": 1}
 STOP = {"joint": 0, "column": 1}
-OPS = {"dense": 0, "conv": 1}
+OPS = {"dense": 0, "conv": 1, "dct": 2}
 DTYPES = {"fp32": 0, "bf16": 1}
 MSTEP = {"gaussian": 0, "nonneg": 1}
-ABI_VERSION = 2  # COFEM_ABI_VERSION of include/cofem.h
+ABI_VERSION = 3  # COFEM_ABI_VERSION of include/cofem.h
 
 # every symbol include/cofem.h declares
 EXPORTS = [
     "cofem_abi_version", "cofem_last_error", "cofem_create", "cofem_destroy", "cofem_set_dictionary",
+    "cofem_set_dct_samples",
     "cofem_fit", "cofem_posterior", "cofem_apply_A", "cofem_set_timing", "cofem_get_timing",
     "cofem_server_create", "cofem_server_destroy", "cofem_server_submit", "cofem_server_step",
     "cofem_server_poll", "cofem_server_get_stats",
@@ -108,6 +109,7 @@ def load() -> ctypes.CDLL:
         "cofem_create": (i32, [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]),
         "cofem_destroy": (None, [vp]),
         "cofem_set_dictionary": (i32, [vp, vp]),
+        "cofem_set_dct_samples": (i32, [vp, vp]),
         "cofem_fit": (i32, [vp, vp]),
         "cofem_posterior": (i32, [vp, vp, vp, vp, ctypes.POINTER(Stats)]),
         "cofem_apply_A": (i32, [vp, vp, vp, vp, i32, i32, vp]),
@@ -187,6 +189,15 @@ class CoFEM:
         return ctypes.c_void_p(t.data_ptr())
 
     def set_dictionary(self, phi):
+        """Dense: the N x D matrix; conv: the taps; DCT: the N kept sample indices (int32)."""
+        import torch
+
+        if self.params.op_kind == OPS["dct"]:
+            if not (isinstance(phi, torch.Tensor) and phi.is_cuda and phi.dtype == torch.int32
+                    and phi.is_contiguous() and phi.numel() == self.N):
+                raise TypeError(f"rows must be a contiguous int32 CUDA tensor of {self.N} sample indices")
+            _check(load().cofem_set_dct_samples(self._h, ctypes.c_void_p(phi.data_ptr())))
+            return
         n = self.N * self.D if self.params.op_kind == 0 else self.params.conv_taps
         _check(load().cofem_set_dictionary(self._h, self._dev(phi, n, "phi")))
 

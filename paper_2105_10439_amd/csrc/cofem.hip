@@ -78,6 +78,10 @@ struct cofem_ctx {
   // convolutional dictionary: padded taps (FP32 and bfloat16)
   float* hp32 = nullptr;
   uint16_t* hp16 = nullptr;
+  // subsampled DCT dictionary: transform tables, mask, kept samples, scratch signal
+  float2 *dct_tw = nullptr, *dct_wq = nullptr, *dct_wh = nullptr, *dct_mz = nullptr;
+  int32_t* dct_rows = nullptr;
+  float* dct_u = nullptr;
   // D- and N-vectors
   float *theta = nullptr, *alpha = nullptr, *alpha_hook = nullptr, *b32 = nullptr, *b16 = nullptr;
   float* minv = nullptr;
@@ -155,6 +159,12 @@ cofem_status validate(const cofem_params* p) {
     if (p->N != p->D) return fail(COFEM_EINVAL, "COFEM_OP_CONV needs N == D");
     if (p->conv_taps < 1 || p->conv_taps > CONV_MAX_TAPS)
       return fail(COFEM_EINVAL, "conv_taps must be in [1, " + std::to_string(CONV_MAX_TAPS) + "]");
+  } else if (p->op_kind == COFEM_OP_DCT) {
+    if (!dct_size_ok(p->D))
+      return fail(COFEM_EINVAL, "COFEM_OP_DCT needs D a power of two in [" + std::to_string(DCT_MIN_D) + ", " +
+                                    std::to_string(DCT_MAX_D) + "]");
+    if (p->N > p->D) return fail(COFEM_EINVAL, "COFEM_OP_DCT needs N <= D");
+    if (p->phi_dtype != COFEM_PHI_FP32) return fail(COFEM_EINVAL, "COFEM_OP_DCT runs in FP32 (phi_dtype)");
   } else if (p->op_kind != COFEM_OP_DENSE) {
     return fail(COFEM_EINVAL, "bad op_kind");
   }
@@ -216,6 +226,37 @@ cofem_status harvest(cofem_ctx* c, int real_steps) {
 
 // Psi = A Pd into c->Psi and pi into the state, for the given alpha buffer.
 // The two filter passes of the convolutional dictionary (pass 2 fuses the finish).
+DctArgs dct_args(const cofem_ctx* c) {
+  DctArgs a{};
+  a.D = c->p.D;
+  a.Dp = c->Dp;
+  a.nbx = (int)((c->Dp + 1023) / 1024);
+  a.s0 = (float)std::sqrt(1.0 / (double)c->p.D);
+  a.s1 = (float)std::sqrt(2.0 / (double)c->p.D);
+  a.tw = c->dct_tw;
+  a.wq = c->dct_wq;
+  a.wh = c->dct_wh;
+  a.mz = c->dct_mz;
+  a.beta = c->p.beta;
+  return a;
+}
+
+// The DCT operator: one launch, one workgroup per column (the transforms in LDS).
+cofem_status apply_dct(cofem_ctx* c, const float* alpha, const SolveCfg& sc, int step) {
+  DctArgs a = dct_args(c);
+  a.in = c->Pd;
+  a.out = c->Psi;
+  a.alpha = alpha;
+  a.pipart = c->pipart;
+  a.done = &c->st->done;
+  TimedLaunch t;
+  cofem_status rc;
+  if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
+  launch_dct_operator(a, sc.Q, c->stream);
+  if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
+  return COFEM_OK;
+}
+
 cofem_status apply_conv(cofem_ctx* c, bool use16, const float* alpha, const SolveCfg& sc, int step) {
   ConvArgs a{};
   a.hp32 = c->hp32;
@@ -259,6 +300,7 @@ cofem_status apply_conv(cofem_ctx* c, bool use16, const float* alpha, const Solv
 
 cofem_status apply_operator(cofem_ctx* c, bool use16, const float* alpha, const SolveCfg& sc, int step) {
   if (c->p.op_kind == COFEM_OP_CONV) return apply_conv(c, use16, alpha, sc, step);
+  if (c->p.op_kind == COFEM_OP_DCT) return apply_dct(c, alpha, sc, step);
   TimedLaunch t;
   cofem_status rc;
   if (use16) {
@@ -304,7 +346,11 @@ void begin_fit(cofem_ctx* c, const float* y) {
   // b = beta Phi^T y, formed with the same dictionary as the operator of each phase: the
   // rounding residual of an FP32 b is not in the range of the bf16 Phi^T, and EM would
   // amplify it through the directions that only diag(alpha) constrains.
-  if (p.op_kind == COFEM_OP_CONV) {
+  if (p.op_kind == COFEM_OP_DCT) {
+    DctArgs a = dct_args(c);
+    a.out = c->b32;
+    launch_dct_rhs(a, c->yv, c->dct_rows, p.N, c->dct_u, c->stream);
+  } else if (p.op_kind == COFEM_OP_CONV) {
     if (c->need32) launch_conv_rhs(c->hp32, nullptr, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b32, c->stream);
     if (c->need16) launch_conv_rhs(c->hp32, c->hp16, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b16, c->stream);
   } else {
@@ -382,6 +428,8 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
     return fail(COFEM_EDEVICE, "hipGetDevice failed");
   }
   const bool conv = p->op_kind == COFEM_OP_CONV;
+  const bool dct = p->op_kind == COFEM_OP_DCT;
+  const bool matrix_free = conv || dct;
   c->Np = round_up(p->N, 256);
   c->Dp = round_up(p->D, 256);
   c->Q = p->K + 1;
@@ -393,10 +441,10 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   c->g1_32 = choose_gemm(c->Np, c->Dp, 0);
   c->g2_32 = choose_gemm(c->Dp, c->Np, 0);
   const int64_t Np = c->Np, Dp = c->Dp, Qp = c->Qp;
-  const int64_t ysplit = conv ? 0
+  const int64_t ysplit = matrix_free ? 0
                               : std::max<int64_t>(std::max<int64_t>(c->g1_16.splits, c->g1_32.splits) * Np,
                                                   std::max<int64_t>(c->g2_16.splits, c->g2_32.splits) * Dp);
-  const size_t nd = conv ? 0 : (size_t)Np * (size_t)Dp;
+  const size_t nd = matrix_free ? 0 : (size_t)Np * (size_t)Dp;
 #define TRY(x)                   \
   do {                           \
     cofem_status r_ = (x);       \
@@ -410,15 +458,24 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
     TRY(dalloc(c, &c->hp32, CONV_HPAD));
     TRY(dalloc(c, &c->hp16, CONV_HPAD));
   }
+  if (dct) {
+    const size_t L = (size_t)(p->D / 2);
+    TRY(dalloc(c, &c->dct_tw, L));
+    TRY(dalloc(c, &c->dct_wq, L + 1));
+    TRY(dalloc(c, &c->dct_wh, L + 1));
+    TRY(dalloc(c, &c->dct_mz, L));
+    TRY(dalloc(c, &c->dct_rows, (size_t)p->N));
+    TRY(dalloc(c, &c->dct_u, (size_t)Dp));
+  }
   if (c->need32) {
-    if (!conv) {
+    if (!matrix_free) {
       TRY(dalloc(c, &c->phi32, nd));
       TRY(dalloc(c, &c->phi32T, nd));
     }
-    TRY(dalloc(c, &c->V, (size_t)Qp * Np));
+    if (!dct) TRY(dalloc(c, &c->V, (size_t)Qp * Np));
   }
   if (c->need16) {
-    if (!conv) {
+    if (!matrix_free) {
       TRY(dalloc(c, &c->phi16, nd));
       TRY(dalloc(c, &c->phi16T, nd));
     }
@@ -475,6 +532,7 @@ COFEM_API void cofem_destroy(cofem_ctx* c) {
 
 COFEM_API cofem_status cofem_set_dictionary(cofem_ctx* c, const float* phi) {
   if (!c || !phi) return fail(COFEM_EINVAL, "NULL argument");
+  if (c->p.op_kind == COFEM_OP_DCT) return fail(COFEM_EINVAL, "a DCT dictionary is loaded by cofem_set_dct_samples");
   const double t0 = now_ms();
   if (c->p.op_kind == COFEM_OP_CONV) {
     launch_conv_setup(phi, c->p.conv_taps, c->p.D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->hp32, c->hp16,
@@ -488,6 +546,31 @@ COFEM_API cofem_status cofem_set_dictionary(cofem_ctx* c, const float* phi) {
   launch_dict_layouts(phi, c->p.N, c->p.D, c->Np, c->Dp, c->phi32, c->phi32T, c->phi16, c->phi16T, c->stream);
   // theta from the caller's FP32 matrix (b is formed per fit from the library's copies)
   launch_theta(phi, c->p.N, c->p.D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->theta, c->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->dict_loaded = true;
+  c->stats.ms_setup = now_ms() - t0;
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_set_dct_samples(cofem_ctx* c, const int32_t* rows) {
+  if (!c || !rows) return fail(COFEM_EINVAL, "NULL argument");
+  if (c->p.op_kind != COFEM_OP_DCT) return fail(COFEM_EINVAL, "cofem_set_dct_samples needs op_kind COFEM_OP_DCT");
+  const double t0 = now_ms();
+  const int64_t N = c->p.N, D = c->p.D;
+  // the kept samples must be distinct indices in [0, D): checked on the host
+  std::vector<int32_t> h(N);
+  HIP_TRY(hipMemcpyAsync(h.data(), rows, sizeof(int32_t) * N, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::vector<char> seen(D, 0);
+  for (int64_t i = 0; i < N; ++i) {
+    if (h[i] < 0 || h[i] >= D) return fail(COFEM_EINVAL, "sample index " + std::to_string(h[i]) + " outside [0, D)");
+    if (seen[h[i]]) return fail(COFEM_EINVAL, "sample index " + std::to_string(h[i]) + " repeated");
+    seen[h[i]] = 1;
+  }
+  HIP_TRY(hipMemcpyAsync(c->dct_rows, h.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, c->stream));
+  launch_dct_setup(c->dct_rows, N, D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->dct_tw, c->dct_wq, c->dct_wh,
+                   c->dct_mz, c->dct_u, c->theta, c->stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->dict_loaded = true;
@@ -594,6 +677,7 @@ COFEM_API cofem_status cofem_mt_create(const cofem_params* p, int32_t L, void* s
   cofem_status rc = validate(p);
   if (rc != COFEM_OK) return rc;
   if (p->mstep_mode != COFEM_MSTEP_GAUSSIAN) return fail(COFEM_EINVAL, "multi-task fits use the Gaussian M-step");
+  if (p->op_kind == COFEM_OP_DCT) return fail(COFEM_EINVAL, "multi-task fits take dense or convolutional dictionaries");
   cofem_mt* m = new (std::nothrow) cofem_mt();
   if (!m) return fail(COFEM_ENOMEM, "host allocation failed");
   std::vector<const float*> mus(L), ss(L);

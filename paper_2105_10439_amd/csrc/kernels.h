@@ -162,4 +162,34 @@ void launch_conv_rhs(const float* hp32, const uint16_t* hp16, int L, int64_t D, 
                      double beta, float* b, hipStream_t s);
 void launch_conv_pass(const ConvArgs& a, int dir, int bf16, hipStream_t s);
 
+// ---- subsampled DCT dictionary (dct.hip) ----------------------------------------
+// Phi = M Omega^{-1}: Omega the orthonormal DCT-II of size D, M keeps N samples.
+// D is a power of two in [DCT_MIN_D, DCT_MAX_D] (the L = D / 2 point complex FFT
+// of one column lives in LDS).
+constexpr int64_t DCT_MIN_D = 16;
+constexpr int64_t DCT_MAX_D = 32768;
+bool dct_size_ok(int64_t D);
+
+struct DctArgs {
+  int64_t D, Dp;
+  int nbx;                           // pi partial chunks per column, cdiv(Dp, 1024)
+  float s0, s1;                      // orthonormal scales sqrt(1/D), sqrt(2/D)
+  const float2 *tw, *wq, *wh, *mz;   // FFT twiddles, DCT phase factors, mask (dct.hip)
+  const float* in;                   // operator: Pd (Qp x Dp); forward: one signal of D samples
+  float* out;                        // operator: Psi; forward: beta Omega in
+  double beta;
+  const float* alpha;                // operator only
+  double* pipart;                    // operator only: [q][chunk]
+  const int* done;                   // operator only, may be null
+};
+// Tables (tw: D/2, wq and wh: D/2 + 1, mz: D/2 entries), the mask (mx: Dp floats of
+// scratch), and theta (Jacobi: column norms of Phi; else ones).  rows: N distinct
+// sample indices in [0, D) on the device.
+void launch_dct_setup(const int32_t* rows, int64_t N, int64_t D, int64_t Dp, int jacobi, float2* tw, float2* wq,
+                      float2* wh, float2* mz, float* mx, float* theta, hipStream_t s);
+// b = beta Phi^T y = beta Omega (M^T y) into a.out (u: Dp floats of scratch).
+void launch_dct_rhs(const DctArgs& a, const float* y, const int32_t* rows, int64_t N, float* u, hipStream_t s);
+// Psi = A Pd for columns q < Q, one workgroup per column, with the pi partials.
+void launch_dct_operator(const DctArgs& a, int Q, hipStream_t s);
+
 }  // namespace cofem

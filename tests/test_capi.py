@@ -68,6 +68,8 @@ def test_struct_layout_matches_c(cls, cname):
     dict(T=513), dict(U=0), dict(tol=-1.0), dict(theta_mode=7), dict(stop_mode=3), dict(phi_dtype=2),
     dict(refine_last=9), dict(alpha_floor=0.0), dict(op_kind=5), dict(mstep_mode=2),
     dict(op_kind=1, conv_taps=0), dict(op_kind=1, conv_taps=257), dict(op_kind=1, N=100, D=200),
+    dict(op_kind=2, D=300), dict(op_kind=2, D=8, N=4), dict(op_kind=2, D=65536), dict(op_kind=2, N=300),
+    dict(op_kind=2, phi_dtype=1),
 ])
 def test_create_rejects_bad_params_without_device_work(bad):
     so = lib.load()
@@ -80,7 +82,7 @@ def test_create_rejects_bad_params_without_device_work(bad):
     assert so.cofem_last_error().decode()
 
 
-@pytest.mark.parametrize("L,bad", [(0, {}), (65, {}), (2, dict(mstep_mode=1)), (2, dict(K=0))])
+@pytest.mark.parametrize("L,bad", [(0, {}), (65, {}), (2, dict(mstep_mode=1)), (2, dict(K=0)), (2, dict(op_kind=2))])
 def test_multitask_create_rejects_bad_arguments_without_device_work(L, bad):
     so = lib.load()
     p = lib.make_params(N=64, D=256, beta=1e4, K=8, T=5, U=10, tol=1e-6)
@@ -97,9 +99,10 @@ def test_null_arguments_are_rejected():
     assert so.cofem_create(None, None, None) == -1
     assert so.cofem_fit(None, None) == -1
     assert so.cofem_set_dictionary(None, None) == -1
+    assert so.cofem_set_dct_samples(None, None) == -1
     assert so.cofem_posterior(None, None, None, None, None) == -1
     so.cofem_destroy(None)
-    assert so.cofem_abi_version() == 2
+    assert so.cofem_abi_version() == 3
 
 
 def test_server_rejects_bad_arguments_without_device_work():

@@ -1,0 +1,157 @@
+"""GPU parity of the subsampled DCT dictionary (Sec. V-A.2): Phi = M Omega^{-1}, Omega
+the orthonormal DCT-II of size D, M keeping N of the D samples; the GPU applies
+A = beta Omega M^T M Omega^T + diag(alpha) with an LDS-resident FFT per column.
+
+* The operator against the oracle (scipy's DCT, itself pinned to the cosine sums):
+  every power of two the kernel supports (16 .. 2^15, so both the radix-4-only and
+  the radix-2-tail FFT lengths), ragged column counts, N = 1, N = D/3 and N = D.
+  The FP32 FFT of length L = D/2 has a normwise error of a few log2(L) * 2^-24;
+  the bar is 2e-5 per column.
+* Fits against the oracle at the same probes, stop rule and tolerance (mu within
+  1e-4, or twice the oracle's own change of mu between tol and tol / 100).
+* N = D: Phi is orthogonal, A is diagonal and theta = 1 gives the exact
+  preconditioner, so every E-step ends after one CG step.
+* The full-size workload (D = 2^15, N = D/3, K = 20, T = 30, tol 1e-4) against
+  the oracle's fit, and bad sample sets rejected.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _ti(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("D,N,ncols", [(16, 5, 3), (32, 32, 9), (64, 1, 2), (128, 42, 17), (256, 85, 21),
+                                       (512, 170, 33), (1024, 341, 21), (2048, 2048, 5), (4096, 1365, 64),
+                                       (8192, 2730, 21), (16384, 5461, 7), (32768, 10922, 21)])
+def test_dct_apply_A_matches_oracle(gpu, D, N, ncols):
+    rng = np.random.default_rng(D + N + ncols)
+    rows = np.sort(rng.permutation(D)[:N])
+    beta = 1e4
+    alpha = np.exp(rng.uniform(-3, 12, D)).astype(np.float32)
+    P = rng.standard_normal((ncols, D)).astype(np.float32)
+    print(f"dct operator D={D} N={N} ncols={ncols}", flush=True)
+    m = gpu.CoFEM(N, D, beta, K=max(ncols - 1, 1), T=1, U=1, tol=0.0, op="dct")
+    m.set_dictionary(_ti(rows))
+    Psi, pi = m.apply_A(_t(alpha), _t(P), want_pi=True)
+    Psi = _np(Psi)
+    m.close()
+    op = oracle.DctOperator(D, rows)
+    Pt = P.T.astype(np.float64)
+    ref = (beta * op.rmatvec(op.matvec(Pt)) + alpha.astype(np.float64)[:, None] * Pt).T
+    errs = [_rel(Psi[q], ref[q]) for q in range(ncols)]
+    print(f"  max column error {max(errs):.2e}")
+    assert max(errs) < 2e-5
+    pi_ref = np.sum(P.astype(np.float64) * Psi, axis=1)
+    assert np.allclose(_np(pi), pi_ref, rtol=1e-10)
+
+
+def _dct_fit(gpu, prob, K, T, U, tol, seed, **kw):
+    m = gpu.CoFEM(prob.N, prob.D, prob.beta, K=K, T=T, U=U, tol=tol, seed=seed, op="dct", **kw)
+    m.set_dictionary(_ti(prob.rows))
+    m.fit(_t(prob.y))
+    mu, s, alpha, st = m.posterior()
+    m.close()
+    return _np(mu), _np(s), _np(alpha), st
+
+
+def _oracle_pair(prob, K, T, U, tol, seed, **kw):
+    op = oracle.DctOperator(prob.D, prob.rows)
+    ref = oracle.cofem(op, prob.y, prob.beta, T=T, K=K, U=U, tol=tol, seed=seed, **kw)
+    tight = oracle.cofem(op, prob.y, prob.beta, T=T, K=K, U=U, tol=tol / 100, seed=seed, **kw)
+    return ref, _rel(ref.mu, tight.mu), _rel(ref.s, tight.s)
+
+
+@pytest.mark.parametrize("theta", ["ones", "jacobi"])
+def test_dct_fit_matches_oracle(gpu, theta):
+    prob = workloads.dct_problem(1024, 341, 122, 0.01, seed=43)
+    K, T, U, tol, seed = 20, 30, 400, 1e-6, 5
+    mu, s, alpha, st = _dct_fit(gpu, prob, K, T, U, tol, seed, theta=theta)
+    ref, sens_mu, sens_s = _oracle_pair(prob, K, T, U, tol, seed, theta_mode=theta)
+    e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
+    print(f"dct fit {theta}: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e}), s rel {e_s:.2e} ({sens_s:.2e}); "
+          f"CG steps gpu {st['total_cg_steps']} oracle {sum(ref.cg_steps)}")
+    assert e_mu <= max(1e-4, 2 * sens_mu)
+    assert e_s <= max(1e-3, 2 * sens_s)
+    assert st["breakdown"] == 0 and all(np.isfinite(x).all() for x in (mu, s, alpha))
+
+
+def test_dct_fit_nonneg_mstep_matches_oracle(gpu):
+    prob = workloads.dct_problem(512, 170, 40, 0.01, seed=47)
+    K, T, U, tol, seed = 16, 20, 400, 1e-6, 9
+    mu, s, alpha, st = _dct_fit(gpu, prob, K, T, U, tol, seed, mstep="nonneg")
+    ref, sens_mu, sens_s = _oracle_pair(prob, K, T, U, tol, seed, mstep="nonneg")
+    e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
+    print(f"dct nonneg fit: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e}), s rel {e_s:.2e} ({sens_s:.2e})")
+    assert e_mu <= max(1e-4, 2 * sens_mu)
+    assert e_s <= max(1e-3, 2 * sens_s)
+
+
+def test_dct_full_sampling_is_one_cg_step(gpu):
+    """N = D: Phi^T Phi = I, so A = beta I + diag(alpha) and M^-1 = A^-1 (theta = 1)."""
+    D = 256
+    prob = workloads.dct_problem(D, D, 20, 0.01, seed=53)
+    mu, s, alpha, st = _dct_fit(gpu, prob, 8, 5, 50, 1e-6, 3)
+    assert st["cg_steps"] == [1] * 5
+    ref = oracle.cofem(oracle.DctOperator(D, prob.rows), prob.y, prob.beta, T=5, K=8, U=50, tol=1e-6, seed=3)
+    assert _rel(mu, ref.mu) < 1e-5
+    assert _rel(s, ref.s) < 1e-5
+
+
+def test_dct_bad_samples_rejected(gpu):
+    so = gpu.load()
+    p = gpu.make_params(N=4, D=16, beta=1e4, K=2, T=1, U=1, tol=0.0, op="dct")
+    h = ctypes.c_void_p()
+    assert so.cofem_create(ctypes.byref(p), None, ctypes.byref(h)) == 0
+    try:
+        for rows in ([0, 1, 1, 3], [0, 1, 2, 16], [-1, 0, 1, 2]):
+            r = _ti(rows)
+            assert so.cofem_set_dct_samples(h, ctypes.c_void_p(r.data_ptr())) == -1
+            assert "sample index" in so.cofem_last_error().decode()
+        r = _ti([3, 0, 15, 7])
+        assert so.cofem_set_dct_samples(h, ctypes.c_void_p(r.data_ptr())) == 0
+        phi = _t(np.zeros(64))
+        assert so.cofem_set_dictionary(h, ctypes.c_void_p(phi.data_ptr())) == -1
+    finally:
+        so.cofem_destroy(h)
+
+
+def test_dct_workload_fit_matches_oracle(gpu):
+    """The benchmark's DCT fit (D = 2^15, N = D/3, d = 0.12 D, K = 20, T = 30, tol 1e-4)."""
+    w = workloads.WORKLOADS["dct"]
+    prob = workloads.make_workload("dct")
+    mu, s, alpha, st = _dct_fit(gpu, prob, w["K"], w["T"], w["U"], w["tol"], 2024)
+    op = oracle.DctOperator(prob.D, prob.rows)
+    ref = oracle.cofem(op, prob.y, prob.beta, T=w["T"], K=w["K"], U=w["U"], tol=w["tol"], seed=2024)
+    tight = oracle.cofem(op, prob.y, prob.beta, T=w["T"], K=w["K"], U=w["U"], tol=w["tol"] / 100, seed=2024)
+    e_mu, sens = _rel(mu, ref.mu), _rel(ref.mu, tight.mu)
+    nrmse = _rel(mu, prob.z)
+    print(f"dct workload: mu rel {e_mu:.2e} (sensitivity {sens:.2e}), NRMSE {nrmse:.3f} (oracle "
+          f"{_rel(ref.mu, prob.z):.3f}), CG steps gpu {st['total_cg_steps']} oracle {sum(ref.cg_steps)}, "
+          f"{st['ms_fit']:.1f} ms")
+    assert e_mu <= max(1e-4, 2 * sens)
+    assert nrmse < 0.1
