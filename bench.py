@@ -91,6 +91,9 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of saturation")
     ap.add_argument("--no-conv", action="store_true", help="skip the convolutional-dictionary fits")
     ap.add_argument("--conv-only", action="store_true", help="only the convolutional-dictionary fits (for profiling)")
+    ap.add_argument("--no-dct", action="store_true", help="skip the DCT-dictionary fits")
+    ap.add_argument("--dct-only", action="store_true", help="only the DCT-dictionary fits (for profiling)")
+    ap.add_argument("--dct-fits", type=int, default=5, help="timed DCT-dictionary fits")
     ap.add_argument("--serve-only", action="store_true", help="only the serving phase (for profiling)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run a 1 GiB copy and three operator applications (for rocprofv3 --pmc)")
@@ -146,6 +149,12 @@ def main():
 
         torch.cuda.set_device(0)
         print(json.dumps({"conv": conv_bench()}), flush=True)
+        return
+    if args.dct_only:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"dct": dct_bench(args.dct_fits)}), flush=True)
         return
     import numpy as np
     import torch
@@ -232,6 +241,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_conv:
         out["conv"] = conv_bench()
+    if not args.no_dct:
+        out["dct"] = dct_bench(args.dct_fits)
     if args.serve_requests > 0:
         out["serving"] = serving(args)
     print(json.dumps(out), flush=True)
@@ -288,6 +299,58 @@ def conv_bench():
                          cg_steps=st["total_cg_steps"], ms_per_cg_step=round(1e3 * el / st["total_cg_steps"], 4),
                          passes=passes)
         log(f"conv {name}: {res[name]}")
+    return res
+
+
+def dct_bench(fits):
+    """The subsampled DCT dictionary at the largest DCT size of the paper's scalability
+    study (D = 2^15, N = D/3, d = 0.12 D spikes, K = 20, T = 30, U = 400, tol 1e-4):
+    one warm-up fit, then `fits` timed fits (sample set loaded once per fit).  Per
+    operator application (Q = K + 1 columns): algorithmic bytes 8 D Q + 4 D (read Pd
+    and alpha, write Psi), and the conventional 5 L log2 L flops of each of the 2 Q
+    complex FFTs of length L = D / 2."""
+    import math
+
+    import torch
+
+    import paper_2105_10439_amd as lib
+    import workloads
+
+    w = dict(workloads.WORKLOADS["dct"])
+    prob = workloads.make_workload("dct")
+    D, N, Q = prob.D, prob.N, w["K"] + 1
+    L = D // 2
+    rows_d = torch.from_numpy(prob.rows).cuda()
+    y_d = torch.from_numpy(prob.y).cuda()
+    bytes_app = 8.0 * D * Q + 4.0 * D
+    flops_app = 2.0 * Q * 5.0 * L * math.log2(L)
+    m = lib.CoFEM(N, D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024, op="dct")
+    m.set_dictionary(rows_d)
+    m.fit(y_d)
+    m.set_timing(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(fits):
+        m.set_dictionary(rows_d)
+        m.fit(y_d)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    mu, _, _, st = m.posterior()
+    ms, n = m.get_timing("fp32")
+    m.close()
+    app_s = ms / n * 1e-3
+    nrmse = float(torch.linalg.vector_norm(mu.double().cpu() - torch.from_numpy(prob.z)) /
+                  torch.linalg.vector_norm(torch.from_numpy(prob.z)))
+    res = dict(workload=f"subsampled DCT dictionary: D={D}, N={N} kept samples, {prob.meta['d']} spikes N(0,5), "
+                        f"sigma={w['sigma']}, K={w['K']} T={w['T']} tol={w['tol']} U={w['U']}, FP32",
+               em_iters_per_s=round(w["T"] * fits / el, 2), ms_per_fit=round(1e3 * el / fits, 2),
+               cg_steps=st["total_cg_steps"], ms_per_cg_step=round(1e3 * el / fits / st["total_cg_steps"], 4),
+               nrmse=round(nrmse, 4),
+               operator=dict(launches=n, avg_us=round(1e6 * app_s, 2), gbps=round(bytes_app / app_s / 1e9, 1),
+                             hbm_frac=round(bytes_app / app_s / 1e9 / HBM_PEAK_GBPS, 4),
+                             fft_tflops=round(flops_app / app_s / 1e12, 3)),
+               paper_context="the paper reports about 2 s per CoFEM fit at this size on an NVIDIA T4 (Sec. V-C)")
+    log(f"dct: {res}")
     return res
 
 

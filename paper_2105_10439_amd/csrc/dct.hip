@@ -24,10 +24,12 @@
 //   parts.  The mask is applied in the reordered domain, where both transforms
 //   meet, so x itself is never formed.
 //
-// The complex DFT is a Stockham autosort FFT (radix 4, a final radix 2 when log2 L
-// is odd) in place in LDS: each pass loads its butterflies into registers, waits
-// at a barrier, and stores the results.  Twiddles, the DCT phase factors and the
-// mask come from small tables built once in FP64 and rounded to FP32.
+// The complex DFT is a Stockham autosort FFT in place in LDS (radix-16 passes, one
+// radix-2, 4 or 8 pass for the rest): each pass loads its butterflies into
+// registers, applies the twiddles and the butterfly there, waits at a barrier and
+// stores; a slot of padding per 16 points keeps the strided stores free of bank
+// conflicts.  Twiddles, the DCT phase factors and the mask come from small tables
+// built once in FP64 and rounded to FP32.
 #include "kernels.h"
 #include "device_common.h"
 
@@ -43,100 +45,171 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 __device__ __forceinline__ float2 ctimes_i(float2 a) { return make_float2(-a.y, a.x); }       // i a
 __device__ __forceinline__ float2 ctimes_minus_i(float2 a) { return make_float2(a.y, -a.x); }  // -i a
 
-// Threads per workgroup for L complex points: one radix-4 butterfly per thread
+// Workgroup barrier that orders LDS only: the waves' global loads (twiddles, the
+// next values of Pd and alpha) stay in flight across it.  Every barrier in this
+// file protects LDS data.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Threads per workgroup for L complex points: one radix-16 butterfly per thread
 // up to 1024 threads, at least one wave.
 constexpr int dct_threads(int log2L) {
-  return ((1 << log2L) / 4 < 64) ? 64 : (((1 << log2L) / 4 > 1024) ? 1024 : (1 << log2L) / 4);
+  return ((1 << log2L) / 16 < 64) ? 64 : (((1 << log2L) / 16 > 1024) ? 1024 : (1 << log2L) / 16);
 }
 
-// One radix-4 Stockham pass over L points with NT threads; ns = size of the
-// sub-transforms already done (1, 4, 16, ...).  Butterfly j reads points
-// j + r L/4, multiplies point r by W_{4 ns}^{k r} (k = j mod ns) and writes its
-// 4-point DFT to (j - k) 4 + k + r ns.  MASK: the pass reads the conjugated
-// output of an inverse transform and applies the sample mask to it (see the
-// operator kernel).
-template <int L, int NT, bool MASK>
-__device__ __forceinline__ void fft_radix4_pass(float2* buf, const float2* __restrict__ tw, int ns,
-                                                const float2* __restrict__ mz) {
-  constexpr int Q4 = L / 4;
-  constexpr int BPT = (Q4 + NT - 1) / NT;
-  float2 a[BPT][4];
+// LDS layout: complex point i lives at float2 slot i + i / 16.  The Stockham passes
+// write with strides of 16, 256, ... points; one slot of padding per 16 points
+// turns each of them into a stride that hits every bank once per half-wave.
+__device__ __forceinline__ int lds_slot(int i) { return i + (i >> 4); }
+// The same buffer read as D real values: value f at float f + 2 (f / 32).
+__device__ __forceinline__ int lds_real(int f) { return f + 2 * (f >> 5); }
+constexpr int lds_slots(int L) { return L + L / 16; }
+
+// In-register forward DFTs of 2, 4, 8 and 16 points, natural order in and out.
+__device__ __forceinline__ void dft2(float2* v) {
+  const float2 a = v[0];
+  v[0] = cadd(a, v[1]);
+  v[1] = csub(a, v[1]);
+}
+__device__ __forceinline__ void dft4(float2* v) {
+  const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  const float2 t2 = cadd(v[1], v[3]), t3 = ctimes_minus_i(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[2] = csub(t0, t2);
+  v[3] = csub(t1, t3);
+}
+// W_16^m = e^{-2 pi i m / 16} = (cos(2 pi m / 16), -sin(2 pi m / 16)); m is a
+// compile-time constant wherever this is called.
+__device__ __forceinline__ float2 w16(int m) {
+  constexpr float C1 = 0.92387953251128674f, C2 = 0.70710678118654752f, C3 = 0.38268343236508977f;
+  constexpr float cs[16] = {1.0f, C1, C2, C3, 0.0f, -C3, -C2, -C1, -1.0f, -C1, -C2, -C3, 0.0f, C3, C2, C1};
+  constexpr float sn[16] = {0.0f, C3, C2, C1, 1.0f, C1, C2, C3, 0.0f, -C3, -C2, -C1, -1.0f, -C1, -C2, -C3};
+  return make_float2(cs[m & 15], -sn[m & 15]);
+}
+// 8 points as 2 x 4: n = 2 n1 + n2, k = k1 + 4 k2.
+__device__ __forceinline__ void dft8(float2* v) {
+  float2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+  dft4(e);
+  dft4(o);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    const float2 t = cmul(o[k1], w16(2 * k1));
+    v[k1] = cadd(e[k1], t);
+    v[k1 + 4] = csub(e[k1], t);
+  }
+}
+// 16 points as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
+__device__ __forceinline__ void dft16(float2* v) {
+  float2 y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) y[n2][n1] = v[4 * n1 + n2];
+    dft4(y[n2]);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 z[4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) z[n2] = (n2 * k1 == 0) ? y[n2][k1] : cmul(y[n2][k1], w16(n2 * k1));
+    dft4(z);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = z[k2];
+  }
+}
+template <int R>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 2) dft2(v);
+  if constexpr (R == 4) dft4(v);
+  if constexpr (R == 8) dft8(v);
+  if constexpr (R == 16) dft16(v);
+}
+
+// One radix-R Stockham pass over L points with NT threads; ns = size of the
+// sub-transforms already done.  Butterfly j reads points j + r L/R, multiplies
+// point r by W_{R ns}^{k r} (k = j mod ns), takes their R-point DFT and, after a
+// barrier (every butterfly has read its inputs), writes output r to point
+// (j - k) R + k + r ns.  MASK: the pass reads the conjugated output of an inverse
+// transform and applies the sample mask to it (see the operator kernel).
+template <int L, int NT, int R, bool MASK>
+__device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__ tw, int ns,
+                                         const float2* __restrict__ mz) {
+  constexpr int NB = L / R;
+  constexpr int BPT = (NB + NT - 1) / NT;
+  float2 v[BPT][R];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     const int j = threadIdx.x + b * NT;
-    if (j < Q4) {
+    if (j < NB) {
+      // W_{R ns}^{k r} = W_L^{r st}: powers 1, 2, 4, 8 from the table (loads issued
+      // first), the others as products of at most four of them
+      const int st = (j & (ns - 1)) * (NB / ns);
+      float2 w[4];
+      if (ns > 1) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float2 v = buf[j + r * Q4];
-        if (MASK) {
-          const float2 m = mz[j + r * Q4];
-          v = make_float2(m.x * v.x, -m.y * v.y);
-        }
-        a[b][r] = v;
+        for (int e = 0; (1 << e) < R; ++e) w[e] = tw[(1 << e) * st];
       }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 x = buf[lds_slot(j + r * NB)];
+        if (MASK) {
+          const float2 m = mz[j + r * NB];
+          x = make_float2(m.x * x.x, -m.y * x.y);
+        }
+        v[b][r] = x;
+      }
+      if (ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 f = make_float2(1.0f, 0.0f);
+          bool first = true;
+#pragma unroll
+          for (int e = 0; (1 << e) < R; ++e)
+            if (r & (1 << e)) {
+              f = first ? w[e] : cmul(f, w[e]);
+              first = false;
+            }
+          v[b][r] = cmul(v[b][r], f);
+        }
+      }
+      dft<R>(v[b]);
     }
   }
-  __syncthreads();
-  const int stride = Q4 / ns;  // table step of W_{4 ns} = W_L^{L / (4 ns)}
+  lds_barrier();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     const int j = threadIdx.x + b * NT;
-    if (j < Q4) {
+    if (j < NB) {
       const int k = j & (ns - 1);
-      const float2 a0 = a[b][0];
-      const float2 a1 = cmul(a[b][1], tw[k * stride]);
-      const float2 a2 = cmul(a[b][2], tw[2 * k * stride]);
-      const float2 a3 = cmul(a[b][3], tw[3 * k * stride]);
-      const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
-      const float2 t2 = cadd(a1, a3), t3 = ctimes_minus_i(csub(a1, a3));
-      const int o = (j - k) * 4 + k;
-      buf[o] = cadd(t0, t2);
-      buf[o + ns] = cadd(t1, t3);
-      buf[o + 2 * ns] = csub(t0, t2);
-      buf[o + 3 * ns] = csub(t1, t3);
+      const int o = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lds_slot(o + r * ns)] = v[b][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
-// The last pass when log2 L is odd: radix 2 with ns = L / 2.
-template <int L, int NT>
-__device__ __forceinline__ void fft_radix2_last(float2* buf, const float2* __restrict__ tw) {
-  constexpr int H = L / 2;
-  constexpr int BPT = (H + NT - 1) / NT;
-  float2 a[BPT][2];
-#pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int j = threadIdx.x + b * NT;
-    if (j < H) {
-      a[b][0] = buf[j];
-      a[b][1] = buf[j + H];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int j = threadIdx.x + b * NT;
-    if (j < H) {
-      const float2 t = cmul(a[b][1], tw[j]);
-      buf[j] = cadd(a[b][0], t);
-      buf[j + H] = csub(a[b][0], t);
-    }
-  }
-  __syncthreads();
-}
-
-// Forward DFT of the L points in buf (natural order in and out).  Callers place a
-// barrier between their last write to buf and this call.
+// Forward DFT of the L points in buf (natural order in and out): radix-16 passes,
+// then one radix-2, 4 or 8 pass for the rest of log2 L.  Callers place a barrier
+// between their last write to buf and this call.
 template <int LOG2L, bool MASK_FIRST>
 __device__ __forceinline__ void fft_forward(float2* buf, const float2* __restrict__ tw,
                                             const float2* __restrict__ mz) {
   constexpr int L = 1 << LOG2L, NT = dct_threads(LOG2L);
-  fft_radix4_pass<L, NT, MASK_FIRST>(buf, tw, 1, mz);
-  int ns = 4;
-#pragma unroll 1
-  for (int p = 1; p < LOG2L / 2; ++p, ns *= 4) fft_radix4_pass<L, NT, false>(buf, tw, ns, mz);
-  if constexpr ((LOG2L & 1) != 0) fft_radix2_last<L, NT>(buf, tw);
+  constexpr int P16 = LOG2L / 4, REM = LOG2L % 4;
+  if constexpr (P16 > 0) {
+    fft_pass<L, NT, 16, MASK_FIRST>(buf, tw, 1, mz);
+    int ns = 16;
+#pragma unroll
+    for (int p = 1; p < P16; ++p, ns *= 16) fft_pass<L, NT, 16, false>(buf, tw, ns, mz);
+    if constexpr (REM != 0) fft_pass<L, NT, (1 << REM), false>(buf, tw, ns, mz);
+  } else {
+    fft_pass<L, NT, (1 << REM), MASK_FIRST>(buf, tw, 1, mz);
+  }
 }
 
 // V(k) = (Za + conj Zb) / 2 - i wh_k (Za - conj Zb) / 2: bin k of the real DFT of
@@ -148,7 +221,7 @@ __device__ __forceinline__ float2 real_split(float2 za, float2 zb, float2 whk) {
 }
 
 // After fft_forward: the DCT-II of the reordered signal, C_k = sum_n x_n
-// cos(pi (2n + 1) k / 2D) (unnormalised), written over buf as D floats.
+// cos(pi (2n + 1) k / 2D) (unnormalised), written over buf as D real values.
 template <int LOG2L>
 __device__ __forceinline__ void dct_post(float2* buf, const DctArgs& a) {
   constexpr int L = 1 << LOG2L, NT = dct_threads(LOG2L);
@@ -159,30 +232,30 @@ __device__ __forceinline__ void dct_post(float2* buf, const DctArgs& a) {
   for (int i = 0; i < IT; ++i) {
     const int t = threadIdx.x + i * NT;
     if (t <= L / 2) {
-      A[i] = buf[t];
-      B[i] = buf[(L - t) & (L - 1)];
+      A[i] = buf[lds_slot(t)];
+      B[i] = buf[lds_slot((L - t) & (L - 1))];
     }
   }
-  __syncthreads();
+  lds_barrier();
   float* cb = reinterpret_cast<float*>(buf);
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const int t = threadIdx.x + i * NT;
     if (t <= L / 2) {
       float2 w = cmul(a.wq[t], real_split(A[i], B[i], a.wh[t]));
-      cb[t] = w.x;
-      if (t > 0) cb[D - t] = -w.y;
+      cb[lds_real(t)] = w.x;
+      if (t > 0) cb[lds_real(D - t)] = -w.y;
       if (t == 0) {
         w = cmul(a.wq[L], real_split(A[i], A[i], a.wh[L]));
-        cb[L] = w.x;
+        cb[lds_real(L)] = w.x;
       } else if (t < L / 2) {
         w = cmul(a.wq[L - t], real_split(B[i], A[i], a.wh[L - t]));
-        cb[L - t] = w.x;
-        cb[L + t] = -w.y;
+        cb[lds_real(L - t)] = w.x;
+        cb[lds_real(L + t)] = -w.y;
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Operator over one column per workgroup: Psi = beta Omega diag(m) Omega^T Pd +
@@ -190,64 +263,118 @@ __device__ __forceinline__ void dct_post(float2* buf, const DctArgs& a) {
 // coordinates at pipart[q * nbx + chunk].
 template <int LOG2L>
 __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_operator(DctArgs a) {
-  constexpr int L = 1 << LOG2L, NT = dct_threads(LOG2L);
-  __shared__ __align__(16) float2 buf[L];
+  constexpr int L = 1 << LOG2L, NT = dct_threads(LOG2L), NW = NT / 64;
+  constexpr int D = 2 * L;
+  constexpr int IT = (L / 2 + 1 + NT - 1) / NT;
+  __shared__ __align__(16) float2 buf[lds_slots(L)];
+  __shared__ double red[(D + 255) / 256 + 4];
   if (a.done && *a.done) return;  // a step enqueued after the stop rule fired
-  const int D = 2 * L;
   const int q = blockIdx.x;
   const float* __restrict__ p = a.in + (int64_t)q * a.Dp;
   // Inverse transform, spectrum side.  With c_k = s_k Pd_k, the Hermitian
   // spectrum of the reordered output is H_0 = c_0, H_k = e^{i pi k / 2D} (c_k -
   // i c_{D-k}) / 2; its half-length form is Z_k = E_k + i O_k with E_k = H_k +
   // conj H_{L-k}, O_k = (H_k - conj H_{L-k}) e^{2 pi i k / D}.  buf gets conj Z,
-  // so that a forward DFT yields the conjugate of the inverse one.
-  auto hval = [&](int k) -> float2 {
-    if (k == 0) return make_float2(a.s0 * p[0], 0.0f);
-    const float ck = a.s1 * p[k], cm = a.s1 * p[D - k];
-    return cscale(cmul(cconj(a.wq[k]), make_float2(ck, -cm)), 0.5f);
+  // so that a forward DFT yields the conjugate of the inverse one.  Item t makes
+  // Z_t and Z_{L-t} from Pd at t, D - t, L - t and L + t (all loads issued first).
+  auto hval = [&](int k, float pk, float pdk, float2 wqk) -> float2 {
+    if (k == 0) return make_float2(a.s0 * pk, 0.0f);
+    return cscale(cmul(cconj(wqk), make_float2(a.s1 * pk, -a.s1 * pdk)), 0.5f);
   };
   auto zval = [&](float2 h1, float2 h2, float2 whk) -> float2 {
     const float2 e = cadd(h1, cconj(h2));
     const float2 o = cmul(csub(h1, cconj(h2)), cconj(whk));
     return cadd(e, ctimes_i(o));
   };
-  for (int t = threadIdx.x; t <= L / 2; t += NT) {
-    const float2 h1 = hval(t), h2 = hval(L - t);
-    buf[t] = cconj(zval(h1, h2, a.wh[t]));
-    if (t > 0 && t < L / 2) buf[L - t] = cconj(zval(h2, h1, a.wh[L - t]));
+  constexpr int G1 = IT < 3 ? IT : 3;  // items whose loads are issued together
+#pragma unroll 1
+  for (int i0 = 0; i0 < IT; i0 += G1) {
+    float c_t[G1], c_dt[G1], c_lt[G1], c_lpt[G1];
+    float2 wq_t[G1], wq_lt[G1], wh_t[G1], wh_lt[G1];
+#pragma unroll
+    for (int g = 0; g < G1; ++g) {
+      const int t = threadIdx.x + (i0 + g) * NT;
+      if (i0 + g < IT && t <= L / 2) {
+        c_t[g] = p[t];
+        c_dt[g] = t > 0 ? p[D - t] : 0.0f;
+        c_lt[g] = p[L - t];
+        c_lpt[g] = p[L + t];
+        wq_t[g] = a.wq[t];
+        wq_lt[g] = a.wq[L - t];
+        wh_t[g] = a.wh[t];
+        wh_lt[g] = a.wh[L - t];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G1; ++g) {
+      const int t = threadIdx.x + (i0 + g) * NT;
+      if (i0 + g < IT && t <= L / 2) {
+        const float2 h1 = hval(t, c_t[g], c_dt[g], wq_t[g]), h2 = hval(L - t, c_lt[g], c_lpt[g], wq_lt[g]);
+        buf[lds_slot(t)] = cconj(zval(h1, h2, wh_t[g]));
+        if (t > 0 && t < L / 2) buf[lds_slot(L - t)] = cconj(zval(h2, h1, wh_lt[g]));
+      }
+    }
   }
-  __syncthreads();
+  lds_barrier();
   fft_forward<LOG2L, false>(buf, a.tw, a.mz);
   // buf = conj(z), z_m = v_2m + i v_{2m+1} the reordered Omega^T Pd.  The next
   // transform's first pass reads z' = (m_2m v_2m, m_{2m+1} v_{2m+1}).
   fft_forward<LOG2L, true>(buf, a.tw, a.mz);
   dct_post<LOG2L>(buf, a);
+  // Psi = beta s_k C_k + alpha_k Pd_k, 4 coordinates per thread and iteration; the
+  // pi partial of each run of 256 coordinates is one wave's sum, and chunk c of
+  // 1024 coordinates adds runs 4c .. 4c + 3 in order.
   const float* __restrict__ cb = reinterpret_cast<const float*>(buf);
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
   float* __restrict__ out = a.out + (int64_t)q * a.Dp;
-  for (int c = wv; c < a.nbx; c += NT / 64) {
-    double acc = 0.0;
+  constexpr int IT2 = (D + 4 * NT - 1) / (4 * NT);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  constexpr int G = IT2 < 4 ? IT2 : 4;  // iterations whose loads are issued together
+#pragma unroll 1
+  for (int i0 = 0; i0 < IT2; i0 += G) {
+    f32x4 pv[G], al[G];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t j = (int64_t)c * VCHUNK + i * 256 + 4 * ln;
-      if (j < a.Dp) {
-        f32x4 ps = {0.f, 0.f, 0.f, 0.f};
-        if (j < D) {
-          const f32x4 pv = *reinterpret_cast<const f32x4*>(p + j);
-          const f32x4 al = *reinterpret_cast<const f32x4*>(a.alpha + j);
-          const f32x4 cv = *reinterpret_cast<const f32x4*>(cb + j);
+    for (int g = 0; g < G; ++g) {
+      const int j = 4 * (threadIdx.x + (i0 + g) * NT);
+      if (i0 + g < IT2 && j < D) {
+        pv[g] = *reinterpret_cast<const f32x4*>(p + j);
+        al[g] = *reinterpret_cast<const f32x4*>(a.alpha + j);
+      }
+    }
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float sk = (j + e == 0) ? a.s0 : a.s1;
-            ps[e] = (float)(a.beta * (double)(sk * cv[e]) + (double)al[e] * (double)pv[e]);
-            acc += (double)pv[e] * (double)ps[e];
-          }
+    for (int g = 0; g < G; ++g) {
+      const int i = i0 + g;
+      if (i >= IT2) break;
+      const int j = 4 * (threadIdx.x + i * NT);
+      double acc = 0.0;
+      if (j < D) {
+        const float2 c01 = *reinterpret_cast<const float2*>(cb + lds_real(j));
+        const float2 c23 = *reinterpret_cast<const float2*>(cb + lds_real(j + 2));
+        const float cv[4] = {c01.x, c01.y, c23.x, c23.y};
+        f32x4 ps;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float sk = (j + e == 0) ? a.s0 : a.s1;
+          ps[e] = (float)(a.beta * (double)(sk * cv[e]) + (double)al[g][e] * (double)pv[g][e]);
+          acc += (double)pv[g][e] * (double)ps[e];
         }
         *reinterpret_cast<f32x4*>(out + j) = ps;
       }
+      if ((i * NT + 64 * wv) * 4 < D) {
+        acc = wave_sum(acc);
+        if (ln == 0) red[i * NW + wv] = acc;
+      }
     }
-    acc = wave_sum(acc);
-    if (ln == 0) a.pipart[(int64_t)q * a.nbx + c] = acc;
+  }
+  // zero Psi on [D, Dp) (D < 256 only)
+  for (int64_t j = D + threadIdx.x; j < a.Dp; j += NT) out[j] = 0.0f;
+  lds_barrier();
+  constexpr int RUNS = (D + 255) / 256;
+  for (int c = threadIdx.x; c < a.nbx; c += NT) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (4 * c + r < RUNS) s += red[4 * c + r];
+    a.pipart[(int64_t)q * a.nbx + c] = s;
   }
 }
 
@@ -256,20 +383,30 @@ __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_operator(DctArgs a) 
 template <int LOG2L>
 __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_forward(DctArgs a) {
   constexpr int L = 1 << LOG2L, NT = dct_threads(LOG2L);
-  __shared__ __align__(16) float2 buf[L];
-  const int D = 2 * L;
+  constexpr int D = 2 * L;
+  constexpr int IT = (L + NT - 1) / NT;
+  __shared__ __align__(16) float2 buf[lds_slots(L)];
   const float* __restrict__ u = a.in;
   // z_m = v_2m + i v_{2m+1} with v_n = u_2n (n < L), v_n = u_{2(D-1-n)+1} (n >= L)
-  for (int m = threadIdx.x; m < L; m += NT) {
-    buf[m] = (m < L / 2) ? make_float2(u[4 * m], u[4 * m + 2]) : make_float2(u[2 * D - 4 * m - 1], u[2 * D - 4 * m - 3]);
+  float2 z[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int m = threadIdx.x + i * NT;
+    if (m < L)
+      z[i] = (m < L / 2) ? make_float2(u[4 * m], u[4 * m + 2]) : make_float2(u[2 * D - 4 * m - 1], u[2 * D - 4 * m - 3]);
   }
-  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int m = threadIdx.x + i * NT;
+    if (m < L) buf[lds_slot(m)] = z[i];
+  }
+  lds_barrier();
   fft_forward<LOG2L, false>(buf, a.tw, a.mz);
   dct_post<LOG2L>(buf, a);
   const float* __restrict__ cb = reinterpret_cast<const float*>(buf);
   for (int64_t j = threadIdx.x; j < a.Dp; j += NT) {
     const float sk = (j == 0) ? a.s0 : a.s1;
-    a.out[j] = (j < D) ? (float)(a.beta * (double)(sk * cb[j])) : 0.0f;
+    a.out[j] = (j < D) ? (float)(a.beta * (double)(sk * cb[lds_real((int)j)])) : 0.0f;
   }
 }
 
