@@ -32,4 +32,5 @@ from .cofem import (  # noqa: F401
     woodbury_sigma,
     nonneg_second_moment,
     cofem_multitask,
+    posterior_variance,
 )

@@ -19,6 +19,8 @@ Contents, each restating one passage of the paper (Lin, Song, Bilgic, Ba,
 * `log_evidence`, `woodbury_sigma`: the objective of Eq. (mle2) and the
   Woodbury form of Eq. (woodbury), used only to pin `exact_em`;
 * `cofem_multitask`, `nonneg_second_moment`: the extensions of Sec. III-E;
+* `posterior_variance`: the post-fit estimate of diag(Sigma) at a fixed alpha
+  with many probes (the variance maps of the MRI appendix);
 * `DenseOperator`, `ConvOperator`, `DctOperator` (with `dct_matrix`): the three
   dictionaries of Sec. V-A.
 
@@ -588,3 +590,40 @@ def cofem_multitask(ops, ys, beta: float, T: int, K: int, U: int, tol: float, se
         if t < T:
             alpha = 1.0 / np.maximum(acc / L, alpha_floor)
     return alpha, mus, ss, steps
+
+
+def posterior_variance(op, y: np.ndarray, beta: float, alpha: np.ndarray, K: int, batches: int, U: int,
+                       tol: float, seed: int = 0, theta_mode: str = "ones", stop_mode: str = "joint",
+                       probes=None):
+    """Post-fit estimate of diag(Sigma) at a given alpha (the variance maps of the
+    MRI appendix, with the identity in place of the image-domain map E).
+
+    Sigma = (beta Phi^T Phi + diag(alpha))^{-1}.  Batch b = 1..batches draws K
+    fresh Rademacher probes (the probe words of iteration key b of the stream
+    started at `seed`, as in Algorithm 1), solves A X = [beta Phi^T y | probes] by
+    `pcg` with the preconditioner of Sec. III-C, and forms the diagonal estimate
+    of Eq. (diag-estimate); the result is the mean over the batches, i.e. the
+    estimate from K * batches probes.  Returns (s, mu, CG steps per batch), mu
+    being the mean of the last batch (every batch solves the same mu system).
+    `probes`, if given, is a callable b -> D x K matrix replacing the hash draw.
+    """
+    op = _as_operator(op)
+    D = op.D
+    alpha = np.asarray(alpha, dtype=np.float64).reshape(-1)
+    b = beta * op.rmatvec(np.asarray(y, dtype=np.float64).reshape(-1, 1))[:, 0]
+    theta = np.ones(D) if theta_mode == "ones" else op.col_sq_norms()
+    minv = 1.0 / (beta * theta + alpha)
+
+    def apply_A(Pd):
+        return beta * op.rmatvec(op.matvec(Pd)) + alpha[:, None] * Pd
+
+    acc = np.zeros(D)
+    steps = []
+    mu = None
+    for bi in range(1, int(batches) + 1):
+        Pr = rademacher_probes(seed, bi, D, K) if probes is None else np.asarray(probes(bi), dtype=np.float64)
+        res = pcg(apply_A, np.column_stack([b, Pr]), minv, U, tol, stop_mode)
+        steps.append(res.steps)
+        acc += diag_estimate(Pr, res.X[:, 1:])
+        mu = res.X[:, 0].copy()
+    return acc / int(batches), mu, steps

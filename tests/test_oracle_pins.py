@@ -514,3 +514,36 @@ def test_multitask_reduces_and_matches_exact_multitask_em():
     assert np.allclose(aL, alpha, rtol=1e-9)
     for m, mm in zip(muL, mus):
         assert np.allclose(m, mm, rtol=1e-9)
+
+
+def test_posterior_variance_hadamard_is_exact_diag_sigma():
+    """K = D Hadamard probes make the diagonal estimate exact: the post-fit variance
+    equals diag((beta Phi^T Phi + diag(alpha))^{-1}) from the explicit inverse, and
+    mu equals the explicit posterior mean."""
+    phi, y, beta = _small_dense(N=16, D=32, d=3, seed=61)
+    rng = np.random.default_rng(62)
+    alpha = np.exp(rng.uniform(-2, 6, 32))
+    H = hadamard_probes(32)
+    s, mu, steps = oracle.posterior_variance(phi, y, beta, alpha, K=32, batches=2, U=400, tol=1e-13,
+                                             probes=lambda b: H)
+    Sigma = np.linalg.inv(beta * phi.T @ phi + np.diag(alpha))
+    assert np.allclose(s, np.diag(Sigma), rtol=1e-8)
+    assert np.allclose(mu, beta * Sigma @ phi.T @ y, rtol=1e-8, atol=1e-12)
+    assert len(steps) == 2
+
+
+def test_posterior_variance_converges_with_probe_count():
+    """Rademacher probes: the estimate is unbiased and its error falls like
+    1 / sqrt(K * batches) (Lemma 1), so 64 batches beat 1 batch by a wide margin."""
+    phi, y, beta = _small_dense(N=24, D=48, d=4, seed=63)
+    alpha = np.exp(np.random.default_rng(64).uniform(-2, 4, 48))
+    exact = np.diag(np.linalg.inv(beta * phi.T @ phi + np.diag(alpha)))
+    err = {}
+    for B in (1, 64):
+        s, _, _ = oracle.posterior_variance(phi, y, beta, alpha, K=8, batches=B, U=400, tol=1e-12, seed=5)
+        err[B] = np.linalg.norm(s - exact) / np.linalg.norm(exact)
+    assert err[64] < 0.3 * err[1]
+    # batch b uses the probes of iteration key b: one batch at key 1 equals the T = 1 fit's s at that alpha
+    s1, mu1, _ = oracle.posterior_variance(phi, y, beta, alpha, K=8, batches=1, U=400, tol=1e-12, seed=5)
+    r = cofem(phi, y, beta, T=1, K=8, U=400, tol=1e-12, seed=5, alpha0=alpha)
+    assert np.allclose(s1, r.s, rtol=1e-9, atol=1e-15) and np.allclose(mu1, r.mu, rtol=1e-9, atol=1e-15)
