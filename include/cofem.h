@@ -181,6 +181,28 @@ cofem_status cofem_fit(cofem_ctx* c, const float* y);
 cofem_status cofem_posterior(cofem_ctx* c, float* mu, float* s, float* alpha, cofem_stats* st);
 
 /*
+ * Post-fit posterior variance (the variance maps of the MRI appendix, with the
+ * identity as the image-domain map): an estimate of diag(Sigma), Sigma = (beta
+ * Phi^T Phi + diag(alpha))^{-1}, from K * batches Rademacher probes.  Batch b =
+ * 1..batches solves A X = [beta Phi^T y | p_1 .. p_K] (Alg. 2 with the context's
+ * stop rule and tolerance, y of the last cofem_fit) with the probes of iteration
+ * key b of the SplitMix64 stream started at `seed` (the construction of the fit's
+ * probes, with b in place of t), and forms the diagonal estimate of Eq.
+ * (diag-estimate); the result is the mean over the batches.
+ *   alpha   D floats on the device, or NULL for the fit's alpha^(T).
+ *   s_out   D floats on the device: the estimate.
+ *   mu_out  D floats on the device, or NULL: the posterior mean at alpha.
+ *   st      optional host record: cg_steps[b-1] and rel_resid[b-1] per batch,
+ *           T = batches, ms_fit = wall time of this call.
+ * The operator is FP32 when the context holds the FP32 dictionary, else bf16.
+ * The fit's mu, s and alpha are kept (cofem_posterior still returns them).
+ * Errors: COFEM_EINVAL (NULL s_out, batches outside [1, COFEM_MAX_T]),
+ * COFEM_ESTATE (no successful fit), COFEM_EDEVICE, COFEM_EBREAKDOWN.
+ */
+cofem_status cofem_variance(cofem_ctx* c, const float* alpha, int32_t batches, uint64_t seed, float* s_out,
+                            float* mu_out, cofem_stats* st);
+
+/*
  * One application of the operator of Alg. 2 (its line "Psi <- A P"):
  * Psi = beta Phi^T (Phi P) + diag(alpha) P for a block of ncols (1..COFEM_MAX_K+1)
  * columns of length D, with the loaded dictionary, alpha (D floats) and the

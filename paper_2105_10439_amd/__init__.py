@@ -28,7 +28,7 @@ ABI_VERSION = 3  # COFEM_ABI_VERSION of include/cofem.h
 EXPORTS = [
     "cofem_abi_version", "cofem_last_error", "cofem_create", "cofem_destroy", "cofem_set_dictionary",
     "cofem_set_dct_samples",
-    "cofem_fit", "cofem_posterior", "cofem_apply_A", "cofem_set_timing", "cofem_get_timing",
+    "cofem_fit", "cofem_posterior", "cofem_variance", "cofem_apply_A", "cofem_set_timing", "cofem_get_timing",
     "cofem_server_create", "cofem_server_destroy", "cofem_server_submit", "cofem_server_step",
     "cofem_server_poll", "cofem_server_get_stats",
     "cofem_mt_create", "cofem_mt_destroy", "cofem_mt_set_dictionary", "cofem_mt_fit", "cofem_mt_posterior",
@@ -113,6 +113,7 @@ def load() -> ctypes.CDLL:
         "cofem_fit": (i32, [vp, vp]),
         "cofem_posterior": (i32, [vp, vp, vp, vp, ctypes.POINTER(Stats)]),
         "cofem_apply_A": (i32, [vp, vp, vp, vp, i32, i32, vp]),
+        "cofem_variance": (i32, [vp, vp, i32, ctypes.c_uint64, vp, vp, ctypes.POINTER(Stats)]),
         "cofem_set_timing": (i32, [vp, i32]),
         "cofem_get_timing": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "cofem_server_create": (i32, [ctypes.c_size_t, i32, i32, vp, ctypes.POINTER(vp)]),
@@ -215,6 +216,19 @@ class CoFEM:
         _check(load().cofem_posterior(self._h, ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(s.data_ptr()),
                                       ctypes.c_void_p(alpha.data_ptr()), ctypes.byref(st)))
         return mu, s, alpha, st.as_dict()
+
+    def variance(self, batches, seed=0, alpha=None):
+        """diag(Sigma) at alpha (default: the fit's) from K * batches probes; returns (s, mu, stats)."""
+        import torch
+
+        dev = torch.device("cuda", torch.cuda.current_device())
+        s = torch.empty(self.D, dtype=torch.float32, device=dev)
+        mu = torch.empty_like(s)
+        st = Stats()
+        a = self._dev(alpha, self.D, "alpha") if alpha is not None else None
+        _check(load().cofem_variance(self._h, a, int(batches), int(seed) & ((1 << 64) - 1),
+                                     ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(mu.data_ptr()), ctypes.byref(st)))
+        return s, mu, st.as_dict()
 
     def apply_A(self, alpha, P, use_bf16=False, want_pi=False):
         """Psi = beta Phi^T Phi P + alpha * P for P of shape (ncols, D) (rows = columns of the block)."""

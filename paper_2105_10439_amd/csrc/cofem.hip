@@ -86,6 +86,8 @@ struct cofem_ctx {
   float *theta = nullptr, *alpha = nullptr, *alpha_hook = nullptr, *b32 = nullptr, *b16 = nullptr;
   float* minv = nullptr;
   float *mu = nullptr, *s = nullptr, *yv = nullptr;
+  // post-fit variance: running sum, one batch's estimate and mean
+  float *var_sum = nullptr, *var_s = nullptr, *var_mu = nullptr;
   // CG blocks
   float *X = nullptr, *R = nullptr, *Pd = nullptr, *Psi = nullptr, *V = nullptr;
   uint16_t *PdH = nullptr, *PdL = nullptr, *VH = nullptr, *VL = nullptr;
@@ -359,14 +361,14 @@ void begin_fit(cofem_ctx* c, const float* y) {
   }
 }
 
-// The E-step of EM iteration t (Algorithm 1) at the given alpha: probes and B, then the
-// PCG of Algorithm 2 in chunks of steps until the device-side stop rule has fired.
-cofem_status run_estep(cofem_ctx* c, int t, const float* alpha) {
+// One E-step (Algorithm 1) with the probes of iteration key `key` at the given
+// alpha: probes and B, then the PCG of Algorithm 2 in chunks of steps until the
+// device-side stop rule has fired.  Reports the steps taken and the final ratio.
+cofem_status solve_estep(cofem_ctx* c, uint64_t key, bool use16, const float* alpha, int* steps, double* delta) {
   const cofem_params& p = c->p;
   const SolveCfg sc = solve_cfg(c);
-  const bool use16 = c->need16 && (t <= p.T - p.refine_last);
-  launch_em_init(sc, estep_key(c, t), p.D, c->Dp, use16 ? c->b16 : c->b32, c->theta, alpha, c->minv, c->X, c->R,
-                 c->Pd, use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr, c->part, c->st, c->stream);
+  launch_em_init(sc, key, p.D, c->Dp, use16 ? c->b16 : c->b32, c->theta, alpha, c->minv, c->X, c->R, c->Pd,
+                 use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr, c->part, c->st, c->stream);
   int prev_steps = 0;
   for (;;) {
     for (int i = 0; i < c->chunk; ++i) {
@@ -382,10 +384,23 @@ cofem_status run_estep(cofem_ctx* c, int t, const float* alpha) {
     prev_steps = c->h_st->steps;
     if (c->h_st->done) break;
   }
-  c->stats.cg_steps[t - 1] = c->h_st->steps;
-  c->stats.rel_resid[t - 1] = c->h_st->delta;
+  *steps = c->h_st->steps;
+  *delta = c->h_st->delta;
+  return COFEM_OK;
+}
+
+// The E-step of EM iteration t at the given alpha, recorded in the fit's stats.
+cofem_status run_estep(cofem_ctx* c, int t, const float* alpha) {
+  const cofem_params& p = c->p;
+  const bool use16 = c->need16 && (t <= p.T - p.refine_last);
+  int steps = 0;
+  double delta = 0.0;
+  cofem_status rc = solve_estep(c, estep_key(c, t), use16, alpha, &steps, &delta);
+  if (rc != COFEM_OK) return rc;
+  c->stats.cg_steps[t - 1] = steps;
+  c->stats.rel_resid[t - 1] = delta;
   c->stats.used_bf16[t - 1] = use16 ? 1 : 0;
-  c->stats.total_cg_steps += c->h_st->steps;
+  c->stats.total_cg_steps += steps;
   return COFEM_OK;
 }
 
@@ -493,6 +508,9 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   TRY(dalloc(c, &c->mu, Dp));
   TRY(dalloc(c, &c->s, Dp));
   TRY(dalloc(c, &c->yv, Np));
+  TRY(dalloc(c, &c->var_sum, Dp));
+  TRY(dalloc(c, &c->var_s, Dp));
+  TRY(dalloc(c, &c->var_mu, Dp));
   TRY(dalloc(c, &c->X, (size_t)Qp * Dp));
   TRY(dalloc(c, &c->R, (size_t)Qp * Dp));
   TRY(dalloc(c, &c->Pd, (size_t)Qp * Dp));
@@ -603,6 +621,49 @@ COFEM_API cofem_status cofem_posterior(cofem_ctx* c, float* mu, float* s, float*
   if (alpha) HIP_TRY(hipMemcpyAsync(alpha, c->alpha, bytes, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (st) *st = c->stats;
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_variance(cofem_ctx* c, const float* alpha, int32_t batches, uint64_t seed, float* s_out,
+                                      float* mu_out, cofem_stats* st) {
+  if (!c || !s_out) return fail(COFEM_EINVAL, "NULL argument");
+  if (batches < 1 || batches > COFEM_MAX_T) return fail(COFEM_EINVAL, "batches must be in [1, COFEM_MAX_T]");
+  if (!c->fitted) return fail(COFEM_ESTATE, "cofem_variance before a successful cofem_fit");
+  const cofem_params& p = c->p;
+  const double t0 = now_ms();
+  const float* a = c->alpha;
+  if (alpha) {
+    launch_copy_pad(alpha, p.D, c->Dp, 1.0f, c->alpha_hook, c->stream);
+    a = c->alpha_hook;
+  }
+  const bool use16 = !c->need32;  // the FP32 operator whenever the context holds it
+  cofem_stats vs{};
+  vs.T = batches;
+  launch_fill(c->var_sum, 0.0f, c->Dp, c->stream);
+  for (int b = 1; b <= batches; ++b) {
+    const uint64_t key = mix64_host(seed + (uint64_t)b * GOLDEN_GAMMA);
+    int steps = 0;
+    double delta = 0.0;
+    cofem_status rc = solve_estep(c, key, use16, a, &steps, &delta);
+    if (rc != COFEM_OK) return rc;
+    vs.cg_steps[b - 1] = steps;
+    vs.rel_resid[b - 1] = delta;
+    vs.used_bf16[b - 1] = use16 ? 1 : 0;
+    vs.total_cg_steps += steps;
+    launch_mstep(solve_cfg(c), key, p.D, c->Dp, c->X, c->var_mu, c->var_s, c->alpha_hook, p.alpha_floor, 0, c->st,
+                 c->stream);
+    launch_axpy(c->var_sum, c->var_s, (float)(1.0 / batches), c->Dp, c->stream);
+  }
+  const size_t bytes = (size_t)p.D * sizeof(float);
+  HIP_TRY(hipMemcpyAsync(s_out, c->var_sum, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (mu_out) HIP_TRY(hipMemcpyAsync(mu_out, c->var_mu, bytes, hipMemcpyDeviceToDevice, c->stream));
+  cofem_status rc = sync_state(c);
+  if (rc != COFEM_OK) return rc;
+  vs.breakdown = c->h_st->breakdown;
+  vs.ms_fit = now_ms() - t0;
+  if (st) *st = vs;
+  if (c->h_st->active[0] == 0 && c->h_st->breakdown > 0 && p.stop_mode == COFEM_STOP_JOINT)
+    return fail(COFEM_EBREAKDOWN, "CG breakdown in the mu column");
   return COFEM_OK;
 }
 

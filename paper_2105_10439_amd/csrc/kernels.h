@@ -62,6 +62,8 @@ void launch_rhs(const float* phi32T, const uint16_t* phi16T, int64_t Np, int64_t
 
 // x[0..n) = v.
 void launch_fill(float* x, float v, int64_t n, hipStream_t s);
+// y[0..n) += a x[0..n).
+void launch_axpy(float* y, const float* x, float a, int64_t n, hipStream_t s);
 
 // ---- per EM iteration --------------------------------------------------------
 // Probes for iteration key `key`, B = [b | p_1..p_K | 0], minv = 1/(beta theta + alpha),

@@ -92,6 +92,11 @@ __global__ void k_fill(float* x, float v, int64_t n) {
   if (i < n) x[i] = v;
 }
 
+__global__ void k_axpy(float* __restrict__ y, const float* __restrict__ x, float a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
 __global__ void k_state_reset(CGState* st, int Q) {
   int* w = reinterpret_cast<int*>(st);
   const int n = (int)(sizeof(CGState) / sizeof(int));
@@ -279,6 +284,10 @@ void launch_rhs(const float* phi32T, const uint16_t* phi16T, int64_t Np, int64_t
 
 void launch_fill(float* x, float v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(cdiv(n, 256)), dim3(256), 0, s, x, v, n);
+}
+
+void launch_axpy(float* y, const float* x, float a, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(cdiv(n, 256)), dim3(256), 0, s, y, x, a, n);
 }
 
 void launch_state_reset(CGState* st, int Q, hipStream_t s) {
