@@ -173,7 +173,7 @@ def main():
     y_d = torch.from_numpy(prob.y).cuda()
     torch.cuda.synchronize()
 
-    def run(phi_dtype, refine_last, steps, warmup, timing):
+    def run(phi_dtype, refine_last, steps, warmup, timing, var_batches=0):
         m = lib.CoFEM(prob.N, prob.D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024,
                       phi_dtype=phi_dtype, refine_last=refine_last)
         for i in range(warmup):
@@ -192,10 +192,23 @@ def main():
         el = time.perf_counter() - t
         mu, s, alpha, st = m.posterior()
         tim = {k: m.get_timing(k) for k in ("bf16", "fp32")} if timing else None
+        var = None
+        if var_batches:
+            m.set_timing(False)
+            torch.cuda.synchronize()
+            tv = time.perf_counter()
+            _, _, vst = m.variance(var_batches, seed=7)
+            torch.cuda.synchronize()
+            ev = time.perf_counter() - tv
+            var = dict(batches=var_batches, probes=var_batches * w["K"], ms=round(1e3 * ev, 1),
+                       cg_steps=vst["cg_steps"], operator="fp32" if not vst["used_bf16"][0] else "bf16")
+            log(f"post-fit variance: {var}")
         m.close()
+        run.var = var
         return el, st, tim, mu
 
-    el, st, tim, mu = run("bf16" if args.workload == "large" else "fp32", refine, args.steps, args.warmup, True)
+    el, st, tim, mu = run("bf16" if args.workload == "large" else "fp32", refine, args.steps, args.warmup, True,
+                          var_batches=2)
     em_iters = w["T"] * args.steps
     value = em_iters / el
     nbytes_launch = {"bf16": prob.N * prob.D * 2, "fp32": prob.N * prob.D * 4}
@@ -224,6 +237,7 @@ def main():
         "operator": ops,
         "cg_steps_per_fit": st["total_cg_steps"],
         "cg_steps_per_em_iter": st["cg_steps"],
+        "posterior_variance": run.var,
     }
     if not args.no_fp32 and args.workload == "large":
         el32, st32, tim32, mu32 = run("fp32", 0, 1, 0, True)
