@@ -356,8 +356,8 @@ void begin_fit(cofem_ctx* c, const float* y) {
     if (c->need32) launch_conv_rhs(c->hp32, nullptr, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b32, c->stream);
     if (c->need16) launch_conv_rhs(c->hp32, c->hp16, p.conv_taps, p.D, c->Dp, c->yv, p.beta, c->b16, c->stream);
   } else {
-    if (c->need32) launch_rhs(c->phi32T, nullptr, c->Np, c->Dp, c->yv, p.beta, c->b32, c->stream);
-    if (c->need16) launch_rhs(nullptr, c->phi16T, c->Np, c->Dp, c->yv, p.beta, c->b16, c->stream);
+    if (c->need32) launch_rhs(c->phi32T, nullptr, dict_ld(c->Np, 4), c->Np, c->Dp, c->yv, p.beta, c->b32, c->stream);
+    if (c->need16) launch_rhs(nullptr, c->phi16T, dict_ld(c->Np, 2), c->Np, c->Dp, c->yv, p.beta, c->b16, c->stream);
   }
 }
 
@@ -459,7 +459,11 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   const int64_t ysplit = matrix_free ? 0
                               : std::max<int64_t>(std::max<int64_t>(c->g1_16.splits, c->g1_32.splits) * Np,
                                                   std::max<int64_t>(c->g2_16.splits, c->g2_32.splits) * Dp);
-  const size_t nd = matrix_free ? 0 : (size_t)Np * (size_t)Dp;
+  // dictionary layouts: rows padded to dict_ld (row-major Np rows, transposed Dp rows)
+  const size_t nd32 = matrix_free ? 0 : (size_t)Np * (size_t)dict_ld(Dp, 4);
+  const size_t nd32T = matrix_free ? 0 : (size_t)Dp * (size_t)dict_ld(Np, 4);
+  const size_t nd16 = matrix_free ? 0 : (size_t)Np * (size_t)dict_ld(Dp, 2);
+  const size_t nd16T = matrix_free ? 0 : (size_t)Dp * (size_t)dict_ld(Np, 2);
 #define TRY(x)                   \
   do {                           \
     cofem_status r_ = (x);       \
@@ -484,15 +488,15 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   }
   if (c->need32) {
     if (!matrix_free) {
-      TRY(dalloc(c, &c->phi32, nd));
-      TRY(dalloc(c, &c->phi32T, nd));
+      TRY(dalloc(c, &c->phi32, nd32));
+      TRY(dalloc(c, &c->phi32T, nd32T));
     }
     if (!dct) TRY(dalloc(c, &c->V, (size_t)Qp * Np));
   }
   if (c->need16) {
     if (!matrix_free) {
-      TRY(dalloc(c, &c->phi16, nd));
-      TRY(dalloc(c, &c->phi16T, nd));
+      TRY(dalloc(c, &c->phi16, nd16));
+      TRY(dalloc(c, &c->phi16T, nd16T));
     }
     TRY(dalloc(c, &c->PdH, (size_t)Qp * Dp));
     TRY(dalloc(c, &c->PdL, (size_t)Qp * Dp));

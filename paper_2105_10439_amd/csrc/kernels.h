@@ -46,19 +46,30 @@ struct SolveCfg {
 };
 
 // ---- setup -----------------------------------------------------------------
+// Row stride (elements) of the library's dictionary layouts: a row of `len` elements
+// of `elem_bytes` each, plus 128 bytes.  Row starts that are an odd multiple of 128
+// bytes spread the rows a contraction tile streams at once over the HBM channels;
+// with rows a multiple of 256 bytes long they would land on the same few (measured
+// on the 16384 x 65536 bf16 operator: 5.06 -> 5.57 TB/s for the D-long rows, 5.46 ->
+// 5.61 TB/s for the N-long ones).
+constexpr int64_t DICT_ROW_PAD_BYTES = 128;
+__host__ __device__ inline int64_t dict_ld(int64_t len, int elem_bytes) { return len + DICT_ROW_PAD_BYTES / elem_bytes; }
+
 // Copy the caller's N x D row-major FP32 dictionary into padded layouts:
-// phi32 (Np x Dp), phi32T (Dp x Np), phi16 (Np x Dp, bf16 bits), phi16T (Dp x Np).
-// Any output pointer may be null.  Padding is zero.
+// phi32 (Np rows of dict_ld(Dp, 4)), phi32T (Dp rows of dict_ld(Np, 4)), phi16 (Np rows
+// of dict_ld(Dp, 2), bf16 bits), phi16T (Dp rows of dict_ld(Np, 2)).  Any output
+// pointer may be null.  Entries past D (or N) up to Dp (or Np) are zero; the row pad
+// past Dp (or Np) is never read.
 void launch_dict_layouts(const float* phi, int64_t N, int64_t D, int64_t Np, int64_t Dp, float* phi32,
                          float* phi32T, uint16_t* phi16, uint16_t* phi16T, hipStream_t s);
 
 // theta_j = sum_i Phi_ij^2 (jacobi) or 1 from the caller's N x D matrix; padding 1.
 void launch_theta(const float* phi, int64_t N, int64_t D, int64_t Dp, int jacobi, float* theta, hipStream_t s);
 
-// b_j = beta * sum_i Phi_ij y_i from the transposed layout (FP32 if phi32T is not
-// null, else bf16), FP64 sums; y is the padded observation (Np floats).
-void launch_rhs(const float* phi32T, const uint16_t* phi16T, int64_t Np, int64_t Dp, const float* y, double beta,
-                float* b, hipStream_t s);
+// b_j = beta * sum_i Phi_ij y_i from a transposed layout with rows of `ld` elements
+// (FP32 if phi32T is not null, else the bf16 phi16T).
+void launch_rhs(const float* phi32T, const uint16_t* phi16T, int64_t ld, int64_t Np, int64_t Dp, const float* y,
+                double beta, float* b, hipStream_t s);
 
 // x[0..n) = v.
 void launch_fill(float* x, float v, int64_t n, hipStream_t s);
@@ -88,6 +99,7 @@ GemmCfg choose_gemm(int64_t rows, int64_t kdim, int bf16);
 
 // Ypart[split][q][row] = sum_{k in split} M[row, k] Z[q, k] for the Q real columns (rows of
 // Ypart past the column tiles are not written); Qp is the padded column count of Z and Ypart.
+// M has rows of dict_ld(kdim, element bytes) elements.
 // bf16: M, ZH, ZL are bf16 bits, products of M with ZH and ZL accumulate in FP32.
 void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
                       const uint16_t* ZL, int Q, int Qp, float* Ypart, const CGState* st, hipStream_t s);

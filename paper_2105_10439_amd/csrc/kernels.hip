@@ -29,22 +29,23 @@ __global__ __launch_bounds__(256) void k_dict_layouts(const float* __restrict__ 
                                                       int64_t Np, int64_t Dp, float* __restrict__ phi32,
                                                       float* __restrict__ phi32T, uint16_t* __restrict__ phi16,
                                                       uint16_t* __restrict__ phi16T) {
+  const int64_t ld32 = dict_ld(Dp, 4), ld32T = dict_ld(Np, 4), ld16 = dict_ld(Dp, 2), ld16T = dict_ld(Np, 2);
   __shared__ float tile[64][65];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t j0 = (int64_t)blockIdx.x * 64, i0 = (int64_t)blockIdx.y * 64;
   for (int r = ty; r < 64; r += 4) {
     const int64_t i = i0 + r, j = j0 + tx;
     const float v = (i < N && j < D) ? phi[i * D + j] : 0.0f;
-    if (phi32) phi32[i * Dp + j] = v;
-    if (phi16) phi16[i * Dp + j] = bf16_rne(v);
+    if (phi32) phi32[i * ld32 + j] = v;
+    if (phi16) phi16[i * ld16 + j] = bf16_rne(v);
     tile[r][tx] = v;
   }
   __syncthreads();
   for (int r = ty; r < 64; r += 4) {
     const int64_t j = j0 + r, i = i0 + tx;
     const float v = tile[tx][r];
-    if (phi32T) phi32T[j * Np + i] = v;
-    if (phi16T) phi16T[j * Np + i] = bf16_rne(v);
+    if (phi32T) phi32T[j * ld32T + i] = v;
+    if (phi16T) phi16T[j * ld16T + i] = bf16_rne(v);
   }
 }
 
@@ -75,12 +76,12 @@ template <>
 __device__ __forceinline__ double ld_val<uint16_t>(const uint16_t* p, int64_t i) { return (double)bf16_val(p[i]); }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_rhs(const T* __restrict__ MT, int64_t Np, int64_t Dp,
+__global__ __launch_bounds__(256) void k_rhs(const T* __restrict__ MT, int64_t ld, int64_t Np, int64_t Dp,
                                              const float* __restrict__ y, double beta, float* __restrict__ b) {
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int ln = threadIdx.x & 63;
   if (j >= Dp) return;
-  const T* row = MT + j * Np;
+  const T* row = MT + j * ld;
   double acc = 0.0;
   for (int64_t i = ln; i < Np; i += 64) acc += ld_val<T>(row, i) * (double)y[i];
   acc = wave_sum(acc);
@@ -274,12 +275,12 @@ void launch_theta(const float* phi, int64_t N, int64_t D, int64_t Dp, int jacobi
   hipLaunchKernelGGL(k_theta, dim3(cdiv(Dp, 256)), dim3(256), 0, s, phi, N, D, Dp, jacobi, theta);
 }
 
-void launch_rhs(const float* phi32T, const uint16_t* phi16T, int64_t Np, int64_t Dp, const float* y, double beta,
-                float* b, hipStream_t s) {
+void launch_rhs(const float* phi32T, const uint16_t* phi16T, int64_t ld, int64_t Np, int64_t Dp, const float* y,
+                double beta, float* b, hipStream_t s) {
   if (phi32T)
-    hipLaunchKernelGGL(k_rhs<float>, dim3(cdiv(Dp, 4)), dim3(256), 0, s, phi32T, Np, Dp, y, beta, b);
+    hipLaunchKernelGGL(k_rhs<float>, dim3(cdiv(Dp, 4)), dim3(256), 0, s, phi32T, ld, Np, Dp, y, beta, b);
   else
-    hipLaunchKernelGGL(k_rhs<uint16_t>, dim3(cdiv(Dp, 4)), dim3(256), 0, s, phi16T, Np, Dp, y, beta, b);
+    hipLaunchKernelGGL(k_rhs<uint16_t>, dim3(cdiv(Dp, 4)), dim3(256), 0, s, phi16T, ld, Np, Dp, y, beta, b);
 }
 
 void launch_fill(float* x, float v, int64_t n, hipStream_t s) {
@@ -333,16 +334,17 @@ static inline void gemm_cols(int Q, int& ct, bool& x1) {
   ct = x1 ? Q / 16 : (Q + 15) / 16;
 }
 
-#define GEMM_BF16(RT, CT, X1)                                                                                      \
-  hipLaunchKernelGGL((k_gemm_bf16<RT, CT, KS_BF16, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, ZH, ZL, kdim, \
+#define GEMM_BF16(RT, CT, X1)                                                                                    \
+  hipLaunchKernelGGL((k_gemm_bf16<RT, CT, KS_BF16, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, ldm, ZH, ZL, kdim, \
                      Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done)
-#define GEMM_F32(RT, CT, X1)                                                                                      \
-  hipLaunchKernelGGL((k_gemm_f32<RT, CT, KS_F32, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, kdim, Z, kdim, Yp,   \
+#define GEMM_F32(RT, CT, X1)                                                                                    \
+  hipLaunchKernelGGL((k_gemm_f32<RT, CT, KS_F32, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, ldm, Z, kdim, Yp,  \
                      rows, Qp, g.kchunk, kdim, nrb, g.splits, done)
 
 template <int RT>
-static void gemm_bf16_rt(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
-                         const uint16_t* ZL, int Q, int Qp, float* Yp, const int* done, hipStream_t s) {
+static void gemm_bf16_rt(const GemmCfg& g, const uint16_t* M, int64_t ldm, int64_t rows, int64_t kdim,
+                         const uint16_t* ZH, const uint16_t* ZL, int Q, int Qp, float* Yp, const int* done,
+                         hipStream_t s) {
   const int nrb = (int)(rows / (64 * RT));
   dim3 grid((unsigned)(nrb * g.splits));
   int ct;
@@ -364,14 +366,15 @@ static void gemm_bf16_rt(const GemmCfg& g, const uint16_t* M, int64_t rows, int6
 void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
                       const uint16_t* ZL, int Q, int Qp, float* Yp, const CGState* st, hipStream_t s) {
   const int* done = st ? &st->done : nullptr;
-  if (g.rt == 4) gemm_bf16_rt<4>(g, M, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
-  else if (g.rt == 2) gemm_bf16_rt<2>(g, M, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
-  else gemm_bf16_rt<1>(g, M, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
+  const int64_t ldm = dict_ld(kdim, 2);
+  if (g.rt == 4) gemm_bf16_rt<4>(g, M, ldm, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
+  else if (g.rt == 2) gemm_bf16_rt<2>(g, M, ldm, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
+  else gemm_bf16_rt<1>(g, M, ldm, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
 }
 
 template <int RT>
-static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Q, int Qp,
-                        float* Yp, const int* done, hipStream_t s) {
+static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t ldm, int64_t rows, int64_t kdim, const float* Z,
+                        int Q, int Qp, float* Yp, const int* done, hipStream_t s) {
   const int nrb = (int)(rows / (64 * RT));
   dim3 grid((unsigned)(nrb * g.splits));
   int ct;
@@ -393,9 +396,10 @@ static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t rows, int64_t 
 void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Q, int Qp,
                      float* Yp, const CGState* st, hipStream_t s) {
   const int* done = st ? &st->done : nullptr;
-  if (g.rt == 4) gemm_f32_rt<4>(g, M, rows, kdim, Z, Q, Qp, Yp, done, s);
-  else if (g.rt == 2) gemm_f32_rt<2>(g, M, rows, kdim, Z, Q, Qp, Yp, done, s);
-  else gemm_f32_rt<1>(g, M, rows, kdim, Z, Q, Qp, Yp, done, s);
+  const int64_t ldm = dict_ld(kdim, 4);
+  if (g.rt == 4) gemm_f32_rt<4>(g, M, ldm, rows, kdim, Z, Q, Qp, Yp, done, s);
+  else if (g.rt == 2) gemm_f32_rt<2>(g, M, ldm, rows, kdim, Z, Q, Qp, Yp, done, s);
+  else gemm_f32_rt<1>(g, M, ldm, rows, kdim, Z, Q, Qp, Yp, done, s);
 }
 
 void launch_finish_pass1(const float* Ypart, int splits, int Q, int Qp, int64_t Np, float* V, uint16_t* VH,

@@ -559,7 +559,7 @@ cofem_status admit(cofem_server* s, int slot, Request& r) {
                      L.Np, L.Dp, phiT);
   hipLaunchKernelGGL(ks_theta, dim3((unsigned)cdivi(L.Dp, 256)), dim3(256), 0, s->stream, phi, L.Np, p.D, L.Dp,
                      p.theta_mode == COFEM_THETA_JACOBI ? 1 : 0, sd.theta);
-  launch_rhs(phiT, nullptr, L.Np, L.Dp, yv, p.beta, sd.b, s->stream);
+  launch_rhs(phiT, nullptr, L.Np, L.Np, L.Dp, yv, p.beta, sd.b, s->stream);
   hipLaunchKernelGGL(ks_slot_start, dim3(64), dim3(256), 0, s->stream, sd.st, sd.alpha, L.Dp);
   SRV_TRY(hipGetLastError());
   // the caller's host buffers have been consumed once the copies above are done
