@@ -43,8 +43,8 @@ METRIC = "CoFEM EM-iters/s + HBM GB/s at D=65536 (BF16 vs FP32); serving p50/p99
 # WRITE_SIZE; KiB per dispatch, averaged over 6 dispatches), each scaled by what the
 # same counter reads for a plain 1 GiB device copy.  It holds only for the kernel
 # source it was taken on: the hash covers the tile function and the launch shape choice.
-GEMM_TRAFFIC = dict(src_sha="0c80e7a9af4a815c", fetch_kib=1065091.1, write_kib=16963.5,
-                    copy_kib=1048576.0, copy_fetch_kib=524304.6, copy_write_kib=1048576.0,
+GEMM_TRAFFIC = dict(src_sha="5e8008e5287144df", fetch_kib=1055284.7, write_kib=16896.0,
+                    copy_kib=1048576.0, copy_fetch_kib=524302.4, copy_write_kib=1048576.0,
                     profile="profiles/hbm_traffic_k_gemm_bf16_dense_N16384_D65536.md")
 
 
@@ -54,11 +54,14 @@ def gemm_source_sha() -> str:
     csrc = os.path.join(ROOT, "paper_2105_10439_amd", "csrc")
     tiles = open(os.path.join(csrc, "tiles.h")).read()
     kern = open(os.path.join(csrc, "kernels.hip")).read()
+    hdr = open(os.path.join(csrc, "kernels.h")).read()
     a = tiles.index("constexpr int GEMM_WAVES")
     b = tiles.index("// FP32: v_mfma_f32_16x16x4_f32.")
     c = kern.index("GemmCfg choose_gemm(")
     d = kern.index("template <int RT>\nstatic void gemm_bf16_rt(")
-    return hashlib.sha256((tiles[a:b] + kern[c:d]).encode()).hexdigest()[:16]
+    e = hdr.index("constexpr int64_t DICT_ROW_PAD_BYTES")
+    f = hdr.index("\n", hdr.index("inline int64_t dict_ld(", e))
+    return hashlib.sha256((tiles[a:b] + kern[c:d] + hdr[e:f]).encode()).hexdigest()[:16]
 
 
 def gemm_traffic(N: int, D: int, dom: str):
