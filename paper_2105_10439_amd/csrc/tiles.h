@@ -172,17 +172,19 @@ __device__ __forceinline__ void store_x1(float (&xacc)[RT], float* __restrict__ 
 
 // bf16: v_mfma_f32_16x16x32_bf16, lane l holds A[l%16][8(l/16) .. +8), B[8(l/16) .. +8)[l%16]
 // and returns D[4(l/16) .. +4)[l%16].  ZH + ZL carries each right-hand side to ~2^-17.
-// X1: one more right-hand side (column 16 CT, e.g. the 33rd of K = 32 probes) on the vector
-// ALU instead of a mostly empty MFMA column tile: lane (r16, g) accumulates its row's
-// products over its k-subset in FP32 (the column's value is hi + lo), and the four
-// g-lanes of a row are summed at the end.
+// X1: one more right-hand side (column 16 CT, e.g. the 33rd of K = 32 probes) in a third
+// MFMA column tile that carries its hi piece as column 0 and its lo piece as column 1 (the
+// other 14 columns of that tile are don't-care: an MFMA output column depends on its own B
+// column only), so it costs one MFMA per row tile and 32-k step instead of two, and the
+// two result columns are added lane to lane at the end.
 template <int RT, int CT, int KS, bool X1>
 __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict__ M, int64_t ldm,
                                                const uint16_t* __restrict__ ZH, const uint16_t* __restrict__ ZL,
                                                int64_t ldz, float* __restrict__ Yp, int64_t ldy, int Qp,
                                                int64_t kchunk, int64_t kdim, int nrb, int splits) {
-  constexpr int NF = KS * CT * 2;  // fragments per stage
-  constexpr int SK = 32 * KS;      // k per stage
+  constexpr int FS = CT * 2 + (X1 ? 1 : 0);  // fragments per 32-k step
+  constexpr int NF = KS * FS;                 // fragments per stage
+  constexpr int SK = 32 * KS;                 // k per stage
   __shared__ bf16x8_t sB[2][NF][64];
   int rb, sp;
   tile_of(L, nrb, splits, rb, sp);
@@ -197,18 +199,26 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
     for (int i = 0; i < (NF + 3) / 4; ++i) {
       const int f = wave + 4 * i;
       if (f < NF) {
-        const int s = f / (CT * 2), rem = f % (CT * 2), ct = rem >> 1, hl = rem & 1;
-        lds_dma16((hl ? ZL : ZH) + (int64_t)(ct * 16 + r16) * ldz + kb + (int64_t)st * SK + s * 32 + 8 * g,
-                  &sB[buf][f][0]);
+        const int s = f / FS, rem = f % FS;
+        const int64_t k = kb + (int64_t)st * SK + s * 32 + 8 * g;
+        if (X1 && rem == CT * 2) {
+          // the extra column: lanes of column 1 take its lo piece, all others its hi piece
+          lds_dma16((r16 == 1 ? ZL : ZH) + (int64_t)(CT * 16) * ldz + k, &sB[buf][f][0]);
+        } else {
+          const int ct = rem >> 1, hl = rem & 1;
+          lds_dma16((hl ? ZL : ZH) + (int64_t)(ct * 16 + r16) * ldz + k, &sB[buf][f][0]);
+        }
       }
     }
   };
   const int64_t row0 = (int64_t)rb * (64 * RT) + (int64_t)wave * (16 * RT);
-  f32x4 acc[RT][CT];
+  f32x4 acc[RT][CT], accx[RT];
 #pragma unroll
-  for (int a = 0; a < RT; ++a)
+  for (int a = 0; a < RT; ++a) {
 #pragma unroll
     for (int b = 0; b < CT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    accx[a] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
   const uint16_t* ap[RT];
 #pragma unroll
   for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 8 * g;
@@ -217,20 +227,6 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
   for (int a = 0; a < RT; ++a)
 #pragma unroll
     for (int s = 0; s < KS; ++s) acur[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + s * 32);
-  // the extra column: this lane's 8 k of each sub-step, hi and lo
-  const uint16_t* xh = ZH + (int64_t)(CT * 16) * ldz + kb + 8 * g;
-  const uint16_t* xl = ZL + (int64_t)(CT * 16) * ldz + kb + 8 * g;
-  u16x8v xcur[KS][2];
-  float xacc[RT];
-  if constexpr (X1) {
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      xcur[s][0] = *reinterpret_cast<const u16x8v*>(xh + s * 32);
-      xcur[s][1] = *reinterpret_cast<const u16x8v*>(xl + s * 32);
-    }
-#pragma unroll
-    for (int a = 0; a < RT; ++a) xacc[a] = 0.0f;
-  }
   issue_B(0, 0);
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
@@ -242,14 +238,6 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int s = 0; s < KS; ++s) anxt[a][s] = *reinterpret_cast<const bf16x8_t*>(ap[a] + (int64_t)nx * SK + s * 32);
-    u16x8v xnxt[KS][2];
-    if constexpr (X1) {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        xnxt[s][0] = *reinterpret_cast<const u16x8v*>(xh + (int64_t)nx * SK + s * 32);
-        xnxt[s][1] = *reinterpret_cast<const u16x8v*>(xl + (int64_t)nx * SK + s * 32);
-      }
-    }
     issue_B(nx, buf ^ 1);
     __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this stage's MFMAs
 #pragma unroll
@@ -257,8 +245,8 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
       bf16x8_t bh[CT], bl[CT];
 #pragma unroll
       for (int b = 0; b < CT; ++b) {
-        bh[b] = sB[buf][(s * CT + b) * 2 + 0][lane];
-        bl[b] = sB[buf][(s * CT + b) * 2 + 1][lane];
+        bh[b] = sB[buf][s * FS + b * 2 + 0][lane];
+        bl[b] = sB[buf][s * FS + b * 2 + 1][lane];
       }
 #pragma unroll
       for (int a = 0; a < RT; ++a)
@@ -268,28 +256,15 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[a][s], bl[b], acc[a][b], 0, 0, 0);
         }
       if constexpr (X1) {
-        float z[8];
+        const bf16x8_t bx = sB[buf][s * FS + CT * 2][lane];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) z[j] = bf16_val(xcur[s][0][j]) + bf16_val(xcur[s][1][j]);
-#pragma unroll
-        for (int a = 0; a < RT; ++a) {
-          const u16x8v av = __builtin_bit_cast(u16x8v, acur[a][s]);
-#pragma unroll
-          for (int j = 0; j < 8; ++j) xacc[a] = __builtin_fmaf(bf16_val(av[j]), z[j], xacc[a]);
-        }
+        for (int a = 0; a < RT; ++a) accx[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[a][s], bx, accx[a], 0, 0, 0);
       }
     }
 #pragma unroll
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int s = 0; s < KS; ++s) acur[a][s] = anxt[a][s];
-    if constexpr (X1) {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        xcur[s][0] = xnxt[s][0];
-        xcur[s][1] = xnxt[s][1];
-      }
-    }
   }
   wait_vm_all();  // the last (self-reloading) DMA has landed before the LDS is released
   float* yb = Yp + (int64_t)sp * Qp * ldy;
@@ -301,7 +276,17 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
       const int64_t row = row0 + a * 16 + 4 * g;
       *reinterpret_cast<f32x4*>(yb + q * ldy + row) = acc[a][b];
     }
-  if constexpr (X1) store_x1<RT>(xacc, yb + (int64_t)(CT * 16) * ldy, row0, r16, g);
+  if constexpr (X1) {
+    // column 16 CT = hi column (lanes r16 = 0) + lo column (lanes r16 = 1)
+    float* ycol = yb + (int64_t)(CT * 16) * ldy;
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      f32x4 v = accx[a];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] += __shfl_down(v[e], 1, 64);
+      if (r16 == 0) *reinterpret_cast<f32x4*>(ycol + row0 + a * 16 + 4 * g) = v;
+    }
+  }
 }
 
 // FP32: v_mfma_f32_16x16x4_f32.  Each lane holds 4 consecutive k of its row (and of its
