@@ -60,7 +60,7 @@ def gemm_source_sha() -> str:
     c = kern.index("GemmCfg choose_gemm(")
     d = kern.index("template <int RT>\nstatic void gemm_bf16_rt(")
     e = hdr.index("constexpr int64_t DICT_ROW_PAD_BYTES")
-    f = hdr.index("\n", hdr.index("inline int64_t dict_ld(", e))
+    f = hdr.index("\n}", hdr.index("inline int64_t dict_ld(", e))
     return hashlib.sha256((tiles[a:b] + kern[c:d] + hdr[e:f]).encode()).hexdigest()[:16]
 
 

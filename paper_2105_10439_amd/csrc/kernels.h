@@ -46,14 +46,16 @@ struct SolveCfg {
 };
 
 // ---- setup -----------------------------------------------------------------
-// Row stride (elements) of the library's dictionary layouts: a row of `len` elements
-// of `elem_bytes` each, plus 128 bytes.  Row starts that are an odd multiple of 128
-// bytes spread the rows a contraction tile streams at once over the HBM channels;
-// with rows a multiple of 256 bytes long they would land on the same few (measured
-// on the 16384 x 65536 bf16 operator: 5.06 -> 5.57 TB/s for the D-long rows, 5.46 ->
-// 5.61 TB/s for the N-long ones).
+// Row stride (elements) of the library's dictionary layouts.  bf16 rows get 128 bytes
+// of padding: row starts that are an odd multiple of 128 bytes spread the rows a
+// contraction tile streams at once over the HBM channels, where rows a multiple of 256
+// bytes long would land on the same few (bf16 tile at 16384 x 65536: 5.06 -> 5.57 TB/s
+// on the D-long rows, 5.46 -> 5.61 TB/s on the N-long ones).  FP32 rows stay unpadded:
+// that contraction is bound by the FP32 matrix rate, and the pad measured 3 % slower.
 constexpr int64_t DICT_ROW_PAD_BYTES = 128;
-__host__ __device__ inline int64_t dict_ld(int64_t len, int elem_bytes) { return len + DICT_ROW_PAD_BYTES / elem_bytes; }
+__host__ __device__ inline int64_t dict_ld(int64_t len, int elem_bytes) {
+  return elem_bytes == 2 ? len + DICT_ROW_PAD_BYTES / elem_bytes : len;
+}
 
 // Copy the caller's N x D row-major FP32 dictionary into padded layouts:
 // phi32 (Np rows of dict_ld(Dp, 4)), phi32T (Dp rows of dict_ld(Np, 4)), phi16 (Np rows
