@@ -79,7 +79,7 @@ struct cofem_ctx {
   float* hp32 = nullptr;
   uint16_t* hp16 = nullptr;
   // subsampled DCT dictionary: transform tables, mask, kept samples, scratch signal
-  float2 *dct_tw = nullptr, *dct_wq = nullptr, *dct_wh = nullptr, *dct_mz = nullptr;
+  float2 *dct_tw = nullptr, *dct_w2 = nullptr, *dct_mz = nullptr;
   int32_t* dct_rows = nullptr;
   float* dct_u = nullptr;
   // D- and N-vectors
@@ -236,9 +236,8 @@ DctArgs dct_args(const cofem_ctx* c) {
   a.s0 = (float)std::sqrt(1.0 / (double)c->p.D);
   a.s1 = (float)std::sqrt(2.0 / (double)c->p.D);
   a.tw = c->dct_tw;
-  a.wq = c->dct_wq;
-  a.wh = c->dct_wh;
   a.mz = c->dct_mz;
+  a.w2 = c->dct_w2;
   a.beta = c->p.beta;
   return a;
 }
@@ -480,8 +479,7 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   if (dct) {
     const size_t L = (size_t)(p->D / 2);
     TRY(dalloc(c, &c->dct_tw, L));
-    TRY(dalloc(c, &c->dct_wq, L + 1));
-    TRY(dalloc(c, &c->dct_wh, L + 1));
+    TRY(dalloc(c, &c->dct_w2, (size_t)DCT_W2_SIZE));
     TRY(dalloc(c, &c->dct_mz, L));
     TRY(dalloc(c, &c->dct_rows, (size_t)p->N));
     TRY(dalloc(c, &c->dct_u, (size_t)Dp));
@@ -591,7 +589,7 @@ COFEM_API cofem_status cofem_set_dct_samples(cofem_ctx* c, const int32_t* rows) 
     seen[h[i]] = 1;
   }
   HIP_TRY(hipMemcpyAsync(c->dct_rows, h.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, c->stream));
-  launch_dct_setup(c->dct_rows, N, D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->dct_tw, c->dct_wq, c->dct_wh,
+  launch_dct_setup(c->dct_rows, N, D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->dct_tw, c->dct_w2,
                    c->dct_mz, c->dct_u, c->theta, c->stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(c->stream));

@@ -30,6 +30,8 @@
 // stores; a slot of padding per 16 points keeps the strided stores free of bank
 // conflicts.  Twiddles, the DCT phase factors and the mask come from small tables
 // built once in FP64 and rounded to FP32.
+#include <algorithm>
+
 #include "kernels.h"
 #include "device_common.h"
 
@@ -67,6 +69,23 @@ __device__ __forceinline__ int lds_slot(int i) { return i + (i >> 4); }
 // The same buffer read as D real values: value f at float f + 2 (f / 32).
 __device__ __forceinline__ int lds_real(int f) { return f + 2 * (f >> 5); }
 constexpr int lds_slots(int L) { return L + L / 16; }
+
+// Phase factors W_4D^m = e^{-2 pi i m / 4D} (m < 4D) from a two-level table kept in LDS:
+// W^m = lo[m mod 2^LO] * hi[m >> LO], 2^LO + 2^HI entries for 4D = 2^(LO + HI).  The
+// DCT factors are e^{-i pi k / 2D} = W_4D^k and e^{-2 pi i k / D} = W_4D^{4k}.
+constexpr int wt_lo(int log2L) { return (log2L + 3 + 1) / 2; }
+constexpr int wt_hi(int log2L) { return log2L + 3 - wt_lo(log2L); }
+constexpr int wt_size(int log2L) { return (1 << wt_lo(log2L)) + (1 << wt_hi(log2L)); }
+template <int LOG2L>
+__device__ __forceinline__ float2 w4d(const float2* wt, int m) {
+  constexpr int LO = wt_lo(LOG2L);
+  return cmul(wt[m & ((1 << LO) - 1)], wt[(1 << LO) + (m >> LO)]);
+}
+// Copy the table into LDS (callers place a barrier before its first use).
+template <int LOG2L, int NT>
+__device__ __forceinline__ void load_wt(float2* wt, const float2* __restrict__ w2) {
+  for (int i = threadIdx.x; i < wt_size(LOG2L); i += NT) wt[i] = w2[i];
+}
 
 // In-register forward DFTs of 2, 4, 8 and 16 points, natural order in and out.
 __device__ __forceinline__ void dft2(float2* v) {
@@ -223,7 +242,7 @@ __device__ __forceinline__ float2 real_split(float2 za, float2 zb, float2 whk) {
 // After fft_forward: the DCT-II of the reordered signal, C_k = sum_n x_n
 // cos(pi (2n + 1) k / 2D) (unnormalised), written over buf as D real values.
 template <int LOG2L>
-__device__ __forceinline__ void dct_post(float2* buf, const DctArgs& a) {
+__device__ __forceinline__ void dct_post(float2* buf, const float2* wt) {
   constexpr int L = 1 << LOG2L, NT = dct_threads(LOG2L);
   constexpr int IT = (L / 2 + 1 + NT - 1) / NT;
   const int D = 2 * L;
@@ -242,14 +261,14 @@ __device__ __forceinline__ void dct_post(float2* buf, const DctArgs& a) {
   for (int i = 0; i < IT; ++i) {
     const int t = threadIdx.x + i * NT;
     if (t <= L / 2) {
-      float2 w = cmul(a.wq[t], real_split(A[i], B[i], a.wh[t]));
+      float2 w = cmul(w4d<LOG2L>(wt, t), real_split(A[i], B[i], w4d<LOG2L>(wt, 4 * t)));
       cb[lds_real(t)] = w.x;
       if (t > 0) cb[lds_real(D - t)] = -w.y;
       if (t == 0) {
-        w = cmul(a.wq[L], real_split(A[i], A[i], a.wh[L]));
+        w = cmul(w4d<LOG2L>(wt, L), real_split(A[i], A[i], w4d<LOG2L>(wt, 4 * L)));
         cb[lds_real(L)] = w.x;
       } else if (t < L / 2) {
-        w = cmul(a.wq[L - t], real_split(B[i], A[i], a.wh[L - t]));
+        w = cmul(w4d<LOG2L>(wt, L - t), real_split(B[i], A[i], w4d<LOG2L>(wt, 4 * (L - t))));
         cb[lds_real(L - t)] = w.x;
         cb[lds_real(L + t)] = -w.y;
       }
@@ -268,9 +287,11 @@ __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_operator(DctArgs a) 
   constexpr int IT = (L / 2 + 1 + NT - 1) / NT;
   __shared__ __align__(16) float2 buf[lds_slots(L)];
   __shared__ double red[(D + 255) / 256 + 4];
+  __shared__ float2 wt[wt_size(LOG2L)];
   if (a.done && *a.done) return;  // a step enqueued after the stop rule fired
   const int q = blockIdx.x;
   const float* __restrict__ p = a.in + (int64_t)q * a.Dp;
+  load_wt<LOG2L, NT>(wt, a.w2);
   // Inverse transform, spectrum side.  With c_k = s_k Pd_k, the Hermitian
   // spectrum of the reordered output is H_0 = c_0, H_k = e^{i pi k / 2D} (c_k -
   // i c_{D-k}) / 2; its half-length form is Z_k = E_k + i O_k with E_k = H_k +
@@ -286,11 +307,11 @@ __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_operator(DctArgs a) 
     const float2 o = cmul(csub(h1, cconj(h2)), cconj(whk));
     return cadd(e, ctimes_i(o));
   };
+  lds_barrier();  // the phase-factor table is in LDS
   constexpr int G1 = IT < 3 ? IT : 3;  // items whose loads are issued together
 #pragma unroll 1
   for (int i0 = 0; i0 < IT; i0 += G1) {
     float c_t[G1], c_dt[G1], c_lt[G1], c_lpt[G1];
-    float2 wq_t[G1], wq_lt[G1], wh_t[G1], wh_lt[G1];
 #pragma unroll
     for (int g = 0; g < G1; ++g) {
       const int t = threadIdx.x + (i0 + g) * NT;
@@ -299,19 +320,16 @@ __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_operator(DctArgs a) 
         c_dt[g] = t > 0 ? p[D - t] : 0.0f;
         c_lt[g] = p[L - t];
         c_lpt[g] = p[L + t];
-        wq_t[g] = a.wq[t];
-        wq_lt[g] = a.wq[L - t];
-        wh_t[g] = a.wh[t];
-        wh_lt[g] = a.wh[L - t];
       }
     }
 #pragma unroll
     for (int g = 0; g < G1; ++g) {
       const int t = threadIdx.x + (i0 + g) * NT;
       if (i0 + g < IT && t <= L / 2) {
-        const float2 h1 = hval(t, c_t[g], c_dt[g], wq_t[g]), h2 = hval(L - t, c_lt[g], c_lpt[g], wq_lt[g]);
-        buf[lds_slot(t)] = cconj(zval(h1, h2, wh_t[g]));
-        if (t > 0 && t < L / 2) buf[lds_slot(L - t)] = cconj(zval(h2, h1, wh_lt[g]));
+        const float2 h1 = hval(t, c_t[g], c_dt[g], w4d<LOG2L>(wt, t));
+        const float2 h2 = hval(L - t, c_lt[g], c_lpt[g], w4d<LOG2L>(wt, L - t));
+        buf[lds_slot(t)] = cconj(zval(h1, h2, w4d<LOG2L>(wt, 4 * t)));
+        if (t > 0 && t < L / 2) buf[lds_slot(L - t)] = cconj(zval(h2, h1, w4d<LOG2L>(wt, 4 * (L - t))));
       }
     }
   }
@@ -320,7 +338,7 @@ __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_operator(DctArgs a) 
   // buf = conj(z), z_m = v_2m + i v_{2m+1} the reordered Omega^T Pd.  The next
   // transform's first pass reads z' = (m_2m v_2m, m_{2m+1} v_{2m+1}).
   fft_forward<LOG2L, true>(buf, a.tw, a.mz);
-  dct_post<LOG2L>(buf, a);
+  dct_post<LOG2L>(buf, wt);
   // Psi = beta s_k C_k + alpha_k Pd_k, 4 coordinates per thread and iteration; the
   // pi partial of each run of 256 coordinates is one wave's sum, and chunk c of
   // 1024 coordinates adds runs 4c .. 4c + 3 in order.
@@ -386,7 +404,9 @@ __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_forward(DctArgs a) {
   constexpr int D = 2 * L;
   constexpr int IT = (L + NT - 1) / NT;
   __shared__ __align__(16) float2 buf[lds_slots(L)];
+  __shared__ float2 wt[wt_size(LOG2L)];
   const float* __restrict__ u = a.in;
+  load_wt<LOG2L, NT>(wt, a.w2);
   // z_m = v_2m + i v_{2m+1} with v_n = u_2n (n < L), v_n = u_{2(D-1-n)+1} (n >= L)
   float2 z[IT];
 #pragma unroll
@@ -402,7 +422,7 @@ __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_forward(DctArgs a) {
   }
   lds_barrier();
   fft_forward<LOG2L, false>(buf, a.tw, a.mz);
-  dct_post<LOG2L>(buf, a);
+  dct_post<LOG2L>(buf, wt);
   const float* __restrict__ cb = reinterpret_cast<const float*>(buf);
   for (int64_t j = threadIdx.x; j < a.Dp; j += NT) {
     const float sk = (j == 0) ? a.s0 : a.s1;
@@ -413,21 +433,25 @@ __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_forward(DctArgs a) {
 // ---------------------------------------------------------------------------
 // Set-up: tables, mask, theta, right-hand side
 // ---------------------------------------------------------------------------
-// tw_i = e^{-2 pi i i / L} (i < L); wq_k = e^{-i pi k / 2D}, wh_k = e^{-2 pi i k / D}
-// (k <= L), from FP64 sincospi (the arguments are exact binary fractions).
-__global__ void k_dct_tables(int L, float2* __restrict__ tw, float2* __restrict__ wq, float2* __restrict__ wh) {
+// tw_i = e^{-2 pi i i / L} (i < L) and the two-level table of W_4D = e^{-2 pi i / 4D}:
+// w2[i] = W^i (i < 2^lo), w2[2^lo + i] = W^(i 2^lo) (i < 2^hi), from FP64 sincospi (the
+// arguments are exact binary fractions).
+__global__ void k_dct_tables(int L, int lo, int hi, float2* __restrict__ tw, float2* __restrict__ w2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > L) return;
   const double D = 2.0 * L;
   double s, c;
+  if (i < (1 << lo)) {
+    sincospi(2.0 * i / (4.0 * D), &s, &c);
+    w2[i] = make_float2((float)c, (float)-s);
+  }
+  if (i < (1 << hi)) {
+    sincospi(2.0 * (double)i * (double)(1 << lo) / (4.0 * D), &s, &c);
+    w2[(1 << lo) + i] = make_float2((float)c, (float)-s);
+  }
   if (i < L) {
     sincospi(2.0 * i / L, &s, &c);
     tw[i] = make_float2((float)c, (float)-s);
   }
-  sincospi(i / (2.0 * D), &s, &c);
-  wq[i] = make_float2((float)c, (float)-s);
-  sincospi(2.0 * i / D, &s, &c);
-  wh[i] = make_float2((float)c, (float)-s);
 }
 
 // mx[rows_i] = v_i (v = null: 1).  mx must be zero beforehand; rows are distinct.
@@ -495,10 +519,12 @@ int log2_half(int64_t D) {
 
 bool dct_size_ok(int64_t D) { return D >= DCT_MIN_D && D <= DCT_MAX_D && (D & (D - 1)) == 0; }
 
-void launch_dct_setup(const int32_t* rows, int64_t N, int64_t D, int64_t Dp, int jacobi, float2* tw, float2* wq,
-                      float2* wh, float2* mz, float* mx, float* theta, hipStream_t s) {
+void launch_dct_setup(const int32_t* rows, int64_t N, int64_t D, int64_t Dp, int jacobi, float2* tw, float2* w2,
+                      float2* mz, float* mx, float* theta, hipStream_t s) {
   const int L = (int)(D / 2);
-  hipLaunchKernelGGL(k_dct_tables, dim3((L + 1 + 255) / 256), dim3(256), 0, s, L, tw, wq, wh);
+  const int lg = log2_half(D) + 3, lo = (lg + 1) / 2, hi = lg - lo;
+  const int n = std::max(L, 1 << lo);
+  hipLaunchKernelGGL(k_dct_tables, dim3((n + 255) / 256), dim3(256), 0, s, L, lo, hi, tw, w2);
   launch_fill(mx, 0.0f, Dp, s);
   hipLaunchKernelGGL(k_dct_scatter, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, rows,
                      static_cast<const float*>(nullptr), N, mx);

@@ -184,13 +184,15 @@ void launch_conv_pass(const ConvArgs& a, int dir, int bf16, hipStream_t s);
 // of one column lives in LDS).
 constexpr int64_t DCT_MIN_D = 16;
 constexpr int64_t DCT_MAX_D = 32768;
+constexpr int DCT_W2_SIZE = 1024;  // >= 2^lo + 2^hi for 4D = 2^(lo + hi) up to 4 DCT_MAX_D
 bool dct_size_ok(int64_t D);
 
 struct DctArgs {
   int64_t D, Dp;
   int nbx;                           // pi partial chunks per column, cdiv(Dp, 1024)
   float s0, s1;                      // orthonormal scales sqrt(1/D), sqrt(2/D)
-  const float2 *tw, *wq, *wh, *mz;   // FFT twiddles, DCT phase factors, mask (dct.hip)
+  const float2 *tw, *mz;             // FFT twiddles (D/2 entries), mask pairs (D/2 entries)
+  const float2* w2;                  // two-level table of e^{-2 pi i m / 4D} (DCT_W2_SIZE entries)
   const float* in;                   // operator: Pd (Qp x Dp); forward: one signal of D samples
   float* out;                        // operator: Psi; forward: beta Omega in
   double beta;
@@ -198,11 +200,11 @@ struct DctArgs {
   double* pipart;                    // operator only: [q][chunk]
   const int* done;                   // operator only, may be null
 };
-// Tables (tw: D/2, wq and wh: D/2 + 1, mz: D/2 entries), the mask (mx: Dp floats of
+// Tables (tw: D/2, w2: DCT_W2_SIZE, mz: D/2 entries), the mask (mx: Dp floats of
 // scratch), and theta (Jacobi: column norms of Phi; else ones).  rows: N distinct
 // sample indices in [0, D) on the device.
-void launch_dct_setup(const int32_t* rows, int64_t N, int64_t D, int64_t Dp, int jacobi, float2* tw, float2* wq,
-                      float2* wh, float2* mz, float* mx, float* theta, hipStream_t s);
+void launch_dct_setup(const int32_t* rows, int64_t N, int64_t D, int64_t Dp, int jacobi, float2* tw, float2* w2,
+                      float2* mz, float* mx, float* theta, hipStream_t s);
 // b = beta Phi^T y = beta Omega (M^T y) into a.out (u: Dp floats of scratch).
 void launch_dct_rhs(const DctArgs& a, const float* y, const int32_t* rows, int64_t N, float* u, hipStream_t s);
 // Psi = A Pd for columns q < Q, one workgroup per column, with the pi partials.
