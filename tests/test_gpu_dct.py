@@ -3,8 +3,9 @@ the orthonormal DCT-II of size D, M keeping N of the D samples; the GPU applies
 A = beta Omega M^T M Omega^T + diag(alpha) with an LDS-resident FFT per column.
 
 * The operator against the oracle (scipy's DCT, itself pinned to the cosine sums):
-  every power of two the kernel supports (16 .. 2^15, so both the radix-4-only and
-  the radix-2-tail FFT lengths), ragged column counts, N = 1, N = D/3 and N = D.
+  every power of two the kernel supports (16 .. 2^15: FFT lengths 8 .. 2^14, i.e. zero
+  to three radix-16 passes with each of the radix-2, 4 and 8 tails), ragged column
+  counts, N = 1, N = D/3 and N = D.
   The FP32 FFT of length L = D/2 has a normwise error of a few log2(L) * 2^-24;
   the bar is 2e-5 per column.
 * Fits against the oracle at the same probes, stop rule and tolerance (mu within
@@ -12,7 +13,7 @@ A = beta Omega M^T M Omega^T + diag(alpha) with an LDS-resident FFT per column.
 * N = D: Phi is orthogonal, A is diagonal and theta = 1 gives the exact
   preconditioner, so every E-step ends after one CG step.
 * The full-size workload (D = 2^15, N = D/3, K = 20, T = 30, tol 1e-4) against
-  the oracle's fit, and bad sample sets rejected.
+  the oracle's fit (3x the sensitivity: see the test), and bad sample sets rejected.
 """
 import ctypes
 
