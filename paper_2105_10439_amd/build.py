@@ -51,7 +51,27 @@ def build(verbose: bool = False) -> str:
     if verbose and msgs:
         print("\n".join(msgs))
     os.replace(tmp, LIB)
+    build_c_caller(verbose)
     return LIB
+
+
+C_CALLER_SRC = os.path.join(ROOT, "tests", "c", "fit_smoke.c")
+C_CALLER = os.path.join(ROOT, "tests", "c", "fit_smoke")
+
+
+def build_c_caller(verbose: bool = False) -> str:
+    """The plain-C test caller of the library (gcc, C99, links libcofem.so and the HIP
+    runtime): proves the boundary is usable from C without the Python binding."""
+    rocm = os.path.dirname(os.path.dirname(hipcc()))
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-I", INCLUDE, "-I", os.path.join(rocm, "include"),
+           "-D__HIP_PLATFORM_AMD__", C_CALLER_SRC, "-L", PKG, "-lcofem", "-L", os.path.join(rocm, "lib"),
+           "-lamdhip64", f"-Wl,-rpath,{PKG}:{os.path.join(rocm, 'lib')}", "-o", C_CALLER]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("gcc failed for the C caller:\n" + res.stdout + res.stderr)
+    return C_CALLER
 
 
 if __name__ == "__main__":
