@@ -306,11 +306,13 @@ cofem_status apply_operator(cofem_ctx* c, bool use16, const float* alpha, const 
   cofem_status rc;
   if (use16) {
     if (c->timing && (rc = timed_begin(c, 1, step, &t)) != COFEM_OK) return rc;
-    launch_gemm_bf16(c->g1_16, c->phi16, c->Np, c->Dp, c->PdH, c->PdL, sc.Q, c->Qp, c->Ypart, c->st, c->stream);
+    launch_gemm_bf16(c->g1_16, c->phi16, c->g1_16.kchunk, c->Np * c->g1_16.kchunk, c->Np, c->Dp, c->PdH, c->PdL, sc.Q,
+                     c->Qp, c->Ypart, c->st, c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
     launch_finish_pass1(c->Ypart, c->g1_16.splits, sc.Q, c->Qp, c->Np, nullptr, c->VH, c->VL, c->st, c->stream);
     if (c->timing && (rc = timed_begin(c, 1, step, &t)) != COFEM_OK) return rc;
-    launch_gemm_bf16(c->g2_16, c->phi16T, c->Dp, c->Np, c->VH, c->VL, sc.Q, c->Qp, c->Ypart, c->st, c->stream);
+    launch_gemm_bf16(c->g2_16, c->phi16T, dict_ld(c->Np, 2), 0, c->Dp, c->Np, c->VH, c->VL, sc.Q, c->Qp, c->Ypart,
+                     c->st, c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
     launch_finish_pass2(sc, c->Ypart, c->g2_16.splits, c->Dp, alpha, c->Pd, c->Psi, c->pipart, c->st, c->stream);
   } else {
@@ -461,7 +463,7 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   // dictionary layouts: rows padded to dict_ld (row-major Np rows, transposed Dp rows)
   const size_t nd32 = matrix_free ? 0 : (size_t)Np * (size_t)dict_ld(Dp, 4);
   const size_t nd32T = matrix_free ? 0 : (size_t)Dp * (size_t)dict_ld(Np, 4);
-  const size_t nd16 = matrix_free ? 0 : (size_t)Np * (size_t)dict_ld(Dp, 2);
+  const size_t nd16 = matrix_free ? 0 : (size_t)c->g1_16.splits * (size_t)Np * (size_t)c->g1_16.kchunk;
   const size_t nd16T = matrix_free ? 0 : (size_t)Dp * (size_t)dict_ld(Np, 2);
 #define TRY(x)                   \
   do {                           \
@@ -563,7 +565,8 @@ COFEM_API cofem_status cofem_set_dictionary(cofem_ctx* c, const float* phi) {
     c->stats.ms_setup = now_ms() - t0;
     return COFEM_OK;
   }
-  launch_dict_layouts(phi, c->p.N, c->p.D, c->Np, c->Dp, c->phi32, c->phi32T, c->phi16, c->phi16T, c->stream);
+  launch_dict_layouts(phi, c->p.N, c->p.D, c->Np, c->Dp, c->g1_16.kchunk, c->phi32, c->phi32T, c->phi16, c->phi16T,
+                      c->stream);
   // theta from the caller's FP32 matrix (b is formed per fit from the library's copies)
   launch_theta(phi, c->p.N, c->p.D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->theta, c->stream);
   HIP_TRY(hipGetLastError());

@@ -46,23 +46,28 @@ struct SolveCfg {
 };
 
 // ---- setup -----------------------------------------------------------------
-// Row stride (elements) of the library's dictionary layouts.  bf16 rows get 128 bytes
-// of padding: row starts that are an odd multiple of 128 bytes spread the rows a
-// contraction tile streams at once over the HBM channels, where rows a multiple of 256
-// bytes long would land on the same few (bf16 tile at 16384 x 65536: 5.06 -> 5.57 TB/s
-// on the D-long rows, 5.46 -> 5.61 TB/s on the N-long ones).  FP32 rows stay unpadded:
-// that contraction is bound by the FP32 matrix rate, and the pad measured 3 % slower.
+// Row stride (elements) of the library's padded dictionary layouts.  The transposed bf16
+// copy gets 128 bytes of padding per row: row starts that are an odd multiple of 128
+// bytes spread the rows a contraction tile streams at once over the HBM channels, where
+// rows a multiple of 256 bytes long would land on the same few (bf16 tile at 16384 x
+// 65536: 5.46 -> 5.61 TB/s on the N-long rows).  The row-major bf16 copy is stored
+// split-blocked instead (see launch_dict_layouts).  FP32 rows stay unpadded: that
+// contraction is bound by the FP32 matrix rate, and the pad measured 3 % slower.
 constexpr int64_t DICT_ROW_PAD_BYTES = 128;
 __host__ __device__ inline int64_t dict_ld(int64_t len, int elem_bytes) {
   return elem_bytes == 2 ? len + DICT_ROW_PAD_BYTES / elem_bytes : len;
 }
 
-// Copy the caller's N x D row-major FP32 dictionary into padded layouts:
-// phi32 (Np rows of dict_ld(Dp, 4)), phi32T (Dp rows of dict_ld(Np, 4)), phi16 (Np rows
-// of dict_ld(Dp, 2), bf16 bits), phi16T (Dp rows of dict_ld(Np, 2)).  Any output
-// pointer may be null.  Entries past D (or N) up to Dp (or Np) are zero; the row pad
-// past Dp (or Np) is never read.
-void launch_dict_layouts(const float* phi, int64_t N, int64_t D, int64_t Np, int64_t Dp, float* phi32,
+// Copy the caller's N x D row-major FP32 dictionary into the library's layouts:
+// phi32 (Np rows of dict_ld(Dp, 4)), phi32T (Dp rows of dict_ld(Np, 4)), phi16T (Dp
+// rows of dict_ld(Np, 2), bf16 bits), and phi16 split-blocked: the reduction range of the
+// first pass cut into the contraction's splits of kc16 columns, split s an Np x kc16
+// row-major block at phi16 + s Np kc16 (cdiv(Dp, kc16) blocks).  Each split then streams
+// whole contiguous rows (16 KB at the large size) instead of 16 KB pieces of 128 KB
+// rows: 5.33 -> 5.73 TB/s on the first pass.  Any output pointer may be null.  Entries
+// past D (or N) up to Dp (or Np) are zero; the row pad and the block tail past Dp are
+// never read.
+void launch_dict_layouts(const float* phi, int64_t N, int64_t D, int64_t Np, int64_t Dp, int64_t kc16, float* phi32,
                          float* phi32T, uint16_t* phi16, uint16_t* phi16T, hipStream_t s);
 
 // theta_j = sum_i Phi_ij^2 (jacobi) or 1 from the caller's N x D matrix; padding 1.
@@ -101,10 +106,13 @@ GemmCfg choose_gemm(int64_t rows, int64_t kdim, int bf16);
 
 // Ypart[split][q][row] = sum_{k in split} M[row, k] Z[q, k] for the Q real columns (rows of
 // Ypart past the column tiles are not written); Qp is the padded column count of Z and Ypart.
-// M has rows of dict_ld(kdim, element bytes) elements.
+// bf16: M has rows of ldm elements, one block of rows (sps = 0) or split-blocked (split s at
+// M + s sps, its rows holding k in [s kchunk, (s + 1) kchunk)).  FP32: rows of
+// dict_ld(kdim, 4) elements.
 // bf16: M, ZH, ZL are bf16 bits, products of M with ZH and ZL accumulate in FP32.
-void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
-                      const uint16_t* ZL, int Q, int Qp, float* Ypart, const CGState* st, hipStream_t s);
+void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t ldm, int64_t sps, int64_t rows, int64_t kdim,
+                      const uint16_t* ZH, const uint16_t* ZL, int Q, int Qp, float* Yp, const CGState* st,
+                      hipStream_t s);
 void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Q, int Qp,
                      float* Ypart, const CGState* st, hipStream_t s);
 

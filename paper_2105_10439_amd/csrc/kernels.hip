@@ -26,10 +26,10 @@ namespace cofem {
 // setup kernels
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_dict_layouts(const float* __restrict__ phi, int64_t N, int64_t D,
-                                                      int64_t Np, int64_t Dp, float* __restrict__ phi32,
+                                                      int64_t Np, int64_t Dp, int64_t kc16, float* __restrict__ phi32,
                                                       float* __restrict__ phi32T, uint16_t* __restrict__ phi16,
                                                       uint16_t* __restrict__ phi16T) {
-  const int64_t ld32 = dict_ld(Dp, 4), ld32T = dict_ld(Np, 4), ld16 = dict_ld(Dp, 2), ld16T = dict_ld(Np, 2);
+  const int64_t ld32 = dict_ld(Dp, 4), ld32T = dict_ld(Np, 4), ld16T = dict_ld(Np, 2);
   __shared__ float tile[64][65];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t j0 = (int64_t)blockIdx.x * 64, i0 = (int64_t)blockIdx.y * 64;
@@ -37,7 +37,10 @@ __global__ __launch_bounds__(256) void k_dict_layouts(const float* __restrict__ 
     const int64_t i = i0 + r, j = j0 + tx;
     const float v = (i < N && j < D) ? phi[i * D + j] : 0.0f;
     if (phi32) phi32[i * ld32 + j] = v;
-    if (phi16) phi16[i * ld16 + j] = bf16_rne(v);
+    if (phi16) {
+      const int64_t sp = j / kc16;  // split-blocked: split sp holds columns [sp kc16, (sp + 1) kc16)
+      phi16[sp * Np * kc16 + i * kc16 + (j - sp * kc16)] = bf16_rne(v);
+    }
     tile[r][tx] = v;
   }
   __syncthreads();
@@ -130,13 +133,13 @@ __global__ __launch_bounds__(VBLOCK) void k_mstep(SolveCfg c, uint64_t key, int6
 
 template <int RT, int CT, int KS, bool X1>
 __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void k_gemm_bf16(const uint16_t* __restrict__ M, int64_t ldm,
-                                                      const uint16_t* __restrict__ ZH,
+                                                      int64_t sps, const uint16_t* __restrict__ ZH,
                                                       const uint16_t* __restrict__ ZL, int64_t ldz,
                                                       float* __restrict__ Yp, int64_t ldy, int Qp, int64_t kchunk,
                                                       int64_t kdim, int nrb, int splits,
                                                       const int* __restrict__ done) {
   if (done && *done) return;
-  gemm_bf16_tile<RT, CT, KS, X1>(blockIdx.x, M, ldm, ZH, ZL, ldz, Yp, ldy, Qp, kchunk, kdim, nrb, splits);
+  gemm_bf16_tile<RT, CT, KS, X1>(blockIdx.x, M, ldm, ZH, ZL, ldz, Yp, ldy, Qp, kchunk, kdim, nrb, splits, sps);
 }
 
 template <int RT, int CT, int KS, bool X1>
@@ -265,10 +268,10 @@ __global__ void k_copy_pad(const float* __restrict__ src, int64_t n, int64_t np,
 // ---------------------------------------------------------------------------
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-void launch_dict_layouts(const float* phi, int64_t N, int64_t D, int64_t Np, int64_t Dp, float* phi32,
+void launch_dict_layouts(const float* phi, int64_t N, int64_t D, int64_t Np, int64_t Dp, int64_t kc16, float* phi32,
                          float* phi32T, uint16_t* phi16, uint16_t* phi16T, hipStream_t s) {
   dim3 grid((unsigned)(Dp / 64), (unsigned)(Np / 64));
-  hipLaunchKernelGGL(k_dict_layouts, grid, dim3(256), 0, s, phi, N, D, Np, Dp, phi32, phi32T, phi16, phi16T);
+  hipLaunchKernelGGL(k_dict_layouts, grid, dim3(256), 0, s, phi, N, D, Np, Dp, kc16, phi32, phi32T, phi16, phi16T);
 }
 
 void launch_theta(const float* phi, int64_t N, int64_t D, int64_t Dp, int jacobi, float* theta, hipStream_t s) {
@@ -334,15 +337,15 @@ static inline void gemm_cols(int Q, int& ct, bool& x1) {
   ct = x1 ? Q / 16 : (Q + 15) / 16;
 }
 
-#define GEMM_BF16(RT, CT, X1)                                                                                    \
-  hipLaunchKernelGGL((k_gemm_bf16<RT, CT, KS_BF16, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, ldm, ZH, ZL, kdim, \
+#define GEMM_BF16(RT, CT, X1)                                                                                      \
+  hipLaunchKernelGGL((k_gemm_bf16<RT, CT, KS_BF16, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, ldm, sps, ZH, ZL, kdim, \
                      Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done)
 #define GEMM_F32(RT, CT, X1)                                                                                    \
   hipLaunchKernelGGL((k_gemm_f32<RT, CT, KS_F32, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, ldm, Z, kdim, Yp,  \
                      rows, Qp, g.kchunk, kdim, nrb, g.splits, done)
 
 template <int RT>
-static void gemm_bf16_rt(const GemmCfg& g, const uint16_t* M, int64_t ldm, int64_t rows, int64_t kdim,
+static void gemm_bf16_rt(const GemmCfg& g, const uint16_t* M, int64_t ldm, int64_t sps, int64_t rows, int64_t kdim,
                          const uint16_t* ZH, const uint16_t* ZL, int Q, int Qp, float* Yp, const int* done,
                          hipStream_t s) {
   const int nrb = (int)(rows / (64 * RT));
@@ -363,13 +366,13 @@ static void gemm_bf16_rt(const GemmCfg& g, const uint16_t* M, int64_t ldm, int64
   }
 }
 
-void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
-                      const uint16_t* ZL, int Q, int Qp, float* Yp, const CGState* st, hipStream_t s) {
+void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t ldm, int64_t sps, int64_t rows, int64_t kdim,
+                      const uint16_t* ZH, const uint16_t* ZL, int Q, int Qp, float* Yp, const CGState* st,
+                      hipStream_t s) {
   const int* done = st ? &st->done : nullptr;
-  const int64_t ldm = dict_ld(kdim, 2);
-  if (g.rt == 4) gemm_bf16_rt<4>(g, M, ldm, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
-  else if (g.rt == 2) gemm_bf16_rt<2>(g, M, ldm, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
-  else gemm_bf16_rt<1>(g, M, ldm, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
+  if (g.rt == 4) gemm_bf16_rt<4>(g, M, ldm, sps, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
+  else if (g.rt == 2) gemm_bf16_rt<2>(g, M, ldm, sps, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
+  else gemm_bf16_rt<1>(g, M, ldm, sps, rows, kdim, ZH, ZL, Q, Qp, Yp, done, s);
 }
 
 template <int RT>

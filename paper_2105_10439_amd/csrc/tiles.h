@@ -177,11 +177,14 @@ __device__ __forceinline__ void store_x1(float (&xacc)[RT], float* __restrict__ 
 // other 14 columns of that tile are don't-care: an MFMA output column depends on its own B
 // column only), so it costs one MFMA per row tile and 32-k step instead of two, and the
 // two result columns are added lane to lane at the end.
+// sps: 0 when M is one block of rows (row r, reduction index k at M[r ldm + k]); else M is
+// split-blocked, split s being its own row block at M + s sps (k at M[s sps + r ldm + k - s
+// kchunk]).
 template <int RT, int CT, int KS, bool X1>
 __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict__ M, int64_t ldm,
                                                const uint16_t* __restrict__ ZH, const uint16_t* __restrict__ ZL,
                                                int64_t ldz, float* __restrict__ Yp, int64_t ldy, int Qp,
-                                               int64_t kchunk, int64_t kdim, int nrb, int splits) {
+                                               int64_t kchunk, int64_t kdim, int nrb, int splits, int64_t sps) {
   constexpr int FS = CT * 2 + (X1 ? 1 : 0);  // fragments per 32-k step
   constexpr int NF = KS * FS;                 // fragments per stage
   constexpr int SK = 32 * KS;                 // k per stage
@@ -221,7 +224,7 @@ __device__ __forceinline__ void gemm_bf16_tile(int L, const uint16_t* __restrict
   }
   const uint16_t* ap[RT];
 #pragma unroll
-  for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 8 * g;
+  for (int a = 0; a < RT; ++a) ap[a] = M + (sps ? (int64_t)sp * sps : kb) + (row0 + a * 16 + r16) * ldm + 8 * g;
   bf16x8_t acur[RT][KS];
 #pragma unroll
   for (int a = 0; a < RT; ++a)
