@@ -43,7 +43,7 @@ METRIC = "CoFEM EM-iters/s + HBM GB/s at D=65536 (BF16 vs FP32); serving p50/p99
 # WRITE_SIZE; KiB per dispatch, averaged over 6 dispatches), each scaled by what the
 # same counter reads for a plain 1 GiB device copy.  It holds only for the kernel
 # source it was taken on: the hash covers the tile function and the launch shape choice.
-GEMM_TRAFFIC = dict(src_sha="45ae9d9139efba30", fetch_kib=1057415.6, write_kib=16896.6,
+GEMM_TRAFFIC = dict(src_sha="b7d58000a61f3170", fetch_kib=1058560.4, write_kib=16913.4,
                     copy_kib=1048576.0, copy_fetch_kib=524302.4, copy_write_kib=1048576.0,
                     profile="profiles/hbm_traffic_k_gemm_bf16_dense_N16384_D65536.md")
 
