@@ -80,6 +80,7 @@ struct cofem_ctx {
   uint16_t* hp16 = nullptr;
   // subsampled DCT dictionary: transform tables, mask, kept samples, scratch signal
   float2 *dct_tw = nullptr, *dct_w2 = nullptr, *dct_mz = nullptr;
+  float2 *dct_mzt = nullptr, *dct_y1 = nullptr, *dct_y2 = nullptr;  // split operator (null: one workgroup per column)
   int32_t* dct_rows = nullptr;
   float* dct_u = nullptr;
   // D- and N-vectors
@@ -238,11 +239,15 @@ DctArgs dct_args(const cofem_ctx* c) {
   a.tw = c->dct_tw;
   a.mz = c->dct_mz;
   a.w2 = c->dct_w2;
+  a.mzt = c->dct_mzt;
+  a.y1 = c->dct_y1;
+  a.y2 = c->dct_y2;
   a.beta = c->p.beta;
   return a;
 }
 
-// The DCT operator: one launch, one workgroup per column (the transforms in LDS).
+// The DCT operator: three launches over several workgroups per column where the split
+// form exists, else one launch with one workgroup per column (the transforms in LDS).
 cofem_status apply_dct(cofem_ctx* c, const float* alpha, const SolveCfg& sc, int step) {
   DctArgs a = dct_args(c);
   a.in = c->Pd;
@@ -485,6 +490,11 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
     TRY(dalloc(c, &c->dct_mz, L));
     TRY(dalloc(c, &c->dct_rows, (size_t)p->N));
     TRY(dalloc(c, &c->dct_u, (size_t)Dp));
+    if (dct_split_ok(p->D)) {
+      TRY(dalloc(c, &c->dct_mzt, L));
+      TRY(dalloc(c, &c->dct_y1, (size_t)Qp * L));
+      TRY(dalloc(c, &c->dct_y2, (size_t)Qp * L));
+    }
   }
   if (c->need32) {
     if (!matrix_free) {
@@ -593,7 +603,7 @@ COFEM_API cofem_status cofem_set_dct_samples(cofem_ctx* c, const int32_t* rows) 
   }
   HIP_TRY(hipMemcpyAsync(c->dct_rows, h.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, c->stream));
   launch_dct_setup(c->dct_rows, N, D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->dct_tw, c->dct_w2,
-                   c->dct_mz, c->dct_u, c->theta, c->stream);
+                   c->dct_mz, c->dct_mzt, c->dct_u, c->theta, c->stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->dict_loaded = true;

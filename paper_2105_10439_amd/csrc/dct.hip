@@ -7,11 +7,13 @@
 // two fast transforms and a mask per right-hand side, O(D log D) work
 // (Sec. III-B: applying a structured Phi costs tau_D = O(D log D)).
 //
-// One workgroup owns one right-hand side and keeps the whole transform chain in
-// LDS, so a column makes one trip through HBM per operator application (read Pd
-// and alpha, write Psi).  Both transforms go through one complex FFT of length
-// L = D / 2 (D a power of two, 16 <= D <= 2^15, so the L complex FP32 points take
-// at most 128 KB of the 160 KB of LDS):
+// Two forms of the operator: for D = 2^11, 2^13 and 2^15 a column is
+// split over several workgroups with a four-step FFT and three launches (see the
+// split operator below); for every other size one workgroup owns one right-hand side
+// and keeps the whole transform chain in LDS, so a column makes one trip through HBM
+// per operator application (read Pd and alpha, write Psi).  Both transforms go
+// through one complex FFT of length L = D / 2 (D a power of two, 16 <= D <= 2^15,
+// so the L complex FP32 points take at most 128 KB of the 160 KB of LDS):
 //
 // * DCT-II via a real DFT of length D (Makhoul, "A fast cosine transform in one
 //   and two dimensions", IEEE TASSP 1980): reorder v_n = x_2n, v_{D-1-n} = x_{2n+1};
@@ -431,6 +433,297 @@ __global__ __launch_bounds__(dct_threads(LOG2L)) void k_dct_forward(DctArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Split operator: one column over several workgroups, three launches
+// ---------------------------------------------------------------------------
+// For L = S^2 (log2 L even) the length-L DFT is a four-step one: with n = n1 + S n2
+// and k = k2 + S k1,
+//   Y[n1][k2] = W_L^{n1 k2} sum_{n2} x[n1 + S n2] W_S^{n2 k2},
+//   X[k2 + S k1] = sum_{n1} Y[n1][k2] W_S^{n1 k1},
+// two sets of S transforms of length S with an exchange through global memory (L2)
+// in between.  The operator's two transforms chain as
+//   launch 1: spectrum of Pd + first half of transform 1 (over n2, per residue n1),
+//   launch 2: second half of transform 1 (over n1, per k2), the mask, and first half
+//             of transform 2: the outputs of transform 1 with a fixed k2 mod S are
+//             exactly the inputs of transform 2 with n1 = k2, so no exchange is needed,
+//   launch 3: second half of transform 2, the DCT post-processing and the epilogue.
+// Each workgroup owns SP_RC residues mod S, chosen closed under r -> -r mod S (the
+// post-processing pairs bins k and L - k, and L - k = -k mod S): rows i < 8 are
+// residues 8g + i, rows 8 + i their negatives (S / 2 in place of S - 0).  Each
+// length-S transform is S = 16 R2 points: a 16-point DFT in registers per (row, a)
+// over n = a + R2 b, the twiddles W_S^{ac}, an LDS exchange, and an R2-point DFT per
+// (row, c), giving bin k = c + 16 d in register d.  A column becomes G = S / SP_RC
+// workgroups, so the 21 or 33 columns of a step fill the chip instead of 21 or 33 CUs.
+constexpr int SP_RC = 16;           // residues (rows) per workgroup
+constexpr int SP_NT = SP_RC * 16;   // threads per workgroup
+constexpr bool dct_split_log2(int log2L) { return log2L == 10 || log2L == 12 || log2L == 14; }
+
+template <int LOG2L>
+struct SplitShape {
+  static constexpr int L = 1 << LOG2L, D = 2 * L, S = 1 << (LOG2L / 2), R2 = S / 16, G = S / SP_RC;
+  static constexpr int CS = SP_RC * R2 + (SP_RC & 31);  // LDS stride per c in the (a, c) exchange
+};
+
+// Residue mod S of row `row` of workgroup g.
+template <int S>
+__device__ __forceinline__ int sp_residue(int g, int row) {
+  const int i = row & 7;
+  if (row < 8) return g * 8 + i;
+  const int r = S - (g * 8 + i);
+  return r == S ? S / 2 : r;
+}
+// The row holding residue -r mod S.
+__device__ __forceinline__ int sp_partner_row(int g, int row) {
+  if (g == 0 && (row & 7) == 0) return row;  // residues 0 and S / 2
+  return row < 8 ? row + 8 : row - 8;
+}
+// Block -> (column, group): with the grid a multiple of 8, the G groups of a column
+// run on one XCD (blocks are dealt to the 8 XCDs round-robin), so the column's
+// exchange buffers and Pd stay in that XCD's L2 across the three launches.
+__device__ __forceinline__ void sp_tile(int G, int& q, int& g) {
+  const int b = blockIdx.x, n = gridDim.x;
+  const int pos = (n & 7) == 0 ? (b & 7) * (n >> 3) + (b >> 3) : b;
+  q = pos / G;
+  g = pos % G;
+}
+
+// First half of a length-S transform: thread (row, a) holds x[a + R2 b] in v[b]; the
+// 16-point DFT over b, the twiddles W_S^{ac}, and the exchange store.
+template <int LOG2L>
+__device__ __forceinline__ void sp_half1(float2 (&v)[16], int row, int a, float2* ex, const float2* twS) {
+  using SS = SplitShape<LOG2L>;
+  dft16(v);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) ex[c * SS::CS + a * SP_RC + row] = (c == 0 || a == 0) ? v[c] : cmul(v[c], twS[a * c]);
+}
+// Second half: thread (row, c) takes the R2 values of its c and their R2-point DFT;
+// y[d] is bin c + 16 d of the row's transform.
+template <int LOG2L>
+__device__ __forceinline__ void sp_half2(float2 (&y)[SplitShape<LOG2L>::R2], int row, int c, const float2* ex) {
+  using SS = SplitShape<LOG2L>;
+#pragma unroll
+  for (int a = 0; a < SS::R2; ++a) y[a] = ex[c * SS::CS + a * SP_RC + row];
+  dft<SS::R2>(y);
+}
+// Tables every split launch uses: the W_4D table and W_S^i = tw[S i].
+template <int LOG2L>
+__device__ __forceinline__ void sp_tables(float2* wt, float2* twS, const DctArgs& a) {
+  using SS = SplitShape<LOG2L>;
+  load_wt<LOG2L, SP_NT>(wt, a.w2);
+  for (int i = threadIdx.x; i < SS::S; i += SP_NT) twS[i] = a.tw[i * SS::S];
+}
+
+// Launch 1: x[m] = conj Z_m (the spectrum side of the inverse transform, as in
+// k_dct_operator) for m = r + S n2, the first half over n2, and
+// y1[q][k2][r] = W_L^{r k2} (its result).  The spectrum is built by all threads into
+// LDS: item m of rows 0..7 makes Z_m and, when its residue r is not 0, also
+// Z_{L-m} (row 8 + i, n2' = S - 1 - n2) from the same four loads of Pd; in group 0,
+// rows 0 and 8 (residues 0 and S / 2) pair within themselves, so row 8's points are
+// items of their own there.
+template <int LOG2L>
+__global__ __launch_bounds__(SP_NT) void k_dct_split1(DctArgs a) {
+  using SS = SplitShape<LOG2L>;
+  constexpr int L = SS::L, D = SS::D, S = SS::S, R2 = SS::R2;
+  constexpr int XS = S + 2;                 // LDS row stride of the spectrum
+  constexpr int NI = 8 * S, IPT = NI / SP_NT;  // items of rows 0..7, per thread
+  static_assert(NI % SP_NT == 0, "items per thread");
+  __shared__ float2 wt[wt_size(LOG2L)];
+  __shared__ float2 twS[S];
+  __shared__ float2 ex[16 * SS::CS];
+  __shared__ float2 xs[SP_RC * XS];
+  if (a.done && *a.done) return;
+  int q, g;
+  sp_tile(SS::G, q, g);
+  const float* __restrict__ p = a.in + (int64_t)q * a.Dp;
+  // item i < IPT: e = tid + i NT (row e % 8, n2 = e / 8); item IPT: group 0's row 8
+  const bool extra = g == 0 && (int)threadIdx.x < S;
+  float pm[IPT + 1], pdm[IPT + 1], plm[IPT + 1], plpm[IPT + 1];
+  int mi[IPT + 1];
+#pragma unroll
+  for (int i = 0; i <= IPT; ++i) {
+    const int e = threadIdx.x + i * SP_NT;
+    const int m = i < IPT ? sp_residue<S>(g, e & 7) + S * (e >> 3) : S / 2 + S * (int)threadIdx.x;
+    mi[i] = m;
+    if (i < IPT || extra) {
+      pm[i] = p[m];
+      pdm[i] = m > 0 ? p[D - m] : 0.0f;
+      plm[i] = p[L - m];
+      plpm[i] = p[L + m];
+    }
+  }
+  sp_tables<LOG2L>(wt, twS, a);
+  lds_barrier();
+#pragma unroll
+  for (int i = 0; i <= IPT; ++i) {
+    if (i == IPT && !extra) break;
+    const int e = threadIdx.x + i * SP_NT;
+    const int m = mi[i], lm = L - m;
+    const int row = i < IPT ? (e & 7) : 8, n2 = i < IPT ? (e >> 3) : (int)threadIdx.x;
+    const float2 h1 = m == 0 ? make_float2(a.s0 * pm[i], 0.0f)
+                             : cscale(cmul(cconj(w4d<LOG2L>(wt, m)), make_float2(a.s1 * pm[i], -a.s1 * pdm[i])), 0.5f);
+    const float2 h2 = cscale(cmul(cconj(w4d<LOG2L>(wt, lm)), make_float2(a.s1 * plm[i], -a.s1 * plpm[i])), 0.5f);
+    const float2 zm = cadd(cadd(h1, cconj(h2)), ctimes_i(cmul(csub(h1, cconj(h2)), cconj(w4d<LOG2L>(wt, 4 * m)))));
+    xs[row * XS + n2] = cconj(zm);
+    if (i < IPT && (m % S) != 0) {
+      const float2 zl = cadd(cadd(h2, cconj(h1)), ctimes_i(cmul(csub(h2, cconj(h1)), cconj(w4d<LOG2L>(wt, 4 * lm)))));
+      xs[(row + 8) * XS + (S - 1 - n2)] = cconj(zl);
+    }
+  }
+  lds_barrier();
+  const int row = threadIdx.x % SP_RC, grp = threadIdx.x / SP_RC;
+  const int r = sp_residue<S>(g, row);
+  if (grp < R2) {
+    float2 v[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = xs[row * XS + grp + R2 * b];
+    sp_half1<LOG2L>(v, row, grp, ex, twS);
+  }
+  lds_barrier();
+  float2 y[R2];
+  sp_half2<LOG2L>(y, row, grp, ex);
+  float2* __restrict__ y1 = a.y1 + (int64_t)q * L;
+#pragma unroll
+  for (int d = 0; d < R2; ++d) {
+    const int k2 = grp + 16 * d;
+    y1[k2 * S + r] = cmul(y[d], w4d<LOG2L>(wt, 8 * r * k2));
+  }
+}
+
+// Launch 2: row k2 = r of y1, the second half of transform 1 (bins r + S k1), the
+// mask, then the first half of transform 2 over k1 (its n2) with n1 = r, and
+// y2[q][k2'][r] = W_L^{r k2'} (its result).
+template <int LOG2L>
+__global__ __launch_bounds__(SP_NT) void k_dct_split2(DctArgs a) {
+  using SS = SplitShape<LOG2L>;
+  constexpr int L = SS::L, S = SS::S, R2 = SS::R2;
+  __shared__ float2 wt[wt_size(LOG2L)];
+  __shared__ float2 twS[S];
+  __shared__ float2 ex[16 * SS::CS];
+  __shared__ float2 ex2[S * SP_RC];
+  if (a.done && *a.done) return;
+  int q, g;
+  sp_tile(SS::G, q, g);
+  const int row = threadIdx.x % SP_RC, grp = threadIdx.x / SP_RC;
+  const int r = sp_residue<S>(g, row);
+  const float2* __restrict__ y1 = a.y1 + (int64_t)q * L + (int64_t)r * S;
+  float2 v[16];
+  if (grp < R2) {
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = y1[grp + R2 * b];
+  }
+  float2 m[R2];
+#pragma unroll
+  for (int d = 0; d < R2; ++d) m[d] = a.mzt[r * S + grp + 16 * d];
+  sp_tables<LOG2L>(wt, twS, a);
+  lds_barrier();
+  if (grp < R2) sp_half1<LOG2L>(v, row, grp, ex, twS);
+  lds_barrier();
+  float2 y[R2];
+  sp_half2<LOG2L>(y, row, grp, ex);
+  // bin k1 = grp + 16 d of transform 1 -> masked input n2 = k1 of transform 2
+#pragma unroll
+  for (int d = 0; d < R2; ++d)
+    ex2[(grp + 16 * d) * SP_RC + row] = make_float2(m[d].x * y[d].x, -m[d].y * y[d].y);
+  lds_barrier();
+  if (grp < R2) {
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = ex2[(grp + R2 * b) * SP_RC + row];
+    sp_half1<LOG2L>(v, row, grp, ex, twS);
+  }
+  lds_barrier();
+  sp_half2<LOG2L>(y, row, grp, ex);
+  float2* __restrict__ y2 = a.y2 + (int64_t)q * L;
+#pragma unroll
+  for (int d = 0; d < R2; ++d) {
+    const int k2 = grp + 16 * d;
+    y2[k2 * S + r] = cmul(y[d], w4d<LOG2L>(wt, 8 * r * k2));
+  }
+}
+
+// Launch 3: row k2' = r of y2, the second half of transform 2 (bins X_k, k = r + S k1),
+// then per bin the DCT post-processing with its partner bin L - k (row of -r, held
+// by this workgroup): C_k and C_{D-k} (and C_L from bin 0), and the epilogue
+// Psi_j = beta s_j C_j + alpha_j Pd_j.  The workgroup's pi partial (FP64, fixed order)
+// goes to pipart[q * nbx + g]; the column's slots G .. nbx - 1 are zeroed.
+template <int LOG2L>
+__global__ __launch_bounds__(SP_NT) void k_dct_split3(DctArgs a) {
+  using SS = SplitShape<LOG2L>;
+  constexpr int L = SS::L, D = SS::D, S = SS::S, R2 = SS::R2, G = SS::G;
+  __shared__ float2 wt[wt_size(LOG2L)];
+  __shared__ float2 twS[S];
+  __shared__ float2 ex[16 * SS::CS];
+  __shared__ float2 ex2[S * SP_RC];
+  __shared__ double red[SP_NT / 64];
+  if (a.done && *a.done) return;
+  int q, g;
+  sp_tile(G, q, g);
+  const int row = threadIdx.x % SP_RC, grp = threadIdx.x / SP_RC;
+  const int r = sp_residue<S>(g, row);
+  const float2* __restrict__ y2 = a.y2 + (int64_t)q * L + (int64_t)r * S;
+  const float* __restrict__ p = a.in + (int64_t)q * a.Dp;
+  float2 v[16];
+  if (grp < R2) {
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = y2[grp + R2 * b];
+  }
+  // Pd and alpha at the outputs k and D - k of this thread's bins
+  float pk[R2], ak[R2], pdk[R2], adk[R2];
+#pragma unroll
+  for (int d = 0; d < R2; ++d) {
+    const int k = r + S * (grp + 16 * d);
+    const int j = k > 0 ? D - k : L;
+    pk[d] = p[k];
+    ak[d] = a.alpha[k];
+    pdk[d] = p[j];
+    adk[d] = a.alpha[j];
+  }
+  sp_tables<LOG2L>(wt, twS, a);
+  lds_barrier();
+  if (grp < R2) sp_half1<LOG2L>(v, row, grp, ex, twS);
+  lds_barrier();
+  float2 y[R2];
+  sp_half2<LOG2L>(y, row, grp, ex);
+#pragma unroll
+  for (int d = 0; d < R2; ++d) ex2[(grp + 16 * d) * SP_RC + row] = y[d];
+  lds_barrier();
+  const int prow = sp_partner_row(g, row);
+  float* __restrict__ out = a.out + (int64_t)q * a.Dp;
+  double acc = 0.0;
+#pragma unroll
+  for (int d = 0; d < R2; ++d) {
+    const int k1 = grp + 16 * d, k = r + S * k1;
+    const int pk1 = r > 0 ? S - 1 - k1 : (S - k1) & (S - 1);
+    const float2 B = ex2[pk1 * SP_RC + prow];
+    const float2 w = cmul(w4d<LOG2L>(wt, k), real_split(y[d], B, w4d<LOG2L>(wt, 4 * k)));
+    const float sk = k == 0 ? a.s0 : a.s1;
+    const float psi_k = (float)(a.beta * (double)(sk * w.x) + (double)ak[d] * (double)pk[d]);
+    out[k] = psi_k;
+    acc += (double)pk[d] * (double)psi_k;
+    // k > 0: C_{D-k} = -Im w;  k = 0: C_L from bin 0 paired with itself
+    float cj;
+    if (k > 0) {
+      cj = -w.y;
+    } else {
+      cj = cmul(w4d<LOG2L>(wt, L), real_split(y[d], y[d], w4d<LOG2L>(wt, 4 * L))).x;
+    }
+    const int j = k > 0 ? D - k : L;
+    const float psi_j = (float)(a.beta * (double)(a.s1 * cj) + (double)adk[d] * (double)pdk[d]);
+    out[j] = psi_j;
+    acc += (double)pdk[d] * (double)psi_j;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  lds_barrier();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < SP_NT / 64; ++w) s += red[w];
+    a.pipart[(int64_t)q * a.nbx + g] = s;
+  }
+  if (g == 0)
+    for (int c = G + (int)threadIdx.x; c < a.nbx; c += SP_NT) a.pipart[(int64_t)q * a.nbx + c] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
 // Set-up: tables, mask, theta, right-hand side
 // ---------------------------------------------------------------------------
 // tw_i = e^{-2 pi i i / L} (i < L) and the two-level table of W_4D = e^{-2 pi i / 4D}:
@@ -463,12 +756,16 @@ __global__ void k_dct_scatter(const int32_t* __restrict__ rows, const float* __r
 
 // The mask in the order of the half-length transform: mz_m = (mv_2m, mv_{2m+1})
 // with mv_n = mx_2n (n < L) and mv_n = mx_{2(D-1-n)+1} (n >= L).
-__global__ void k_dct_mask(int L, const float* __restrict__ mx, float2* __restrict__ mz) {
+// With mzt (S = sqrt L), also the transposed copy mzt[(m mod S) S + m / S] = mz_m.
+__global__ void k_dct_mask(int L, int S, const float* __restrict__ mx, float2* __restrict__ mz,
+                           float2* __restrict__ mzt) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= L) return;
   const int D = 2 * L;
   auto mv = [&](int n) { return n < L ? mx[2 * n] : mx[2 * (D - 1 - n) + 1]; };
-  mz[m] = make_float2(mv(2 * m), mv(2 * m + 1));
+  const float2 z = make_float2(mv(2 * m), mv(2 * m + 1));
+  mz[m] = z;
+  if (mzt) mzt[(m % S) * S + m / S] = z;
 }
 
 // Jacobi theta_j = sum_i Omega_{j, rows_i}^2 = s_j^2 sum_i cos^2(pi (2 rows_i + 1) j / 2D),
@@ -519,8 +816,10 @@ int log2_half(int64_t D) {
 
 bool dct_size_ok(int64_t D) { return D >= DCT_MIN_D && D <= DCT_MAX_D && (D & (D - 1)) == 0; }
 
+bool dct_split_ok(int64_t D) { return dct_size_ok(D) && dct_split_log2(log2_half(D)); }
+
 void launch_dct_setup(const int32_t* rows, int64_t N, int64_t D, int64_t Dp, int jacobi, float2* tw, float2* w2,
-                      float2* mz, float* mx, float* theta, hipStream_t s) {
+                      float2* mz, float2* mzt, float* mx, float* theta, hipStream_t s) {
   const int L = (int)(D / 2);
   const int lg = log2_half(D) + 3, lo = (lg + 1) / 2, hi = lg - lo;
   const int n = std::max(L, 1 << lo);
@@ -528,7 +827,8 @@ void launch_dct_setup(const int32_t* rows, int64_t N, int64_t D, int64_t Dp, int
   launch_fill(mx, 0.0f, Dp, s);
   hipLaunchKernelGGL(k_dct_scatter, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, rows,
                      static_cast<const float*>(nullptr), N, mx);
-  hipLaunchKernelGGL(k_dct_mask, dim3((L + 255) / 256), dim3(256), 0, s, L, mx, mz);
+  const int S = dct_split_ok(D) ? 1 << (log2_half(D) / 2) : 1;
+  hipLaunchKernelGGL(k_dct_mask, dim3((L + 255) / 256), dim3(256), 0, s, L, S, mx, mz, dct_split_ok(D) ? mzt : nullptr);
   if (jacobi)
     hipLaunchKernelGGL(k_dct_theta, dim3((unsigned)((Dp + 255) / 256)), dim3(256), 0, s, rows, N, D, Dp, theta);
   else
@@ -543,6 +843,24 @@ void launch_dct_rhs(const DctArgs& a, const float* y, const int32_t* rows, int64
   DCT_DISPATCH(k_dct_forward, 1, f, s);
 }
 
-void launch_dct_operator(const DctArgs& a, int Q, hipStream_t s) { DCT_DISPATCH(k_dct_operator, Q, a, s); }
+template <int LOG2L>
+void launch_split(const DctArgs& a, int Q, hipStream_t s) {
+  const dim3 grid((unsigned)(Q * SplitShape<LOG2L>::G)), block(SP_NT);
+  hipLaunchKernelGGL(k_dct_split1<LOG2L>, grid, block, 0, s, a);
+  hipLaunchKernelGGL(k_dct_split2<LOG2L>, grid, block, 0, s, a);
+  hipLaunchKernelGGL(k_dct_split3<LOG2L>, grid, block, 0, s, a);
+}
+
+void launch_dct_operator(const DctArgs& a, int Q, hipStream_t s) {
+  if (a.y1 && a.y2 && a.mzt && dct_split_ok(a.D)) {
+    switch (log2_half(a.D)) {
+      case 10: launch_split<10>(a, Q, s); return;
+      case 12: launch_split<12>(a, Q, s); return;
+      case 14: launch_split<14>(a, Q, s); return;
+      default: break;
+    }
+  }
+  DCT_DISPATCH(k_dct_operator, Q, a, s);
+}
 
 }  // namespace cofem

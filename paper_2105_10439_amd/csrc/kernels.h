@@ -207,12 +207,17 @@ struct DctArgs {
   const float* alpha;                // operator only
   double* pipart;                    // operator only: [q][chunk]
   const int* done;                   // operator only, may be null
+  float2 *y1, *y2;                   // split operator only: exchange buffers, Qp x D/2 each
+  const float2* mzt;                 // split operator only: mask pairs transposed, [k mod S][k / S]
 };
-// Tables (tw: D/2, w2: DCT_W2_SIZE, mz: D/2 entries), the mask (mx: Dp floats of
+// The split form of the operator (one column over several workgroups, three
+// launches) exists for D = 2^11, 2^13 and 2^15; it needs y1, y2 and mzt.
+bool dct_split_ok(int64_t D);
+// Tables (tw: D/2, w2: DCT_W2_SIZE, mz: D/2 entries; mzt: D/2 entries or null), the mask (mx: Dp floats of
 // scratch), and theta (Jacobi: column norms of Phi; else ones).  rows: N distinct
 // sample indices in [0, D) on the device.
 void launch_dct_setup(const int32_t* rows, int64_t N, int64_t D, int64_t Dp, int jacobi, float2* tw, float2* w2,
-                      float2* mz, float* mx, float* theta, hipStream_t s);
+                      float2* mz, float2* mzt, float* mx, float* theta, hipStream_t s);
 // b = beta Phi^T y = beta Omega (M^T y) into a.out (u: Dp floats of scratch).
 void launch_dct_rhs(const DctArgs& a, const float* y, const int32_t* rows, int64_t N, float* u, hipStream_t s);
 // Psi = A Pd for columns q < Q, one workgroup per column, with the pi partials.

@@ -3,9 +3,10 @@ the orthonormal DCT-II of size D, M keeping N of the D samples; the GPU applies
 A = beta Omega M^T M Omega^T + diag(alpha) with an LDS-resident FFT per column.
 
 * The operator against the oracle (scipy's DCT, itself pinned to the cosine sums):
-  every power of two the kernel supports (16 .. 2^15: FFT lengths 8 .. 2^14, i.e. zero
-  to three radix-16 passes with each of the radix-2, 4 and 8 tails), ragged column
-  counts, N = 1, N = D/3 and N = D.
+  every power of two the kernels support (16 .. 2^15: FFT lengths 8 .. 2^14, i.e. zero
+  to three radix-16 passes with each of the radix-2, 4 and 8 tails in the
+  one-workgroup form; D = 2^11, 2^13, 2^15 take the split four-step form, with 2, 4
+  and 8 workgroups per column), ragged column counts, N = 1, N = D/3 and N = D.
   The FP32 FFT of length L = D/2 has a normwise error of a few log2(L) * 2^-24;
   the bar is 2e-5 per column.
 * Fits against the oracle at the same probes, stop rule and tolerance (mu within
@@ -48,7 +49,8 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("D,N,ncols", [(16, 5, 3), (32, 32, 9), (64, 1, 2), (128, 42, 17), (256, 85, 21),
                                        (512, 170, 33), (1024, 341, 21), (2048, 2048, 5), (4096, 1365, 64),
-                                       (8192, 2730, 21), (16384, 5461, 7), (32768, 10922, 21)])
+                                       (8192, 2730, 21), (16384, 5461, 7), (32768, 10922, 21),
+                                       (2048, 682, 64), (32768, 1, 33)])
 def test_dct_apply_A_matches_oracle(gpu, D, N, ncols):
     rng = np.random.default_rng(D + N + ncols)
     rows = np.sort(rng.permutation(D)[:N])
@@ -121,6 +123,17 @@ def test_dct_full_sampling_is_one_cg_step(gpu):
     ref = oracle.cofem(oracle.DctOperator(D, prob.rows), prob.y, prob.beta, T=5, K=8, U=50, tol=1e-6, seed=3)
     assert _rel(mu, ref.mu) < 1e-5
     assert _rel(s, ref.s) < 1e-5
+
+
+def test_dct_split_fit_is_deterministic(gpu):
+    """The split form reduces pi in a fixed order (one FP64 partial per workgroup), so a
+    fit repeated on the same inputs is bitwise the same."""
+    prob = workloads.dct_problem(2048, 682, 245, 0.01, seed=59)
+    a = _dct_fit(gpu, prob, 16, 6, 400, 1e-6, 11)
+    b = _dct_fit(gpu, prob, 16, 6, 400, 1e-6, 11)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert a[3]["cg_steps"] == b[3]["cg_steps"]
 
 
 def test_dct_bad_samples_rejected(gpu):
