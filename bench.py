@@ -43,25 +43,33 @@ METRIC = "CoFEM EM-iters/s + HBM GB/s at D=65536 (BF16 vs FP32); serving p50/p99
 # WRITE_SIZE; KiB per dispatch, averaged over 6 dispatches), each scaled by what the
 # same counter reads for a plain 1 GiB device copy.  It holds only for the kernel
 # source it was taken on: the hash covers the tile function and the launch shape choice.
-GEMM_TRAFFIC = dict(src_sha="b7d58000a61f3170", fetch_kib=1058560.4, write_kib=16913.4,
+GEMM_TRAFFIC = dict(src_sha="372cee0ad138146f", fetch_kib=1058560.4, write_kib=16913.4,
                     copy_kib=1048576.0, copy_fetch_kib=524302.4, copy_write_kib=1048576.0,
                     profile="profiles/hbm_traffic_k_gemm_bf16_dense_N16384_D65536.md")
 
 
 def gemm_source_sha() -> str:
+    """Hash of the sources the bf16 operator kernel is built from: its tile, its kernel
+    wrapper, the tiling choice and launch code, and the dictionary row padding."""
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_2105_10439_amd", "csrc")
     tiles = open(os.path.join(csrc, "tiles.h")).read()
     kern = open(os.path.join(csrc, "kernels.hip")).read()
     hdr = open(os.path.join(csrc, "kernels.h")).read()
-    a = tiles.index("constexpr int GEMM_WAVES")
-    b = tiles.index("// FP32: v_mfma_f32_16x16x4_f32.")
-    c = kern.index("GemmCfg choose_gemm(")
-    d = kern.index("template <int RT>\nstatic void gemm_bf16_rt(")
-    e = hdr.index("constexpr int64_t DICT_ROW_PAD_BYTES")
-    f = hdr.index("\n}", hdr.index("inline int64_t dict_ld(", e))
-    return hashlib.sha256((tiles[a:b] + kern[c:d] + hdr[e:f]).encode()).hexdigest()[:16]
+
+    def cut(s, a, b):
+        i = s.index(a)
+        return s[i:s.index(b, i)]
+
+    parts = [cut(tiles, "constexpr int GEMM_WAVES", "// FP32: v_mfma_f32_16x16x4_f32."),
+             cut(kern, "template <int RT, int CT, int KS, bool X1>\n__global__ __launch_bounds__(64 * GEMM_WAVES, 2) "
+                       "void k_gemm_bf16(", "\n}\n"),
+             cut(kern, "GemmCfg choose_gemm(", "constexpr int KS_F32"),
+             cut(kern, "static inline void gemm_cols(", "#define GEMM_F32("),
+             cut(kern, "template <int RT>\nstatic void gemm_bf16_rt(", "template <int RT>\nstatic void gemm_f32_rt("),
+             cut(hdr, "constexpr int64_t DICT_ROW_PAD_BYTES", "\n}")]
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
 def gemm_traffic(N: int, D: int, dom: str):

@@ -92,6 +92,7 @@ struct cofem_ctx {
   // CG blocks
   float *X = nullptr, *R = nullptr, *Pd = nullptr, *Psi = nullptr, *V = nullptr;
   uint16_t *PdH = nullptr, *PdL = nullptr, *VH = nullptr, *VL = nullptr;
+  uint16_t *PdX = nullptr, *VX = nullptr;  // third slices of Pd and V for the FP32 dense operator
   float* Ypart = nullptr;
   double* part = nullptr;    // em_init partials and CG-update partials
   double* pipart = nullptr;  // pi partials
@@ -322,11 +323,14 @@ cofem_status apply_operator(cofem_ctx* c, bool use16, const float* alpha, const 
     launch_finish_pass2(sc, c->Ypart, c->g2_16.splits, c->Dp, alpha, c->Pd, c->Psi, c->pipart, c->st, c->stream);
   } else {
     if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
-    launch_gemm_f32(c->g1_32, c->phi32, c->Np, c->Dp, c->Pd, sc.Q, c->Qp, c->Ypart, c->st, c->stream);
+    launch_gemm_f32(c->g1_32, c->phi32, c->Np, c->Dp, c->PdH, c->PdL, c->PdX, sc.Q, c->Qp, c->Ypart, c->st,
+                    c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
-    launch_finish_pass1(c->Ypart, c->g1_32.splits, sc.Q, c->Qp, c->Np, c->V, nullptr, nullptr, c->st, c->stream);
+    launch_finish_pass1(c->Ypart, c->g1_32.splits, sc.Q, c->Qp, c->Np, nullptr, c->VH, c->VL, c->st, c->stream,
+                        c->VX);
     if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
-    launch_gemm_f32(c->g2_32, c->phi32T, c->Dp, c->Np, c->V, sc.Q, c->Qp, c->Ypart, c->st, c->stream);
+    launch_gemm_f32(c->g2_32, c->phi32T, c->Dp, c->Np, c->VH, c->VL, c->VX, sc.Q, c->Qp, c->Ypart, c->st,
+                    c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
     launch_finish_pass2(sc, c->Ypart, c->g2_32.splits, c->Dp, alpha, c->Pd, c->Psi, c->pipart, c->st, c->stream);
   }
@@ -373,16 +377,21 @@ void begin_fit(cofem_ctx* c, const float* y) {
 cofem_status solve_estep(cofem_ctx* c, uint64_t key, bool use16, const float* alpha, int* steps, double* delta) {
   const cofem_params& p = c->p;
   const SolveCfg sc = solve_cfg(c);
-  launch_em_init(sc, key, p.D, c->Dp, use16 ? c->b16 : c->b32, c->theta, alpha, c->minv, c->X, c->R, c->Pd,
-                 use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr, c->part, c->st, c->stream);
+  // slices of Pd: hi/lo for the bf16 operator, hi/lo and the third slice for the dense
+  // FP32 one (which takes its right-hand sides as three bf16 slices)
+  const bool sliced32 = !use16 && c->PdX;
+  uint16_t* sH = (use16 || sliced32) ? c->PdH : nullptr;
+  uint16_t* sL = (use16 || sliced32) ? c->PdL : nullptr;
+  uint16_t* sX = sliced32 ? c->PdX : nullptr;
+  launch_em_init(sc, key, p.D, c->Dp, use16 ? c->b16 : c->b32, c->theta, alpha, c->minv, c->X, c->R, c->Pd, sH, sL,
+                 c->part, c->st, c->stream, sX);
   int prev_steps = 0;
   for (;;) {
     for (int i = 0; i < c->chunk; ++i) {
       cofem_status rc = apply_operator(c, use16, alpha, sc, i);
       if (rc != COFEM_OK) return rc;
       launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream);
-      launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, use16 ? c->PdH : nullptr, use16 ? c->PdL : nullptr,
-                          c->st, c->stream);
+      launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, sH, sL, c->st, c->stream, sX);
     }
     cofem_status rc = sync_state(c);
     if (rc != COFEM_OK) return rc;
@@ -501,17 +510,26 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
       TRY(dalloc(c, &c->phi32, nd32));
       TRY(dalloc(c, &c->phi32T, nd32T));
     }
-    if (!dct) TRY(dalloc(c, &c->V, (size_t)Qp * Np));
+    if (conv) TRY(dalloc(c, &c->V, (size_t)Qp * Np));
   }
   if (c->need16) {
     if (!matrix_free) {
       TRY(dalloc(c, &c->phi16, nd16));
       TRY(dalloc(c, &c->phi16T, nd16T));
     }
+  }
+  // hi/lo slices of Pd and V: the bf16 operators; with the third slices also the dense
+  // FP32 operator
+  const bool dense32 = c->need32 && !matrix_free;
+  if (c->need16 || dense32) {
     TRY(dalloc(c, &c->PdH, (size_t)Qp * Dp));
     TRY(dalloc(c, &c->PdL, (size_t)Qp * Dp));
     TRY(dalloc(c, &c->VH, (size_t)Qp * Np));
     TRY(dalloc(c, &c->VL, (size_t)Qp * Np));
+  }
+  if (dense32) {
+    TRY(dalloc(c, &c->PdX, (size_t)Qp * Dp));
+    TRY(dalloc(c, &c->VX, (size_t)Qp * Np));
   }
   TRY(dalloc(c, &c->theta, Dp));
   TRY(dalloc(c, &c->alpha, Dp));
@@ -546,6 +564,7 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
   if (c->V) zero_ok &= hipMemsetAsync(c->V, 0, (size_t)Qp * Np * sizeof(float), c->stream) == hipSuccess;
   if (c->VH) zero_ok &= hipMemsetAsync(c->VH, 0, (size_t)Qp * Np * sizeof(uint16_t), c->stream) == hipSuccess;
   if (c->VL) zero_ok &= hipMemsetAsync(c->VL, 0, (size_t)Qp * Np * sizeof(uint16_t), c->stream) == hipSuccess;
+  if (c->VX) zero_ok &= hipMemsetAsync(c->VX, 0, (size_t)Qp * Np * sizeof(uint16_t), c->stream) == hipSuccess;
   if (!zero_ok || hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
     free_all(c);
     delete c;
@@ -692,8 +711,9 @@ COFEM_API cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const flo
   SolveCfg sc = solve_cfg(c);
   sc.Q = ncols;
   launch_copy_pad(alpha, c->p.D, c->Dp, 1.0f, c->alpha_hook, c->stream);
-  launch_pack_block(P, ncols, c->p.D, c->Qp, c->Dp, c->Pd, use_bf16 ? c->PdH : nullptr, use_bf16 ? c->PdL : nullptr,
-                    c->stream);
+  const bool sliced32 = !use_bf16 && c->PdX;
+  launch_pack_block(P, ncols, c->p.D, c->Qp, c->Dp, c->Pd, (use_bf16 || sliced32) ? c->PdH : nullptr,
+                    (use_bf16 || sliced32) ? c->PdL : nullptr, c->stream, sliced32 ? c->PdX : nullptr);
   launch_state_reset(c->st, c->Q, c->stream);
   cofem_status rc = apply_operator(c, use_bf16 != 0, c->alpha_hook, sc, 0);
   if (rc != COFEM_OK) return rc;

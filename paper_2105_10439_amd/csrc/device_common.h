@@ -41,14 +41,27 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) 
   hi = bf16_rne(x);
   lo = bf16_rne(x - bf16_val(hi));
 }
-__device__ __forceinline__ void store_split4(uint16_t* H, uint16_t* L, int64_t o, const f32x4& v) {
-  uint16_t h[4], l[4];
+// The third slice of x after split_bf16: x = hi + lo + x3 exactly (x - hi - lo has at
+// most 8 significant bits, so both subtractions are exact and x3 is a bf16 value).
+__device__ __forceinline__ uint16_t slice3_bf16(float x, uint16_t hi, uint16_t lo) {
+  return bf16_rne((x - bf16_val(hi)) - bf16_val(lo));
+}
+// Four values' hi/lo slices (and, with X, their third slices) at offset o.
+__device__ __forceinline__ void store_split4(uint16_t* H, uint16_t* L, int64_t o, const f32x4& v,
+                                             uint16_t* X = nullptr) {
+  uint16_t h[4], l[4], x[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) split_bf16(v[e], h[e], l[e]);
+  for (int e = 0; e < 4; ++e) {
+    split_bf16(v[e], h[e], l[e]);
+    x[e] = slice3_bf16(v[e], h[e], l[e]);
+  }
   *reinterpret_cast<uint2*>(H + o) =
       make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
   *reinterpret_cast<uint2*>(L + o) =
       make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16), (uint32_t)l[2] | ((uint32_t)l[3] << 16));
+  if (X)
+    *reinterpret_cast<uint2*>(X + o) =
+        make_uint2((uint32_t)x[0] | ((uint32_t)x[1] << 16), (uint32_t)x[2] | ((uint32_t)x[3] << 16));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

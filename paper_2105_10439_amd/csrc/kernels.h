@@ -85,11 +85,13 @@ void launch_axpy(float* y, const float* x, float a, int64_t n, hipStream_t s);
 
 // ---- per EM iteration --------------------------------------------------------
 // Probes for iteration key `key`, B = [b | p_1..p_K | 0], minv = 1/(beta theta + alpha),
-// X = 0, R = B, Pd = W = minv R (FP32 and, if PdH != null, bf16 hi/lo); then one
-// block sets the initial rho, ||B_q||^2, active flags and resets done/steps (two launches).
+// X = 0, R = B, Pd = W = minv R (FP32 and, if PdH != null, bf16 hi/lo, and if PdX != null
+// the third slice: Pd = hi + lo + X exactly); then one block sets the initial rho,
+// ||B_q||^2, active flags and resets done/steps (two launches).
 void launch_em_init(const SolveCfg& c, uint64_t key, int64_t D, int64_t Dp, const float* b,
                     const float* theta, const float* alpha, float* minv, float* X, float* R, float* Pd,
-                    uint16_t* PdH, uint16_t* PdL, double* part, CGState* st, hipStream_t s);
+                    uint16_t* PdH, uint16_t* PdL, double* part, CGState* st, hipStream_t s,
+                    uint16_t* PdX = nullptr);
 
 // mu = X_0, s = (1/K) sum_k p_k X_k (probes regenerated from `key`); if do_mstep,
 // alpha = 1 / max(mu^2 + s, floor) and clamp events are counted in st->clamped.
@@ -110,15 +112,18 @@ GemmCfg choose_gemm(int64_t rows, int64_t kdim, int bf16);
 // M + s sps, its rows holding k in [s kchunk, (s + 1) kchunk)).  FP32: rows of
 // dict_ld(kdim, 4) elements.
 // bf16: M, ZH, ZL are bf16 bits, products of M with ZH and ZL accumulate in FP32.
+// FP32: M is FP32, Z is given as its three bf16 slices ZH + ZM + ZL (exact); the
+// products are formed on the bf16 matrix cores from slices of both operands.
 void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t ldm, int64_t sps, int64_t rows, int64_t kdim,
                       const uint16_t* ZH, const uint16_t* ZL, int Q, int Qp, float* Yp, const CGState* st,
                       hipStream_t s);
-void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Q, int Qp,
-                     float* Ypart, const CGState* st, hipStream_t s);
+void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
+                     const uint16_t* ZM, const uint16_t* ZL, int Q, int Qp, float* Ypart, const CGState* st,
+                     hipStream_t s);
 
-// V = sum_split Ypart (rows Np); writes V (FP32) and/or VH/VL (bf16 hi/lo).
+// V = sum_split Ypart (rows Np); writes V (FP32) and/or VH/VL (bf16 hi/lo) and VX (third slice).
 void launch_finish_pass1(const float* Ypart, int splits, int Q, int Qp, int64_t Np, float* V, uint16_t* VH,
-                         uint16_t* VL, const CGState* st, hipStream_t s);
+                         uint16_t* VL, const CGState* st, hipStream_t s, uint16_t* VX = nullptr);
 
 // Psi = beta * sum_split Ypart + alpha * Pd (columns q < c.Q) and per-chunk partials of
 // pi_q = sum_j Pd_jq Psi_jq into pipart ([q][chunk], chunks of 1024 coordinates).
@@ -133,9 +138,9 @@ void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipS
 // and computes eta (two launches; three when a first block reduces the pi partials).
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
                       const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s);
-// Pd = minv R + eta Pd (FP32, and bf16 hi/lo if PdH != null).
+// Pd = minv R + eta Pd (FP32, and bf16 hi/lo if PdH != null, and the third slice if PdX != null).
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
-                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s);
+                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX = nullptr);
 
 // Multi-task M-step over L tasks' mu and s (device arrays of L device pointers).
 void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int64_t D, float* alpha, double floor,
@@ -143,9 +148,9 @@ void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int
 
 // ---- test-hook helpers ---------------------------------------------------------
 // Copy ncols columns of length D (caller layout) into a Qp x Dp block (zero padding),
-// optionally also as bf16 hi/lo.
+// optionally also as bf16 hi/lo (and the third slice dX).
 void launch_pack_block(const float* src, int ncols, int64_t D, int Qp, int64_t Dp, float* dst, uint16_t* dH,
-                       uint16_t* dL, hipStream_t s);
+                       uint16_t* dL, hipStream_t s, uint16_t* dX = nullptr);
 void launch_unpack_block(const float* src, int ncols, int64_t D, int64_t Dp, float* dst, hipStream_t s);
 void launch_copy_pad(const float* src, int64_t n, int64_t np, float pad, float* dst, hipStream_t s);
 void launch_state_reset(CGState* st, int Q, hipStream_t s);

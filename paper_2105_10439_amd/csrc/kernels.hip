@@ -115,8 +115,9 @@ __global__ __launch_bounds__(VBLOCK) void k_em_init(SolveCfg c, uint64_t key, in
                                                     const float* __restrict__ alpha, float* __restrict__ minv,
                                                     float* __restrict__ X, float* __restrict__ R,
                                                     float* __restrict__ Pd, uint16_t* __restrict__ PdH,
-                                                    uint16_t* __restrict__ PdL, double* __restrict__ part) {
-  em_init_block(c, key, D, Dp, blockIdx.x, b, theta, alpha, minv, X, R, Pd, PdH, PdL, part);
+                                                    uint16_t* __restrict__ PdL, uint16_t* __restrict__ PdX,
+                                                    double* __restrict__ part) {
+  em_init_block(c, key, D, Dp, blockIdx.x, b, theta, alpha, minv, X, R, Pd, PdH, PdL, PdX, part);
 }
 
 __global__ __launch_bounds__(VBLOCK) void k_em_scalars(SolveCfg c, int64_t D, int nblk,
@@ -144,20 +145,21 @@ __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void k_gemm_bf16(const uint16_t
 
 template <int RT, int CT, int KS, bool X1>
 __global__ __launch_bounds__(64 * GEMM_WAVES, 2) void k_gemm_f32(const float* __restrict__ M, int64_t ldm,
-                                                     const float* __restrict__ Z, int64_t ldz,
+                                                     const uint16_t* __restrict__ ZH, const uint16_t* __restrict__ ZM,
+                                                     const uint16_t* __restrict__ ZL, int64_t ldz,
                                                      float* __restrict__ Yp, int64_t ldy, int Qp, int64_t kchunk,
                                                      int64_t kdim, int nrb, int splits,
                                                      const int* __restrict__ done) {
   if (done && *done) return;
-  gemm_f32_tile<RT, CT, KS, X1>(blockIdx.x, M, ldm, Z, ldz, Yp, ldy, Qp, kchunk, kdim, nrb, splits);
+  gemm_f32s_tile<RT, CT, KS, X1>(blockIdx.x, M, ldm, ZH, ZM, ZL, ldz, Yp, ldy, Qp, kchunk, kdim, nrb, splits);
 }
 
 __global__ __launch_bounds__(256) void k_finish_pass1(const float* __restrict__ Yp, int splits, int64_t Np,
                                                       float* __restrict__ V, uint16_t* __restrict__ VH,
-                                                      uint16_t* __restrict__ VL, int Qp,
+                                                      uint16_t* __restrict__ VL, uint16_t* __restrict__ VX, int Qp,
                                                       const int* __restrict__ done) {
   if (*done) return;
-  finish1_tile(blockIdx.x, blockIdx.y, Yp, splits, Np, V, VH, VL, Qp);
+  finish1_tile(blockIdx.x, blockIdx.y, Yp, splits, Np, V, VH, VL, Qp, VX);
 }
 
 __global__ __launch_bounds__(VBLOCK) void k_finish_pass2(SolveCfg c, const float* __restrict__ Yp, int splits,
@@ -193,9 +195,9 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(SolveCfg c, int nbx, const 
 __global__ __launch_bounds__(VBLOCK) void k_cg_direction(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                          const float* __restrict__ R, float* __restrict__ Pd,
                                                          uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
-                                                         const CGState* __restrict__ st) {
+                                                         uint16_t* __restrict__ PdX, const CGState* __restrict__ st) {
   if (st->done) return;
-  cg_direction_tile(blockIdx.x, blockIdx.y, Dp, minv, R, Pd, PdH, PdL, st);
+  cg_direction_tile(blockIdx.x, blockIdx.y, Dp, minv, R, Pd, PdH, PdL, st, PdX);
 }
 
 // One block: pi_q into the state (used by the single-application test hook).
@@ -236,7 +238,8 @@ __global__ __launch_bounds__(VBLOCK) void k_mt_mstep(const float* const* __restr
 // test-hook helpers
 // ---------------------------------------------------------------------------
 __global__ void k_pack_block(const float* __restrict__ src, int ncols, int64_t D, int Qp, int64_t Dp,
-                             float* __restrict__ dst, uint16_t* __restrict__ dH, uint16_t* __restrict__ dL) {
+                             float* __restrict__ dst, uint16_t* __restrict__ dH, uint16_t* __restrict__ dL,
+                             uint16_t* __restrict__ dX) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (j >= Dp || q >= Qp) return;
@@ -248,6 +251,7 @@ __global__ void k_pack_block(const float* __restrict__ src, int ncols, int64_t D
     split_bf16(v, h, l);
     dH[o] = h;
     dL[o] = l;
+    if (dX) dX[o] = slice3_bf16(v, h, l);
   }
 }
 __global__ void k_unpack_block(const float* __restrict__ src, int ncols, int64_t D, int64_t Dp,
@@ -300,10 +304,10 @@ void launch_state_reset(CGState* st, int Q, hipStream_t s) {
 
 void launch_em_init(const SolveCfg& c, uint64_t key, int64_t D, int64_t Dp, const float* b, const float* theta,
                     const float* alpha, float* minv, float* X, float* R, float* Pd, uint16_t* PdH, uint16_t* PdL,
-                    double* part, CGState* st, hipStream_t s) {
+                    double* part, CGState* st, hipStream_t s, uint16_t* PdX) {
   const int nblk = (int)(Dp / VBLOCK);
   hipLaunchKernelGGL(k_em_init, dim3((unsigned)nblk), dim3(VBLOCK), 0, s, c, key, D, Dp, b, theta, alpha, minv, X,
-                     R, Pd, PdH, PdL, part);
+                     R, Pd, PdH, PdL, PdX, part);
   hipLaunchKernelGGL(k_em_scalars, dim3(1), dim3(VBLOCK), 0, s, c, D, nblk, (const double*)part, st);
 }
 
@@ -328,7 +332,7 @@ GemmCfg choose_gemm(int64_t rows, int64_t kdim, int bf16) {
 }
 
 constexpr int KS_BF16 = 2;  // 32-k steps per stage (64 k)
-constexpr int KS_F32 = 4;   // 16-k steps per stage (64 k)
+constexpr int KS_F32 = 1;   // 32-k steps per stage (32 k)
 
 // Column tiles for Q right-hand sides: MFMA tiles of 16, except that a lone column past one
 // or two full tiles (Q = 17, 33) goes to the vector ALU instead of a mostly padded tile.
@@ -341,7 +345,7 @@ static inline void gemm_cols(int Q, int& ct, bool& x1) {
   hipLaunchKernelGGL((k_gemm_bf16<RT, CT, KS_BF16, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, ldm, sps, ZH, ZL, kdim, \
                      Yp, rows, Qp, g.kchunk, kdim, nrb, g.splits, done)
 #define GEMM_F32(RT, CT, X1)                                                                                    \
-  hipLaunchKernelGGL((k_gemm_f32<RT, CT, KS_F32, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, ldm, Z, kdim, Yp,  \
+  hipLaunchKernelGGL((k_gemm_f32<RT, CT, KS_F32, X1>), grid, dim3(64 * GEMM_WAVES), 0, s, M, ldm, ZH, ZM, ZL, kdim, Yp, \
                      rows, Qp, g.kchunk, kdim, nrb, g.splits, done)
 
 template <int RT>
@@ -376,8 +380,9 @@ void launch_gemm_bf16(const GemmCfg& g, const uint16_t* M, int64_t ldm, int64_t 
 }
 
 template <int RT>
-static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t ldm, int64_t rows, int64_t kdim, const float* Z,
-                        int Q, int Qp, float* Yp, const int* done, hipStream_t s) {
+static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t ldm, int64_t rows, int64_t kdim, const uint16_t* ZH,
+                        const uint16_t* ZM, const uint16_t* ZL, int Q, int Qp, float* Yp, const int* done,
+                        hipStream_t s) {
   const int nrb = (int)(rows / (64 * RT));
   dim3 grid((unsigned)(nrb * g.splits));
   int ct;
@@ -396,19 +401,20 @@ static void gemm_f32_rt(const GemmCfg& g, const float* M, int64_t ldm, int64_t r
   }
 }
 
-void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const float* Z, int Q, int Qp,
-                     float* Yp, const CGState* st, hipStream_t s) {
+void launch_gemm_f32(const GemmCfg& g, const float* M, int64_t rows, int64_t kdim, const uint16_t* ZH,
+                     const uint16_t* ZM, const uint16_t* ZL, int Q, int Qp, float* Yp, const CGState* st,
+                     hipStream_t s) {
   const int* done = st ? &st->done : nullptr;
   const int64_t ldm = dict_ld(kdim, 4);
-  if (g.rt == 4) gemm_f32_rt<4>(g, M, ldm, rows, kdim, Z, Q, Qp, Yp, done, s);
-  else if (g.rt == 2) gemm_f32_rt<2>(g, M, ldm, rows, kdim, Z, Q, Qp, Yp, done, s);
-  else gemm_f32_rt<1>(g, M, ldm, rows, kdim, Z, Q, Qp, Yp, done, s);
+  if (g.rt == 4) gemm_f32_rt<4>(g, M, ldm, rows, kdim, ZH, ZM, ZL, Q, Qp, Yp, done, s);
+  else if (g.rt == 2) gemm_f32_rt<2>(g, M, ldm, rows, kdim, ZH, ZM, ZL, Q, Qp, Yp, done, s);
+  else gemm_f32_rt<1>(g, M, ldm, rows, kdim, ZH, ZM, ZL, Q, Qp, Yp, done, s);
 }
 
 void launch_finish_pass1(const float* Ypart, int splits, int Q, int Qp, int64_t Np, float* V, uint16_t* VH,
-                         uint16_t* VL, const CGState* st, hipStream_t s) {
+                         uint16_t* VL, const CGState* st, hipStream_t s, uint16_t* VX) {
   dim3 grid(cdiv(Np, VCHUNK), (unsigned)Q);
-  hipLaunchKernelGGL(k_finish_pass1, grid, dim3(256), 0, s, Ypart, splits, Np, V, VH, VL, Qp, &st->done);
+  hipLaunchKernelGGL(k_finish_pass1, grid, dim3(256), 0, s, Ypart, splits, Np, V, VH, VL, VX, Qp, &st->done);
 }
 
 void launch_finish_pass2(const SolveCfg& c, const float* Ypart, int splits, int64_t Dp, const float* alpha,
@@ -440,9 +446,9 @@ void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipS
 }
 
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
-                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s) {
+                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX) {
   hipLaunchKernelGGL(k_cg_direction, dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd,
-                     PdH, PdL, st);
+                     PdH, PdL, PdX, st);
 }
 
 void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int64_t D, float* alpha, double floor,
@@ -451,9 +457,9 @@ void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int
 }
 
 void launch_pack_block(const float* src, int ncols, int64_t D, int Qp, int64_t Dp, float* dst, uint16_t* dH,
-                       uint16_t* dL, hipStream_t s) {
+                       uint16_t* dL, hipStream_t s, uint16_t* dX) {
   hipLaunchKernelGGL(k_pack_block, dim3(cdiv(Dp, 256), (unsigned)Qp), dim3(256), 0, s, src, ncols, D, Qp, Dp, dst,
-                     dH, dL);
+                     dH, dL, dX);
 }
 void launch_unpack_block(const float* src, int ncols, int64_t D, int64_t Dp, float* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack_block, dim3(cdiv(D, 256), (unsigned)ncols), dim3(256), 0, s, src, ncols, D, Dp,

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(VBLOCK) void ks_em_init(const SlotDev* __restrict__
     const int local = t - tab->em[i];
     if (sd.st->phase != PH_INIT || local >= (int)(sd.Dp / VBLOCK)) continue;
     em_init_block(sd.c, iteration_key(sd.seed, sd.st->t), sd.D, sd.Dp, local, sd.b, sd.theta, sd.alpha, sd.minv,
-                  sd.X, sd.R, sd.Pd, nullptr, nullptr, sd.part);
+                  sd.X, sd.R, sd.Pd, nullptr, nullptr, nullptr, sd.part);
   }
 }
 

@@ -19,7 +19,7 @@ __device__ __forceinline__ void em_init_block(const SolveCfg& c, uint64_t key, i
                                               const float* __restrict__ alpha, float* __restrict__ minv,
                                               float* __restrict__ X, float* __restrict__ R, float* __restrict__ Pd,
                                               uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
-                                              double* __restrict__ part) {
+                                              uint16_t* __restrict__ PdX, double* __restrict__ part) {
   const int64_t j = (int64_t)blk * VBLOCK + threadIdx.x;  // Dp is a multiple of VBLOCK
   const bool real = j < D;
   const float mi = (float)(1.0 / (c.beta * (double)theta[j] + (double)alpha[j]));
@@ -40,6 +40,7 @@ __device__ __forceinline__ void em_init_block(const SolveCfg& c, uint64_t key, i
       split_bf16(p, h, l);
       PdH[o] = h;
       PdL[o] = l;
+      if (PdX) PdX[o] = slice3_bf16(p, h, l);
     }
   }
   // rho_0 = sum_j b_j (minv_j b_j); rho_q = sum_j minv_j for probes (entries square to 1); ||b||^2
@@ -405,21 +406,188 @@ __device__ __forceinline__ void gemm_f32_tile(int L, const float* __restrict__ M
 }
 
 
+// FP32 operands on the bf16 matrix cores.  Every FP32 value x is cut into three bf16
+// slices x = h + m + l exactly: h = bf16(x), m = bf16(x - h), l = x - h - m (x - h has
+// at most 16 significant bits and x - h - m at most 8, so both differences are exact in
+// FP32 and l is a bf16 value).  A product x y is the sum of the six slice products of
+// order 2^-16 |x y| or more (hh, hm, mh, hl, mm, lh); the three dropped ones are below
+// 2^-26 |x y| (round-to-nearest slices), under the FP32 rounding of the product itself.
+// v_mfma_f32_16x16x32_bf16 forms each slice product exactly and accumulates in FP32, so
+// six of them per 32-k step take 3/8 of the matrix-core time of the eight
+// v_mfma_f32_16x16x4_f32 the same step needs: the FP32 operator stays off the FP32
+// matrix peak, which it would otherwise need 81 % of to stream at 8 TB/s.  The
+// right-hand sides arrive already sliced (split3_bf16 where they are produced); the
+// dictionary is sliced in registers on the vector ALU beside the MFMAs (about 5.5
+// operations per value).
+__device__ __forceinline__ void slice3(const f32x4& x0, const f32x4& x1, bf16x8_t& h, bf16x8_t& m, bf16x8_t& l) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float x = e < 4 ? x0[e] : x1[e - 4];
+    const __bf16 hb = (__bf16)x;
+    const float r = x - (float)hb;
+    const __bf16 mb = (__bf16)r;
+    h[e] = hb;
+    m[e] = mb;
+    l[e] = (__bf16)(r - (float)mb);
+  }
+}
+
+// The FP32 contraction on sliced operands: the layout of gemm_bf16_tile (lane l holds
+// A[l%16][8(l/16) .. +8) and B[8(l/16) .. +8)[l%16]), with A read as FP32 straight from
+// HBM (two 16-byte loads per row tile and 32-k step) and sliced in registers, and the
+// right-hand sides' three slices ZH, ZM, ZL staged through LDS by DMA as in the bf16
+// tile.  X1: the extra column's slices h, m, l ride as columns 0, 1, 2 of one more MFMA
+// tile (the other columns are don't-care), multiplied by all three slices of A, so that
+// tile's columns 0 + 1 + 2 are the full product; they are added lane to lane at the end.
+template <int RT, int CT, int KS, bool X1>
+__device__ __forceinline__ void gemm_f32s_tile(int L, const float* __restrict__ M, int64_t ldm,
+                                               const uint16_t* __restrict__ ZH, const uint16_t* __restrict__ ZM,
+                                               const uint16_t* __restrict__ ZL, int64_t ldz, float* __restrict__ Yp,
+                                               int64_t ldy, int Qp, int64_t kchunk, int64_t kdim, int nrb,
+                                               int splits) {
+  constexpr int FS = CT * 3 + (X1 ? 1 : 0);  // fragments per 32-k step
+  constexpr int NF = KS * FS;                 // fragments per stage
+  constexpr int SK = 32 * KS;                 // k per stage
+  __shared__ bf16x8_t sB[2][NF][64];
+  int rb, sp;
+  tile_of(L, nrb, splits, rb, sp);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int64_t kb = (int64_t)sp * kchunk;
+  const int64_t ke = (kb + kchunk < kdim) ? kb + kchunk : kdim;
+  const int nst = (ke > kb) ? (int)((ke - kb) / SK) : 0;
+  if (nst == 0 || wave >= GEMM_WAVES) return;  // the tile is 64 RT rows: waves past the fourth have none
+  auto issue_B = [&](int st, int buf) {
+#pragma unroll
+    for (int i = 0; i < (NF + 3) / 4; ++i) {
+      const int f = wave + 4 * i;
+      if (f < NF) {
+        const int s = f / FS, rem = f % FS;
+        const int64_t k = kb + (int64_t)st * SK + s * 32 + 8 * g;
+        if (X1 && rem == CT * 3) {
+          // the extra column: lanes of columns 1 and 2 take its m and l slices, all others h
+          lds_dma16((r16 == 1 ? ZM : (r16 == 2 ? ZL : ZH)) + (int64_t)(CT * 16) * ldz + k, &sB[buf][f][0]);
+        } else {
+          const int ct = rem / 3, piece = rem % 3;
+          lds_dma16((piece == 0 ? ZH : (piece == 1 ? ZM : ZL)) + (int64_t)(ct * 16 + r16) * ldz + k,
+                    &sB[buf][f][0]);
+        }
+      }
+    }
+  };
+  const int64_t row0 = (int64_t)rb * (64 * RT) + (int64_t)wave * (16 * RT);
+  f32x4 acc[RT][CT], accx[RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a) {
+#pragma unroll
+    for (int b = 0; b < CT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    accx[a] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const float* ap[RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a) ap[a] = M + (row0 + a * 16 + r16) * ldm + kb + 8 * g;
+  f32x4 acur[RT][KS][2];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) acur[a][s][h] = *reinterpret_cast<const f32x4*>(ap[a] + s * 32 + 4 * h);
+  issue_B(0, 0);
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    wait_vm_all();    // this wave's A and B pieces of stage st
+    __syncthreads();  // every wave's B pieces; buf ^ 1 is no longer read
+    const int nx = (st + 1 < nst) ? st + 1 : st;
+    f32x4 anxt[RT][KS][2];
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          anxt[a][s][h] = *reinterpret_cast<const f32x4*>(ap[a] + (int64_t)nx * SK + s * 32 + 4 * h);
+    issue_B(nx, buf ^ 1);
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this stage's MFMAs
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      bf16x8_t bh[CT], bm[CT], bl[CT];
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        bh[b] = sB[buf][s * FS + 3 * b + 0][lane];
+        bm[b] = sB[buf][s * FS + 3 * b + 1][lane];
+        bl[b] = sB[buf][s * FS + 3 * b + 2][lane];
+      }
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        bf16x8_t ah, am, al;
+        slice3(acur[a][s][0], acur[a][s][1], ah, am, al);
+#pragma unroll
+        for (int b = 0; b < CT; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
+        }
+        if constexpr (X1) {
+          const bf16x8_t bx = sB[buf][s * FS + CT * 3][lane];
+          accx[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bx, accx[a], 0, 0, 0);
+          accx[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bx, accx[a], 0, 0, 0);
+          accx[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bx, accx[a], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acur[a][s][h] = anxt[a][s][h];
+  }
+  wait_vm_all();  // the last (self-reloading) DMA has landed before the LDS is released
+  float* yb = Yp + (int64_t)sp * Qp * ldy;
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int64_t q = b * 16 + r16;
+      const int64_t row = row0 + a * 16 + 4 * g;
+      *reinterpret_cast<f32x4*>(yb + q * ldy + row) = acc[a][b];
+    }
+  if constexpr (X1) {
+    // column 16 CT = columns 0 + 1 + 2 of the extra tile (lanes r16 = 0, 1, 2)
+    float* ycol = yb + (int64_t)(CT * 16) * ldy;
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      f32x4 v = accx[a];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float c1 = __shfl_down(v[e], 1, 64), c2 = __shfl_down(v[e], 2, 64);
+        v[e] = (v[e] + c1) + c2;
+      }
+      if (r16 == 0) *reinterpret_cast<f32x4*>(ycol + row0 + a * 16 + 4 * g) = v;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Split-K finishes and the CG vector updates.  Vector tiles: (chunk bx of VCHUNK
 // coordinates, column q); each thread owns 4 consecutive coordinates.
 // ---------------------------------------------------------------------------
-// V[q][i] = sum_split Ypart[split][q][i] (fixed split order); V (FP32) and/or VH/VL.
+// V[q][i] = sum_split Ypart[split][q][i] (fixed split order); V (FP32) and/or VH/VL (and
+// the third slice VX).
 __device__ __forceinline__ void finish1_tile(int bx, int q, const float* __restrict__ Yp, int splits, int64_t Np,
                                              float* __restrict__ V, uint16_t* __restrict__ VH,
-                                             uint16_t* __restrict__ VL, int Qp) {
+                                             uint16_t* __restrict__ VL, int Qp, uint16_t* __restrict__ VX = nullptr) {
   const int64_t i = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
   if (i >= Np) return;
   const int64_t o = (int64_t)q * Np + i;
   f32x4 v = *reinterpret_cast<const f32x4*>(Yp + o);
   for (int sp = 1; sp < splits; ++sp) v += *reinterpret_cast<const f32x4*>(Yp + (int64_t)sp * Qp * Np + o);
   if (V) *reinterpret_cast<f32x4*>(V + o) = v;
-  if (VH) store_split4(VH, VL, o, v);
+  if (VH) store_split4(VH, VL, o, v, VX);
 }
 
 // Psi = beta * sum_split Ypart + alpha Pd and the tile's partial of pi_q = sum_j Pd_jq Psi_jq
@@ -578,11 +746,12 @@ __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, con
   st->done = done;
 }
 
-// P = M^-1 R + eta P (FP32, and bf16 hi/lo when PdH is not null).
+// P = M^-1 R + eta P (FP32, and bf16 hi/lo when PdH is not null, and the third slice
+// when PdX is not null).
 __device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, const float* __restrict__ minv,
                                                   const float* __restrict__ R, float* __restrict__ Pd,
                                                   uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
-                                                  const CGState* __restrict__ st) {
+                                                  const CGState* __restrict__ st, uint16_t* __restrict__ PdX = nullptr) {
   const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
   if (j >= Dp) return;
   const double eta = st->eta[q];
@@ -593,7 +762,7 @@ __device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, con
 #pragma unroll
   for (int e = 0; e < 4; ++e) p[e] = (float)((double)mi[e] * (double)r[e] + eta * (double)p[e]);
   *reinterpret_cast<f32x4*>(Pd + o) = p;
-  if (PdH) store_split4(PdH, PdL, o, p);
+  if (PdH) store_split4(PdH, PdL, o, p, PdX);
 }
 
 }  // namespace cofem

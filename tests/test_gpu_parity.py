@@ -72,6 +72,30 @@ def test_apply_A_matches_oracle(gpu, N, D, ncols, dtype):
     m.close()
 
 
+@pytest.mark.parametrize("N,D,ncols", [(1024, 2048, 33), (513, 777, 21), (256, 512, 49)])
+def test_fp32_operator_is_fp32_accurate(gpu, N, D, ncols):
+    """The FP32 operator runs on three exact bf16 slices of each operand; with the six
+    leading slice products it is as accurate as FP32 arithmetic.  Bar: 1e-6 per column,
+    which two slices (about 2^-17 = 7.6e-6 per product) or a dropped slice product of
+    order 2^-16 would miss."""
+    rng = np.random.default_rng(N + 5 * D)
+    phi = workloads.gaussian_dictionary(N, D, seed=3 * N + D)
+    beta = 1e4
+    alpha = np.exp(rng.uniform(-3, 3, D)).astype(np.float32)
+    P = rng.standard_normal((ncols, D)).astype(np.float32)
+    m = gpu.CoFEM(N, D, beta, K=max(ncols - 1, 1), T=1, U=1, tol=0.0, phi_dtype="fp32")
+    m.set_dictionary(_t(phi))
+    Psi, _ = m.apply_A(_t(alpha), _t(P), use_bf16=False, want_pi=True)
+    Psi = _np(Psi)
+    m.close()
+    op = oracle.DenseOperator(phi)
+    Pt = P.T.astype(np.float64)
+    ref = (beta * op.rmatvec(op.matvec(Pt)) + alpha.astype(np.float64)[:, None] * Pt).T
+    errs = [_rel(Psi[q], ref[q]) for q in range(ncols)]
+    print(f"FP32 operator N={N} D={D} ncols={ncols}: max column error {max(errs):.2e}")
+    assert max(errs) < 1e-6
+
+
 # ---------------------------------------------------------------------------
 # full fits
 # ---------------------------------------------------------------------------
