@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define COFEM_ABI_VERSION 3
+#define COFEM_ABI_VERSION 4
 #define COFEM_MAX_T 512 /* longest EM run recorded in cofem_stats */
 #define COFEM_MAX_K 63  /* probes per EM iteration (one 64-bit hash word per coordinate) */
 
@@ -61,6 +61,7 @@ typedef enum { COFEM_STOP_JOINT = 0, COFEM_STOP_COLUMN = 1 } cofem_stop_mode;
 typedef enum { COFEM_OP_DENSE = 0, COFEM_OP_CONV = 1, COFEM_OP_DCT = 2 } cofem_op_kind;
 typedef enum { COFEM_PHI_FP32 = 0, COFEM_PHI_BF16 = 1 } cofem_phi_dtype;
 typedef enum { COFEM_MSTEP_GAUSSIAN = 0, COFEM_MSTEP_NONNEG = 1 } cofem_mstep_mode;
+typedef enum { COFEM_PROBES_HASH = 0, COFEM_PROBES_HADAMARD = 1 } cofem_probe_mode;
 
 /*
  * Fit parameters.  Names follow Algorithms 1 and 2.
@@ -212,6 +213,21 @@ cofem_status cofem_variance(cofem_ctx* c, const float* alpha, int32_t batches, u
  */
 cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const float* P, float* Psi,
                            int32_t ncols, int32_t use_bf16, double* pi);
+
+/*
+ * Test hook: the probes of every later E-step (fits and cofem_variance).
+ *   COFEM_PROBES_HASH (default): Rademacher probes from the counter-based hash,
+ *     redrawn each EM iteration (Sec. III-A, Alg. 1).
+ *   COFEM_PROBES_HADAMARD: probe k (k < K) is column k of the D x D
+ *     Sylvester-Hadamard matrix, entry (j, k) = (-1)^popcount(j & k), the same in
+ *     every EM iteration.  With K = D the cross terms of the diagonal estimate
+ *     (Eq. diag-estimate) cancel, because distinct rows of a Hadamard matrix are
+ *     orthogonal, and CoFEM reproduces EM with the explicit covariance up to the CG
+ *     tolerance: a check of the whole path against a closed form.
+ * Errors: COFEM_EINVAL (NULL context, unknown mode; Hadamard with D not a power of
+ * two or K > D).
+ */
+cofem_status cofem_set_probe_mode(cofem_ctx* c, int32_t mode);
 
 /*
  * Accumulated device time of the operator's matrix kernels (the two passes of

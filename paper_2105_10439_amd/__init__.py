@@ -22,13 +22,14 @@ STOP = {"joint": 0, "column": 1}
 OPS = {"dense": 0, "conv": 1, "dct": 2}
 DTYPES = {"fp32": 0, "bf16": 1}
 MSTEP = {"gaussian": 0, "nonneg": 1}
-ABI_VERSION = 3  # COFEM_ABI_VERSION of include/cofem.h
+PROBE_MODES = {"hash": 0, "hadamard": 1}
+ABI_VERSION = 4  # COFEM_ABI_VERSION of include/cofem.h
 
 # every symbol include/cofem.h declares
 EXPORTS = [
     "cofem_abi_version", "cofem_last_error", "cofem_create", "cofem_destroy", "cofem_set_dictionary",
     "cofem_set_dct_samples",
-    "cofem_fit", "cofem_posterior", "cofem_variance", "cofem_apply_A", "cofem_set_timing", "cofem_get_timing",
+    "cofem_fit", "cofem_posterior", "cofem_variance", "cofem_apply_A", "cofem_set_probe_mode", "cofem_set_timing", "cofem_get_timing",
     "cofem_server_create", "cofem_server_destroy", "cofem_server_submit", "cofem_server_step",
     "cofem_server_poll", "cofem_server_get_stats",
     "cofem_mt_create", "cofem_mt_destroy", "cofem_mt_set_dictionary", "cofem_mt_fit", "cofem_mt_posterior",
@@ -115,6 +116,7 @@ def load() -> ctypes.CDLL:
         "cofem_apply_A": (i32, [vp, vp, vp, vp, i32, i32, vp]),
         "cofem_variance": (i32, [vp, vp, i32, ctypes.c_uint64, vp, vp, ctypes.POINTER(Stats)]),
         "cofem_set_timing": (i32, [vp, i32]),
+        "cofem_set_probe_mode": (i32, [vp, i32]),
         "cofem_get_timing": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "cofem_server_create": (i32, [ctypes.c_size_t, i32, i32, vp, ctypes.POINTER(vp)]),
         "cofem_server_destroy": (None, [vp]),
@@ -245,6 +247,10 @@ class CoFEM:
 
     def set_timing(self, enable: bool):
         _check(load().cofem_set_timing(self._h, int(bool(enable))))
+
+    def set_probe_mode(self, mode: str):
+        """Test hook: "hash" (default) or "hadamard" probes for later E-steps."""
+        _check(load().cofem_set_probe_mode(self._h, PROBE_MODES[mode]))
 
     def get_timing(self, which: str):
         ms = ctypes.c_double()

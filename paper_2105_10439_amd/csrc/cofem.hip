@@ -81,6 +81,7 @@ struct cofem_ctx {
   // subsampled DCT dictionary: transform tables, mask, kept samples, scratch signal
   float2 *dct_tw = nullptr, *dct_w2 = nullptr, *dct_mz = nullptr;
   float2 *dct_mzt = nullptr, *dct_y1 = nullptr, *dct_y2 = nullptr;  // split operator (null: one workgroup per column)
+  int probe_mode = COFEM_PROBES_HASH;
   int32_t* dct_rows = nullptr;
   float* dct_u = nullptr;
   // D- and N-vectors
@@ -185,6 +186,7 @@ SolveCfg solve_cfg(const cofem_ctx* c) {
   s.nonneg = c->p.mstep_mode == COFEM_MSTEP_NONNEG ? 1 : 0;
   s.tol = c->p.tol;
   s.beta = c->p.beta;
+  s.hadamard = c->probe_mode;
   return s;
 }
 
@@ -723,6 +725,18 @@ COFEM_API cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const flo
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (c->timing && (rc = harvest(c, 1)) != COFEM_OK) return rc;
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_set_probe_mode(cofem_ctx* c, int32_t mode) {
+  if (!c) return fail(COFEM_EINVAL, "NULL context");
+  if (mode != COFEM_PROBES_HASH && mode != COFEM_PROBES_HADAMARD) return fail(COFEM_EINVAL, "bad probe mode");
+  if (mode == COFEM_PROBES_HADAMARD) {
+    const int64_t D = c->p.D;
+    if ((D & (D - 1)) != 0) return fail(COFEM_EINVAL, "Hadamard probes need D a power of two");
+    if (c->p.K > D) return fail(COFEM_EINVAL, "Hadamard probes need K <= D");
+  }
+  c->probe_mode = mode;
   return COFEM_OK;
 }
 

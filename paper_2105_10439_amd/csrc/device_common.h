@@ -27,6 +27,10 @@ __device__ __forceinline__ uint64_t probe_word(uint64_t key, int64_t j) {
   return mix64(key + (uint64_t)(j + 1) * GOLDEN_GAMMA);
 }
 __device__ __forceinline__ float probe_sign(uint64_t w, int k) { return ((w >> k) & 1ull) ? -1.0f : 1.0f; }
+// Entry (j, k) of the Sylvester-Hadamard matrix: (-1)^popcount(j & k).
+__device__ __forceinline__ float hadamard_sign(int64_t j, int k) {
+  return (__popcll((unsigned long long)j & (unsigned long long)k) & 1) ? -1.0f : 1.0f;
+}
 
 // float -> bfloat16, round to nearest even (NaN -> quiet NaN).
 __device__ __forceinline__ uint16_t bf16_rne(float f) {

@@ -41,8 +41,9 @@ struct CGState {
 
 struct SolveCfg {
   int Q, Qp, K, U, stop_mode;
-  int nonneg;  // M-step of the non-negative model (Sec. III-E.2)
+  int nonneg;        // M-step of the non-negative model (Sec. III-E.2)
   double tol, beta;
+  int hadamard = 0;  // probes: 0 the SplitMix64 hash, 1 columns 0..K-1 of the Sylvester-Hadamard matrix
 };
 
 // ---- setup -----------------------------------------------------------------

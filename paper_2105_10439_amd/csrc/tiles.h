@@ -29,7 +29,7 @@ __device__ __forceinline__ void em_init_block(const SolveCfg& c, uint64_t key, i
   const float bj = real ? b[j] : 0.0f;
   for (int q = 0; q < c.Qp; ++q) {
     float bq = 0.0f;
-    if (real) bq = (q == 0) ? bj : (q <= c.K ? probe_sign(w, q - 1) : 0.0f);
+    if (real) bq = (q == 0) ? bj : (q <= c.K ? (c.hadamard ? hadamard_sign(j, q - 1) : probe_sign(w, q - 1)) : 0.0f);
     const int64_t o = (int64_t)q * Dp + j;
     X[o] = 0.0f;
     R[o] = bq;
@@ -108,7 +108,10 @@ __device__ __forceinline__ void mstep_block(const SolveCfg& c, uint64_t key, int
     const float m = X[j];
     const uint64_t w = probe_word(key, j);
     double acc = 0.0;
-    for (int k = 0; k < c.K; ++k) acc += (double)probe_sign(w, k) * (double)X[(int64_t)(k + 1) * Dp + j];
+    for (int k = 0; k < c.K; ++k) {
+      const float pk = c.hadamard ? hadamard_sign(j, k) : probe_sign(w, k);
+      acc += (double)pk * (double)X[(int64_t)(k + 1) * Dp + j];
+    }
     const double s = acc / (double)c.K;
     mu[j] = m;
     s_out[j] = (float)s;

@@ -100,9 +100,10 @@ def test_null_arguments_are_rejected():
     assert so.cofem_fit(None, None) == -1
     assert so.cofem_set_dictionary(None, None) == -1
     assert so.cofem_set_dct_samples(None, None) == -1
+    assert so.cofem_set_probe_mode(None, 1) == -1
     assert so.cofem_posterior(None, None, None, None, None) == -1
     so.cofem_destroy(None)
-    assert so.cofem_abi_version() == 3
+    assert so.cofem_abi_version() == 4
 
 
 def test_server_rejects_bad_arguments_without_device_work():
