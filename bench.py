@@ -103,6 +103,8 @@ def parse():
     ap.add_argument("--no-conv", action="store_true", help="skip the convolutional-dictionary fits")
     ap.add_argument("--conv-only", action="store_true", help="only the convolutional-dictionary fits (for profiling)")
     ap.add_argument("--no-dct", action="store_true", help="skip the DCT-dictionary fits")
+    ap.add_argument("--no-multitask", action="store_true", help="skip the multi-task fit")
+    ap.add_argument("--multitask-only", action="store_true", help="only the multi-task fit (for profiling)")
     ap.add_argument("--dct-only", action="store_true", help="only the DCT-dictionary fits (for profiling)")
     ap.add_argument("--dct-fits", type=int, default=5, help="timed DCT-dictionary fits")
     ap.add_argument("--serve-only", action="store_true", help="only the serving phase (for profiling)")
@@ -166,6 +168,12 @@ def main():
 
         torch.cuda.set_device(0)
         print(json.dumps({"dct": dct_bench(args.dct_fits)}), flush=True)
+        return
+    if args.multitask_only:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"multitask": multitask_bench()}), flush=True)
         return
     import numpy as np
     import torch
@@ -268,6 +276,8 @@ def main():
         out["conv"] = conv_bench()
     if not args.no_dct:
         out["dct"] = dct_bench(args.dct_fits)
+    if not args.no_multitask:
+        out["multitask"] = multitask_bench()
     if args.serve_requests > 0:
         out["serving"] = serving(args)
     print(json.dumps(out), flush=True)
@@ -275,8 +285,10 @@ def main():
 
 def conv_bench():
     """The convolutional dictionary (D = 2^20 causal FIR, 256 taps): one warm-up and
-    one timed fit with bf16 taps and the last 3 EM iterations on FP32 taps, and one
-    timed all-FP32 fit.  Per operator application (both filter passes): algorithmic
+    one timed fit with bf16 taps and the last 3 EM iterations on FP32 taps, one timed
+    all-FP32 fit, and one timed bf16-refined fit with the non-negative M-step of
+    Sec. III-E.2 (the model of the calcium-deconvolution application); NRMSE of mu
+    against the true spikes for each.  Per operator application (both filter passes): algorithmic
     flops 4 L D Q (Q = K + 1 real columns) against the MFMA peak of the dtype, and
     algorithmic bytes (pass 1 reads Pd and writes V, pass 2 reads V, Pd, alpha and
     writes Psi: 20 D Q + 4 D bytes, signals as FP32 or as bf16 hi/lo pairs) against 8 TB/s."""
@@ -295,9 +307,11 @@ def conv_bench():
     peak = {"bf16": 2500.0, "fp32": 157.3}
     res = dict(workload=f"causal FIR dictionary: D=N={D}, {L} taps of exp(-t/{w['tau']:g}), Bernoulli({w['p']})*Exp(1) "
                         f"spikes, sigma={w['sigma']}, K={w['K']} T={w['T']} tol={w['tol']} U={w['U']}")
-    for name, dt, refine in (("bf16_refined", "bf16", 3), ("fp32", "fp32", 0)):
+    z = torch.from_numpy(prob.z)
+    for name, dt, refine, mstep in (("bf16_refined", "bf16", 3, "gaussian"), ("fp32", "fp32", 0, "gaussian"),
+                                    ("bf16_refined_nonneg", "bf16", 3, "nonneg")):
         m = lib.CoFEM(D, D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024, op="conv",
-                      conv_taps=L, phi_dtype=dt, refine_last=refine)
+                      conv_taps=L, phi_dtype=dt, refine_last=refine, mstep=mstep)
         if dt == "bf16":
             m.set_dictionary(h_d)
             m.fit(y_d)
@@ -308,7 +322,8 @@ def conv_bench():
         m.fit(y_d)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
-        _, _, _, st = m.posterior()
+        mu, _, _, st = m.posterior()
+        nrmse = float(torch.linalg.vector_norm(mu.double().cpu() - z) / torch.linalg.vector_norm(z))
         passes = {}
         for k in ("bf16", "fp32"):
             ms, n = m.get_timing(k)
@@ -322,8 +337,50 @@ def conv_bench():
         m.close()
         res[name] = dict(em_iters_per_s=round(w["T"] / el, 3), ms_per_fit=round(1e3 * el, 1),
                          cg_steps=st["total_cg_steps"], ms_per_cg_step=round(1e3 * el / st["total_cg_steps"], 4),
-                         passes=passes)
+                         nrmse=round(nrmse, 4), passes=passes)
         log(f"conv {name}: {res[name]}")
+    return res
+
+
+def multitask_bench():
+    """Multi-task CoFEM (Sec. III-E.1): L = 4 tasks of the medium shape (N = 2048,
+    D = 8192, FP32 dictionaries, 64 MiB each) sharing one support of 5 % spikes, K = 20,
+    T = 30, tol 1e-5: one warm-up and one timed fit.  The value is shared-alpha EM
+    iterations per second (each = L covariance-free E-steps and one joint M-step)."""
+    import torch
+
+    import paper_2105_10439_amd as lib
+    import workloads
+
+    w = dict(workloads.WORKLOADS["multitask"])
+    probs = workloads.make_workload("multitask")
+    L, N, D = w["L"], w["N"], w["D"]
+    phis = [torch.from_numpy(p.phi).cuda() for p in probs]
+    ys = [torch.from_numpy(p.y).cuda() for p in probs]
+    m = lib.MultiTask(L, N, D, probs[0].beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024)
+    for l in range(L):
+        m.set_dictionary(l, phis[l])
+    m.fit(ys)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    m.fit(ys)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    steps, nrmse = [], []
+    for l in range(L):
+        mu, _, _, st = m.posterior(l)
+        steps.append(st["total_cg_steps"])
+        z = torch.from_numpy(probs[l].z)
+        nrmse.append(round(float(torch.linalg.vector_norm(mu.double().cpu() - z) / torch.linalg.vector_norm(z)), 4))
+    m.close()
+    op_bytes = 2.0 * N * D * 4 * sum(steps)  # two FP32 dictionary passes per CG step of each task
+    res = dict(workload=f"multi-task dense: L={L} tasks of N={N} D={D}, shared support of {w['d']} spikes, "
+                        f"sigma={w['sigma']}, K={w['K']} T={w['T']} tol={w['tol']} U={w['U']}, FP32",
+               em_iters_per_s=round(w["T"] / el, 3), ms_per_fit=round(1e3 * el, 1), cg_steps_per_task=steps,
+               ms_per_cg_step=round(1e3 * el / sum(steps), 4), nrmse_per_task=nrmse,
+               dictionary_gbps_whole_fit=round(op_bytes / el / 1e9, 1),
+               note="dictionaries (4 x 64 MiB) fit in the 256 MB Infinity Cache, so this is not an HBM figure")
+    log(f"multitask: {res}")
     return res
 
 

@@ -208,7 +208,8 @@ def dct_problem(D: int, N: int, d: int, sigma: float, seed: int, name: str = "dc
 # "conv": D=2^20 causal FIR with 256 taps of exp(-t/50), Bernoulli(0.01)*Exp(1)
 # spikes, sigma=0.05, K=20, T=30.  "dct": the DCT scalability setting of Sec. V-C at
 # its largest size, D=2^15, N=floor(D/3), d=floor(0.12 D) spikes N(0, 5), sigma=0.01,
-# K=20, T=30, U=400, tol=1e-4.
+# K=20, T=30, U=400, tol=1e-4.  "multitask": L=4 tasks of the medium shape (N=2048,
+# D=8192) sharing one support of 5% spikes (multitask_problems), K=20, T=30, tol=1e-5.
 # ---------------------------------------------------------------------------
 WORKLOADS = {
     "small": dict(N=64, D=256, d=10, sigma=0.01, K=8, T=50, tol=1e-6, U=256, seed=1001),
@@ -217,12 +218,16 @@ WORKLOADS = {
     "conv": dict(D=1 << 20, taps=256, tau=50.0, p=0.01, sigma=0.05, K=20, T=30, tol=1e-5, U=400, seed=1005),
     "dct": dict(D=1 << 15, N=(1 << 15) // 3, d=int(0.12 * (1 << 15)), sigma=0.01, K=20, T=30, tol=1e-4, U=400,
                 seed=1006, dictionary="dct"),
+    "multitask": dict(L=4, N=2048, D=8192, d=409, sigma=0.01, K=20, T=30, tol=1e-5, U=400, seed=1007),
 }
 
 
-def make_workload(name: str, **override) -> Problem:
+def make_workload(name: str, **override):
+    """The named workload's Problem (a list of L Problems for "multitask")."""
     w = dict(WORKLOADS[name])
     w.update(override)
+    if name == "multitask":
+        return multitask_problems(w["L"], w["N"], w["D"], w["d"], w["sigma"], w["seed"])
     if name == "conv" or "taps" in w:
         return conv_problem(w["D"], w["taps"], w["tau"], w["p"], w["sigma"], w["seed"], name=name)
     if w.get("dictionary") == "dct":
