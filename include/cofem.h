@@ -254,7 +254,10 @@ typedef struct cofem_mt cofem_mt;
 /*
  * Validate *p (the shape N x D and the settings every task shares; mstep_mode must
  * be COFEM_MSTEP_GAUSSIAN), allocate L task workspaces on the current device and
- * bind them to `stream`.  1 <= L <= COFEM_MAX_TASKS.
+ * bind them to `stream`: task 0 runs on `stream`, every other task on a stream the
+ * library creates (and destroys with the handle); cofem_mt_fit orders them after
+ * `stream` at its start and `stream` after them at its end, so the caller sees the
+ * fit's work on `stream` alone.  1 <= L <= COFEM_MAX_TASKS.
  * Errors: COFEM_EINVAL, COFEM_ENOMEM, COFEM_EDEVICE.
  */
 cofem_status cofem_mt_create(const cofem_params* p, int32_t L, void* stream, cofem_mt** out);

@@ -82,6 +82,7 @@ struct cofem_ctx {
   float2 *dct_tw = nullptr, *dct_w2 = nullptr, *dct_mz = nullptr;
   float2 *dct_mzt = nullptr, *dct_y1 = nullptr, *dct_y2 = nullptr;  // split operator (null: one workgroup per column)
   int probe_mode = COFEM_PROBES_HASH;
+  int estep_prev = 0;  // CG steps of the running E-step already harvested
   int32_t* dct_rows = nullptr;
   float* dct_u = nullptr;
   // D- and N-vectors
@@ -373,51 +374,108 @@ void begin_fit(cofem_ctx* c, const float* y) {
   }
 }
 
-// One E-step (Algorithm 1) with the probes of iteration key `key` at the given
-// alpha: probes and B, then the PCG of Algorithm 2 in chunks of steps until the
-// device-side stop rule has fired.  Reports the steps taken and the final ratio.
-cofem_status solve_estep(cofem_ctx* c, uint64_t key, bool use16, const float* alpha, int* steps, double* delta) {
-  const cofem_params& p = c->p;
-  const SolveCfg sc = solve_cfg(c);
-  // slices of Pd: hi/lo for the bf16 operator, hi/lo and the third slice for the dense
-  // FP32 one (which takes its right-hand sides as three bf16 slices)
+// Slices of Pd the producers write: hi/lo for the bf16 operator, hi/lo and the third
+// slice for the dense FP32 one (which takes its right-hand sides as three bf16 slices).
+struct PdSlices {
+  uint16_t *H, *L, *X;
+};
+PdSlices pd_slices(const cofem_ctx* c, bool use16) {
   const bool sliced32 = !use16 && c->PdX;
-  uint16_t* sH = (use16 || sliced32) ? c->PdH : nullptr;
-  uint16_t* sL = (use16 || sliced32) ? c->PdL : nullptr;
-  uint16_t* sX = sliced32 ? c->PdX : nullptr;
-  launch_em_init(sc, key, p.D, c->Dp, use16 ? c->b16 : c->b32, c->theta, alpha, c->minv, c->X, c->R, c->Pd, sH, sL,
-                 c->part, c->st, c->stream, sX);
-  int prev_steps = 0;
-  for (;;) {
-    for (int i = 0; i < c->chunk; ++i) {
-      cofem_status rc = apply_operator(c, use16, alpha, sc, i);
-      if (rc != COFEM_OK) return rc;
-      launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream);
-      launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, sH, sL, c->st, c->stream, sX);
-    }
-    cofem_status rc = sync_state(c);
+  return PdSlices{(use16 || sliced32) ? c->PdH : nullptr, (use16 || sliced32) ? c->PdL : nullptr,
+                  sliced32 ? c->PdX : nullptr};
+}
+
+// One E-step (Algorithm 1) in three parts, so that several contexts can interleave:
+// estep_begin draws the probes of iteration key `key` and sets up B and the PCG of
+// Algorithm 2 at the given alpha; estep_chunk enqueues c->chunk CG steps (those past the
+// device-side stop rule return at once); estep_poll waits for them and reports whether
+// the stop rule has fired.
+void estep_begin(cofem_ctx* c, uint64_t key, bool use16, const float* alpha) {
+  const SolveCfg sc = solve_cfg(c);
+  const PdSlices sl = pd_slices(c, use16);
+  launch_em_init(sc, key, c->p.D, c->Dp, use16 ? c->b16 : c->b32, c->theta, alpha, c->minv, c->X, c->R, c->Pd, sl.H,
+                 sl.L, c->part, c->st, c->stream, sl.X);
+  c->estep_prev = 0;
+}
+cofem_status estep_chunk(cofem_ctx* c, bool use16, const float* alpha) {
+  const SolveCfg sc = solve_cfg(c);
+  const PdSlices sl = pd_slices(c, use16);
+  for (int i = 0; i < c->chunk; ++i) {
+    cofem_status rc = apply_operator(c, use16, alpha, sc, i);
     if (rc != COFEM_OK) return rc;
-    if (c->timing && (rc = harvest(c, c->h_st->steps - prev_steps)) != COFEM_OK) return rc;
-    prev_steps = c->h_st->steps;
-    if (c->h_st->done) break;
+    launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream);
+    launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, sl.H, sl.L, c->st, c->stream, sl.X);
+  }
+  return COFEM_OK;
+}
+cofem_status estep_poll(cofem_ctx* c, bool* done) {
+  cofem_status rc = sync_state(c);
+  if (rc != COFEM_OK) return rc;
+  if (c->timing && (rc = harvest(c, c->h_st->steps - c->estep_prev)) != COFEM_OK) return rc;
+  c->estep_prev = c->h_st->steps;
+  *done = c->h_st->done != 0;
+  return COFEM_OK;
+}
+
+// One E-step on its own: reports the steps taken and the final ratio.
+cofem_status solve_estep(cofem_ctx* c, uint64_t key, bool use16, const float* alpha, int* steps, double* delta) {
+  estep_begin(c, key, use16, alpha);
+  for (bool done = false; !done;) {
+    cofem_status rc = estep_chunk(c, use16, alpha);
+    if (rc == COFEM_OK) rc = estep_poll(c, &done);
+    if (rc != COFEM_OK) return rc;
   }
   *steps = c->h_st->steps;
   *delta = c->h_st->delta;
   return COFEM_OK;
 }
 
+bool estep_use16(const cofem_ctx* c, int t) { return c->need16 && (t <= c->p.T - c->p.refine_last); }
+
+// The fit's record of EM iteration t.
+void record_estep(cofem_ctx* c, int t, bool use16) {
+  c->stats.cg_steps[t - 1] = c->h_st->steps;
+  c->stats.rel_resid[t - 1] = c->h_st->delta;
+  c->stats.used_bf16[t - 1] = use16 ? 1 : 0;
+  c->stats.total_cg_steps += c->h_st->steps;
+}
+
 // The E-step of EM iteration t at the given alpha, recorded in the fit's stats.
 cofem_status run_estep(cofem_ctx* c, int t, const float* alpha) {
-  const cofem_params& p = c->p;
-  const bool use16 = c->need16 && (t <= p.T - p.refine_last);
+  const bool use16 = estep_use16(c, t);
   int steps = 0;
   double delta = 0.0;
   cofem_status rc = solve_estep(c, estep_key(c, t), use16, alpha, &steps, &delta);
   if (rc != COFEM_OK) return rc;
-  c->stats.cg_steps[t - 1] = steps;
-  c->stats.rel_resid[t - 1] = delta;
-  c->stats.used_bf16[t - 1] = use16 ? 1 : 0;
-  c->stats.total_cg_steps += steps;
+  record_estep(c, t, use16);
+  return COFEM_OK;
+}
+
+// The E-steps of EM iteration t of several contexts, each on its own stream, at one
+// alpha: the host enqueues a chunk of CG steps for every context still iterating before
+// it waits on any of them, so small problems overlap on the device.
+cofem_status run_esteps(const std::vector<cofem_ctx*>& cs, int t, const float* alpha) {
+  const int n = (int)cs.size();
+  std::vector<char> live(n, 1);
+  for (cofem_ctx* c : cs) estep_begin(c, estep_key(c, t), estep_use16(c, t), alpha);
+  for (int left = n; left > 0;) {
+    for (int l = 0; l < n; ++l) {
+      if (!live[l]) continue;
+      cofem_status rc = estep_chunk(cs[l], estep_use16(cs[l], t), alpha);
+      if (rc != COFEM_OK) return rc;
+    }
+    for (int l = 0; l < n; ++l) {
+      if (!live[l]) continue;
+      bool done = false;
+      cofem_status rc = estep_poll(cs[l], &done);
+      if (rc != COFEM_OK) return rc;
+      if (done) {
+        record_estep(cs[l], t, estep_use16(cs[l], t));
+        live[l] = 0;
+        --left;
+      }
+    }
+  }
   return COFEM_OK;
 }
 
@@ -763,6 +821,10 @@ COFEM_API cofem_status cofem_get_timing(cofem_ctx* c, int32_t which, double* tot
 // ---------------------------------------------------------------------------
 struct cofem_mt {
   std::vector<cofem_ctx*> tasks;
+  // task 0 runs on the caller's stream, task l > 0 on streams[l - 1] (created here, default
+  // priority); ev[l] orders the tasks' streams around the shared alpha
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> ev;
   const float** d_mus = nullptr;  // device arrays of the tasks' mu and s pointers
   const float** d_ss = nullptr;
   bool fitted = false;
@@ -773,6 +835,10 @@ namespace {
 void mt_free(cofem_mt* m) {
   for (cofem_ctx* c : m->tasks) cofem_destroy(c);
   m->tasks.clear();
+  for (hipStream_t s : m->streams) (void)hipStreamDestroy(s);
+  m->streams.clear();
+  for (hipEvent_t e : m->ev) (void)hipEventDestroy(e);
+  m->ev.clear();
   if (m->d_mus) (void)hipFree(m->d_mus);
   if (m->d_ss) (void)hipFree(m->d_ss);
   m->d_mus = m->d_ss = nullptr;
@@ -792,10 +858,28 @@ COFEM_API cofem_status cofem_mt_create(const cofem_params* p, int32_t L, void* s
   if (!m) return fail(COFEM_ENOMEM, "host allocation failed");
   std::vector<const float*> mus(L), ss(L);
   for (int l = 0; l < L; ++l) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      mt_free(m);
+      delete m;
+      return fail(COFEM_EDEVICE, "hipEventCreateWithFlags failed");
+    }
+    m->ev.push_back(e);
+    void* task_stream = stream;
+    if (l > 0) {
+      hipStream_t s = nullptr;
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        mt_free(m);
+        delete m;
+        return fail(COFEM_EDEVICE, "hipStreamCreateWithFlags failed");
+      }
+      m->streams.push_back(s);
+      task_stream = s;
+    }
     cofem_params q = *p;
     q.seed = p->seed + (uint64_t)l;  // task l's probes
     cofem_ctx* c = nullptr;
-    rc = cofem_create(&q, stream, &c);
+    rc = cofem_create(&q, task_stream, &c);
     if (rc != COFEM_OK) {
       mt_free(m);
       delete m;
@@ -843,24 +927,42 @@ COFEM_API cofem_status cofem_mt_fit(cofem_mt* m, const float* const* ys) {
   cofem_ctx* c0 = m->tasks[0];
   const cofem_params& p = c0->p;
   float* alpha = c0->alpha;  // the shared alpha
+  // every task stream after the caller's stream (the observations, then alpha)
+  auto fork = [&]() -> cofem_status {
+    HIP_TRY(hipEventRecord(m->ev[0], c0->stream));
+    for (int l = 1; l < L; ++l) HIP_TRY(hipStreamWaitEvent(m->tasks[l]->stream, m->ev[0], 0));
+    return COFEM_OK;
+  };
+  // the caller's stream after every task stream
+  auto join = [&]() -> cofem_status {
+    for (int l = 1; l < L; ++l) {
+      HIP_TRY(hipEventRecord(m->ev[l], m->tasks[l]->stream));
+      HIP_TRY(hipStreamWaitEvent(c0->stream, m->ev[l], 0));
+    }
+    return COFEM_OK;
+  };
+  cofem_status rc = fork();
+  if (rc != COFEM_OK) return rc;
   for (int l = 0; l < L; ++l) begin_fit(m->tasks[l], ys[l]);
   launch_fill(alpha, 1.0f, c0->Dp, c0->stream);
   for (int t = 1; t <= p.T; ++t) {
+    // the L E-steps run concurrently, one stream each, at the shared alpha
+    if ((rc = fork()) != COFEM_OK) return rc;
+    if ((rc = run_esteps(m->tasks, t, alpha)) != COFEM_OK) return rc;
     for (int l = 0; l < L; ++l) {
       cofem_ctx* c = m->tasks[l];
-      cofem_status rc = run_estep(c, t, alpha);
-      if (rc != COFEM_OK) return rc;
       // mu_l and s_l only; the joint M-step follows
       launch_mstep(solve_cfg(c), estep_key(c, t), p.D, c->Dp, c->X, c->mu, c->s, nullptr, p.alpha_floor, 0, c->st,
                    c->stream);
     }
+    if ((rc = join()) != COFEM_OK) return rc;
     if (t < p.T) launch_mt_mstep(m->d_mus, m->d_ss, L, p.D, alpha, p.alpha_floor, &c0->st->clamped, c0->stream);
   }
   cofem_status worst = COFEM_OK;
   for (int l = 0; l < L; ++l) {
-    cofem_status rc = end_fit(m->tasks[l], t0);
-    if (rc == COFEM_EBREAKDOWN) worst = rc;
-    else if (rc != COFEM_OK) return rc;
+    const cofem_status r = end_fit(m->tasks[l], t0);
+    if (r == COFEM_EBREAKDOWN) worst = r;
+    else if (r != COFEM_OK) return r;
   }
   m->fitted = true;
   return worst;
