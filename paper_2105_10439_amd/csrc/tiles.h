@@ -721,31 +721,35 @@ __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, con
     }
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  double rsum = 0.0;
-  for (int q = 0; q < c.Q; ++q) rsum += s_rr[q];
-  const double delta = sqrt(rsum / st->bnorm2);
-  st->delta = delta;
-  const int steps = st->steps + 1;
-  st->steps = steps;
-  int done = 0;
-  if (c.stop_mode == 0) {
-    if (delta <= c.tol) done = 1;
-  } else {
-    int nact = 0;
-    for (int q = 0; q < c.Q; ++q) {
-      if (st->active[q] && sqrt(s_rr[q] / st->bn2[q]) <= c.tol) st->active[q] = 0;
-      nact += st->active[q];
+  // per column, one thread each: the column stop test (column mode), ||R_q||^2, eta and rho
+  __shared__ int s_act[QMAX];
+  const int q = threadIdx.x;
+  if (q < c.Q) {
+    int act = st->active[q];
+    if (c.stop_mode != 0 && act && sqrt(s_rr[q] / st->bn2[q]) <= c.tol) {
+      act = 0;
+      st->active[q] = 0;
     }
-    if (nact == 0) done = 1;
-  }
-  if (steps >= c.U) done = 1;
-  for (int q = 0; q < c.Q; ++q) {
+    s_act[q] = act;
     st->rn2[q] = s_rr[q];
     const double old = st->rho[q];
     st->eta[q] = (old != 0.0) ? s_rw[q] / old : 0.0;
     st->rho[q] = s_rw[q];
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double rsum = 0.0;
+  int nact = 0;
+  for (int k = 0; k < c.Q; ++k) {
+    rsum += s_rr[k];
+    nact += s_act[k];
+  }
+  const double delta = sqrt(rsum / st->bnorm2);
+  st->delta = delta;
+  const int steps = st->steps + 1;
+  st->steps = steps;
+  int done = (c.stop_mode == 0) ? (delta <= c.tol) : (nact == 0);
+  if (steps >= c.U) done = 1;
   st->done = done;
 }
 
