@@ -204,7 +204,7 @@ cofem_status cofem_variance(cofem_ctx* c, const float* alpha, int32_t batches, u
                             float* mu_out, cofem_stats* st);
 
 /*
- * One application of the operator of Alg. 2 (its line "Psi <- A P"):
+ * One application of the operator of Alg. 2 (the product of A with the search directions):
  * Psi = beta Phi^T (Phi P) + diag(alpha) P for a block of ncols (1..COFEM_MAX_K+1)
  * columns of length D, with the loaded dictionary, alpha (D floats) and the
  * FP32 (use_bf16 = 0) or bfloat16 (use_bf16 = 1, needs phi_dtype = BF16) operator.
