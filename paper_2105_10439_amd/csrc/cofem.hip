@@ -188,6 +188,7 @@ SolveCfg solve_cfg(const cofem_ctx* c) {
   s.tol = c->p.tol;
   s.beta = c->p.beta;
   s.hadamard = c->probe_mode;
+  s.sigblk = c->p.op_kind == COFEM_OP_CONV ? 1 : 0;
   return s;
 }
 
@@ -773,7 +774,8 @@ COFEM_API cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const flo
   launch_copy_pad(alpha, c->p.D, c->Dp, 1.0f, c->alpha_hook, c->stream);
   const bool sliced32 = !use_bf16 && c->PdX;
   launch_pack_block(P, ncols, c->p.D, c->Qp, c->Dp, c->Pd, (use_bf16 || sliced32) ? c->PdH : nullptr,
-                    (use_bf16 || sliced32) ? c->PdL : nullptr, c->stream, sliced32 ? c->PdX : nullptr);
+                    (use_bf16 || sliced32) ? c->PdL : nullptr, c->stream, sliced32 ? c->PdX : nullptr,
+                    c->p.op_kind == COFEM_OP_CONV ? 1 : 0);
   launch_state_reset(c->st, c->Q, c->stream);
   cofem_status rc = apply_operator(c, use_bf16 != 0, c->alpha_hook, sc, 0);
   if (rc != COFEM_OK) return rc;

@@ -14,14 +14,16 @@
 // input blocks pass through a sliding window of NB VGPR slots, so each input
 // sample is loaded once per run and used NB times.  The anti-causal filter is
 // the same with T_d^T and the window running forward.  The second pass fuses
-// the rest of the line "Psi <- A P": Psi = beta (.) + alpha Pd and the FP64
+// the rest of the operator application: Psi = beta (.) + alpha Pd and the FP64
 // partials of pi_q = sum_j Pd_jq Psi_jq, one per (column, VCHUNK run), in the
 // layout the CG update kernel reduces.
 //
 // FP32 form: v_mfma_f32_16x16x4_f32, taps and signals in FP32.
 // bf16 form: v_mfma_f32_16x16x32_bf16 with the taps rounded to bfloat16 once (the
 // dictionary of the precision form) and each signal carried as a hi + lo pair of
-// bfloat16 (about 2^-17 relative), over 32-sample input blocks: output block
+// bfloat16 (about 2^-17 relative) in the tile-interleaved layout of sig_index, so a
+// wave's load of one block of its 16 columns is one contiguous 1 KB segment (column-major
+// signals made it sixteen 64-byte pieces 2 MB apart), over 32-sample input blocks: output block
 // a = 2 m + par is sum_d T^(par)_d Pd_{m-d} with T^(par)_d[r][c] = h[32 d + 16 par
 // + r - c], d = 0 .. NB-1, NB = floor((L + 30) / 32) + 1 (9 for L = 256).
 #include <algorithm>
@@ -99,7 +101,7 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, int dir, int64_
   if (dir == 0) {
     if (qv) {
       if (a.out32) *reinterpret_cast<f32x4*>(a.out32 + o) = v;
-      if (a.outH) store_split4(a.outH, a.outL, o, v);
+      if (a.outH) store_split4(a.outH, a.outL, sig_index(q, row, a.Dp), v);
     }
   } else {
     f32x4 ps;
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(256) void k_conv_f32(ConvArgs a) {
 
 template <int NB, int DIR>
 __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
-  constexpr int PF = 3, S = NB + PF;
+  constexpr int PF = DIR == 1 ? 2 : 3, S = NB + PF;  // the anti-causal pass also holds its epilogue operands
   if (a.done && *a.done) return;
   const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wid >= a.nbx * a.nct) return;
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
   const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
   const int64_t q = ct * 16 + r16;
   const bool qv = q < a.Q;
-  const int64_t qld = qv ? q : 0;
+  const int64_t qld = qv ? q : 0;  // FP32 Pd of idle columns: column 0 (no extra lines), zeros used
   const int64_t nb32 = a.Dp >> 5;
   const int64_t m0 = (int64_t)bx * (VCHUNK / 32);
   const int cnt = (int)std::min<int64_t>(VCHUNK / 32, nb32 - m0);
@@ -228,15 +230,17 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
       A[par][d] = __builtin_bit_cast(bf16x8_t, t);
     }
 
-  const uint16_t* sh = a.inH + qld * a.Dp + 8 * g;
-  const uint16_t* sl = a.inL + qld * a.Dp + 8 * g;
+  // signal slices in the tile-interleaved layout: block b of this tile is 512 contiguous
+  // elements, lane (r16, g) at 32 r16 + 8 g (padding columns exist and are zero)
+  const uint16_t* sh = a.inH + sig_index(q, 8 * g, a.Dp);
+  const uint16_t* sl = a.inL + sig_index(q, 8 * g, a.Dp);
   const float* pdp = a.Pd ? a.Pd + qld * a.Dp : nullptr;
   const int64_t base = DIR == 0 ? m0 - (NB - 1) : m0;
   const bf16x8_t zero = __builtin_bit_cast(bf16x8_t, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
   auto load = [&](const uint16_t* s, int64_t b) -> bf16x8_t {
-    const bool ok = qv && b >= 0 && b < nb32;
-    const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(s + 32 * (ok ? b : 0));
-    return ok ? v : zero;
+    const bool inb = b >= 0 && b < nb32;  // idle columns load the same segment and use zeros
+    const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(s + 512 * (inb ? b : 0));
+    return (qv && inb) ? v : zero;
   };
   auto rowp_of = [&](int i) -> int64_t { return (m0 + std::min(i, cnt - 1)) * 32 + 4 * g; };
 
@@ -246,6 +250,16 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
     wh[p] = load(sh, base + p);
     wl[p] = load(sl, base + p);
   }
+  // epilogue operands (anti-causal pass), fetched one iteration ahead
+  f32x4 aln[2], pdn[2];
+#pragma unroll
+  for (int par = 0; par < 2; ++par) {
+    aln[par] = pdn[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (DIR == 1) {
+      aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(0) + 16 * par);
+      pdn[par] = *reinterpret_cast<const f32x4*>(pdp + rowp_of(0) + 16 * par);
+    }
+  }
   double pacc = 0.0;
   for (int i0 = 0; i0 < cnt; i0 += S) {
 #pragma unroll
@@ -253,34 +267,35 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
       const int i = i0 + u;
       wh[(u + S - 1) % S] = load(sh, base + i + S - 1);
       wl[(u + S - 1) % S] = load(sl, base + i + S - 1);
-      // epilogue operands of this iteration (registers are too tight to fetch them earlier)
       f32x4 al[2], pd[2];
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
-        al[par] = pd[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+        al[par] = aln[par];
+        pd[par] = pdn[par];
         if (DIR == 1) {
-          al[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(i) + 16 * par);
-          pd[par] = *reinterpret_cast<const f32x4*>(pdp + rowp_of(i) + 16 * par);
+          aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(i + 1) + 16 * par);
+          pdn[par] = *reinterpret_cast<const f32x4*>(pdp + rowp_of(i + 1) + 16 * par);
         }
       }
       __builtin_amdgcn_sched_barrier(0);
       if (i < cnt) {
-        f32x4 ah[2], aL[2];
+        // hi and lo products accumulate together, as in the dense bf16 contraction
+        f32x4 acc[2];
 #pragma unroll
-        for (int par = 0; par < 2; ++par) ah[par] = aL[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int par = 0; par < 2; ++par) acc[par] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int d = 0; d < NB; ++d) {
           const int w = DIR == 0 ? (u + NB - 1 - d) % S : (u + d) % S;
 #pragma unroll
           for (int par = 0; par < 2; ++par) {
-            ah[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wh[w], ah[par], 0, 0, 0);
-            aL[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wl[w], aL[par], 0, 0, 0);
+            acc[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wh[w], acc[par], 0, 0, 0);
+            acc[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wl[w], acc[par], 0, 0, 0);
           }
         }
         const int64_t rowp = (m0 + i) * 32 + 4 * g;  // row of par 0; par 1 is 16 further
 #pragma unroll
         for (int par = 0; par < 2; ++par)
-          conv_epilogue(a, DIR, q, qv, rowp + 16 * par, ah[par] + aL[par], al[par], pd[par], pacc);
+          conv_epilogue(a, DIR, q, qv, rowp + 16 * par, acc[par], al[par], pd[par], pacc);
       }
     }
   }

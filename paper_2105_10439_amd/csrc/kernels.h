@@ -44,6 +44,7 @@ struct SolveCfg {
   int nonneg;        // M-step of the non-negative model (Sec. III-E.2)
   double tol, beta;
   int hadamard = 0;  // probes: 0 the SplitMix64 hash, 1 columns 0..K-1 of the Sylvester-Hadamard matrix
+  int sigblk = 0;    // bf16 slices of Pd in the tile-interleaved layout (sig_index): the FIR dictionary
 };
 
 // ---- setup -----------------------------------------------------------------
@@ -149,9 +150,9 @@ void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int
 
 // ---- test-hook helpers ---------------------------------------------------------
 // Copy ncols columns of length D (caller layout) into a Qp x Dp block (zero padding),
-// optionally also as bf16 hi/lo (and the third slice dX).
+// optionally also as bf16 hi/lo (and the third slice dX), at sig_index when sigblk.
 void launch_pack_block(const float* src, int ncols, int64_t D, int Qp, int64_t Dp, float* dst, uint16_t* dH,
-                       uint16_t* dL, hipStream_t s, uint16_t* dX = nullptr);
+                       uint16_t* dL, hipStream_t s, uint16_t* dX = nullptr, int sigblk = 0);
 void launch_unpack_block(const float* src, int ncols, int64_t D, int64_t Dp, float* dst, hipStream_t s);
 void launch_copy_pad(const float* src, int64_t n, int64_t np, float pad, float* dst, hipStream_t s);
 void launch_state_reset(CGState* st, int Q, hipStream_t s);
@@ -165,7 +166,8 @@ constexpr int CONV_HPAD = 384;
 // One filter pass over the Qp x Dp blocks (columns q < Q are computed; runs of 1024
 // samples per wave and 16-column tile).  dir 0: out = Phi in.  dir 1: out = beta Phi^T in
 // + alpha Pd and the pi partials into pipart[q * nbx + run].  FP32 reads in32; bf16
-// reads the hi/lo pair inH/inL.  Pass 1 writes out32 and/or outH/outL.
+// reads the hi/lo pair inH/inL (tile-interleaved, sig_index).  Pass 1 writes out32
+// and/or outH/outL (tile-interleaved).
 struct ConvArgs {
   const float* hp32;
   const uint16_t* hp16;

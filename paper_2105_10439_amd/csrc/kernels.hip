@@ -197,7 +197,39 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction(SolveCfg c, int64_t Dp,
                                                          uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
                                                          uint16_t* __restrict__ PdX, const CGState* __restrict__ st) {
   if (st->done) return;
-  cg_direction_tile(blockIdx.x, blockIdx.y, Dp, minv, R, Pd, PdH, PdL, st, PdX);
+  cg_direction_tile(blockIdx.x, blockIdx.y, Dp, minv, R, Pd, PdH, PdL, st, PdX, c.sigblk != 0);
+}
+
+// The direction update with the bf16 slices in the tile-interleaved layout (the FIR
+// dictionary's bf16 phase): a block covers one 16-column tile and 256 coordinates in
+// four steps of 64, 16 threads per column, so each step's slice stores are two
+// contiguous 1 KB segments.
+constexpr int DIR_SIG_COORDS = 256;
+__global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
+                                                             const float* __restrict__ R, float* __restrict__ Pd,
+                                                             uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
+                                                             const CGState* __restrict__ st) {
+  if (st->done) return;
+  const int q = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (q >= c.Q) return;
+  const double eta = st->eta[q];
+  const int64_t j0 = (int64_t)blockIdx.x * DIR_SIG_COORDS + 4 * (threadIdx.x & 15);
+  f32x4 mi[4], r[4], p[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t j = j0 + 64 * k, o = (int64_t)q * Dp + j;
+    mi[k] = *reinterpret_cast<const f32x4*>(minv + j);
+    r[k] = *reinterpret_cast<const f32x4*>(R + o);
+    p[k] = *reinterpret_cast<const f32x4*>(Pd + o);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t j = j0 + 64 * k, o = (int64_t)q * Dp + j;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) p[k][e] = (float)((double)mi[k][e] * (double)r[k][e] + eta * (double)p[k][e]);
+    *reinterpret_cast<f32x4*>(Pd + o) = p[k];
+    store_split4(PdH, PdL, sig_index(q, j, Dp), p[k]);
+  }
 }
 
 // One block: pi_q into the state (used by the single-application test hook).
@@ -239,7 +271,7 @@ __global__ __launch_bounds__(VBLOCK) void k_mt_mstep(const float* const* __restr
 // ---------------------------------------------------------------------------
 __global__ void k_pack_block(const float* __restrict__ src, int ncols, int64_t D, int Qp, int64_t Dp,
                              float* __restrict__ dst, uint16_t* __restrict__ dH, uint16_t* __restrict__ dL,
-                             uint16_t* __restrict__ dX) {
+                             uint16_t* __restrict__ dX, int sigblk) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (j >= Dp || q >= Qp) return;
@@ -249,9 +281,10 @@ __global__ void k_pack_block(const float* __restrict__ src, int ncols, int64_t D
   if (dH) {
     uint16_t h, l;
     split_bf16(v, h, l);
-    dH[o] = h;
-    dL[o] = l;
-    if (dX) dX[o] = slice3_bf16(v, h, l);
+    const int64_t os = sigblk ? sig_index(q, j, Dp) : o;
+    dH[os] = h;
+    dL[os] = l;
+    if (dX) dX[os] = slice3_bf16(v, h, l);
   }
 }
 __global__ void k_unpack_block(const float* __restrict__ src, int ncols, int64_t D, int64_t Dp,
@@ -447,6 +480,11 @@ void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipS
 
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
                          uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX) {
+  if (c.sigblk && PdH) {
+    hipLaunchKernelGGL(k_cg_direction_sig, dim3((unsigned)(Dp / DIR_SIG_COORDS), cdiv(c.Q, 16)), dim3(VBLOCK), 0, s,
+                       c, Dp, minv, R, Pd, PdH, PdL, st);
+    return;
+  }
   hipLaunchKernelGGL(k_cg_direction, dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd,
                      PdH, PdL, PdX, st);
 }
@@ -457,9 +495,9 @@ void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int
 }
 
 void launch_pack_block(const float* src, int ncols, int64_t D, int Qp, int64_t Dp, float* dst, uint16_t* dH,
-                       uint16_t* dL, hipStream_t s, uint16_t* dX) {
+                       uint16_t* dL, hipStream_t s, uint16_t* dX, int sigblk) {
   hipLaunchKernelGGL(k_pack_block, dim3(cdiv(Dp, 256), (unsigned)Qp), dim3(256), 0, s, src, ncols, D, Qp, Dp, dst,
-                     dH, dL, dX);
+                     dH, dL, dX, sigblk);
 }
 void launch_unpack_block(const float* src, int ncols, int64_t D, int64_t Dp, float* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack_block, dim3(cdiv(D, 256), (unsigned)ncols), dim3(256), 0, s, src, ncols, D, Dp,
