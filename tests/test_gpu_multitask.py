@@ -100,3 +100,38 @@ def test_multitask_concurrent_fit_is_deterministic(gpu):
     for l in range(L):
         for a, b in zip(runs[0][l], runs[1][l]):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_multitask_conv_matches_oracle(gpu, dtype):
+    """Multi-task fits on FIR dictionaries (each task its own filter and data, one shared
+    alpha): FP32, and all-bf16 E-steps against the oracle on the bf16-rounded taps (the
+    right-hand side b formed from the same taps).  mu within 1e-4 (FP32) or 1e-3 (bf16:
+    the signals travel as hi/lo bf16 pairs), or twice the oracle's own change of mu
+    between tol and tol / 100, whichever is larger (the FIR systems are ill-conditioned)."""
+    D, taps, L = 1200, 64, 2
+    probs = [workloads.conv_problem(D, taps, tau, 0.02, 0.05, seed=64 + l) for l, tau in enumerate((20.0, 30.0))]
+    K, T, U, tol, seed = 8, 12, 400, 1e-6, 5
+    kw = dict(phi_dtype="bf16", refine_last=0) if dtype == "bf16" else {}
+    m = gpu.MultiTask(L, D, D, probs[0].beta, K=K, T=T, U=U, tol=tol, seed=seed, op="conv", conv_taps=taps, **kw)
+    for l, p in enumerate(probs):
+        m.set_dictionary(l, _t(p.h))
+    m.fit([_t(p.y) for p in probs])
+    out = [m.posterior(l) for l in range(L)]
+    m.close()
+
+    def rne(x):
+        u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+    ops = [oracle.ConvOperator(rne(p.h) if dtype == "bf16" else p.h, D) for p in probs]
+    ys = [p.y for p in probs]
+    _, mus, ss, _ = oracle.cofem_multitask(ops, ys, probs[0].beta, T=T, K=K, U=U, tol=tol, seed=seed)
+    _, mus_t, _, _ = oracle.cofem_multitask(ops, ys, probs[0].beta, T=T, K=K, U=U, tol=tol / 100, seed=seed)
+    bar = 1e-3 if dtype == "bf16" else 1e-4
+    for l in range(L):
+        e_mu, sens = _rel(_np(out[l][0]), mus[l]), _rel(mus[l], mus_t[l])
+        print(f"multi-task conv {dtype} task {l}: mu rel {e_mu:.2e} (sensitivity {sens:.2e}), "
+              f"s rel {_rel(_np(out[l][1]), ss[l]):.2e}")
+        assert e_mu <= max(bar, 2 * sens)
