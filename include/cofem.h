@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define COFEM_ABI_VERSION 4
+#define COFEM_ABI_VERSION 5
 #define COFEM_MAX_T 512 /* longest EM run recorded in cofem_stats */
 #define COFEM_MAX_K 63  /* probes per EM iteration (one 64-bit hash word per coordinate) */
 
@@ -255,9 +255,10 @@ typedef struct cofem_mt cofem_mt;
  * Validate *p (the shape N x D and the settings every task shares; mstep_mode must
  * be COFEM_MSTEP_GAUSSIAN), allocate L task workspaces on the current device and
  * bind them to `stream`: task 0 runs on `stream`, every other task on a stream the
- * library creates (and destroys with the handle); cofem_mt_fit orders them after
- * `stream` at its start and `stream` after them at its end, so the caller sees the
- * fit's work on `stream` alone.  1 <= L <= COFEM_MAX_TASKS.
+ * library creates (and destroys with the handle); the loading calls and cofem_mt_fit
+ * order them after `stream` at their start and cofem_mt_fit orders `stream` after them
+ * at its end, so the caller sees the fit's work on `stream` alone.  Dense, FIR and
+ * subsampled-DCT dictionaries.  1 <= L <= COFEM_MAX_TASKS.
  * Errors: COFEM_EINVAL, COFEM_ENOMEM, COFEM_EDEVICE.
  */
 cofem_status cofem_mt_create(const cofem_params* p, int32_t L, void* stream, cofem_mt** out);
@@ -267,6 +268,9 @@ void cofem_mt_destroy(cofem_mt* m);
 
 /* Load task `task`'s dictionary (as cofem_set_dictionary).  Errors: COFEM_EINVAL, COFEM_EDEVICE. */
 cofem_status cofem_mt_set_dictionary(cofem_mt* m, int32_t task, const float* phi);
+/* Load task `task`'s kept DCT samples (as cofem_set_dct_samples; op_kind COFEM_OP_DCT).
+ * Errors: COFEM_EINVAL, COFEM_EDEVICE. */
+cofem_status cofem_mt_set_dct_samples(cofem_mt* m, int32_t task, const int32_t* rows);
 
 /*
  * Run the multi-task EM: `ys` is a host array of L device pointers, ys[l] holding

@@ -23,7 +23,7 @@ OPS = {"dense": 0, "conv": 1, "dct": 2}
 DTYPES = {"fp32": 0, "bf16": 1}
 MSTEP = {"gaussian": 0, "nonneg": 1}
 PROBE_MODES = {"hash": 0, "hadamard": 1}
-ABI_VERSION = 4  # COFEM_ABI_VERSION of include/cofem.h
+ABI_VERSION = 5  # COFEM_ABI_VERSION of include/cofem.h
 
 # every symbol include/cofem.h declares
 EXPORTS = [
@@ -32,7 +32,8 @@ EXPORTS = [
     "cofem_fit", "cofem_posterior", "cofem_variance", "cofem_apply_A", "cofem_set_probe_mode", "cofem_set_timing", "cofem_get_timing",
     "cofem_server_create", "cofem_server_destroy", "cofem_server_submit", "cofem_server_step",
     "cofem_server_poll", "cofem_server_get_stats",
-    "cofem_mt_create", "cofem_mt_destroy", "cofem_mt_set_dictionary", "cofem_mt_fit", "cofem_mt_posterior",
+    "cofem_mt_create", "cofem_mt_destroy", "cofem_mt_set_dictionary", "cofem_mt_set_dct_samples", "cofem_mt_fit",
+    "cofem_mt_posterior",
 ]
 REQ_STATE = {0: "pending", 1: "running", 2: "done", -1: "unknown"}
 
@@ -127,6 +128,7 @@ def load() -> ctypes.CDLL:
         "cofem_mt_create": (i32, [ctypes.POINTER(Params), i32, vp, ctypes.POINTER(vp)]),
         "cofem_mt_destroy": (None, [vp]),
         "cofem_mt_set_dictionary": (i32, [vp, i32, vp]),
+        "cofem_mt_set_dct_samples": (i32, [vp, i32, vp]),
         "cofem_mt_fit": (i32, [vp, ctypes.POINTER(vp)]),
         "cofem_mt_posterior": (i32, [vp, i32, vp, vp, vp, ctypes.POINTER(Stats)]),
     }
@@ -284,6 +286,15 @@ class MultiTask(CoFEM):
     __del__ = close
 
     def set_dictionary(self, task, phi):
+        """Task `task`'s dictionary: as CoFEM.set_dictionary (DCT: int32 sample indices)."""
+        import torch
+
+        if self.params.op_kind == OPS["dct"]:
+            if not (isinstance(phi, torch.Tensor) and phi.is_cuda and phi.dtype == torch.int32
+                    and phi.is_contiguous() and phi.numel() == self.N):
+                raise TypeError(f"rows must be a contiguous int32 CUDA tensor of {self.N} sample indices")
+            _check(load().cofem_mt_set_dct_samples(self._h, int(task), ctypes.c_void_p(phi.data_ptr())))
+            return
         n = self.N * self.D if self.params.op_kind == 0 else self.params.conv_taps
         _check(load().cofem_mt_set_dictionary(self._h, int(task), self._dev(phi, n, "phi")))
 

@@ -855,7 +855,6 @@ COFEM_API cofem_status cofem_mt_create(const cofem_params* p, int32_t L, void* s
   cofem_status rc = validate(p);
   if (rc != COFEM_OK) return rc;
   if (p->mstep_mode != COFEM_MSTEP_GAUSSIAN) return fail(COFEM_EINVAL, "multi-task fits use the Gaussian M-step");
-  if (p->op_kind == COFEM_OP_DCT) return fail(COFEM_EINVAL, "multi-task fits take dense or convolutional dictionaries");
   cofem_mt* m = new (std::nothrow) cofem_mt();
   if (!m) return fail(COFEM_ENOMEM, "host allocation failed");
   std::vector<const float*> mus(L), ss(L);
@@ -912,9 +911,27 @@ COFEM_API void cofem_mt_destroy(cofem_mt* m) {
   delete m;
 }
 
+// Task `task`'s stream after the caller's stream (task 0's), so that the task reads
+// caller data only once the caller's stream has produced it.
+static cofem_status mt_after_caller(cofem_mt* m, int task) {
+  if (task == 0) return COFEM_OK;
+  HIP_TRY(hipEventRecord(m->ev[0], m->tasks[0]->stream));
+  HIP_TRY(hipStreamWaitEvent(m->tasks[task]->stream, m->ev[0], 0));
+  return COFEM_OK;
+}
+
 COFEM_API cofem_status cofem_mt_set_dictionary(cofem_mt* m, int32_t task, const float* phi) {
   if (!m || task < 0 || task >= (int32_t)m->tasks.size()) return fail(COFEM_EINVAL, "bad task");
+  cofem_status rc = mt_after_caller(m, task);
+  if (rc != COFEM_OK) return rc;
   return cofem_set_dictionary(m->tasks[task], phi);
+}
+
+COFEM_API cofem_status cofem_mt_set_dct_samples(cofem_mt* m, int32_t task, const int32_t* rows) {
+  if (!m || task < 0 || task >= (int32_t)m->tasks.size()) return fail(COFEM_EINVAL, "bad task");
+  cofem_status rc = mt_after_caller(m, task);
+  if (rc != COFEM_OK) return rc;
+  return cofem_set_dct_samples(m->tasks[task], rows);
 }
 
 COFEM_API cofem_status cofem_mt_fit(cofem_mt* m, const float* const* ys) {

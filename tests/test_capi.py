@@ -82,7 +82,7 @@ def test_create_rejects_bad_params_without_device_work(bad):
     assert so.cofem_last_error().decode()
 
 
-@pytest.mark.parametrize("L,bad", [(0, {}), (65, {}), (2, dict(mstep_mode=1)), (2, dict(K=0)), (2, dict(op_kind=2))])
+@pytest.mark.parametrize("L,bad", [(0, {}), (65, {}), (2, dict(mstep_mode=1)), (2, dict(K=0)), (2, dict(op_kind=2, D=300))])
 def test_multitask_create_rejects_bad_arguments_without_device_work(L, bad):
     so = lib.load()
     p = lib.make_params(N=64, D=256, beta=1e4, K=8, T=5, U=10, tol=1e-6)
@@ -100,10 +100,11 @@ def test_null_arguments_are_rejected():
     assert so.cofem_fit(None, None) == -1
     assert so.cofem_set_dictionary(None, None) == -1
     assert so.cofem_set_dct_samples(None, None) == -1
+    assert so.cofem_mt_set_dct_samples(None, 0, None) == -1
     assert so.cofem_set_probe_mode(None, 1) == -1
     assert so.cofem_posterior(None, None, None, None, None) == -1
     so.cofem_destroy(None)
-    assert so.cofem_abi_version() == 4
+    assert so.cofem_abi_version() == 5
 
 
 def test_server_rejects_bad_arguments_without_device_work():

@@ -135,3 +135,28 @@ def test_multitask_conv_matches_oracle(gpu, dtype):
         print(f"multi-task conv {dtype} task {l}: mu rel {e_mu:.2e} (sensitivity {sens:.2e}), "
               f"s rel {_rel(_np(out[l][1]), ss[l]):.2e}")
         assert e_mu <= max(bar, 2 * sens)
+
+
+def test_multitask_dct_matches_oracle(gpu):
+    """Multi-task fits on subsampled DCT dictionaries (each task its own kept samples and
+    data, one shared alpha; D = 2^11 takes the split DCT operator) against the oracle."""
+    D, N, L = 2048, 682, 3
+    probs = [workloads.dct_problem(D, N, 150, 0.01, seed=66 + l) for l in range(L)]
+    K, T, U, tol, seed = 8, 10, 400, 1e-6, 6
+    m = gpu.MultiTask(L, N, D, probs[0].beta, K=K, T=T, U=U, tol=tol, seed=seed, op="dct")
+    for l, p in enumerate(probs):
+        import torch
+
+        m.set_dictionary(l, torch.from_numpy(np.ascontiguousarray(p.rows, dtype=np.int32)).cuda())
+    m.fit([_t(p.y) for p in probs])
+    out = [m.posterior(l) for l in range(L)]
+    m.close()
+    ops = [oracle.DctOperator(D, p.rows) for p in probs]
+    ys = [p.y for p in probs]
+    _, mus, ss, _ = oracle.cofem_multitask(ops, ys, probs[0].beta, T=T, K=K, U=U, tol=tol, seed=seed)
+    _, mus_t, _, _ = oracle.cofem_multitask(ops, ys, probs[0].beta, T=T, K=K, U=U, tol=tol / 100, seed=seed)
+    for l in range(L):
+        e_mu, sens = _rel(_np(out[l][0]), mus[l]), _rel(mus[l], mus_t[l])
+        print(f"multi-task DCT task {l}: mu rel {e_mu:.2e} (sensitivity {sens:.2e}), "
+              f"s rel {_rel(_np(out[l][1]), ss[l]):.2e}")
+        assert e_mu <= max(1e-4, 2 * sens)
