@@ -387,7 +387,8 @@ def multitask_bench():
 def dct_bench(fits):
     """The subsampled DCT dictionary at the largest DCT size of the paper's scalability
     study (D = 2^15, N = D/3, d = 0.12 D spikes, K = 20, T = 30, U = 400, tol 1e-4):
-    one warm-up fit, then `fits` timed fits (sample set loaded once per fit).  Per
+    one warm-up fit, then `fits` timed fits (sample set loaded once per fit), then one fit
+    with per-launch events for the operator's own time.  Per
     operator application (Q = K + 1 columns): algorithmic bytes 8 D Q + 4 D (read Pd
     and alpha, write Psi), and the conventional 5 L log2 L flops of each of the 2 Q
     complex FFTs of length L = D / 2."""
@@ -409,7 +410,6 @@ def dct_bench(fits):
     m = lib.CoFEM(N, D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024, op="dct")
     m.set_dictionary(rows_d)
     m.fit(y_d)
-    m.set_timing(True)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(fits):
@@ -418,6 +418,10 @@ def dct_bench(fits):
     torch.cuda.synchronize()
     el = time.perf_counter() - t
     mu, _, _, st = m.posterior()
+    # the operator's launches timed with events in one more fit (kept out of the fit timing:
+    # at ~27 us per application the event pairs are a visible share of a CG step)
+    m.set_timing(True)
+    m.fit(y_d)
     ms, n = m.get_timing("fp32")
     m.close()
     app_s = ms / n * 1e-3

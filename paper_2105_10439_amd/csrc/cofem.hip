@@ -102,6 +102,15 @@ struct cofem_ctx {
   CGState* h_st = nullptr;  // pinned host mirror
   GemmCfg g1_16{}, g2_16{}, g1_32{}, g2_32{};
   int chunk = 8;
+  // A chunk of CG steps captured once as a graph per operator phase (bf16 or FP32) and
+  // alpha buffer, replayed on `stream` (launch latency dominates small problems).  The
+  // capture runs on cap_stream: the caller's stream may be the legacy default stream,
+  // which cannot be captured.  Not used while operator timing is on.
+  struct ChunkGraph {
+    hipGraphExec_t exec = nullptr;
+    const float* alpha = nullptr;
+  } graphs[2];
+  hipStream_t cap_stream = nullptr;
   cofem_stats stats{};
   // operator timing
   bool timing = false;
@@ -129,6 +138,12 @@ cofem_status dalloc(cofem_ctx* c, T** out, size_t n) {
 }
 
 void free_all(cofem_ctx* c) {
+  for (auto& g : c->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+  }
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  c->cap_stream = nullptr;
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->h_st) (void)hipHostFree(c->h_st);
@@ -398,7 +413,7 @@ void estep_begin(cofem_ctx* c, uint64_t key, bool use16, const float* alpha) {
                  sl.L, c->part, c->st, c->stream, sl.X);
   c->estep_prev = 0;
 }
-cofem_status estep_chunk(cofem_ctx* c, bool use16, const float* alpha) {
+cofem_status estep_chunk_launches(cofem_ctx* c, bool use16, const float* alpha) {
   const SolveCfg sc = solve_cfg(c);
   const PdSlices sl = pd_slices(c, use16);
   for (int i = 0; i < c->chunk; ++i) {
@@ -407,6 +422,42 @@ cofem_status estep_chunk(cofem_ctx* c, bool use16, const float* alpha) {
     launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream);
     launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, sl.H, sl.L, c->st, c->stream, sl.X);
   }
+  return COFEM_OK;
+}
+// Capture the chunk's launches (every argument is fixed for the context, use16 and alpha;
+// the per-step state lives on the device) into g.
+cofem_status capture_chunk(cofem_ctx* c, bool use16, const float* alpha, cofem_ctx::ChunkGraph& g) {
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t caller = c->stream;
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  c->stream = c->cap_stream;
+  const cofem_status rc = estep_chunk_launches(c, use16, alpha);
+  c->stream = caller;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  if (rc != COFEM_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc != COFEM_OK ? rc : fail(COFEM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    g.exec = nullptr;
+    return fail(COFEM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  g.alpha = alpha;
+  return COFEM_OK;
+}
+cofem_status estep_chunk(cofem_ctx* c, bool use16, const float* alpha) {
+  if (c->timing) return estep_chunk_launches(c, use16, alpha);  // per-launch events: no graph
+  cofem_ctx::ChunkGraph& g = c->graphs[use16 ? 1 : 0];
+  if (!g.exec || g.alpha != alpha) {
+    const cofem_status rc = capture_chunk(c, use16, alpha, g);
+    if (rc != COFEM_OK) return rc;
+  }
+  HIP_TRY(hipGraphLaunch(g.exec, c->stream));
   return COFEM_OK;
 }
 cofem_status estep_poll(cofem_ctx* c, bool* done) {

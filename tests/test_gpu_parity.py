@@ -230,3 +230,40 @@ def test_fit_nonneg_mstep_matches_oracle(gpu):
     assert e_s <= 1e-3
     assert np.max(np.abs(np.log(alpha[sup] / ref.alpha[sup]))) < 1e-3
     assert _rel(gauss.mu, ref.mu) > 10 * e_mu   # the M-step really changed the fit
+
+
+@pytest.mark.parametrize("kind", ["dense", "dense_bf16", "conv", "dct"])
+def test_graph_replay_matches_eager(gpu, kind):
+    """Without operator timing a context replays each chunk of CG steps as a captured
+    HIP graph; with timing on it launches every kernel eagerly.  The kernels and their
+    order are the same, so every replay (many per fit, with the host's state reads and
+    synchronizations in between) must give the eager fit bitwise."""
+    import torch
+
+    if kind == "conv":
+        prob = workloads.conv_problem(1200, 64, 20.0, 0.02, 0.05, seed=81)
+        make = lambda: gpu.CoFEM(prob.D, prob.D, prob.beta, K=8, T=6, U=300, tol=1e-6, seed=3, op="conv",
+                                 conv_taps=64, phi_dtype="bf16", refine_last=2)
+        dictionary = _t(prob.h)
+    elif kind == "dct":
+        prob = workloads.dct_problem(2048, 682, 150, 0.01, seed=82)
+        make = lambda: gpu.CoFEM(prob.N, prob.D, prob.beta, K=8, T=6, U=300, tol=1e-6, seed=3, op="dct")
+        dictionary = torch.from_numpy(np.ascontiguousarray(prob.rows, dtype=np.int32)).cuda()
+    else:
+        prob = workloads.dense_problem(300, 1000, 30, 0.01, seed=83)
+        kw = dict(phi_dtype="bf16", refine_last=2) if kind == "dense_bf16" else {}
+        make = lambda: gpu.CoFEM(prob.N, prob.D, prob.beta, K=8, T=6, U=300, tol=1e-6, seed=3, **kw)
+        dictionary = _t(prob.phi)
+    out = []
+    for timing in (True, False):
+        m = make()
+        m.set_dictionary(dictionary)
+        m.set_timing(timing)
+        m.fit(_t(prob.y))
+        m.fit(_t(prob.y))  # a second fit replays the graphs captured in the first
+        mu, s, alpha, st = m.posterior()
+        m.close()
+        out.append((_np(mu), _np(s), _np(alpha), st["cg_steps"]))
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, b)
+    assert out[0][3] == out[1][3]
