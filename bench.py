@@ -83,6 +83,32 @@ def gemm_traffic(N: int, D: int, dom: str):
     return dict(total=rd + wr, read=rd, write=wr)
 
 
+def stream_peaks():
+    """Measured HBM rate on this GPU for context: a 1 GiB device copy (read + write bytes),
+    best of 10, timed with events."""
+    import torch
+
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    res = {}
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 2 * 4 * n),):
+        fn()
+        best = None
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        res[name] = round(nbytes / (best * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return res
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -244,6 +270,9 @@ def main():
     if traf:
         roof.update(traffic_read=round(traf["read"]), traffic_write=round(traf["write"]),
                     traffic_over_algorithmic=round(traf["total"] / nbytes_launch[dom], 4))
+    peaks = stream_peaks()
+    roof.update(measured_copy_gbps=peaks["copy"], frac_of_measured_copy=round(ops[dom]["gbps"] / peaks["copy"], 4))
+    log(f"measured stream rates: {peaks}")
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "EM-iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 2), "higher_is_better": True,
