@@ -111,6 +111,7 @@ struct cofem_ctx {
     const float* alpha = nullptr;
   } graphs[2];
   hipStream_t cap_stream = nullptr;
+  bool graph_off = false;  // a capture failed: eager launches from then on
   cofem_stats stats{};
   // operator timing
   bool timing = false;
@@ -451,11 +452,15 @@ cofem_status capture_chunk(cofem_ctx* c, bool use16, const float* alpha, cofem_c
   return COFEM_OK;
 }
 cofem_status estep_chunk(cofem_ctx* c, bool use16, const float* alpha) {
-  if (c->timing) return estep_chunk_launches(c, use16, alpha);  // per-launch events: no graph
+  // per-launch events (timing) stay eager, and so does a context whose capture failed
+  if (c->timing || c->graph_off) return estep_chunk_launches(c, use16, alpha);
   cofem_ctx::ChunkGraph& g = c->graphs[use16 ? 1 : 0];
   if (!g.exec || g.alpha != alpha) {
-    const cofem_status rc = capture_chunk(c, use16, alpha, g);
-    if (rc != COFEM_OK) return rc;
+    if (capture_chunk(c, use16, alpha, g) != COFEM_OK) {
+      (void)hipGetLastError();
+      c->graph_off = true;
+      return estep_chunk_launches(c, use16, alpha);
+    }
   }
   HIP_TRY(hipGraphLaunch(g.exec, c->stream));
   return COFEM_OK;
