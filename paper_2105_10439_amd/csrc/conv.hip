@@ -23,7 +23,8 @@
 // dictionary of the precision form) and each signal carried as a hi + lo pair of
 // bfloat16 (about 2^-17 relative) in the tile-interleaved layout of sig_index, so a
 // wave's load of one block of its 16 columns is one contiguous 1 KB segment (column-major
-// signals made it sixteen 64-byte pieces 2 MB apart), over 32-sample input blocks: output block
+// signals made it sixteen 64-byte pieces 2 MB apart; the last tile stores only its real
+// columns, so padding columns cost no traffic), over 32-sample input blocks: output block
 // a = 2 m + par is sum_d T^(par)_d Pd_{m-d} with T^(par)_d[r][c] = h[32 d + 16 par
 // + r - c], d = 0 .. NB-1, NB = floor((L + 30) / 32) + 1 (9 for L = 256).
 #include <algorithm>
@@ -101,7 +102,7 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, int dir, int64_
   if (dir == 0) {
     if (qv) {
       if (a.out32) *reinterpret_cast<f32x4*>(a.out32 + o) = v;
-      if (a.outH) store_split4(a.outH, a.outL, sig_index(q, row, a.Dp), v);
+      if (a.outH) store_split4(a.outH, a.outL, sig_index(q, row, a.Dp, a.Q), v);
     }
   } else {
     f32x4 ps;
@@ -230,16 +231,19 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
       A[par][d] = __builtin_bit_cast(bf16x8_t, t);
     }
 
-  // signal slices in the tile-interleaved layout: block b of this tile is 512 contiguous
-  // elements, lane (r16, g) at 32 r16 + 8 g (padding columns exist and are zero)
-  const uint16_t* sh = a.inH + sig_index(q, 8 * g, a.Dp);
-  const uint16_t* sl = a.inL + sig_index(q, 8 * g, a.Dp);
+  // signal slices in the tile-interleaved layout: block b of this tile is 32 w contiguous
+  // elements for the tile's w real columns, lane (r16, g) at 32 r16 + 8 g; lanes of padding
+  // columns load column 16 ct's segment and use zeros
+  const int64_t qs = qv ? q : (int64_t)ct * 16;
+  const int64_t bstride = 32 * sig_tile_width(qs, a.Q);
+  const uint16_t* sh = a.inH + sig_index(qs, 8 * g, a.Dp, a.Q);
+  const uint16_t* sl = a.inL + sig_index(qs, 8 * g, a.Dp, a.Q);
   const float* pdp = a.Pd ? a.Pd + qld * a.Dp : nullptr;
   const int64_t base = DIR == 0 ? m0 - (NB - 1) : m0;
   const bf16x8_t zero = __builtin_bit_cast(bf16x8_t, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
   auto load = [&](const uint16_t* s, int64_t b) -> bf16x8_t {
-    const bool inb = b >= 0 && b < nb32;  // idle columns load the same segment and use zeros
-    const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(s + 512 * (inb ? b : 0));
+    const bool inb = b >= 0 && b < nb32;
+    const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(s + bstride * (inb ? b : 0));
     return (qv && inb) ? v : zero;
   };
   auto rowp_of = [&](int i) -> int64_t { return (m0 + std::min(i, cnt - 1)) * 32 + 4 * g; };

@@ -50,11 +50,18 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) 
 __device__ __forceinline__ uint16_t slice3_bf16(float x, uint16_t hi, uint16_t lo) {
   return bf16_rne((x - bf16_val(hi)) - bf16_val(lo));
 }
-// Tile-interleaved layout of the FIR dictionary's bf16 signal slices (Qp x Dp): for each
-// 16-column tile and 32-sample block, the 16 columns' 32 samples lie together (1 KB), so
-// that the filter kernels' loads of one block for a tile are one contiguous segment.
-__host__ __device__ __forceinline__ int64_t sig_index(int64_t q, int64_t j, int64_t Dp) {
-  return (((q >> 4) * (Dp >> 5) + (j >> 5)) * 16 + (q & 15)) * 32 + (j & 31);
+// Tile-interleaved layout of the FIR dictionary's bf16 signal slices of Q real columns
+// (q < Q, j < Dp): for each 16-column tile and 32-sample block, the tile's columns' 32
+// samples lie together (1 KB for a full tile), so that the filter kernels' loads of one
+// block for a tile are one contiguous segment.  The last tile holds only its real columns
+// (w = min(16, Q - 16 (q / 16))), so padding columns take neither space nor traffic; the
+// whole layout spans Q Dp elements.
+__host__ __device__ __forceinline__ int64_t sig_tile_width(int64_t q, int64_t Q) {
+  const int64_t w = Q - (q & ~int64_t(15));
+  return w < 16 ? w : 16;
+}
+__host__ __device__ __forceinline__ int64_t sig_index(int64_t q, int64_t j, int64_t Dp, int64_t Q) {
+  return (q & ~int64_t(15)) * Dp + (j >> 5) * (32 * sig_tile_width(q, Q)) + (q & 15) * 32 + (j & 31);
 }
 // Four values' hi/lo slices (and, with X, their third slices) at offset o.
 __device__ __forceinline__ void store_split4(uint16_t* H, uint16_t* L, int64_t o, const f32x4& v,

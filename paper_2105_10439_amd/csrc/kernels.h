@@ -150,7 +150,8 @@ void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int
 
 // ---- test-hook helpers ---------------------------------------------------------
 // Copy ncols columns of length D (caller layout) into a Qp x Dp block (zero padding),
-// optionally also as bf16 hi/lo (and the third slice dX), at sig_index when sigblk.
+// optionally also as bf16 hi/lo (and the third slice dX), at sig_index of the ncols real
+// columns when sigblk.
 void launch_pack_block(const float* src, int ncols, int64_t D, int Qp, int64_t Dp, float* dst, uint16_t* dH,
                        uint16_t* dL, hipStream_t s, uint16_t* dX = nullptr, int sigblk = 0);
 void launch_unpack_block(const float* src, int ncols, int64_t D, int64_t Dp, float* dst, hipStream_t s);

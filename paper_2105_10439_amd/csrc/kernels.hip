@@ -197,7 +197,7 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction(SolveCfg c, int64_t Dp,
                                                          uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
                                                          uint16_t* __restrict__ PdX, const CGState* __restrict__ st) {
   if (st->done) return;
-  cg_direction_tile(blockIdx.x, blockIdx.y, Dp, minv, R, Pd, PdH, PdL, st, PdX, c.sigblk != 0);
+  cg_direction_tile(blockIdx.x, blockIdx.y, Dp, minv, R, Pd, PdH, PdL, st, PdX);
 }
 
 // The direction update with the bf16 slices in the tile-interleaved layout (the FIR
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t
 #pragma unroll
     for (int e = 0; e < 4; ++e) p[k][e] = (float)((double)mi[k][e] * (double)r[k][e] + eta * (double)p[k][e]);
     *reinterpret_cast<f32x4*>(Pd + o) = p[k];
-    store_split4(PdH, PdL, sig_index(q, j, Dp), p[k]);
+    store_split4(PdH, PdL, sig_index(q, j, Dp, c.Q), p[k]);
   }
 }
 
@@ -278,10 +278,10 @@ __global__ void k_pack_block(const float* __restrict__ src, int ncols, int64_t D
   const float v = (q < ncols && j < D) ? src[(int64_t)q * D + j] : 0.0f;
   const int64_t o = (int64_t)q * Dp + j;
   dst[o] = v;
-  if (dH) {
+  if (dH && (!sigblk || q < ncols)) {  // the interleaved layout holds the real columns only
     uint16_t h, l;
     split_bf16(v, h, l);
-    const int64_t os = sigblk ? sig_index(q, j, Dp) : o;
+    const int64_t os = sigblk ? sig_index(q, j, Dp, ncols) : o;
     dH[os] = h;
     dL[os] = l;
     if (dX) dX[os] = slice3_bf16(v, h, l);

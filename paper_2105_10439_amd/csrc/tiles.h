@@ -35,10 +35,10 @@ __device__ __forceinline__ void em_init_block(const SolveCfg& c, uint64_t key, i
     R[o] = bq;
     const float p = (float)(mid * (double)bq);
     Pd[o] = p;
-    if (PdH) {
+    if (PdH && (!c.sigblk || q < c.Q)) {  // the interleaved layout holds the real columns only
       uint16_t h, l;
       split_bf16(p, h, l);
-      const int64_t os = c.sigblk ? sig_index(q, j, Dp) : o;
+      const int64_t os = c.sigblk ? sig_index(q, j, Dp, c.Q) : o;
       PdH[os] = h;
       PdL[os] = l;
       if (PdX) PdX[os] = slice3_bf16(p, h, l);
@@ -755,12 +755,12 @@ __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, con
 }
 
 // P = M^-1 R + eta P (FP32, and bf16 hi/lo when PdH is not null, and the third slice
-// when PdX is not null; the slices at sig_index when sigblk).
+// when PdX is not null; column-major slices: the interleaved layout of the FIR dictionary
+// has a kernel of its own).
 __device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, const float* __restrict__ minv,
                                                   const float* __restrict__ R, float* __restrict__ Pd,
                                                   uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
-                                                  const CGState* __restrict__ st, uint16_t* __restrict__ PdX = nullptr,
-                                                  bool sigblk = false) {
+                                                  const CGState* __restrict__ st, uint16_t* __restrict__ PdX = nullptr) {
   const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
   if (j >= Dp) return;
   const double eta = st->eta[q];
@@ -771,7 +771,7 @@ __device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, con
 #pragma unroll
   for (int e = 0; e < 4; ++e) p[e] = (float)((double)mi[e] * (double)r[e] + eta * (double)p[e]);
   *reinterpret_cast<f32x4*>(Pd + o) = p;
-  if (PdH) store_split4(PdH, PdL, sigblk ? sig_index(q, j, Dp) : o, p, PdX);
+  if (PdH) store_split4(PdH, PdL, o, p, PdX);
 }
 
 }  // namespace cofem
