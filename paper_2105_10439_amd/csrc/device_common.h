@@ -104,10 +104,12 @@ __device__ __forceinline__ double block_sum(double v) {
   return r;
 }
 
-// Sum of p[i * stride] over i < n by one wave, in a fixed order (all lanes get it).
+// Sum of p[i * stride] over i < n by one wave, in a fixed order (all lanes get it).  The
+// unrolled loop issues a lane's loads together; the additions keep their order.
 __device__ __forceinline__ double wave_sum_strided(const double* p, int n, int stride) {
   const int lane = threadIdx.x & 63;
   double a = 0.0;
+#pragma unroll 8
   for (int i = lane; i < n; i += 64) a += p[(int64_t)i * stride];
   return wave_sum(a);
 }

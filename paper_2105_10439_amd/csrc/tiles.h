@@ -709,7 +709,8 @@ __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, con
   for (int q = wv; q < c.Q; q += nw) {
     const double2* pq = reinterpret_cast<const double2*>(part + (int64_t)q * nbx * 2);
     double a = 0.0, b = 0.0;
-    for (int i = ln; i < nbx; i += 64) {
+#pragma unroll 8
+    for (int i = ln; i < nbx; i += 64) {  // loads issued together, additions in order
       const double2 v = pq[i];
       a += v.x;
       b += v.y;
