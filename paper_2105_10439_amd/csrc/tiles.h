@@ -659,6 +659,18 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
                                                float* __restrict__ R, const float* __restrict__ Pd,
                                                const float* __restrict__ Psi, const double* __restrict__ pipart,
                                                double* __restrict__ part, CGState* __restrict__ st) {
+  // the block's loads go out before gamma's reduction, which they do not depend on
+  const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
+  const bool in = j < Dp;
+  const int64_t o = (int64_t)q * Dp + j;
+  f32x4 mi, x, r, p, ps;
+  if (in) {
+    mi = *reinterpret_cast<const f32x4*>(minv + j);
+    x = *reinterpret_cast<const f32x4*>(X + o);
+    r = *reinterpret_cast<const f32x4*>(R + o);
+    p = *reinterpret_cast<const f32x4*>(Pd + o);
+    ps = *reinterpret_cast<const f32x4*>(Psi + o);
+  }
   double gam;
   if (PRE) {
     gam = st->gamma[q];
@@ -671,15 +683,8 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
     __syncthreads();
     gam = s_gam;
   }
-  const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
   double rr = 0.0, rw = 0.0;
-  if (j < Dp) {
-    const int64_t o = (int64_t)q * Dp + j;
-    const f32x4 mi = *reinterpret_cast<const f32x4*>(minv + j);
-    f32x4 x = *reinterpret_cast<const f32x4*>(X + o);
-    f32x4 r = *reinterpret_cast<const f32x4*>(R + o);
-    const f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
-    const f32x4 ps = *reinterpret_cast<const f32x4*>(Psi + o);
+  if (in) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       x[e] = (float)((double)x[e] + gam * (double)p[e]);
