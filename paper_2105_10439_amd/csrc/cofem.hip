@@ -205,6 +205,7 @@ SolveCfg solve_cfg(const cofem_ctx* c) {
   s.beta = c->p.beta;
   s.hadamard = c->probe_mode;
   s.sigblk = c->p.op_kind == COFEM_OP_CONV ? 1 : 0;
+  s.nt_store = c->p.op_kind == COFEM_OP_DCT ? 0 : 1;
   return s;
 }
 

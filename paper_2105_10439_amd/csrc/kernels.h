@@ -45,6 +45,9 @@ struct SolveCfg {
   double tol, beta;
   int hadamard = 0;  // probes: 0 the SplitMix64 hash, 1 columns 0..K-1 of the Sylvester-Hadamard matrix
   int sigblk = 0;    // bf16 slices of Pd in the tile-interleaved layout (sig_index): the FIR dictionary
+  int nt_store = 0;  // launch choice: X, and P when its bf16 slices feed the operator, stored
+                     // non-temporally (the operator streams more than the caches hold before
+                     // they are read again)
 };
 
 // ---- setup -----------------------------------------------------------------

@@ -170,14 +170,14 @@ __global__ __launch_bounds__(VBLOCK) void k_finish_pass2(SolveCfg c, const float
   finish2_tile(c, blockIdx.x, blockIdx.y, gridDim.x, Yp, splits, Dp, alpha, Pd, Psi, pipart);
 }
 
-template <bool PRE>
+template <bool PRE, bool NT>
 __global__ __launch_bounds__(VBLOCK) void k_cg_update(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                       float* __restrict__ X, float* __restrict__ R,
                                                       const float* __restrict__ Pd, const float* __restrict__ Psi,
                                                       const double* __restrict__ pipart, double* __restrict__ part,
                                                       CGState* __restrict__ st) {
   if (st->done) return;
-  cg_update_tile<PRE>(c, blockIdx.x, blockIdx.y, gridDim.x, Dp, minv, X, R, Pd, Psi, pipart, part, st);
+  cg_update_tile<PRE, NT>(c, blockIdx.x, blockIdx.y, gridDim.x, Dp, minv, X, R, Pd, Psi, pipart, part, st);
 }
 
 __global__ __launch_bounds__(1024) void k_cg_gamma(SolveCfg c, int nbx, const double* __restrict__ pipart,
@@ -192,12 +192,13 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(SolveCfg c, int nbx, const 
   cg_scalars_block(c, nbx, part, st);
 }
 
+template <bool NT>
 __global__ __launch_bounds__(VBLOCK) void k_cg_direction(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                          const float* __restrict__ R, float* __restrict__ Pd,
                                                          uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
                                                          uint16_t* __restrict__ PdX, const CGState* __restrict__ st) {
   if (st->done) return;
-  cg_direction_tile(blockIdx.x, blockIdx.y, Dp, minv, R, Pd, PdH, PdL, st, PdX);
+  cg_direction_tile<NT>(blockIdx.x, blockIdx.y, Dp, minv, R, Pd, PdH, PdL, st, PdX);
 }
 
 // The direction update with the bf16 slices in the tile-interleaved layout (the FIR
@@ -205,6 +206,7 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction(SolveCfg c, int64_t Dp,
 // four steps of 64, 16 threads per column, so each step's slice stores are two
 // contiguous 1 KB segments.
 constexpr int DIR_SIG_COORDS = 256;
+template <bool NT>
 __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                              const float* __restrict__ R, float* __restrict__ Pd,
                                                              uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
@@ -227,7 +229,8 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t
     const int64_t j = j0 + 64 * k, o = (int64_t)q * Dp + j;
 #pragma unroll
     for (int e = 0; e < 4; ++e) p[k][e] = (float)((double)mi[k][e] * (double)r[k][e] + eta * (double)p[k][e]);
-    *reinterpret_cast<f32x4*>(Pd + o) = p[k];
+    if constexpr (NT) __builtin_nontemporal_store(p[k], reinterpret_cast<f32x4*>(Pd + o));
+    else *reinterpret_cast<f32x4*>(Pd + o) = p[k];
     store_split4(PdH, PdL, sig_index(q, j, Dp, c.Q), p[k]);
   }
 }
@@ -463,14 +466,12 @@ constexpr int GAMMA_PRE_MIN_CHUNKS = 128;
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
                       const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s) {
   const unsigned nbx = cdiv(Dp, VCHUNK);
-  if (nbx > (unsigned)GAMMA_PRE_MIN_CHUNKS) {
-    hipLaunchKernelGGL(k_cg_gamma, dim3(1), dim3(1024), 0, s, c, (int)nbx, pipart, st);
-    hipLaunchKernelGGL(k_cg_update<true>, dim3(nbx, (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi,
-                       pipart, part, st);
-  } else {
-    hipLaunchKernelGGL(k_cg_update<false>, dim3(nbx, (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi,
-                       pipart, part, st);
-  }
+  const dim3 grid(nbx, (unsigned)c.Q);
+  const bool pre = nbx > (unsigned)GAMMA_PRE_MIN_CHUNKS;
+  if (pre) hipLaunchKernelGGL(k_cg_gamma, dim3(1), dim3(1024), 0, s, c, (int)nbx, pipart, st);
+  auto kern = pre ? (c.nt_store ? k_cg_update<true, true> : k_cg_update<true, false>)
+                  : (c.nt_store ? k_cg_update<false, true> : k_cg_update<false, false>);
+  hipLaunchKernelGGL(kern, grid, dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi, pipart, part, st);
   hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(1024), 0, s, c, (int)nbx, (const double*)part, st);
 }
 
@@ -480,13 +481,16 @@ void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipS
 
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
                          uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX) {
+  // FP32 P non-temporally only when the operator reads the slices instead
+  const bool nt = c.nt_store && PdH;
   if (c.sigblk && PdH) {
-    hipLaunchKernelGGL(k_cg_direction_sig, dim3((unsigned)(Dp / DIR_SIG_COORDS), cdiv(c.Q, 16)), dim3(VBLOCK), 0, s,
-                       c, Dp, minv, R, Pd, PdH, PdL, st);
+    hipLaunchKernelGGL(nt ? k_cg_direction_sig<true> : k_cg_direction_sig<false>,
+                       dim3((unsigned)(Dp / DIR_SIG_COORDS), cdiv(c.Q, 16)), dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd,
+                       PdH, PdL, st);
     return;
   }
-  hipLaunchKernelGGL(k_cg_direction, dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q), dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd,
-                     PdH, PdL, PdX, st);
+  hipLaunchKernelGGL(nt ? k_cg_direction<true> : k_cg_direction<false>, dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q),
+                     dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd, PdH, PdL, PdX, st);
 }
 
 void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int64_t D, float* alpha, double floor,

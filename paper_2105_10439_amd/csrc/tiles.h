@@ -653,7 +653,7 @@ __device__ __forceinline__ void cg_gamma_block(const SolveCfg& c, int nbx, const
 // part[(q * nbx + bx) * 2 + {0, 1}].  gamma_q comes from the state (PRE, after
 // cg_gamma_block) or is reduced here by every tile of the column, in the same order, so
 // all tiles get the same value (the tile of chunk 0 records it).
-template <bool PRE>
+template <bool PRE, bool NT = false>  // NT: X stored non-temporally
 __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q, int nbx, int64_t Dp,
                                                const float* __restrict__ minv, float* __restrict__ X,
                                                float* __restrict__ R, const float* __restrict__ Pd,
@@ -693,7 +693,8 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
       rr += rd * rd;
       rw += rd * ((double)mi[e] * rd);
     }
-    *reinterpret_cast<f32x4*>(X + o) = x;
+    if constexpr (NT) __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(X + o));
+    else *reinterpret_cast<f32x4*>(X + o) = x;
     *reinterpret_cast<f32x4*>(R + o) = r;
   }
   rr = block_sum(rr);
@@ -762,7 +763,8 @@ __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, con
 
 // P = M^-1 R + eta P (FP32, and bf16 hi/lo when PdH is not null, and the third slice
 // when PdX is not null; column-major slices: the interleaved layout of the FIR dictionary
-// has a kernel of its own).
+// has a kernel of its own).  NT: P stored non-temporally (the slices are what the operator reads).
+template <bool NT = false>
 __device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, const float* __restrict__ minv,
                                                   const float* __restrict__ R, float* __restrict__ Pd,
                                                   uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
@@ -776,7 +778,8 @@ __device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, con
   f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
 #pragma unroll
   for (int e = 0; e < 4; ++e) p[e] = (float)((double)mi[e] * (double)r[e] + eta * (double)p[e]);
-  *reinterpret_cast<f32x4*>(Pd + o) = p;
+  if constexpr (NT) __builtin_nontemporal_store(p, reinterpret_cast<f32x4*>(Pd + o));
+  else *reinterpret_cast<f32x4*>(Pd + o) = p;
   if (PdH) store_split4(PdH, PdL, o, p, PdX);
 }
 
