@@ -299,6 +299,7 @@ cofem_status apply_conv(cofem_ctx* c, bool use16, const float* alpha, const Solv
   a.done = &c->st->done;
   ConvArgs p1 = a, p2 = a;
   if (use16) {
+    p1.xclear = &c->st->xpend;
     p1.inH = c->PdH;
     p1.inL = c->PdL;
     p1.outH = c->VH;
@@ -421,8 +422,11 @@ cofem_status estep_chunk_launches(cofem_ctx* c, bool use16, const float* alpha) 
   for (int i = 0; i < c->chunk; ++i) {
     cofem_status rc = apply_operator(c, use16, alpha, sc, i);
     if (rc != COFEM_OK) return rc;
-    launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream);
-    launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, sl.H, sl.L, c->st, c->stream, sl.X);
+    // FIR dictionary, bf16 form: X += gamma P moves from the update to the direction kernel
+    const bool xdir = sc.sigblk && sl.H;
+    launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream, xdir);
+    launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, sl.H, sl.L, c->st, c->stream, sl.X,
+                        xdir ? c->X : nullptr);
   }
   return COFEM_OK;
 }

@@ -204,6 +204,7 @@ __global__ __launch_bounds__(256) void k_conv_f32(ConvArgs a) {
 template <int NB, int DIR>
 __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
   constexpr int PF = DIR == 1 ? 2 : 3, S = NB + PF;  // the anti-causal pass also holds its epilogue operands
+  if (DIR == 0 && a.xclear && blockIdx.x == 0 && threadIdx.x == 0) *a.xclear = 0;  // a new CG step
   if (a.done && *a.done) return;
   const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wid >= a.nbx * a.nct) return;

@@ -36,7 +36,7 @@ struct CGState {
   int phase;            // serving: 0 idle, 1 needs E-step init, 2 in CG, 3 finished
   int t;                // serving: current EM iteration (1-based)
   int total_steps;      // serving: CG steps over the fit
-  int pad_;
+  int xpend;            // this step's update ran and left X += gamma P to the direction kernel
 };
 
 struct SolveCfg {
@@ -141,11 +141,17 @@ void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipS
 // gamma_q = rho_q / pi_q (pi reduced from pipart), X += Pd gamma, R -= Psi gamma, partials
 // of ||R_q||^2 and rho'_q = sum R minv R into part; then one block applies the stop rule
 // and computes eta (two launches; three when a first block reduces the pi partials).
+// xdir: X += gamma Pd is left to launch_cg_direction (FIR dictionary, bf16 form: its direction
+// kernel reads Pd anyway; pass 1 of the filter clears the state's flag each step).
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
-                      const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s);
+                      const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s,
+                      bool xdir = false);
 // Pd = minv R + eta Pd (FP32, and bf16 hi/lo if PdH != null, and the third slice if PdX != null).
+// With X (only with c.sigblk and PdH: the update's xdir form), first X += gamma Pd when the
+// step's update ran, also on the step whose update met the stop rule.
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
-                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX = nullptr);
+                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX = nullptr,
+                         float* X = nullptr);
 
 // Multi-task M-step over L tasks' mu and s (device arrays of L device pointers).
 void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int64_t D, float* alpha, double floor,
@@ -187,6 +193,7 @@ struct ConvArgs {
   const float* Pd;
   double* pipart;
   const int* done;
+  int* xclear;  // pass 1 of a CG step zeroes the state's xpend flag (before the done test)
 };
 int conv_blocks_f32(int L);
 int conv_blocks_bf16(int L);

@@ -170,14 +170,14 @@ __global__ __launch_bounds__(VBLOCK) void k_finish_pass2(SolveCfg c, const float
   finish2_tile(c, blockIdx.x, blockIdx.y, gridDim.x, Yp, splits, Dp, alpha, Pd, Psi, pipart);
 }
 
-template <bool PRE, bool NT>
+template <bool PRE, bool NT, bool XU>
 __global__ __launch_bounds__(VBLOCK) void k_cg_update(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                       float* __restrict__ X, float* __restrict__ R,
                                                       const float* __restrict__ Pd, const float* __restrict__ Psi,
                                                       const double* __restrict__ pipart, double* __restrict__ part,
                                                       CGState* __restrict__ st) {
   if (st->done) return;
-  cg_update_tile<PRE, NT>(c, blockIdx.x, blockIdx.y, gridDim.x, Dp, minv, X, R, Pd, Psi, pipart, part, st);
+  cg_update_tile<PRE, NT, XU>(c, blockIdx.x, blockIdx.y, gridDim.x, Dp, minv, X, R, Pd, Psi, pipart, part, st);
 }
 
 __global__ __launch_bounds__(1024) void k_cg_gamma(SolveCfg c, int nbx, const double* __restrict__ pipart,
@@ -206,15 +206,16 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction(SolveCfg c, int64_t Dp,
 // four steps of 64, 16 threads per column, so each step's slice stores are two
 // contiguous 1 KB segments.
 constexpr int DIR_SIG_COORDS = 256;
-template <bool NT>
+// XD: also X += gamma P (the update left it here) when the step's update ran (xpend), before
+// the done test, so the step that meets the stop rule still moves X.
+template <bool NT, bool XD>
 __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                              const float* __restrict__ R, float* __restrict__ Pd,
                                                              uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
-                                                             const CGState* __restrict__ st) {
-  if (st->done) return;
+                                                             float* __restrict__ X, const CGState* __restrict__ st) {
+  if (XD ? !st->xpend : st->done) return;
   const int q = blockIdx.y * 16 + (threadIdx.x >> 4);
   if (q >= c.Q) return;
-  const double eta = st->eta[q];
   const int64_t j0 = (int64_t)blockIdx.x * DIR_SIG_COORDS + 4 * (threadIdx.x & 15);
   f32x4 mi[4], r[4], p[4];
 #pragma unroll
@@ -224,6 +225,20 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t
     r[k] = *reinterpret_cast<const f32x4*>(R + o);
     p[k] = *reinterpret_cast<const f32x4*>(Pd + o);
   }
+  if constexpr (XD) {
+    const double gam = st->gamma[q];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t o = (int64_t)q * Dp + j0 + 64 * k;
+      f32x4 x = *reinterpret_cast<const f32x4*>(X + o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = (float)((double)x[e] + gam * (double)p[k][e]);
+      if constexpr (NT) __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(X + o));
+      else *reinterpret_cast<f32x4*>(X + o) = x;
+    }
+    if (st->done) return;
+  }
+  const double eta = st->eta[q];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int64_t j = j0 + 64 * k, o = (int64_t)q * Dp + j;
@@ -464,13 +479,14 @@ void launch_finish_pass2(const SolveCfg& c, const float* Ypart, int splits, int6
 constexpr int GAMMA_PRE_MIN_CHUNKS = 128;
 
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
-                      const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s) {
+                      const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s, bool xdir) {
   const unsigned nbx = cdiv(Dp, VCHUNK);
   const dim3 grid(nbx, (unsigned)c.Q);
   const bool pre = nbx > (unsigned)GAMMA_PRE_MIN_CHUNKS;
   if (pre) hipLaunchKernelGGL(k_cg_gamma, dim3(1), dim3(1024), 0, s, c, (int)nbx, pipart, st);
-  auto kern = pre ? (c.nt_store ? k_cg_update<true, true> : k_cg_update<true, false>)
-                  : (c.nt_store ? k_cg_update<false, true> : k_cg_update<false, false>);
+  auto kern = xdir ? (pre ? k_cg_update<true, true, false> : k_cg_update<false, true, false>)
+             : pre  ? (c.nt_store ? k_cg_update<true, true, true> : k_cg_update<true, false, true>)
+                    : (c.nt_store ? k_cg_update<false, true, true> : k_cg_update<false, false, true>);
   hipLaunchKernelGGL(kern, grid, dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi, pipart, part, st);
   hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(1024), 0, s, c, (int)nbx, (const double*)part, st);
 }
@@ -480,13 +496,14 @@ void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipS
 }
 
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
-                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX) {
+                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX, float* X) {
   // FP32 P non-temporally only when the operator reads the slices instead
   const bool nt = c.nt_store && PdH;
   if (c.sigblk && PdH) {
-    hipLaunchKernelGGL(nt ? k_cg_direction_sig<true> : k_cg_direction_sig<false>,
-                       dim3((unsigned)(Dp / DIR_SIG_COORDS), cdiv(c.Q, 16)), dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd,
-                       PdH, PdL, st);
+    auto kern = X ? (nt ? k_cg_direction_sig<true, true> : k_cg_direction_sig<false, true>)
+                  : (nt ? k_cg_direction_sig<true, false> : k_cg_direction_sig<false, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(Dp / DIR_SIG_COORDS), cdiv(c.Q, 16)), dim3(VBLOCK), 0, s, c, Dp, minv,
+                       R, Pd, PdH, PdL, X, st);
     return;
   }
   hipLaunchKernelGGL(nt ? k_cg_direction<true> : k_cg_direction<false>, dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q),

@@ -89,6 +89,7 @@ __device__ __forceinline__ void em_scalars_block(const SolveCfg& c, int64_t D, i
   st->delta = 1.0;
   st->steps = 0;
   st->done = (c.stop_mode == 1 && nact == 0) ? 1 : 0;
+  st->xpend = 0;
 }
 
 // mu = X_0, s_j = (1/K) sum_k p_kj X_kj (Eq. diag-estimate; probes regenerated from
@@ -653,7 +654,9 @@ __device__ __forceinline__ void cg_gamma_block(const SolveCfg& c, int nbx, const
 // part[(q * nbx + bx) * 2 + {0, 1}].  gamma_q comes from the state (PRE, after
 // cg_gamma_block) or is reduced here by every tile of the column, in the same order, so
 // all tiles get the same value (the tile of chunk 0 records it).
-template <bool PRE, bool NT = false>  // NT: X stored non-temporally
+// XU = false (the FIR dictionary's bf16 form): X is left to the direction kernel, which
+// reads P anyway; block (0, 0) flags it in the state (xpend).
+template <bool PRE, bool NT = false, bool XU = true>  // NT: X stored non-temporally
 __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q, int nbx, int64_t Dp,
                                                const float* __restrict__ minv, float* __restrict__ X,
                                                float* __restrict__ R, const float* __restrict__ Pd,
@@ -666,11 +669,14 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
   f32x4 mi, x, r, p, ps;
   if (in) {
     mi = *reinterpret_cast<const f32x4*>(minv + j);
-    x = *reinterpret_cast<const f32x4*>(X + o);
+    if constexpr (XU) {
+      x = *reinterpret_cast<const f32x4*>(X + o);
+      p = *reinterpret_cast<const f32x4*>(Pd + o);
+    }
     r = *reinterpret_cast<const f32x4*>(R + o);
-    p = *reinterpret_cast<const f32x4*>(Pd + o);
     ps = *reinterpret_cast<const f32x4*>(Psi + o);
   }
+  if (!XU && bx == 0 && q == 0 && threadIdx.x == 0) st->xpend = 1;
   double gam;
   if (PRE) {
     gam = st->gamma[q];
@@ -687,14 +693,16 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
   if (in) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      x[e] = (float)((double)x[e] + gam * (double)p[e]);
+      if constexpr (XU) x[e] = (float)((double)x[e] + gam * (double)p[e]);
       r[e] = (float)((double)r[e] - gam * (double)ps[e]);
       const double rd = (double)r[e];
       rr += rd * rd;
       rw += rd * ((double)mi[e] * rd);
     }
-    if constexpr (NT) __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(X + o));
-    else *reinterpret_cast<f32x4*>(X + o) = x;
+    if constexpr (XU) {
+      if constexpr (NT) __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(X + o));
+      else *reinterpret_cast<f32x4*>(X + o) = x;
+    }
     *reinterpret_cast<f32x4*>(R + o) = r;
   }
   rr = block_sum(rr);

@@ -134,6 +134,22 @@ def test_conv_fit_bf16_matches_rounded_oracle_and_refines(gpu):
     assert e2 <= max(2e-2, 2 * sens32)
 
 
+@pytest.mark.parametrize("K", [15, 16, 31])
+def test_conv_fit_bf16_tile_widths(gpu, K):
+    """Whole bf16 fits whose last 16-column tile of the interleaved signal slices is full (Q = 16,
+    32) or one column wide (Q = 17): the E-step init, the direction update and both filter passes
+    address that tile by its own width."""
+    prob = workloads.conv_problem(800, 256, 50.0, 0.01, 0.05, seed=43 + K)
+    T, U, tol, seed = 3, 400, 1e-6, 13
+    mu, s, _, st = _conv_fit(gpu, prob, K, T, U, tol, seed, phi_dtype="bf16")
+    assert all(st["used_bf16"][:T])
+    ref, sens_mu, sens_s = _oracle_pair(prob, _bf16_rne(prob.h), K, T, U, tol, seed)
+    e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
+    print(f"conv bf16 K={K}: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e}), s rel {e_s:.2e} ({sens_s:.2e})")
+    assert e_mu <= max(1e-3, 2 * sens_mu)
+    assert e_s <= max(1e-2, 2 * sens_s)
+
+
 # ---------------------------------------------------------------------------
 # full size: D = 2^20, 256 taps of exp(-t/50), K = 20
 # ---------------------------------------------------------------------------
