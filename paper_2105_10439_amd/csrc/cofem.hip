@@ -313,7 +313,12 @@ cofem_status apply_conv(cofem_ctx* c, bool use16, const float* alpha, const Solv
   }
   p2.out32 = c->Psi;
   p2.alpha = alpha;
-  p2.Pd = c->Pd;
+  if (use16) {  // the bf16 form carries Pd as its hi/lo pair
+    p2.PdH = c->PdH;
+    p2.PdL = c->PdL;
+  } else {
+    p2.Pd = c->Pd;
+  }
   p2.pipart = c->pipart;
   TimedLaunch t;
   cofem_status rc;

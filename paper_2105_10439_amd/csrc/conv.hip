@@ -35,6 +35,7 @@
 namespace cofem {
 
 typedef __attribute__((ext_vector_type(8))) unsigned short u16x8;
+typedef __attribute__((ext_vector_type(4))) unsigned short u16x4;
 
 // Padded taps: hp[CONV_HOFF + m] = h[m] for 0 <= m < L, zero for the rest of the
 // CONV_HPAD entries (every index the Toeplitz blocks touch stays inside).
@@ -212,7 +213,6 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
   const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
   const int64_t q = ct * 16 + r16;
   const bool qv = q < a.Q;
-  const int64_t qld = qv ? q : 0;  // FP32 Pd of idle columns: column 0 (no extra lines), zeros used
   const int64_t nb32 = a.Dp >> 5;
   const int64_t m0 = (int64_t)bx * (VCHUNK / 32);
   const int cnt = (int)std::min<int64_t>(VCHUNK / 32, nb32 - m0);
@@ -239,7 +239,6 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
   const int64_t bstride = 32 * sig_tile_width(qs, a.Q);
   const uint16_t* sh = a.inH + sig_index(qs, 8 * g, a.Dp, a.Q);
   const uint16_t* sl = a.inL + sig_index(qs, 8 * g, a.Dp, a.Q);
-  const float* pdp = a.Pd ? a.Pd + qld * a.Dp : nullptr;
   const int64_t base = DIR == 0 ? m0 - (NB - 1) : m0;
   const bf16x8_t zero = __builtin_bit_cast(bf16x8_t, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
   auto load = [&](const uint16_t* s, int64_t b) -> bf16x8_t {
@@ -248,6 +247,23 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
     return (qv && inb) ? v : zero;
   };
   auto rowp_of = [&](int i) -> int64_t { return (m0 + std::min(i, cnt - 1)) * 32 + 4 * g; };
+  // the epilogue's Pd: its hi/lo pair (the value the filter passes used) for rows
+  // 32 (m0 + i) + 16 par + 4 g .. + 3 of column qs, at block stride bstride like the
+  // signal; fetched as raw halves and summed at use
+  struct PdRaw {
+    u16x4 h, l;
+  };
+  const int64_t pd0 = DIR == 1 ? sig_index(qs, 4 * g, a.Dp, a.Q) + m0 * bstride : 0;
+  auto pd_fetch = [&](int i, int par) -> PdRaw {
+    const int64_t o = pd0 + std::min(i, cnt - 1) * bstride + 16 * par;
+    return PdRaw{*reinterpret_cast<const u16x4*>(a.PdH + o), *reinterpret_cast<const u16x4*>(a.PdL + o)};
+  };
+  auto pd_value = [](const PdRaw& r) -> f32x4 {
+    f32x4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = bf16_val(r.h[e]) + bf16_val(r.l[e]);
+    return v;
+  };
 
   bf16x8_t wh[S], wl[S];
 #pragma unroll
@@ -256,13 +272,15 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
     wl[p] = load(sl, base + p);
   }
   // epilogue operands (anti-causal pass), fetched one iteration ahead
-  f32x4 aln[2], pdn[2];
+  f32x4 aln[2];
+  PdRaw pdn[2];
 #pragma unroll
   for (int par = 0; par < 2; ++par) {
-    aln[par] = pdn[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+    aln[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+    pdn[par] = PdRaw{u16x4{0, 0, 0, 0}, u16x4{0, 0, 0, 0}};
     if (DIR == 1) {
       aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(0) + 16 * par);
-      pdn[par] = *reinterpret_cast<const f32x4*>(pdp + rowp_of(0) + 16 * par);
+      pdn[par] = pd_fetch(0, par);
     }
   }
   double pacc = 0.0;
@@ -272,14 +290,15 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
       const int i = i0 + u;
       wh[(u + S - 1) % S] = load(sh, base + i + S - 1);
       wl[(u + S - 1) % S] = load(sl, base + i + S - 1);
-      f32x4 al[2], pd[2];
+      f32x4 al[2];
+      PdRaw pd[2];
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
         al[par] = aln[par];
         pd[par] = pdn[par];
         if (DIR == 1) {
           aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(i + 1) + 16 * par);
-          pdn[par] = *reinterpret_cast<const f32x4*>(pdp + rowp_of(i + 1) + 16 * par);
+          pdn[par] = pd_fetch(i + 1, par);
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -300,7 +319,7 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
         const int64_t rowp = (m0 + i) * 32 + 4 * g;  // row of par 0; par 1 is 16 further
 #pragma unroll
         for (int par = 0; par < 2; ++par)
-          conv_epilogue(a, DIR, q, qv, rowp + 16 * par, acc[par], al[par], pd[par], pacc);
+          conv_epilogue(a, DIR, q, qv, rowp + 16 * par, acc[par], al[par], pd_value(pd[par]), pacc);
       }
     }
   }

@@ -190,7 +190,8 @@ struct ConvArgs {
   uint16_t *outH, *outL;
   double beta;
   const float* alpha;
-  const float* Pd;
+  const float* Pd;               // FP32 form: Pd for the epilogue of pass 2
+  const uint16_t *PdH, *PdL;     // bf16 form: Pd's hi/lo slices (tile-interleaved), its value there
   double* pipart;
   const int* done;
   int* xclear;  // pass 1 of a CG step zeroes the state's xpend flag (before the done test)

@@ -206,8 +206,10 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction(SolveCfg c, int64_t Dp,
 // four steps of 64, 16 threads per column, so each step's slice stores are two
 // contiguous 1 KB segments.
 constexpr int DIR_SIG_COORDS = 256;
-// XD: also X += gamma P (the update left it here) when the step's update ran (xpend), before
-// the done test, so the step that meets the stop rule still moves X.
+typedef __attribute__((ext_vector_type(4))) unsigned short u16x4v;
+// XD (the bf16 form, whose direction is its hi/lo pair: the FP32 Pd is neither read nor
+// written): also X += gamma P (the update left it here) when the step's update ran
+// (xpend), before the done test, so the step that meets the stop rule still moves X.
 template <bool NT, bool XD>
 __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                              const float* __restrict__ R, float* __restrict__ Pd,
@@ -223,7 +225,14 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t
     const int64_t j = j0 + 64 * k, o = (int64_t)q * Dp + j;
     mi[k] = *reinterpret_cast<const f32x4*>(minv + j);
     r[k] = *reinterpret_cast<const f32x4*>(R + o);
-    p[k] = *reinterpret_cast<const f32x4*>(Pd + o);
+    if constexpr (XD) {
+      const int64_t os = sig_index(q, j, Dp, c.Q);
+      const u16x4v h = *reinterpret_cast<const u16x4v*>(PdH + os), l = *reinterpret_cast<const u16x4v*>(PdL + os);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p[k][e] = bf16_val(h[e]) + bf16_val(l[e]);
+    } else {
+      p[k] = *reinterpret_cast<const f32x4*>(Pd + o);
+    }
   }
   if constexpr (XD) {
     const double gam = st->gamma[q];
@@ -244,8 +253,10 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t
     const int64_t j = j0 + 64 * k, o = (int64_t)q * Dp + j;
 #pragma unroll
     for (int e = 0; e < 4; ++e) p[k][e] = (float)((double)mi[k][e] * (double)r[k][e] + eta * (double)p[k][e]);
-    if constexpr (NT) __builtin_nontemporal_store(p[k], reinterpret_cast<f32x4*>(Pd + o));
-    else *reinterpret_cast<f32x4*>(Pd + o) = p[k];
+    if constexpr (!XD) {
+      if constexpr (NT) __builtin_nontemporal_store(p[k], reinterpret_cast<f32x4*>(Pd + o));
+      else *reinterpret_cast<f32x4*>(Pd + o) = p[k];
+    }
     store_split4(PdH, PdL, sig_index(q, j, Dp, c.Q), p[k]);
   }
 }

@@ -64,7 +64,11 @@ def test_conv_apply_A_matches_oracle(gpu, D, L, ncols, dtype):
     errs = [_rel(Psi[q], ref[q]) for q in range(ncols)]
     print(f"conv D={D} L={L} {dtype}: max column error {max(errs):.2e}")
     assert max(errs) < tol
-    pi_ref = np.sum(P.astype(np.float64) * Psi, axis=1)
+    # pi_q = sum_j P_jq Psi_jq over the direction the operator applied: in the bf16 form P
+    # travels as its hi/lo bf16 pair, hi = RNE(P), lo = RNE(P - hi)
+    hi = _bf16_rne(P)
+    Pq = P.astype(np.float64) if dtype == "fp32" else hi.astype(np.float64) + _bf16_rne(P - hi).astype(np.float64)
+    pi_ref = np.sum(Pq * Psi, axis=1)
     assert np.allclose(_np(pi), pi_ref, rtol=1e-10)
     if dtype == "bf16" and L > 1:
         op32 = oracle.ConvOperator(h, D)
