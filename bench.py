@@ -136,6 +136,9 @@ def parse():
     ap.add_argument("--serve-only", action="store_true", help="only the serving phase (for profiling)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run a 1 GiB copy and three operator applications (for rocprofv3 --pmc)")
+    ap.add_argument("--pmc-probe-conv", action="store_true",
+                    help="only run a 1 GiB copy and three bf16 FIR operator applications at D=2^20 "
+                         "(for rocprofv3 --pmc)")
     return ap.parse_args()
 
 
@@ -169,6 +172,37 @@ def pmc_probe():
     log("pmc probe done")
 
 
+def pmc_probe_conv():
+    """As pmc_probe, for the FIR dictionary: the 1 GiB copy, then three applications of the
+    bf16 operator at D = 2^20, 256 taps, K = 20 (one causal and one anti-causal filter pass
+    each)."""
+    import numpy as np
+    import torch
+
+    import paper_2105_10439_amd as lib
+    import workloads
+
+    torch.cuda.set_device(0)
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    w = workloads.WORKLOADS["conv"]
+    prob = workloads.make_workload("conv")
+    m = lib.CoFEM(prob.D, prob.D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], op="conv",
+                  conv_taps=prob.h.shape[0], phi_dtype="bf16")
+    m.set_dictionary(torch.from_numpy(prob.h).cuda())
+    rng = np.random.default_rng(0)
+    P = torch.from_numpy(rng.standard_normal((w["K"] + 1, prob.D)).astype(np.float32)).cuda()
+    al = torch.ones(prob.D, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        m.apply_A(al, P, use_bf16=True)
+    torch.cuda.synchronize()
+    m.close()
+    log("pmc probe (FIR) done")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -176,6 +210,9 @@ def main():
         sys.exit(2)
     if args.pmc_probe:
         pmc_probe()
+        return
+    if args.pmc_probe_conv:
+        pmc_probe_conv()
         return
     if args.serve_only:
         import torch
