@@ -206,7 +206,7 @@ def pmc_probe_conv():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; run with --gpus 1 (multi-GPU sharding is a design, not an implementation)"}))
         sys.exit(2)
     if args.pmc_probe:
         pmc_probe()
