@@ -209,6 +209,9 @@ cofem_status cofem_variance(cofem_ctx* c, const float* alpha, int32_t batches, u
  * columns of length D, with the loaded dictionary, alpha (D floats) and the
  * FP32 (use_bf16 = 0) or bfloat16 (use_bf16 = 1, needs phi_dtype = BF16) operator.
  * If pi is non-NULL (device, ncols doubles) it receives pi_q = sum_j P_jq Psi_jq.
+ * The bfloat16 operator applies the rounded dictionary to P's hi/lo bfloat16 pair
+ * (hi = RNE(P), lo = RNE(P - hi)); for the FIR dictionary that pair is also the P of
+ * diag(alpha) P and of pi (the form its CG steps carry), for the others P itself is.
  * Errors: COFEM_ESTATE (no dictionary), COFEM_EINVAL.
  */
 cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const float* P, float* Psi,
