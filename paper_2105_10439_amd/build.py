@@ -52,6 +52,7 @@ def build(verbose: bool = False) -> str:
         print("\n".join(msgs))
     os.replace(tmp, LIB)
     build_c_caller(verbose)
+    build_layout_check(verbose)
     return LIB
 
 
@@ -72,6 +73,24 @@ def build_c_caller(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError("gcc failed for the C caller:\n" + res.stdout + res.stderr)
     return C_CALLER
+
+
+LAYOUT_CHECK_SRC = os.path.join(ROOT, "tests", "c", "layout_check.hip")
+LAYOUT_CHECK = os.path.join(ROOT, "tests", "c", "layout_check")
+
+
+def build_layout_check(verbose: bool = False) -> str:
+    """A host program that checks the FIR signal-slice layout function of the device helpers
+    (it runs on the CPU; no device code is launched)."""
+    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared", "-fvisibility=hidden")]
+    cmd = [hipcc(), *flags, "-I", INCLUDE, "-I", CSRC, "-o", LAYOUT_CHECK, LAYOUT_CHECK_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        msgs = [l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l]
+        raise RuntimeError("hipcc failed for the layout check:\n" + "\n".join(msgs))
+    return LAYOUT_CHECK
 
 
 if __name__ == "__main__":
