@@ -218,6 +218,38 @@ cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const float* P, flo
                            int32_t ncols, int32_t use_bf16, double* pi);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the FP32 operator of
+ * cofem_apply_A for the FIR dictionary (Phi_ij = h[i - j], 0 <= i - j < L, N = D),
+ * with no context and no allocation.  Same kernels, same launch order, same
+ * results as cofem_apply_A on a context with op_kind = COFEM_OP_CONV, conv_taps = L
+ * and the taps h loaded, use_bf16 = 0.
+ *   h       L floats on the device (1 <= L <= 256): the filter taps.
+ *   D       signal length, >= 1.
+ *   beta    > 0.
+ *   alpha   D floats on the device.
+ *   P, Psi  blocks of ncols (1..COFEM_MAX_K+1) columns of length D on the device:
+ *           Psi = beta Phi^T (Phi P) + diag(alpha) P.
+ *   pi      NULL, or ncols doubles on the device: pi_q = sum_j P_jq Psi_jq.
+ *   stream  HIP stream (NULL = the default stream) on the current device.
+ * Scratch: every intermediate lives in one static device array of
+ * COFEM_STATIC_SCRATCH_BYTES per device, held until the process ends; the call
+ * needs 12 Qp Dp + 4 Dp + 8 Qp cdiv(Dp, 1024) bytes plus about 6 KB (Dp = D rounded
+ * up to 256, Qp = ncols rounded up to 16), e.g. D = 2^16 with up to 64 columns or
+ * D = 2^18 with up to 16.  The first call on a device
+ * looks up that device's copy of the array (hipGetSymbolAddress): make it outside
+ * graph capture.  Calls on one device share the array: calls that overlap in time
+ * on one device (other streams, other threads) race and give wrong results.
+ * The call only enqueues work on `stream` and returns; it does not synchronize.
+ * Errors: COFEM_EINVAL (NULL h/alpha/P/Psi, L, D, ncols or beta out of range, or a
+ * size that needs more scratch than the array holds; nothing is enqueued),
+ * COFEM_EDEVICE (address lookup or launch failure).
+ */
+#define COFEM_STATIC_SCRATCH_BYTES (64u << 20)
+cofem_status cofem_conv_apply_A_static(const float* h, int32_t L, int64_t D, double beta, const float* alpha,
+                                       const float* P, float* Psi, int32_t ncols, double* pi, void* stream);
+
+/*
  * Test hook: the probes of every later E-step (fits and cofem_variance).
  *   COFEM_PROBES_HASH (default): Rademacher probes from the counter-based hash,
  *     redrawn each EM iteration (Sec. III-A, Alg. 1).

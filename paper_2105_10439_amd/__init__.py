@@ -29,7 +29,8 @@ ABI_VERSION = 5  # COFEM_ABI_VERSION of include/cofem.h
 EXPORTS = [
     "cofem_abi_version", "cofem_last_error", "cofem_create", "cofem_destroy", "cofem_set_dictionary",
     "cofem_set_dct_samples",
-    "cofem_fit", "cofem_posterior", "cofem_variance", "cofem_apply_A", "cofem_set_probe_mode", "cofem_set_timing", "cofem_get_timing",
+    "cofem_fit", "cofem_posterior", "cofem_variance", "cofem_apply_A", "cofem_conv_apply_A_static",
+    "cofem_set_probe_mode", "cofem_set_timing", "cofem_get_timing",
     "cofem_server_create", "cofem_server_destroy", "cofem_server_submit", "cofem_server_step",
     "cofem_server_poll", "cofem_server_get_stats",
     "cofem_mt_create", "cofem_mt_destroy", "cofem_mt_set_dictionary", "cofem_mt_set_dct_samples", "cofem_mt_fit",
@@ -115,6 +116,7 @@ def load() -> ctypes.CDLL:
         "cofem_fit": (i32, [vp, vp]),
         "cofem_posterior": (i32, [vp, vp, vp, vp, ctypes.POINTER(Stats)]),
         "cofem_apply_A": (i32, [vp, vp, vp, vp, i32, i32, vp]),
+        "cofem_conv_apply_A_static": (i32, [vp, i32, i64, dbl, vp, vp, vp, i32, vp, vp]),
         "cofem_variance": (i32, [vp, vp, i32, ctypes.c_uint64, vp, vp, ctypes.POINTER(Stats)]),
         "cofem_set_timing": (i32, [vp, i32]),
         "cofem_set_probe_mode": (i32, [vp, i32]),
@@ -259,6 +261,33 @@ class CoFEM:
         n = ctypes.c_int64()
         _check(load().cofem_get_timing(self._h, 1 if which == "bf16" else 0, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # COFEM_STATIC_SCRATCH_BYTES of include/cofem.h
+
+
+def conv_apply_A_static(h, alpha, P, beta, want_pi=False, stream=None):
+    """cofem_conv_apply_A_static: Psi = beta Phi^T Phi P + alpha * P for the FIR dictionary with
+    taps h, P of shape (ncols, D), with no context and no device allocation by the library
+    (its scratch is a static device array).  Only enqueues on `stream` (default: torch's
+    current stream); the outputs are allocated here by torch, not by the library."""
+    import torch
+
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    for name, t in (("h", h), ("alpha", alpha), ("P", P)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    ncols, D = int(P.shape[0]), int(P.shape[1])
+    if alpha.numel() != D:
+        raise ValueError(f"alpha must have {D} elements")
+    Psi = torch.empty_like(P)
+    pi = torch.empty(ncols, dtype=torch.float64, device=P.device) if want_pi else None
+    _check(load().cofem_conv_apply_A_static(ctypes.c_void_p(h.data_ptr()), int(h.numel()), D, float(beta),
+                                            ctypes.c_void_p(alpha.data_ptr()), ctypes.c_void_p(P.data_ptr()),
+                                            ctypes.c_void_p(Psi.data_ptr()), ncols,
+                                            ctypes.c_void_p(pi.data_ptr()) if pi is not None else None,
+                                            ctypes.c_void_p(stream.cuda_stream)))
+    return (Psi, pi) if want_pi else Psi
 
 
 class MultiTask(CoFEM):

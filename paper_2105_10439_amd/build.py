@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcofem.so")
 
-SOURCES = ["kernels.hip", "conv.hip", "dct.hip", "cofem.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "conv.hip", "dct.hip", "cofem.hip", "serve.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -845,7 +845,7 @@ COFEM_API cofem_status cofem_apply_A(cofem_ctx* c, const float* alpha, const flo
   launch_state_reset(c->st, c->Q, c->stream);
   cofem_status rc = apply_operator(c, use_bf16 != 0, c->alpha_hook, sc, 0);
   if (rc != COFEM_OK) return rc;
-  launch_reduce_pi(ncols, c->Dp, c->pipart, c->st, c->stream);
+  launch_reduce_pi(ncols, c->Dp, c->pipart, c->st->pi, c->stream);
   launch_unpack_block(c->Psi, ncols, c->p.D, c->Dp, Psi, c->stream);
   if (pi) HIP_TRY(hipMemcpyAsync(pi, c->st->pi, sizeof(double) * ncols, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(hipGetLastError());

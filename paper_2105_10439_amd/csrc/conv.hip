@@ -334,9 +334,13 @@ static inline unsigned cdiv_(int64_t a, int64_t b) { return (unsigned)((a + b - 
 int conv_blocks_f32(int L) { return (L + 14) / 16 + 1; }
 int conv_blocks_bf16(int L) { return (L + 30) / 32 + 1; }
 
+void launch_conv_taps(const float* h, int L, float* hp32, uint16_t* hp16, hipStream_t s) {
+  hipLaunchKernelGGL(k_conv_taps, dim3(1), dim3(256), 0, s, h, L, hp32, hp16);
+}
+
 void launch_conv_setup(const float* h, int L, int64_t D, int64_t Dp, int jacobi, float* hp32, uint16_t* hp16,
                        float* theta, hipStream_t s) {
-  hipLaunchKernelGGL(k_conv_taps, dim3(1), dim3(256), 0, s, h, L, hp32, hp16);
+  launch_conv_taps(h, L, hp32, hp16, s);
   hipLaunchKernelGGL(k_conv_theta, dim3(cdiv_(Dp, 256)), dim3(256), 0, s, (const float*)hp32, L, D, Dp, jacobi,
                      theta);
 }

@@ -134,8 +134,8 @@ void launch_finish_pass1(const float* Ypart, int splits, int Q, int Qp, int64_t 
 // pi_q = sum_j Pd_jq Psi_jq into pipart ([q][chunk], chunks of 1024 coordinates).
 void launch_finish_pass2(const SolveCfg& c, const float* Ypart, int splits, int64_t Dp, const float* alpha,
                          const float* Pd, float* Psi, double* pipart, const CGState* st, hipStream_t s);
-// st->pi[q] = sum of the pi partials (test hook only; the CG update reduces them itself).
-void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipStream_t s);
+// pi[q] = sum of the pi partials, q < Q (test hooks only; the CG update reduces them itself).
+void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, double* pi, hipStream_t s);
 
 // ---- CG vector updates (Algorithm 2 after the operator) -----------------------
 // gamma_q = rho_q / pi_q (pi reduced from pipart), X += Pd gamma, R -= Psi gamma, partials
@@ -198,6 +198,8 @@ struct ConvArgs {
 };
 int conv_blocks_f32(int L);
 int conv_blocks_bf16(int L);
+// Pad the device taps h[0..L) into hp32 and hp16 (CONV_HPAD entries each).
+void launch_conv_taps(const float* h, int L, float* hp32, uint16_t* hp16, hipStream_t s);
 // Pad the device taps h[0..L) into hp32/hp16 and fill theta (Jacobi: column norms).
 void launch_conv_setup(const float* h, int L, int64_t D, int64_t Dp, int jacobi, float* hp32, uint16_t* hp16,
                        float* theta, hipStream_t s);

@@ -263,11 +263,11 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t
 
 // One block: pi_q into the state (used by the single-application test hook).
 __global__ __launch_bounds__(VBLOCK) void k_reduce_pi(int Q, int nbx, const double* __restrict__ pipart,
-                                                      CGState* __restrict__ st) {
+                                                      double* __restrict__ pi) {
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
   for (int q = wv; q < Q; q += 4) {
     const double a = wave_sum_strided(pipart + (int64_t)q * nbx, nbx, 1);
-    if (ln == 0) st->pi[q] = a;
+    if (ln == 0) pi[q] = a;
   }
 }
 
@@ -502,8 +502,8 @@ void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X
   hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(1024), 0, s, c, (int)nbx, (const double*)part, st);
 }
 
-void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, CGState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_pi, dim3(1), dim3(VBLOCK), 0, s, Q, (int)cdiv(Dp, VCHUNK), pipart, st);
+void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, double* pi, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_pi, dim3(1), dim3(VBLOCK), 0, s, Q, (int)cdiv(Dp, VCHUNK), pipart, pi);
 }
 
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,

@@ -117,3 +117,27 @@ def test_server_rejects_bad_arguments_without_device_work():
     assert not h.value
     assert so.cofem_server_step(None, None, None) == -1
     so.cofem_server_destroy(None)
+
+
+def test_static_conv_operator_rejects_without_device_work():
+    """cofem_conv_apply_A_static validates every argument, including the scratch its size
+    needs against the static array, before touching the device (the pointers here are
+    never dereferenced)."""
+    so = lib.load()
+    p = ctypes.c_void_p(0x1000)
+    cases = [
+        ((None, 4, 16, 400.0, p, p, p, 1, None, None), "NULL"),
+        ((p, 0, 16, 400.0, p, p, p, 1, None, None), "L must"),
+        ((p, 257, 16, 400.0, p, p, p, 1, None, None), "L must"),
+        ((p, 4, 0, 400.0, p, p, p, 1, None, None), "D must"),
+        ((p, 4, 16, 0.0, p, p, p, 1, None, None), "beta"),
+        ((p, 4, 16, float("inf"), p, p, p, 1, None, None), "beta"),
+        ((p, 4, 16, 400.0, p, p, p, 0, None, None), "ncols"),
+        ((p, 4, 16, 400.0, p, p, p, 65, None, None), "ncols"),
+        ((p, 256, 1 << 20, 400.0, p, p, p, 33, None, None), "scratch"),   # about 600 MB of scratch
+        ((p, 256, 1 << 17, 400.0, p, p, p, 33, None, None), "scratch"),   # 75 MB: just over the 64 MiB
+    ]
+    for args, msg in cases:
+        assert so.cofem_conv_apply_A_static(*args) == -1, args
+        assert msg in so.cofem_last_error().decode(), (args, so.cofem_last_error())
+    assert lib.STATIC_SCRATCH_BYTES == 64 << 20
