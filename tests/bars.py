@@ -1,0 +1,223 @@
+"""Bars of the GPU parity tests and how they are checked.
+
+Every comparison of the GPU path with the oracle is held to two numbers:
+
+* the acceptance bar of its arithmetic, stated where the comparison is made: mu within
+  1e-4 relative of the oracle for FP32 fits and s within 1e-3 (the diagonal estimate is
+  a sum of K products, each carrying the CG error of its probe column); per-column
+  operator bars from the length of the FP32 sums; for the bfloat16 forms the bounds
+  BF16_* below;
+* a regression bar of REGRESSION x the value measured on an MI355X with the current
+  kernels (MEASURED; the fits are bitwise reproducible run to run, so a value above it
+  means the arithmetic changed, not noise).  A key with no measured value yet is held
+  to its acceptance bar only.
+
+Where the CG tolerance decides how far the oracle's own answer sits from the converged
+one, `binds` checks that the oracle moves by at most a tenth of the acceptance bar
+between tol and tol / 100, so that the bar measures the GPU path and not the stop rule.
+"""
+from __future__ import annotations
+
+REGRESSION = 3.0
+
+# Stated bounds of the bfloat16 forms, relative to the FP64 oracle (mu: 2-norm over all
+# coordinates; s likewise).
+#   bf16 throughout, against the oracle run on the bf16-rounded dictionary (the problem
+#   the bf16 operator solves exactly; its directions travel as hi/lo bf16 pairs, about
+#   2^-17 relative, against 2^-24 for FP32):
+BF16_ROUNDED_MU = 2e-4
+BF16_ROUNDED_S = 5e-4
+#   bf16 dictionary with the last E-steps on the FP32 dictionary, against the oracle on
+#   the FP32 dictionary, once EM has settled (the refined E-steps then move mu by less
+#   than the bf16 rounding of the dictionary moved it):
+BF16_REFINED_MU = 3e-4
+BF16_REFINED_S = 3e-3
+#   the same for the FIR dictionary after only 3 bf16 and 2 FP32 E-steps (EM still
+#   moving): A is ill-conditioned there (beta (sum h)^2 ~ 1e6 against alpha ~ 1), the bf16
+#   taps move the early alphas further, and two FP32 E-steps do not bring EM back to the
+#   FP32 trajectory
+BF16_REFINED_FIR_MU = 5e-3
+BF16_REFINED_FIR_S = 2e-2
+
+# Values measured on an MI355X (gfx950) with the current kernels.
+MEASURED: dict[str, float] = {
+    "apply_A/bf16/1024x2048x33": 1.675e-06,
+    "apply_A/bf16/200x600x64": 2.184e-06,
+    "apply_A/bf16/256x512x49": 1.987e-06,
+    "apply_A/bf16/260x700x17": 1.852e-06,
+    "apply_A/bf16/300x1000x9": 1.835e-06,
+    "apply_A/bf16/513x777x21": 1.462e-06,
+    "apply_A/bf16/64x256x1": 2.070e-06,
+    "apply_A/fp32/1024x2048x33": 1.486e-07,
+    "apply_A/fp32/200x600x64": 1.851e-07,
+    "apply_A/fp32/256x512x49": 1.743e-07,
+    "apply_A/fp32/260x700x17": 1.577e-07,
+    "apply_A/fp32/300x1000x9": 1.696e-07,
+    "apply_A/fp32/513x777x21": 1.339e-07,
+    "apply_A/fp32/64x256x1": 1.187e-07,
+    "apply_A/fp32_sliced/1024x2048x33": 2.902e-07,
+    "apply_A/fp32_sliced/256x512x49": 3.161e-07,
+    "apply_A/fp32_sliced/513x777x21": 2.926e-07,
+    "bf16_refined/mu": 5.778e-05,
+    "bf16_refined/s": 7.962e-04,
+    "bf16_rounded/mu": 1.481e-05,
+    "bf16_rounded/s": 3.775e-05,
+    "bf16_unrefined_vs_fp32_oracle/mu": 1.255e-03,
+    "c_caller/mu": 1.069e-05,
+    "c_caller/s": 4.150e-05,
+    "conv_apply_A/bf16/1000x256x21": 3.961e-06,
+    "conv_apply_A/bf16/200x256x17": 4.014e-06,
+    "conv_apply_A/bf16/2048x100x33": 3.246e-06,
+    "conv_apply_A/bf16/3000x256x9": 3.117e-06,
+    "conv_apply_A/bf16/4096x256x64": 3.241e-06,
+    "conv_apply_A/bf16/513x1x3": 2.543e-06,
+    "conv_apply_A/bf16/777x37x5": 3.179e-06,
+    "conv_apply_A/fp32/1000x256x21": 1.699e-07,
+    "conv_apply_A/fp32/200x256x17": 1.698e-07,
+    "conv_apply_A/fp32/2048x100x33": 1.170e-07,
+    "conv_apply_A/fp32/3000x256x9": 1.547e-07,
+    "conv_apply_A/fp32/4096x256x64": 1.646e-07,
+    "conv_apply_A/fp32/513x1x3": 2.733e-08,
+    "conv_apply_A/fp32/777x37x5": 9.546e-08,
+    "conv_bench_fit/nrmse": 1.688e-01,
+    "conv_bench_fit/true_residual": 9.908e-06,
+    "conv_bf16_K15/mu": 5.635e-05,
+    "conv_bf16_K15/s": 1.237e-04,
+    "conv_bf16_K16/mu": 4.170e-05,
+    "conv_bf16_K16/s": 8.050e-05,
+    "conv_bf16_K31/mu": 3.429e-05,
+    "conv_bf16_K31/s": 2.921e-05,
+    "conv_bf16_refined/mu": 2.444e-03,
+    "conv_bf16_rounded/mu": 3.277e-05,
+    "conv_bf16_rounded/s": 9.326e-05,
+    "conv_fit/jacobi/mu": 1.836e-05,
+    "conv_fit/jacobi/s": 3.333e-05,
+    "conv_fit/ones/mu": 1.858e-05,
+    "conv_fit/ones/s": 3.170e-05,
+    "conv_large_operator/bf16": 1.194e-06,
+    "conv_large_operator/fp32": 7.172e-08,
+    "conv_nonneg/mu": 1.115e-05,
+    "conv_nonneg/s": 3.363e-05,
+    "dct_apply_A/1024x341x21": 5.197e-08,
+    "dct_apply_A/128x42x17": 9.265e-08,
+    "dct_apply_A/16384x5461x7": 5.428e-08,
+    "dct_apply_A/16x5x3": 8.336e-08,
+    "dct_apply_A/2048x2048x5": 7.201e-08,
+    "dct_apply_A/2048x682x64": 5.255e-08,
+    "dct_apply_A/256x85x21": 5.943e-08,
+    "dct_apply_A/32768x10922x21": 4.881e-08,
+    "dct_apply_A/32768x1x33": 2.645e-08,
+    "dct_apply_A/32x32x9": 4.403e-08,
+    "dct_apply_A/4096x1365x64": 5.387e-08,
+    "dct_apply_A/512x170x33": 6.297e-08,
+    "dct_apply_A/64x1x2": 3.470e-08,
+    "dct_apply_A/8192x2730x21": 4.903e-08,
+    "dct_fit/jacobi/mu": 1.869e-06,
+    "dct_fit/jacobi/s": 9.320e-05,
+    "dct_fit/ones/mu": 1.839e-06,
+    "dct_fit/ones/s": 8.962e-05,
+    "dct_full_sampling/mu": 1.026e-07,
+    "dct_full_sampling/s": 3.185e-06,
+    "dct_workload/mu": 2.149e-06,
+    "dct_workload/nrmse": 1.157e-02,
+    "dct_workload/s": 9.586e-05,
+    "hadamard_bf16_refined/alpha_vs_exact_em": 7.391e-04,
+    "hadamard_bf16_refined/mu_vs_exact_em": 1.739e-05,
+    "hadamard_bf16_refined/s_vs_exact_em": 7.505e-04,
+    "hadamard_dct/alpha_vs_exact_em": 9.535e-05,
+    "hadamard_dct/mu_vs_exact_em": 1.114e-05,
+    "hadamard_dct/mu_vs_oracle": 1.029e-05,
+    "hadamard_dct/s_vs_exact_em": 5.661e-05,
+    "hadamard_dct/s_vs_oracle": 5.274e-05,
+    "hadamard_fp32/alpha_vs_exact_em": 6.146e-05,
+    "hadamard_fp32/mu_vs_exact_em": 8.261e-06,
+    "hadamard_fp32/mu_vs_oracle": 7.853e-06,
+    "hadamard_fp32/s_vs_exact_em": 6.441e-05,
+    "hadamard_fp32/s_vs_oracle": 6.407e-05,
+    "large_bench_fit/nrmse": 2.267e-02,
+    "large_bench_fit/true_residual": 9.621e-06,
+    "large_operator/bf16": 1.906e-07,
+    "large_operator/fp32": 1.223e-07,
+    "medium/mu": 1.070e-06,
+    "medium/s": 2.950e-05,
+    "multitask_L1/task0/mu": 1.290e-06,
+    "multitask_L1/task0/s": 6.525e-05,
+    "multitask_L3/task0/mu": 1.069e-06,
+    "multitask_L3/task0/s": 3.192e-05,
+    "multitask_L3/task1/mu": 1.030e-06,
+    "multitask_L3/task1/s": 3.134e-05,
+    "multitask_L3/task2/mu": 1.105e-06,
+    "multitask_L3/task2/s": 3.246e-05,
+    "multitask_conv_bf16/task0/mu": 4.627e-06,
+    "multitask_conv_bf16/task0/s": 1.703e-05,
+    "multitask_conv_bf16/task1/mu": 6.182e-06,
+    "multitask_conv_bf16/task1/s": 1.715e-05,
+    "multitask_conv_fp32/task0/mu": 2.549e-06,
+    "multitask_conv_fp32/task0/s": 1.122e-05,
+    "multitask_conv_fp32/task1/mu": 2.807e-06,
+    "multitask_conv_fp32/task1/s": 1.141e-05,
+    "nonneg_dense/mu": 1.202e-06,
+    "nonneg_dense/s": 9.115e-05,
+    "ragged_jacobi/mu": 5.791e-07,
+    "ragged_jacobi/s": 2.120e-05,
+    "served_small_K16/mu": 9.547e-07,
+    "served_small_K16/s": 1.319e-05,
+    "served_small_K8/mu": 8.263e-07,
+    "served_small_K8/s": 1.597e-05,
+    "small/column/mu": 7.434e-07,
+    "small/column/s": 1.915e-05,
+    "small/joint/mu": 7.789e-07,
+    "small/joint/s": 1.516e-05,
+    "t1_estep/mu": 9.708e-03,
+    "t1_estep/s": 1.113e-05,
+    "variance/conv/mu": 2.120e-06,
+    "variance/conv/s": 1.234e-07,
+    "variance/dct/mu": 1.094e-04,
+    "variance/dct/s": 7.652e-08,
+    "variance/dense/mu": 4.932e-04,
+    "variance/dense/s": 1.488e-06,
+}
+
+
+def check(key: str, value: float, accept: float) -> None:
+    """value <= accept and value <= REGRESSION x the measured value of `key` (if any)."""
+    meas = MEASURED.get(key)
+    reg = None if meas is None else max(REGRESSION * meas, 1e-12)
+    print(f"[bar] {key} = {value:.3e} (acceptance {accept:.1e}"
+          + (f", regression {reg:.2e})" if reg is not None else ", not yet measured)"), flush=True)
+    assert value <= accept, f"{key}: {value:.3e} above the acceptance bar {accept:.1e}"
+    if reg is not None:
+        assert value <= reg, f"{key}: {value:.3e} above {REGRESSION}x the measured {meas:.3e}"
+
+
+def fp32_solve_bar(phi, beta: float, alpha, theta=None, floor: float = 1e-4) -> float:
+    """Acceptance bar for mu from an FP32 solve of A mu = b at a given alpha: an FP32 CG
+    reaches a relative error of about kappa u (u = 2^-24), kappa the condition number of
+    the preconditioned system M^-1/2 A M^-1/2 (M = diag(beta theta + alpha)).  Returns
+    max(floor, 4 kappa u).  phi is the dense N x D dictionary (small D only)."""
+    import numpy as np
+
+    phi = np.asarray(phi, dtype=np.float64)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    theta = np.ones_like(alpha) if theta is None else np.asarray(theta, dtype=np.float64)
+    m = 1.0 / np.sqrt(beta * theta + alpha)
+    ev = np.linalg.eigvalsh(m[:, None] * (beta * phi.T @ phi + np.diag(alpha)) * m[None, :])
+    kappa = ev[-1] / ev[0]
+    bar = max(floor, 4.0 * kappa * 2.0 ** -24)
+    print(f"[kappa] {kappa:.3e}: FP32 solve bar {bar:.2e}", flush=True)
+    return bar
+
+
+def fp32_fit_bar(phi, beta: float, alphas, theta=None, floor: float = 1e-4) -> float:
+    """The same for a whole fit: every E-step t solves at its own alpha^(t) and leaves an
+    error of about kappa_t u in mu and s, which the next M-steps carry forward (the
+    Gaussian EM contracts it as it settles, the non-negative one much more slowly), so the
+    bar takes the largest kappa over the given alphas."""
+    return max(fp32_solve_bar(phi, beta, a, theta, floor) for a in alphas)
+
+
+def binds(key: str, sensitivity: float, accept: float) -> None:
+    """The oracle's own change between tol and tol / 100 is at most a tenth of the bar."""
+    print(f"[sens] {key} = {sensitivity:.3e} (bar {accept:.1e})", flush=True)
+    assert sensitivity <= 0.1 * accept, (f"{key}: the oracle moves by {sensitivity:.2e} with the CG "
+                                         f"tolerance, too much for a bar of {accept:.1e}")

@@ -2,8 +2,9 @@
 build step with gcc against include/cofem.h, libcofem.so and the HIP runtime, no
 Python binding in the loop) fits the small dense workload; its mu and s are
 compared with the FP64 oracle at the same probes, stop rule and tolerance, to the
-same bar as the Python-driven fits: 1e-4 (mu) and 1e-3 (s) relative, or twice the
-oracle's own change between tol and tol / 100, whichever is larger.
+same bar as the Python-driven fits: 1e-4 (mu) and 1e-3 (s) relative.  At T = 20 the
+oracle's own mu still moves by 2e-4 between tol 1e-6 and 1e-8 on this workload, so
+the fit runs at tol 1e-8, where that change is far below the bar.
 """
 import os
 import struct
@@ -14,6 +15,7 @@ import pytest
 
 import oracle
 import workloads
+from bars import binds, check
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +26,7 @@ EXE = os.path.join(ROOT, "tests", "c", "fit_smoke")
 def test_plain_c_caller_matches_oracle(gpu, tmp_path):
     if not os.path.exists(EXE):
         pytest.fail(f"{EXE} is missing: run the package build (python -m paper_2105_10439_amd.build)")
-    w = dict(workloads.WORKLOADS["small"])
+    w = dict(workloads.WORKLOADS["small"], tol=1e-8)
     T, seed = 20, 77
     prob = workloads.make_workload("small")
     inp, out = tmp_path / "in.bin", tmp_path / "out.bin"
@@ -52,7 +54,8 @@ def test_plain_c_caller_matches_oracle(gpu, tmp_path):
 
     e_mu, e_s = rel(mu, ref.mu), rel(s, ref.s)
     sens_mu, sens_s = rel(ref.mu, tight.mu), rel(ref.s, tight.s)
-    print(f"C caller vs oracle: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e}), s rel {e_s:.2e} ({sens_s:.2e}), "
-          f"CG steps {steps} (oracle {sum(ref.cg_steps)})")
-    assert e_mu <= max(1e-4, 2 * sens_mu) and e_s <= max(1e-3, 2 * sens_s)
+    print(f"C caller: CG steps {steps} (oracle {sum(ref.cg_steps)})")
+    binds("c_caller", sens_mu, 1e-4)
+    check("c_caller/mu", e_mu, 1e-4)
+    check("c_caller/s", e_s, 1e-3)
     assert np.all(np.isfinite(alpha)) and steps > 0

@@ -8,9 +8,10 @@
   column), and for bf16 the rounded taps applied to signals carried as hi + lo
   bfloat16 pairs (1e-4 against the oracle with the same rounded taps).
 * Fits against the oracle at the same probes, stop rule and tolerance.  On this
-  dictionary A is ill-conditioned (beta (sum h)^2 ~ 1e6 against alpha ~ 1), so
-  mu moves visibly with the CG tolerance itself; the bar is 1e-4 or twice the
-  oracle's own change of mu between tol and tol / 100, whichever is larger.
+  dictionary A is ill-conditioned (beta (sum h)^2 ~ 1e6 against alpha ~ 1), so mu
+  moves visibly with the CG tolerance itself (7.8e-5 between tol 1e-6 and 1e-8 at
+  D = 1500); the fits run at tol 1e-8 (U = 600), where that change is 7e-7, so the
+  FP32 bar of 1e-4 on mu (1e-3 on s) measures the GPU path.
 * The full-size workload (D = 2^20, L = 256, K = 20): sampled operator rows, and
   the benchmark's fit by properties (true FP64 residual of mu, recovery).
 """
@@ -19,6 +20,7 @@ import pytest
 
 import oracle
 import workloads
+from bars import BF16_REFINED_FIR_MU, BF16_REFINED_FIR_S, BF16_ROUNDED_MU, BF16_ROUNDED_S, binds, check
 
 pytestmark = pytest.mark.gpu
 
@@ -62,8 +64,7 @@ def test_conv_apply_A_matches_oracle(gpu, D, L, ncols, dtype):
     ref = (beta * op.rmatvec(op.matvec(Pt)) + alpha.astype(np.float64)[:, None] * Pt).T
     tol = 2e-5 if dtype == "fp32" else 1e-4
     errs = [_rel(Psi[q], ref[q]) for q in range(ncols)]
-    print(f"conv D={D} L={L} {dtype}: max column error {max(errs):.2e}")
-    assert max(errs) < tol
+    check(f"conv_apply_A/{dtype}/{D}x{L}x{ncols}", max(errs), tol)
     # pi_q = sum_j P_jq Psi_jq over the direction the operator applied: in the bf16 form P
     # travels as its hi/lo bf16 pair, hi = RNE(P), lo = RNE(P - hi)
     hi = _bf16_rne(P)
@@ -93,49 +94,52 @@ def _oracle_pair(prob, h, K, T, U, tol, seed, **kw):
     return ref, _rel(ref.mu, tight.mu), _rel(ref.s, tight.s)
 
 
+# tol and U of the small fits: see the module docstring
+FIT_TOL, FIT_U = 1e-8, 600
+
+
 @pytest.mark.parametrize("theta", ["ones", "jacobi"])
 def test_conv_fit_fp32_matches_oracle(gpu, theta):
     prob = workloads.conv_problem(1500, 256, 50.0, 0.01, 0.05, seed=31)
-    K, T, U, tol, seed = 20, 5, 400, 1e-6, 7
+    K, T, U, tol, seed = 20, 5, FIT_U, FIT_TOL, 7
     mu, s, alpha, st = _conv_fit(gpu, prob, K, T, U, tol, seed, theta=theta)
     ref, sens_mu, sens_s = _oracle_pair(prob, prob.h, K, T, U, tol, seed, theta_mode=theta)
     e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
-    print(f"conv fit {theta}: mu rel {e_mu:.2e} (oracle tol sensitivity {sens_mu:.2e}), s rel {e_s:.2e} "
-          f"({sens_s:.2e}); CG steps gpu {st['cg_steps'][:T]} oracle {ref.cg_steps}")
-    assert e_mu <= max(1e-4, 2 * sens_mu)
-    assert e_s <= max(1e-3, 2 * sens_s)
+    print(f"conv fit {theta}: CG steps gpu {st['cg_steps'][:T]} oracle {ref.cg_steps}")
+    binds(f"conv_fit/{theta}", sens_mu, 1e-4)
+    check(f"conv_fit/{theta}/mu", e_mu, 1e-4)
+    check(f"conv_fit/{theta}/s", e_s, 1e-3)
     assert st["breakdown"] == 0 and all(np.isfinite(x).all() for x in (mu, s, alpha))
 
 
 def test_conv_fit_nonneg_mstep_matches_oracle(gpu):
     """Calcium-like use: non-negative spikes, the rectified-Gaussian M-step (Sec. III-E.2)."""
     prob = workloads.conv_problem(1500, 256, 50.0, 0.01, 0.05, seed=37)
-    K, T, U, tol, seed = 20, 5, 400, 1e-6, 11
+    K, T, U, tol, seed = 20, 5, FIT_U, FIT_TOL, 11
     mu, s, alpha, st = _conv_fit(gpu, prob, K, T, U, tol, seed, mstep="nonneg")
     ref, sens_mu, sens_s = _oracle_pair(prob, prob.h, K, T, U, tol, seed, mstep="nonneg")
-    e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
-    print(f"conv nonneg fit: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e}), s rel {e_s:.2e} ({sens_s:.2e})")
-    assert e_mu <= max(1e-4, 2 * sens_mu)
-    assert e_s <= max(1e-3, 2 * sens_s)
+    binds("conv_nonneg", sens_mu, 1e-4)
+    check("conv_nonneg/mu", _rel(mu, ref.mu), 1e-4)
+    check("conv_nonneg/s", _rel(s, ref.s), 1e-3)
 
 
 def test_conv_fit_bf16_matches_rounded_oracle_and_refines(gpu):
     prob = workloads.conv_problem(1200, 256, 50.0, 0.01, 0.05, seed=41)
-    K, T, U, tol, seed = 20, 5, 400, 1e-6, 9
+    K, T, U, tol, seed = 20, 5, FIT_U, FIT_TOL, 9
     # bf16 throughout: the oracle with the same rounded taps
     mu, s, _, st = _conv_fit(gpu, prob, K, T, U, tol, seed, phi_dtype="bf16")
     assert all(st["used_bf16"][:T])
     ref, sens_mu, _ = _oracle_pair(prob, _bf16_rne(prob.h), K, T, U, tol, seed)
-    e_mu = _rel(mu, ref.mu)
-    print(f"conv bf16 vs rounded-taps oracle: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e})")
-    assert e_mu <= max(1e-3, 2 * sens_mu)
+    binds("conv_bf16_rounded", sens_mu, BF16_ROUNDED_MU)
+    check("conv_bf16_rounded/mu", _rel(mu, ref.mu), BF16_ROUNDED_MU)
+    check("conv_bf16_rounded/s", _rel(s, ref.s), BF16_ROUNDED_S)
     # bf16 with the last 2 E-steps on the FP32 taps: against the FP32 oracle
-    mu2, _, _, st2 = _conv_fit(gpu, prob, K, T, U, tol, seed, phi_dtype="bf16", refine_last=2)
+    mu2, s2, _, st2 = _conv_fit(gpu, prob, K, T, U, tol, seed, phi_dtype="bf16", refine_last=2)
     assert list(st2["used_bf16"][:T]) == [1, 1, 1, 0, 0]
     ref32, sens32, _ = _oracle_pair(prob, prob.h, K, T, U, tol, seed)
-    e2 = _rel(mu2, ref32.mu)
-    print(f"conv bf16 + 2 FP32 refinements vs FP32 oracle: mu rel {e2:.2e} (sensitivity {sens32:.2e})")
-    assert e2 <= max(2e-2, 2 * sens32)
+    binds("conv_bf16_refined", sens32, BF16_REFINED_FIR_MU)
+    check("conv_bf16_refined/mu", _rel(mu2, ref32.mu), BF16_REFINED_FIR_MU)
+    check("conv_bf16_refined/s", _rel(s2, ref32.s), BF16_REFINED_FIR_S)
 
 
 @pytest.mark.parametrize("K", [15, 16, 31])
@@ -144,14 +148,13 @@ def test_conv_fit_bf16_tile_widths(gpu, K):
     32) or one column wide (Q = 17): the E-step init, the direction update and both filter passes
     address that tile by its own width."""
     prob = workloads.conv_problem(800, 256, 50.0, 0.01, 0.05, seed=43 + K)
-    T, U, tol, seed = 3, 400, 1e-6, 13
+    T, U, tol, seed = 3, FIT_U, FIT_TOL, 13
     mu, s, _, st = _conv_fit(gpu, prob, K, T, U, tol, seed, phi_dtype="bf16")
     assert all(st["used_bf16"][:T])
     ref, sens_mu, sens_s = _oracle_pair(prob, _bf16_rne(prob.h), K, T, U, tol, seed)
-    e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
-    print(f"conv bf16 K={K}: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e}), s rel {e_s:.2e} ({sens_s:.2e})")
-    assert e_mu <= max(1e-3, 2 * sens_mu)
-    assert e_s <= max(1e-2, 2 * sens_s)
+    binds(f"conv_bf16_K{K}", sens_mu, BF16_ROUNDED_MU)
+    check(f"conv_bf16_K{K}/mu", _rel(mu, ref.mu), BF16_ROUNDED_MU)
+    check(f"conv_bf16_K{K}/s", _rel(s, ref.s), BF16_ROUNDED_S)
 
 
 # ---------------------------------------------------------------------------
@@ -186,8 +189,7 @@ def test_conv_large_operator_sampled(gpu, conv_large, dtype):
     scale = absop.normal_rows(np.abs(P.T), alpha, prob.beta, rows)   # size of the summed terms
     err = np.abs(Psi[:, rows].T - ref) / scale
     tol = 1e-5 if dtype == "fp32" else 1e-4
-    print(f"conv large {dtype}: max scaled error {err.max():.2e}")
-    assert err.max() < tol
+    check(f"conv_large_operator/{dtype}", err.max(), tol)
 
 
 def test_conv_large_bench_fit_properties(gpu, conv_large):
@@ -206,6 +208,10 @@ def test_conv_large_bench_fit_properties(gpu, conv_large):
     Amu = prob.beta * op.rmatvec(op.matvec(mu)) + alpha * mu
     res = np.linalg.norm(b - Amu) / np.linalg.norm(b)
     nrmse = np.linalg.norm(mu - prob.z) / np.linalg.norm(prob.z)
-    print(f"conv bench fit: {st['total_cg_steps']} CG steps, true residual {res:.2e}, NRMSE {nrmse:.3f}")
-    assert res < 100 * w["tol"]
-    assert nrmse < 0.5
+    print(f"conv bench fit: {st['total_cg_steps']} CG steps")
+    # the joint stop rule bounds the recursive residual of all columns together by tol, and
+    # the mu column carries most of ||B||_F; FP32 rounding lets the true residual of mu
+    # drift from the recursive one by a small factor (measured 0.98 tol)
+    check("conv_bench_fit/true_residual", res, 3 * w["tol"])
+    # recovery of the Bernoulli(0.01) Exp(1) spikes (sanity, not parity; measured 16.9 %)
+    check("conv_bench_fit/nrmse", nrmse, 0.18)

@@ -10,11 +10,13 @@ A = beta Omega M^T M Omega^T + diag(alpha) with an LDS-resident FFT per column.
   The FP32 FFT of length L = D/2 has a normwise error of a few log2(L) * 2^-24;
   the bar is 2e-5 per column.
 * Fits against the oracle at the same probes, stop rule and tolerance (mu within
-  1e-4, or twice the oracle's own change of mu between tol and tol / 100).
+  1e-4, s within 1e-3), at tolerances where the oracle's own mu moves by at most a
+  tenth of the bar between tol and tol / 100.
 * N = D: Phi is orthogonal, A is diagonal and theta = 1 gives the exact
   preconditioner, so every E-step ends after one CG step.
-* The full-size workload (D = 2^15, N = D/3, K = 20, T = 30, tol 1e-4) against
-  the oracle's fit (3x the sensitivity: see the test), and bad sample sets rejected.
+* The full-size workload (D = 2^15, N = D/3, K = 20, T = 30) against the oracle's
+  fit at tol 1e-7 (the benchmark runs it at the paper's 1e-4, where the oracle's own
+  mu still moves by about 1 % with the tolerance), and bad sample sets rejected.
 """
 import ctypes
 
@@ -23,6 +25,7 @@ import pytest
 
 import oracle
 import workloads
+from bars import binds, check, fp32_fit_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -67,8 +70,7 @@ def test_dct_apply_A_matches_oracle(gpu, D, N, ncols):
     Pt = P.T.astype(np.float64)
     ref = (beta * op.rmatvec(op.matvec(Pt)) + alpha.astype(np.float64)[:, None] * Pt).T
     errs = [_rel(Psi[q], ref[q]) for q in range(ncols)]
-    print(f"  max column error {max(errs):.2e}")
-    assert max(errs) < 2e-5
+    check(f"dct_apply_A/{D}x{N}x{ncols}", max(errs), 2e-5)
     pi_ref = np.sum(P.astype(np.float64) * Psi, axis=1)
     assert np.allclose(_np(pi), pi_ref, rtol=1e-10)
 
@@ -92,26 +94,34 @@ def _oracle_pair(prob, K, T, U, tol, seed, **kw):
 @pytest.mark.parametrize("theta", ["ones", "jacobi"])
 def test_dct_fit_matches_oracle(gpu, theta):
     prob = workloads.dct_problem(1024, 341, 122, 0.01, seed=43)
-    K, T, U, tol, seed = 20, 30, 400, 1e-6, 5
+    K, T, U, tol, seed = 20, 30, 400, 1e-8, 5
     mu, s, alpha, st = _dct_fit(gpu, prob, K, T, U, tol, seed, theta=theta)
     ref, sens_mu, sens_s = _oracle_pair(prob, K, T, U, tol, seed, theta_mode=theta)
     e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
-    print(f"dct fit {theta}: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e}), s rel {e_s:.2e} ({sens_s:.2e}); "
-          f"CG steps gpu {st['total_cg_steps']} oracle {sum(ref.cg_steps)}")
-    assert e_mu <= max(1e-4, 2 * sens_mu)
-    assert e_s <= max(1e-3, 2 * sens_s)
+    print(f"dct fit {theta}: CG steps gpu {st['total_cg_steps']} oracle {sum(ref.cg_steps)}")
+    binds(f"dct_fit/{theta}", sens_mu, 1e-4)
+    check(f"dct_fit/{theta}/mu", e_mu, 1e-4)
+    check(f"dct_fit/{theta}/s", e_s, 1e-3)
     assert st["breakdown"] == 0 and all(np.isfinite(x).all() for x in (mu, s, alpha))
 
 
 def test_dct_fit_nonneg_mstep_matches_oracle(gpu):
     prob = workloads.dct_problem(512, 170, 40, 0.01, seed=47)
-    K, T, U, tol, seed = 16, 20, 400, 1e-6, 9
+    # tol 1e-9: at 1e-8 the oracle's mu still moves by 1.0e-5 with the tolerance here
+    K, T, U, tol, seed = 16, 20, 400, 1e-9, 9
     mu, s, alpha, st = _dct_fit(gpu, prob, K, T, U, tol, seed, mstep="nonneg")
-    ref, sens_mu, sens_s = _oracle_pair(prob, K, T, U, tol, seed, mstep="nonneg")
+    ref, sens_mu, sens_s = _oracle_pair(prob, K, T, U, tol, seed, mstep="nonneg", record=True)
     e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
-    print(f"dct nonneg fit: mu rel {e_mu:.2e} (sensitivity {sens_mu:.2e}), s rel {e_s:.2e} ({sens_s:.2e})")
-    assert e_mu <= max(1e-4, 2 * sens_mu)
-    assert e_s <= max(1e-3, 2 * sens_s)
+    # with theta = 1 and N = D/3 the first E-steps solve systems with kappa 1e4 - 2e4 (the
+    # D - N directions outside the range of Phi^T are held by alpha alone); each leaves an
+    # FP32 error of about kappa 2^-24 (1.1e-3 in mu after E-step 1, measured against the
+    # exact solve at the same alpha), which the non-negative EM carries to the end (the
+    # Gaussian one contracts it to 3e-6 by t = 20): the bar is that floor, taken over the
+    # oracle's alphas
+    bar = fp32_fit_bar(oracle.DctOperator(prob.D, prob.rows).dense(), prob.beta, ref.alphas)
+    binds("dct_nonneg", sens_mu, 1e-4)
+    check("dct_nonneg/mu", e_mu, bar)
+    check("dct_nonneg/s", e_s, 10 * bar)
 
 
 def test_dct_full_sampling_is_one_cg_step(gpu):
@@ -121,8 +131,8 @@ def test_dct_full_sampling_is_one_cg_step(gpu):
     mu, s, alpha, st = _dct_fit(gpu, prob, 8, 5, 50, 1e-6, 3)
     assert st["cg_steps"] == [1] * 5
     ref = oracle.cofem(oracle.DctOperator(D, prob.rows), prob.y, prob.beta, T=5, K=8, U=50, tol=1e-6, seed=3)
-    assert _rel(mu, ref.mu) < 1e-5
-    assert _rel(s, ref.s) < 1e-5
+    check("dct_full_sampling/mu", _rel(mu, ref.mu), 1e-5)
+    check("dct_full_sampling/s", _rel(s, ref.s), 1e-5)
 
 
 def test_dct_split_fit_is_deterministic(gpu):
@@ -155,19 +165,20 @@ def test_dct_bad_samples_rejected(gpu):
 
 
 def test_dct_workload_fit_matches_oracle(gpu):
-    """The benchmark's DCT fit (D = 2^15, N = D/3, d = 0.12 D, K = 20, T = 30, tol 1e-4)."""
-    w = workloads.WORKLOADS["dct"]
+    """The benchmark's DCT problem (D = 2^15, N = D/3, d = 0.12 D, K = 20, T = 30) at tol
+    1e-7: mu within 1e-4 and s within 1e-3 of the oracle."""
+    w = dict(workloads.WORKLOADS["dct"], tol=1e-7)
     prob = workloads.make_workload("dct")
     mu, s, alpha, st = _dct_fit(gpu, prob, w["K"], w["T"], w["U"], w["tol"], 2024)
+    print("dct workload: GPU fit done, running the oracle at tol and tol / 100", flush=True)
     op = oracle.DctOperator(prob.D, prob.rows)
     ref = oracle.cofem(op, prob.y, prob.beta, T=w["T"], K=w["K"], U=w["U"], tol=w["tol"], seed=2024)
+    print(f"dct workload: oracle at tol done ({sum(ref.cg_steps)} CG steps)", flush=True)
     tight = oracle.cofem(op, prob.y, prob.beta, T=w["T"], K=w["K"], U=w["U"], tol=w["tol"] / 100, seed=2024)
-    e_mu, sens = _rel(mu, ref.mu), _rel(ref.mu, tight.mu)
     nrmse = _rel(mu, prob.z)
-    print(f"dct workload: mu rel {e_mu:.2e} (sensitivity {sens:.2e}), NRMSE {nrmse:.3f} (oracle "
-          f"{_rel(ref.mu, prob.z):.3f}), CG steps gpu {st['total_cg_steps']} oracle {sum(ref.cg_steps)}, "
-          f"{st['ms_fit']:.1f} ms")
-    # at tol 1e-4 each side's mu sits within about `sens` of the converged one, and 30 EM
-    # iterations compound the difference of CG step counts; 3x leaves room for both
-    assert e_mu <= max(1e-4, 3 * sens)
-    assert nrmse < 0.1
+    print(f"dct workload: NRMSE {nrmse:.3f} (oracle {_rel(ref.mu, prob.z):.3f}), CG steps gpu "
+          f"{st['total_cg_steps']} oracle {sum(ref.cg_steps)}, {st['ms_fit']:.1f} ms")
+    binds("dct_workload", _rel(ref.mu, tight.mu), 1e-4)
+    check("dct_workload/mu", _rel(mu, ref.mu), 1e-4)
+    check("dct_workload/s", _rel(s, ref.s), 1e-3)
+    check("dct_workload/nrmse", nrmse, 0.1)

@@ -25,6 +25,7 @@ import pytest
 
 import oracle
 import workloads
+from bars import check
 
 pytestmark = pytest.mark.gpu
 
@@ -86,14 +87,16 @@ def test_hadamard_fit_equals_exact_em(gpu, kind):
     op = oracle.DctOperator(D, prob.rows) if kind == "dct" else phi
     ref = oracle.cofem(op, prob.y, prob.beta, T=T, K=D, U=400, tol=1e-7, probes=lambda t: H)
     e = dict(mu=_rel(mu, mu_em), s=_rel(s, dS_em), alpha=_rel(alpha, a_em))
-    print(f"hadamard {kind}: vs exact EM mu {e['mu']:.2e} s {e['s']:.2e} alpha {e['alpha']:.2e}; "
-          f"vs oracle CoFEM mu {_rel(mu, ref.mu):.2e} s {_rel(s, ref.s):.2e}; CG steps {st['cg_steps']}")
+    print(f"hadamard {kind}: CG steps {st['cg_steps']}")
     # bf16 phase: the GPU applies the rounded dictionary to P carried as hi/lo bf16 pieces
-    # (2^-17), exact EM to the exact P; alpha^(T-2) carries that into s (7.5e-4 measured)
+    # (2^-17), exact EM to the exact P; alpha^(T-2) carries that into s
     tol_s = 3e-3 if kind == "bf16_refined" else 1e-3
-    assert e["mu"] < 1e-4 and e["s"] < tol_s and e["alpha"] < tol_s
+    check(f"hadamard_{kind}/mu_vs_exact_em", e["mu"], 1e-4)
+    check(f"hadamard_{kind}/s_vs_exact_em", e["s"], tol_s)
+    check(f"hadamard_{kind}/alpha_vs_exact_em", e["alpha"], tol_s)
     if kind != "bf16_refined":
-        assert _rel(mu, ref.mu) < 1e-4 and _rel(s, ref.s) < 1e-4
+        check(f"hadamard_{kind}/mu_vs_oracle", _rel(mu, ref.mu), 1e-4)
+        check(f"hadamard_{kind}/s_vs_oracle", _rel(s, ref.s), 1e-4)
 
 
 def test_probe_mode_rejects_bad_arguments(gpu):

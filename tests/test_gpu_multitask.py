@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import workloads
+from bars import BF16_ROUNDED_MU, binds, check, fp32_fit_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -43,10 +44,9 @@ def test_multitask_matches_oracle(gpu, L):
     for l in range(L):
         mu, s, a, st = out[l]
         e_mu, e_s = _rel(_np(mu), mus_ref[l]), _rel(_np(s), ss_ref[l])
-        print(f"L={L} task {l}: mu rel {e_mu:.2e}, s rel {e_s:.2e}, CG steps {st['total_cg_steps']} "
-              f"(oracle {sum(r[l] for r in steps_ref)})")
-        assert e_mu <= 1e-4
-        assert e_s <= 1e-3
+        print(f"L={L} task {l}: CG steps {st['total_cg_steps']} (oracle {sum(r[l] for r in steps_ref)})")
+        check(f"multitask_L{L}/task{l}/mu", e_mu, 1e-4)
+        check(f"multitask_L{L}/task{l}/s", e_s, 1e-3)
         assert np.array_equal(_np(a), alpha)        # every task reports the shared alpha
     assert np.max(np.abs(np.log(alpha[sup] / a_ref[sup]))) < 1e-3
     if L == 1:
@@ -106,12 +106,12 @@ def test_multitask_concurrent_fit_is_deterministic(gpu):
 def test_multitask_conv_matches_oracle(gpu, dtype):
     """Multi-task fits on FIR dictionaries (each task its own filter and data, one shared
     alpha): FP32, and all-bf16 E-steps against the oracle on the bf16-rounded taps (the
-    right-hand side b formed from the same taps).  mu within 1e-4 (FP32) or 1e-3 (bf16:
-    the signals travel as hi/lo bf16 pairs), or twice the oracle's own change of mu
-    between tol and tol / 100, whichever is larger (the FIR systems are ill-conditioned)."""
+    right-hand side b formed from the same taps).  mu within 1e-4 (FP32) or the bf16 bound
+    (the signals travel as hi/lo bf16 pairs); tol 1e-8, where the oracle's own mu moves by
+    far less than that with the tolerance (the FIR systems are ill-conditioned)."""
     D, taps, L = 1200, 64, 2
     probs = [workloads.conv_problem(D, taps, tau, 0.02, 0.05, seed=64 + l) for l, tau in enumerate((20.0, 30.0))]
-    K, T, U, tol, seed = 8, 12, 400, 1e-6, 5
+    K, T, U, tol, seed = 8, 12, 600, 1e-8, 5
     kw = dict(phi_dtype="bf16", refine_last=0) if dtype == "bf16" else {}
     m = gpu.MultiTask(L, D, D, probs[0].beta, K=K, T=T, U=U, tol=tol, seed=seed, op="conv", conv_taps=taps, **kw)
     for l, p in enumerate(probs):
@@ -129,12 +129,11 @@ def test_multitask_conv_matches_oracle(gpu, dtype):
     ys = [p.y for p in probs]
     _, mus, ss, _ = oracle.cofem_multitask(ops, ys, probs[0].beta, T=T, K=K, U=U, tol=tol, seed=seed)
     _, mus_t, _, _ = oracle.cofem_multitask(ops, ys, probs[0].beta, T=T, K=K, U=U, tol=tol / 100, seed=seed)
-    bar = 1e-3 if dtype == "bf16" else 1e-4
+    bar = BF16_ROUNDED_MU if dtype == "bf16" else 1e-4
     for l in range(L):
-        e_mu, sens = _rel(_np(out[l][0]), mus[l]), _rel(mus[l], mus_t[l])
-        print(f"multi-task conv {dtype} task {l}: mu rel {e_mu:.2e} (sensitivity {sens:.2e}), "
-              f"s rel {_rel(_np(out[l][1]), ss[l]):.2e}")
-        assert e_mu <= max(bar, 2 * sens)
+        binds(f"multitask_conv_{dtype}/task{l}", _rel(mus[l], mus_t[l]), bar)
+        check(f"multitask_conv_{dtype}/task{l}/mu", _rel(_np(out[l][0]), mus[l]), bar)
+        check(f"multitask_conv_{dtype}/task{l}/s", _rel(_np(out[l][1]), ss[l]), 10 * bar)
 
 
 def test_multitask_dct_matches_oracle(gpu):
@@ -142,7 +141,8 @@ def test_multitask_dct_matches_oracle(gpu):
     data, one shared alpha; D = 2^11 takes the split DCT operator) against the oracle."""
     D, N, L = 2048, 682, 3
     probs = [workloads.dct_problem(D, N, 150, 0.01, seed=66 + l) for l in range(L)]
-    K, T, U, tol, seed = 8, 10, 400, 1e-6, 6
+    # tol 1e-9: at 1e-8 the oracle's mu still moves by 1.0e-5 with the tolerance here
+    K, T, U, tol, seed = 8, 10, 400, 1e-9, 6
     m = gpu.MultiTask(L, N, D, probs[0].beta, K=K, T=T, U=U, tol=tol, seed=seed, op="dct")
     for l, p in enumerate(probs):
         import torch
@@ -153,10 +153,12 @@ def test_multitask_dct_matches_oracle(gpu):
     m.close()
     ops = [oracle.DctOperator(D, p.rows) for p in probs]
     ys = [p.y for p in probs]
-    _, mus, ss, _ = oracle.cofem_multitask(ops, ys, probs[0].beta, T=T, K=K, U=U, tol=tol, seed=seed)
+    a_ref, mus, ss, _ = oracle.cofem_multitask(ops, ys, probs[0].beta, T=T, K=K, U=U, tol=tol, seed=seed)
     _, mus_t, _, _ = oracle.cofem_multitask(ops, ys, probs[0].beta, T=T, K=K, U=U, tol=tol / 100, seed=seed)
     for l in range(L):
-        e_mu, sens = _rel(_np(out[l][0]), mus[l]), _rel(mus[l], mus_t[l])
-        print(f"multi-task DCT task {l}: mu rel {e_mu:.2e} (sensitivity {sens:.2e}), "
-              f"s rel {_rel(_np(out[l][1]), ss[l]):.2e}")
-        assert e_mu <= max(1e-4, 2 * sens)
+        # E-step 1 (alpha = 1) solves a system with kappa ~ 1e4 here (N = D/3, theta = 1); its
+        # FP32 floor of about kappa 2^-24 is still partly in mu after 10 EM iterations
+        bar = fp32_fit_bar(ops[l].dense(), probs[0].beta, [np.ones(D), a_ref])
+        binds(f"multitask_dct/task{l}", _rel(mus[l], mus_t[l]), 1e-4)
+        check(f"multitask_dct/task{l}/mu", _rel(_np(out[l][0]), mus[l]), bar)
+        check(f"multitask_dct/task{l}/s", _rel(_np(out[l][1]), ss[l]), 10 * bar)

@@ -6,13 +6,15 @@ normwise error is a small multiple of sqrt(N + D) * 2^-24; the bfloat16
 operator applies the bf16-rounded dictionary exactly (integer-like products,
 FP32 accumulation) to right-hand sides carried as two bf16 pieces, i.e. to
 about 2^-17 relative precision.  Fits are compared at the same probes, stop
-rule and tolerance; the acceptance bar on mu is 1e-4 relative for FP32.
+rule and tolerance; the acceptance bar on mu is 1e-4 relative for FP32, and every
+bar also has a regression bound at 3x its measured value (tests/bars.py).
 """
 import numpy as np
 import pytest
 
 import oracle
 import workloads
+from bars import BF16_REFINED_MU, BF16_REFINED_S, BF16_ROUNDED_MU, BF16_ROUNDED_S, binds, check, fp32_solve_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -59,8 +61,7 @@ def test_apply_A_matches_oracle(gpu, N, D, ncols, dtype):
     Pt = P.T.astype(np.float64)
     ref = (beta * op.rmatvec(op.matvec(Pt)) + alpha.astype(np.float64)[:, None] * Pt).T
     tol = 2e-5 if dtype == "fp32" else 1e-4
-    for q in range(ncols):
-        assert _rel(Psi[q], ref[q]) < tol, (q, _rel(Psi[q], ref[q]))
+    check(f"apply_A/{dtype}/{N}x{D}x{ncols}", max(_rel(Psi[q], ref[q]) for q in range(ncols)), tol)
     # pi_q = sum_j P_jq Psi_jq, FP64 on the device over the device's own Psi
     pi_ref = np.sum(P.astype(np.float64) * Psi, axis=1)
     assert np.allclose(_np(pi), pi_ref, rtol=1e-10)
@@ -92,8 +93,7 @@ def test_fp32_operator_is_fp32_accurate(gpu, N, D, ncols):
     Pt = P.T.astype(np.float64)
     ref = (beta * op.rmatvec(op.matvec(Pt)) + alpha.astype(np.float64)[:, None] * Pt).T
     errs = [_rel(Psi[q], ref[q]) for q in range(ncols)]
-    print(f"FP32 operator N={N} D={D} ncols={ncols}: max column error {max(errs):.2e}")
-    assert max(errs) < 1e-6
+    check(f"apply_A/fp32_sliced/{N}x{D}x{ncols}", max(errs), 1e-6)
 
 
 # ---------------------------------------------------------------------------
@@ -113,6 +113,12 @@ def _oracle_fit(prob, w, phi=None, **kw):
     return oracle.cofem(phi, prob.y, prob.beta, T=w["T"], K=w["K"], U=w["U"], tol=w["tol"], **kw)
 
 
+def _sensitivity(prob, w, ref, phi=None, **kw):
+    """Relative change of the oracle's mu between tol and tol / 100."""
+    tight = _oracle_fit(prob, dict(w, tol=w["tol"] / 100), phi=phi, **kw)
+    return _rel(ref.mu, tight.mu)
+
+
 def _support(mu_ref):
     return np.abs(mu_ref) > 1e-3 * np.abs(mu_ref).max()
 
@@ -124,10 +130,10 @@ def test_fit_small_workload_fp32(gpu, stop):
     seed = 1234
     mu, s, alpha, st = _fit(gpu, prob, w, seed=seed, stop=stop)
     ref = _oracle_fit(prob, w, seed=seed, stop_mode=stop)
-    print("small", stop, "mu rel", _rel(mu, ref.mu), "s rel", _rel(s, ref.s),
-          "steps gpu/oracle", st["total_cg_steps"], sum(ref.cg_steps))
-    assert _rel(mu, ref.mu) <= 1e-4
-    assert _rel(s, ref.s) <= 1e-3
+    print("small", stop, "steps gpu/oracle", st["total_cg_steps"], sum(ref.cg_steps))
+    binds(f"small/{stop}", _sensitivity(prob, w, ref, seed=seed, stop_mode=stop), 1e-4)
+    check(f"small/{stop}/mu", _rel(mu, ref.mu), 1e-4)
+    check(f"small/{stop}/s", _rel(s, ref.s), 1e-3)
     sup = _support(ref.mu)
     assert np.max(np.abs(np.log(alpha[sup] / ref.alpha[sup]))) < 1e-3
     # FP32 rounding of the operator and of X, R, Pd slows CG down near tol = 1e-6 (a CPU
@@ -145,9 +151,9 @@ def test_fit_ragged_jacobi_fp32(gpu):
     w = dict(K=11, T=40, U=300, tol=1e-6)
     mu, s, alpha, st = _fit(gpu, prob, w, seed=9, theta="jacobi")
     ref = _oracle_fit(prob, w, seed=9, theta_mode="jacobi")
-    print("ragged jacobi mu rel", _rel(mu, ref.mu), "s rel", _rel(s, ref.s))
-    assert _rel(mu, ref.mu) <= 1e-4
-    assert _rel(s, ref.s) <= 1e-3
+    binds("ragged_jacobi", _sensitivity(prob, w, ref, seed=9, theta_mode="jacobi"), 1e-4)
+    check("ragged_jacobi/mu", _rel(mu, ref.mu), 1e-4)
+    check("ragged_jacobi/s", _rel(s, ref.s), 1e-3)
 
 
 def test_fit_t1_estep_probe_dependent(gpu):
@@ -158,7 +164,11 @@ def test_fit_t1_estep_probe_dependent(gpu):
     mu, s, alpha, st = _fit(gpu, prob, w, seed=31337)
     ref = _oracle_fit(prob, w, seed=31337)
     other = _oracle_fit(prob, w, seed=31338)
-    assert _rel(s, ref.s) < 1e-4
+    check("t1_estep/s", _rel(s, ref.s), 1e-4)
+    # at alpha = 1 the mu system has kappa ~ 9e4 (D - N directions held by alpha alone), so
+    # an FP32 solve of it is good to about kappa 2^-24 only; s is dominated by the
+    # well-determined directions and holds the 1e-4 bar
+    check("t1_estep/mu", _rel(mu, ref.mu), fp32_solve_bar(prob.phi, prob.beta, np.ones(prob.D)))
     assert _rel(other.s, ref.s) > 1e-2
     assert np.array_equal(alpha, np.ones(prob.D))
 
@@ -173,28 +183,37 @@ def test_fit_is_deterministic(gpu):
     assert a[3]["cg_steps"] == b[3]["cg_steps"]
 
 
+# T = 20 on the small workload: at tol 1e-6 the oracle's own mu still moves by 2e-4 with the
+# tolerance there, so these fits run at tol 1e-8, where it moves by far less than the bars
+BF16_SMALL = dict(T=20, tol=1e-8)
+
+
 def test_fit_bf16_matches_oracle_on_rounded_dictionary(gpu):
     """BF16 without refinement solves the problem of the bf16-rounded dictionary."""
-    w = dict(workloads.WORKLOADS["small"])
-    w["T"] = 20
+    w = dict(workloads.WORKLOADS["small"], **BF16_SMALL)
     prob = workloads.make_workload("small")
     mu, s, alpha, st = _fit(gpu, prob, w, seed=5, phi_dtype="bf16")
-    ref = _oracle_fit(prob, w, phi=_bf16_rne(prob.phi), seed=5)
-    print("bf16 vs rounded-dictionary oracle: mu rel", _rel(mu, ref.mu), "s rel", _rel(s, ref.s))
+    phi16 = _bf16_rne(prob.phi)
+    ref = _oracle_fit(prob, w, phi=phi16, seed=5)
     assert all(st["used_bf16"])
-    assert _rel(mu, ref.mu) <= 1e-3
-    assert _rel(s, ref.s) <= 1e-2
+    binds("bf16_rounded", _sensitivity(prob, w, ref, phi=phi16, seed=5), BF16_ROUNDED_MU)
+    check("bf16_rounded/mu", _rel(mu, ref.mu), BF16_ROUNDED_MU)
+    check("bf16_rounded/s", _rel(s, ref.s), BF16_ROUNDED_S)
 
 
 def test_fit_bf16_refined_against_fp32_oracle(gpu):
-    w = dict(workloads.WORKLOADS["small"])
-    w["T"] = 20
+    w = dict(workloads.WORKLOADS["small"], **BF16_SMALL)
     prob = workloads.make_workload("small")
     mu, s, alpha, st = _fit(gpu, prob, w, seed=5, phi_dtype="bf16", refine_last=3)
     ref = _oracle_fit(prob, w, seed=5)
-    print("bf16+3 refined vs fp32 oracle: mu rel", _rel(mu, ref.mu), "s rel", _rel(s, ref.s))
     assert st["used_bf16"] == [1] * 17 + [0] * 3
-    assert _rel(mu, ref.mu) <= 2e-2
+    binds("bf16_refined", _sensitivity(prob, w, ref, seed=5), BF16_REFINED_MU)
+    check("bf16_refined/mu", _rel(mu, ref.mu), BF16_REFINED_MU)
+    check("bf16_refined/s", _rel(s, ref.s), BF16_REFINED_S)
+    # without the FP32 E-steps the fit stays on the rounded dictionary's answer
+    mu16, _, _, _ = _fit(gpu, prob, w, seed=5, phi_dtype="bf16")
+    check("bf16_unrefined_vs_fp32_oracle/mu", _rel(mu16, ref.mu), 1e-2)
+    assert _rel(mu, ref.mu) < 0.1 * _rel(mu16, ref.mu)
 
 
 def test_fit_medium_workload_fp32(gpu):
@@ -208,10 +227,10 @@ def test_fit_medium_workload_fp32(gpu):
     e_mu, e_s = _rel(mu, ref["mu"]), _rel(s, ref["s"])
     sup = _support(ref["mu"])
     e_sup = _rel(mu[sup], ref["mu"][sup])
-    print(f"medium: mu rel {e_mu:.2e} (support {e_sup:.2e}), s rel {e_s:.2e}, CG steps {st['total_cg_steps']} "
+    print(f"medium: support mu rel {e_sup:.2e}, CG steps {st['total_cg_steps']} "
           f"(oracle {int(ref['cg_steps'].sum())})")
-    assert e_mu <= 1e-4
-    assert e_s <= 1e-3
+    check("medium/mu", e_mu, 1e-4)
+    check("medium/s", e_s, 1e-3)
 
 
 def test_fit_nonneg_mstep_matches_oracle(gpu):
@@ -224,10 +243,10 @@ def test_fit_nonneg_mstep_matches_oracle(gpu):
     gauss = _oracle_fit(prob, w, seed=5)
     e_mu, e_s = _rel(mu, ref.mu), _rel(s, ref.s)
     sup = _support(ref.mu)
-    print(f"nonneg fit: mu rel {e_mu:.2e}, s rel {e_s:.2e}; the Gaussian M-step's mu differs by "
-          f"{_rel(gauss.mu, ref.mu):.2e}")
-    assert e_mu <= 1e-4
-    assert e_s <= 1e-3
+    print(f"nonneg fit: the Gaussian M-step's mu differs by {_rel(gauss.mu, ref.mu):.2e}")
+    binds("nonneg_dense", _sensitivity(prob, w, ref, seed=5, mstep="nonneg"), 1e-4)
+    check("nonneg_dense/mu", e_mu, 1e-4)
+    check("nonneg_dense/s", e_s, 1e-3)
     assert np.max(np.abs(np.log(alpha[sup] / ref.alpha[sup]))) < 1e-3
     assert _rel(gauss.mu, ref.mu) > 10 * e_mu   # the M-step really changed the fit
 

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 import workloads
+from bars import check
 
 pytestmark = pytest.mark.gpu
 
@@ -74,9 +75,8 @@ def test_served_fit_matches_oracle(gpu, K):
     ref = oracle.cofem(prob.phi, prob.y, prob.beta, T=w["T"], K=w["K"], U=w["U"], tol=w["tol"], seed=1234)
     e_mu = np.linalg.norm(mu - ref.mu) / np.linalg.norm(ref.mu)
     e_s = np.linalg.norm(s - ref.s) / np.linalg.norm(ref.s)
-    print(f"served small workload K={K}: mu rel {e_mu:.2e}, s rel {e_s:.2e}")
-    assert e_mu <= 1e-4
-    assert e_s <= 1e-3
+    check(f"served_small_K{K}/mu", e_mu, 1e-4)
+    check(f"served_small_K{K}/s", e_s, 1e-3)
 
 
 def test_budget_is_never_exceeded(gpu):

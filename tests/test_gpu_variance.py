@@ -3,9 +3,11 @@ fixed alpha, Sigma = (beta Phi^T Phi + diag(alpha))^{-1}, from K * batches probe
 
 * Against `oracle.posterior_variance` at the same alpha (the oracle's own fitted
   alpha, rounded to FP32, so that CG converges as it does after a fit), probes,
-  stop rule and tolerance, on the dense, convolutional and
-  DCT dictionaries: s within 1e-4 or twice the oracle's own change between tol and
-  tol / 100, whichever is larger (the same bar as the fits).
+  stop rule and tolerance 1e-8 (where the oracle's own answer moves by far less than
+  the bar with the tolerance), on the dense, convolutional and DCT dictionaries: s
+  within 1e-4; mu within 1e-4 or 4 kappa 2^-24, whichever is larger (alpha after 8
+  EM iterations leaves the mu system with kappa up to 2.4e4, and an FP32 CG solve is
+  good to about kappa 2^-24 there; fits run to convergence have far smaller kappa).
 * Against the exact diag(Sigma) from the explicit inverse: the error of the GPU
   estimate falls as the probe count grows (Lemma 1: ~ 1 / sqrt(K * batches)).
 * alpha = NULL means the fit's alpha^(T): the same result as passing it, bitwise;
@@ -18,6 +20,7 @@ import pytest
 
 import oracle
 import workloads
+from bars import binds, check, fp32_solve_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +71,7 @@ def test_variance_matches_oracle(gpu, kind):
         prob = workloads.conv_problem(1200, 64, 20.0, 0.02, 0.05, seed=72)
     else:
         prob = workloads.dct_problem(1024, 341, 60, 0.01, seed=73)
-    K, tol, batches, seed = 16, 1e-6, 4, 77
+    K, tol, batches, seed = 16, 1e-8, 4, 77
     m, op = _model(gpu, kind, prob, K, tol)
     alpha = oracle.cofem(op, prob.y, prob.beta, T=8, K=K, U=400, tol=tol, seed=1).alpha.astype(np.float32)
     s, mu, st = m.variance(batches, seed=seed, alpha=_t(alpha))
@@ -78,11 +81,13 @@ def test_variance_matches_oracle(gpu, kind):
     tight_s, tight_mu, _ = oracle.posterior_variance(op, prob.y, prob.beta, alpha, K, batches, 400, tol / 100, seed)
     sens_s, sens_mu = _rel(ref_s, tight_s), _rel(ref_mu, tight_mu)
     e_s, e_mu = _rel(s, ref_s), _rel(mu, ref_mu)
-    print(f"variance {kind}: s rel {e_s:.2e} (sensitivity {sens_s:.2e}), mu rel {e_mu:.2e} ({sens_mu:.2e}); "
-          f"CG steps gpu {st['cg_steps']} oracle {ref_steps}")
+    print(f"variance {kind}: CG steps gpu {st['cg_steps']} oracle {ref_steps}")
     assert st["T"] == batches and len(st["cg_steps"]) == batches
-    assert e_s <= max(1e-4, 2 * sens_s)
-    assert e_mu <= max(1e-4, 2 * sens_mu)
+    binds(f"variance/{kind}/s", sens_s, 1e-4)
+    bar_mu = fp32_solve_bar(op.dense(), prob.beta, alpha)
+    binds(f"variance/{kind}/mu", sens_mu, bar_mu)
+    check(f"variance/{kind}/s", e_s, 1e-4)
+    check(f"variance/{kind}/mu", e_mu, bar_mu)
 
 
 def test_variance_converges_to_exact_diag_sigma(gpu):
