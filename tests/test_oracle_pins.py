@@ -183,6 +183,31 @@ def test_woodbury_equals_inverse():
     assert np.allclose(woodbury_sigma(phi, beta, alpha), Sig, rtol=1e-8, atol=1e-12)
 
 
+def test_log_evidence_by_bayes_rule_over_z():
+    """log p(y | alpha) without the N x N marginal covariance: for any z, Bayes' rule gives
+    log p(y) = log p(y | z) + log p(z) - log p(z | y), each a Gaussian density (noise
+    N(Phi z, I / beta), prior N(0, diag(alpha)^-1), posterior N(mu, Sigma) with Sigma the
+    explicit inverse of beta Phi^T Phi + diag(alpha) and mu = beta Sigma Phi^T y), evaluated
+    by scipy at two different z; and the scalar case N = D = 1 against the normal density
+    with variance 1 / beta + phi^2 / alpha."""
+    from scipy.stats import multivariate_normal, norm
+
+    phi, y, beta = _small_dense()
+    N, D = phi.shape
+    rng = np.random.default_rng(12)
+    alpha = np.exp(rng.uniform(-2, 6, D))
+    Sig = np.linalg.inv(beta * phi.T @ phi + np.diag(alpha))
+    mu = beta * Sig @ phi.T @ y
+    for z in (np.zeros(D), rng.standard_normal(D)):
+        via_z = (multivariate_normal(phi @ z, np.eye(N) / beta).logpdf(y)
+                 + multivariate_normal(np.zeros(D), np.diag(1.0 / alpha)).logpdf(z)
+                 - multivariate_normal(mu, Sig).logpdf(z))
+        assert log_evidence(phi, y, beta, alpha) == pytest.approx(via_z, rel=1e-9, abs=1e-7)
+    p1, y1, b1, a1 = np.array([[0.7]]), np.array([-1.3]), 4.0, np.array([2.5])
+    assert log_evidence(p1, y1, b1, a1) == pytest.approx(norm(0.0, math.sqrt(1 / b1 + 0.49 / 2.5)).logpdf(-1.3),
+                                                         rel=1e-12)
+
+
 def test_exact_em_increases_evidence():
     phi, y, beta = _small_dense()
     _, _, _, alphas = exact_em(phi, y, beta, T=25, record=True)
