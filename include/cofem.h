@@ -407,6 +407,14 @@ cofem_status cofem_server_step(cofem_server* s, int32_t* n_running, int32_t* n_p
 cofem_status cofem_server_poll(cofem_server* s, int64_t id, float* mu, float* s_out, float* alpha,
                                cofem_request_info* info);
 
+/*
+ * Withdraw request `id`: a pending request leaves the queue; a running one stops (its
+ * slot and workspace bytes are free for the next admission at once); a finished one's
+ * results are discarded.  The id is unknown afterwards.  Other requests are not
+ * affected (their results stay bitwise the same).  Errors: COFEM_EINVAL (unknown id).
+ */
+cofem_status cofem_server_cancel(cofem_server* s, int64_t id);
+
 /* Counters of the server (host struct). */
 cofem_status cofem_server_get_stats(cofem_server* s, cofem_server_stats* out);
 

@@ -32,7 +32,7 @@ EXPORTS = [
     "cofem_fit", "cofem_posterior", "cofem_variance", "cofem_apply_A", "cofem_conv_apply_A_static",
     "cofem_set_probe_mode", "cofem_set_timing", "cofem_get_timing",
     "cofem_server_create", "cofem_server_destroy", "cofem_server_submit", "cofem_server_step",
-    "cofem_server_poll", "cofem_server_get_stats",
+    "cofem_server_poll", "cofem_server_cancel", "cofem_server_get_stats",
     "cofem_mt_create", "cofem_mt_destroy", "cofem_mt_set_dictionary", "cofem_mt_set_dct_samples", "cofem_mt_fit",
     "cofem_mt_posterior",
 ]
@@ -127,6 +127,7 @@ def load() -> ctypes.CDLL:
         "cofem_server_step": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cofem_server_poll": (i32, [vp, i64, vp, vp, vp, ctypes.POINTER(RequestInfo)]),
         "cofem_server_get_stats": (i32, [vp, ctypes.POINTER(ServerStats)]),
+        "cofem_server_cancel": (i32, [vp, i64]),
         "cofem_mt_create": (i32, [ctypes.POINTER(Params), i32, vp, ctypes.POINTER(vp)]),
         "cofem_mt_destroy": (None, [vp]),
         "cofem_mt_set_dictionary": (i32, [vp, i32, vp]),
@@ -424,6 +425,12 @@ class Server:
                                         s.ctypes.data_as(ctypes.c_void_p), alpha.ctypes.data_as(ctypes.c_void_p),
                                         None))
         return mu, s, alpha, inf
+
+    def cancel(self, rid: int) -> None:
+        """Withdraw a pending, running or finished request (its id is unknown afterwards)."""
+        _check(load().cofem_server_cancel(self._h, int(rid)))
+        self._held.pop(rid, None)
+        self._D.pop(rid, None)
 
     def stats(self) -> dict:
         st = ServerStats()

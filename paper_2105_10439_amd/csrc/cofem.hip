@@ -382,6 +382,7 @@ void begin_fit(cofem_ctx* c, const float* y) {
   c->fitted = false;
   launch_state_reset(c->st, c->Q, c->stream);
   launch_copy_pad(y, p.N, c->Np, 0.0f, c->yv, c->stream);
+  launch_count_nonfinite(y, p.N, &c->st->nonfinite, c->stream);
   // b = beta Phi^T y, formed with the same dictionary as the operator of each phase: the
   // rounding residual of an FP32 b is not in the range of the bf16 Phi^T, and EM would
   // amplify it through the directions that only diag(alpha) constrains.
@@ -396,6 +397,17 @@ void begin_fit(cofem_ctx* c, const float* y) {
     if (c->need32) launch_rhs(c->phi32T, nullptr, dict_ld(c->Np, 4), c->Np, c->Dp, c->yv, p.beta, c->b32, c->stream);
     if (c->need16) launch_rhs(nullptr, c->phi16T, dict_ld(c->Np, 2), c->Np, c->Dp, c->yv, p.beta, c->b16, c->stream);
   }
+}
+
+// After an input was counted into the state (begin_fit, set_dictionary): COFEM_EINVAL if
+// it holds a NaN or an infinity, before any EM work uses it.
+cofem_status check_finite(cofem_ctx* c, const char* what) {
+  cofem_status rc = sync_state(c);
+  if (rc != COFEM_OK) return rc;
+  if (c->h_st->nonfinite > 0)
+    return fail(COFEM_EINVAL, std::string(what) + " has " + std::to_string(c->h_st->nonfinite) +
+                                  " non-finite entries (NaN or infinity)");
+  return COFEM_OK;
 }
 
 // Slices of Pd the producers write: hi/lo for the bf16 operator, hi/lo and the third
@@ -712,21 +724,27 @@ COFEM_API cofem_status cofem_set_dictionary(cofem_ctx* c, const float* phi) {
   if (!c || !phi) return fail(COFEM_EINVAL, "NULL argument");
   if (c->p.op_kind == COFEM_OP_DCT) return fail(COFEM_EINVAL, "a DCT dictionary is loaded by cofem_set_dct_samples");
   const double t0 = now_ms();
+  c->dict_loaded = false;
+  launch_state_reset(c->st, c->Q, c->stream);
   if (c->p.op_kind == COFEM_OP_CONV) {
+    launch_count_nonfinite(phi, c->p.conv_taps, &c->st->nonfinite, c->stream);
     launch_conv_setup(phi, c->p.conv_taps, c->p.D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->hp32, c->hp16,
                       c->theta, c->stream);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    cofem_status rc = check_finite(c, "the filter taps");
+    if (rc != COFEM_OK) return rc;
     c->dict_loaded = true;
     c->stats.ms_setup = now_ms() - t0;
     return COFEM_OK;
   }
+  launch_count_nonfinite(phi, c->p.N * c->p.D, &c->st->nonfinite, c->stream);
   launch_dict_layouts(phi, c->p.N, c->p.D, c->Np, c->Dp, c->g1_16.kchunk, c->phi32, c->phi32T, c->phi16, c->phi16T,
                       c->stream);
   // theta from the caller's FP32 matrix (b is formed per fit from the library's copies)
   launch_theta(phi, c->p.N, c->p.D, c->Dp, c->p.theta_mode == COFEM_THETA_JACOBI, c->theta, c->stream);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  cofem_status rc = check_finite(c, "the dictionary");
+  if (rc != COFEM_OK) return rc;
   c->dict_loaded = true;
   c->stats.ms_setup = now_ms() - t0;
   return COFEM_OK;
@@ -763,6 +781,8 @@ COFEM_API cofem_status cofem_fit(cofem_ctx* c, const float* y) {
   const double t0 = now_ms();
   const cofem_params& p = c->p;
   begin_fit(c, y);
+  cofem_status rc0 = check_finite(c, "y");
+  if (rc0 != COFEM_OK) return rc0;
   launch_fill(c->alpha, 1.0f, c->Dp, c->stream);
   for (int t = 1; t <= p.T; ++t) {
     cofem_status rc = run_estep(c, t, c->alpha);
@@ -1029,6 +1049,10 @@ COFEM_API cofem_status cofem_mt_fit(cofem_mt* m, const float* const* ys) {
   cofem_status rc = fork();
   if (rc != COFEM_OK) return rc;
   for (int l = 0; l < L; ++l) begin_fit(m->tasks[l], ys[l]);
+  for (int l = 0; l < L; ++l) {
+    const std::string what = "ys[" + std::to_string(l) + "]";
+    if ((rc = check_finite(m->tasks[l], what.c_str())) != COFEM_OK) return rc;
+  }
   launch_fill(alpha, 1.0f, c0->Dp, c0->stream);
   for (int t = 1; t <= p.T; ++t) {
     // the L E-steps run concurrently, one stream each, at the shared alpha

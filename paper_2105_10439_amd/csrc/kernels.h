@@ -37,6 +37,7 @@ struct CGState {
   int t;                // serving: current EM iteration (1-based)
   int total_steps;      // serving: CG steps over the fit
   int xpend;            // this step's update ran and left X += gamma P to the direction kernel
+  int nonfinite;        // non-finite entries found in the last checked input (y, Phi or taps)
 };
 
 struct SolveCfg {
@@ -85,6 +86,8 @@ void launch_rhs(const float* phi32T, const uint16_t* phi16T, int64_t ld, int64_t
 
 // x[0..n) = v.
 void launch_fill(float* x, float v, int64_t n, hipStream_t s);
+// *count += the number of entries of x[0..n) that are NaN or infinite.
+void launch_count_nonfinite(const float* x, int64_t n, int* count, hipStream_t s);
 // y[0..n) += a x[0..n).
 void launch_axpy(float* y, const float* x, float a, int64_t n, hipStream_t s);
 

@@ -96,6 +96,14 @@ __global__ void k_fill(float* x, float v, int64_t n) {
   if (i < n) x[i] = v;
 }
 
+__global__ __launch_bounds__(256) void k_count_nonfinite(const float* __restrict__ x, int64_t n,
+                                                         int* __restrict__ count) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad += __builtin_isfinite(x[i]) ? 0 : 1;
+  if (bad) atomicAdd(count, bad);
+}
+
 __global__ void k_axpy(float* __restrict__ y, const float* __restrict__ x, float a, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] += a * x[i];
@@ -534,6 +542,10 @@ void launch_pack_block(const float* src, int ncols, int64_t D, int Qp, int64_t D
 void launch_unpack_block(const float* src, int ncols, int64_t D, int64_t Dp, float* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack_block, dim3(cdiv(D, 256), (unsigned)ncols), dim3(256), 0, s, src, ncols, D, Dp,
                      dst);
+}
+void launch_count_nonfinite(const float* x, int64_t n, int* count, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>(cdiv(n, 256), 1), 4096);
+  hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)blocks), dim3(256), 0, s, x, n, count);
 }
 void launch_copy_pad(const float* src, int64_t n, int64_t np, float pad, float* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_pad, dim3(cdiv(np, 256)), dim3(256), 0, s, src, n, np, pad, dst);

@@ -651,6 +651,11 @@ COFEM_API cofem_status cofem_server_submit(cofem_server* s, const cofem_params* 
     s->stats.rejected++;
     return rc;
   }
+  for (int64_t i = 0; i < p->N; ++i)
+    if (!std::isfinite(y[i])) {
+      s->stats.rejected++;
+      return sfail(COFEM_EINVAL, "y[" + std::to_string(i) + "] is not finite");
+    }
   const SlotLayout L = layout_of(*p);
   if (L.total > s->arena.size) {
     s->stats.rejected++;
@@ -776,6 +781,26 @@ COFEM_API cofem_status cofem_server_poll(cofem_server* s, int64_t id, float* mu,
     if (alpha) std::memcpy(alpha, r.alpha.data(), bytes);
     if (mu) s->reqs.erase(it);
   }
+  return COFEM_OK;
+}
+
+COFEM_API cofem_status cofem_server_cancel(cofem_server* s, int64_t id) {
+  if (!s) return sfail(COFEM_EINVAL, "NULL server");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return sfail(COFEM_EINVAL, "unknown request id");
+  Request& r = it->second;
+  if (r.state == COFEM_REQ_PENDING) {
+    s->pending.erase(std::find(s->pending.begin(), s->pending.end(), id));
+  } else if (r.state == COFEM_REQ_RUNNING) {
+    // every cofem_server_step ends with the server's stream drained, so no kernel of this
+    // request is in flight: its slot and arena bytes can be handed back at once (the next
+    // tick's table leaves the slot out, and a later admission re-initialises it)
+    s->arena.release(r.off, r.bytes);
+    s->stats.bytes_in_use -= (int64_t)r.bytes;
+    s->slot_req[r.slot] = -1;
+    s->table_dirty = true;
+  }
+  s->reqs.erase(it);
   return COFEM_OK;
 }
 

@@ -88,6 +88,7 @@ MEASURED: dict[str, float] = {
     "conv_bf16_K31/mu": 3.429e-05,
     "conv_bf16_K31/s": 2.921e-05,
     "conv_bf16_refined/mu": 2.444e-03,
+    "conv_bf16_refined/s": 1.169e-02,
     "conv_bf16_rounded/mu": 3.277e-05,
     "conv_bf16_rounded/s": 9.326e-05,
     "conv_fit/jacobi/mu": 1.836e-05,
@@ -118,6 +119,8 @@ MEASURED: dict[str, float] = {
     "dct_fit/ones/s": 8.962e-05,
     "dct_full_sampling/mu": 1.026e-07,
     "dct_full_sampling/s": 3.185e-06,
+    "dct_nonneg/mu": 1.128e-03,
+    "dct_nonneg/s": 1.991e-03,
     "dct_workload/mu": 2.149e-06,
     "dct_workload/nrmse": 1.157e-02,
     "dct_workload/s": 9.586e-05,
@@ -156,6 +159,12 @@ MEASURED: dict[str, float] = {
     "multitask_conv_fp32/task0/s": 1.122e-05,
     "multitask_conv_fp32/task1/mu": 2.807e-06,
     "multitask_conv_fp32/task1/s": 1.141e-05,
+    "multitask_dct/task0/mu": 2.673e-04,
+    "multitask_dct/task0/s": 2.857e-04,
+    "multitask_dct/task1/mu": 2.885e-04,
+    "multitask_dct/task1/s": 2.770e-04,
+    "multitask_dct/task2/mu": 2.736e-04,
+    "multitask_dct/task2/s": 2.794e-04,
     "nonneg_dense/mu": 1.202e-06,
     "nonneg_dense/s": 9.115e-05,
     "ragged_jacobi/mu": 5.791e-07,

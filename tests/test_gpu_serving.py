@@ -6,7 +6,10 @@
 * a served fit matches the FP64 oracle to the same bar as a single fit;
 * admission never exceeds the memory budget; a request larger than the whole
   budget is rejected;
-* requests that arrive while others run are admitted and overlap with them.
+* requests that arrive while others run are admitted and overlap with them;
+* cancelling a pending or a running request frees its queue place, slot and bytes
+  at once and leaves the other requests' results bitwise unchanged;
+* an observation with a NaN is rejected at submission.
 """
 import numpy as np
 import pytest
@@ -137,4 +140,51 @@ def test_arrivals_overlap_running_requests(gpu):
     # the later requests were admitted while the first was still running
     assert all(infos[r]["t_admit_ms"] < infos[first]["t_finish_ms"] for r in later)
     assert srv.stats()["max_active"] == len(probs)
+    srv.close()
+
+
+def test_cancel_pending_and_running_requests(gpu):
+    probs = [_req(D, 80 + i) for i, D in enumerate([700, 900, 1100, 1300])]
+    kw = dict(K=8, T=6, U=300, tol=1e-5, seed=17)
+    alone = [_run(gpu, [p], kw)[0][0] for p in (probs[0], probs[3])]
+    srv = gpu.Server(GiB, max_slots=2, steps_per_tick=2)
+    ids = [srv.submit(p.phi, p.y, beta=p.beta, **kw) for p in probs]
+    srv.step()                                   # two slots: requests 0 and 1 run, 2 and 3 wait
+    assert [srv.info(r)["state"] for r in ids] == ["running", "running", "pending", "pending"]
+    before = srv.stats()["bytes_in_use"]
+    b1 = srv.info(ids[1])["bytes"]
+    srv.cancel(ids[1])                           # running: its slot and bytes come back at once
+    assert srv.stats()["bytes_in_use"] == before - b1
+    srv.cancel(ids[2])                           # pending: leaves the queue
+    for r in (ids[1], ids[2]):
+        with pytest.raises(gpu.CofemError) as e:
+            srv.info(r)
+        assert e.value.status == -1
+    out = {}
+    for _ in range(100000):
+        srv.step()
+        for i in (0, 3):
+            if i not in out:
+                res = srv.result(ids[i])
+                if res is not None:
+                    out[i] = res
+        if len(out) == 2:
+            break
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 2 and st["bytes_in_use"] == 0 and st["admitted"] == 3
+    for k, i in enumerate((0, 3)):
+        for a, b in zip(out[i][:3], alone[k][:3]):
+            assert np.array_equal(a, b), f"request {i} changed by the cancellations"
+
+
+def test_submit_rejects_non_finite_observation(gpu):
+    p = _req(512, 5)
+    y = p.y.copy()
+    y[7] = np.nan
+    srv = gpu.Server(GiB, max_slots=2)
+    with pytest.raises(gpu.CofemError) as e:
+        srv.submit(p.phi, y, beta=p.beta, K=8, T=2, U=10, tol=1e-5)
+    assert e.value.status == -1 and "y[7]" in str(e.value)
+    assert srv.stats()["rejected"] == 1
     srv.close()
