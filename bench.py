@@ -20,8 +20,11 @@ Prints one JSON line.  `value` is EM iterations per second.  Beside it:
   serving       the continuous-batching server on a stream of independent
                 requests (D uniform in [512, 16384], N = D/4, 5 % spikes, sigma in
                 {0.01, 0.05}, K = 16, T = 30, FP32): saturated request rate from a
-                pilot batch, then Poisson arrivals at 0.8x that rate; p50/p99 latency
-                from submission to completion.
+                pilot batch, then Poisson arrivals at 0.8x that rate (the 512-request
+                stream) and at 0.5x and 0.95x (shorter streams); p50/p99 latency from
+                submission to completion; the serving contraction's dictionary bytes
+                (CG steps x 2 passes x N D x 4 per request) over the device time of
+                the ticks, against 8 TB/s.
 """
 from __future__ import annotations
 
@@ -84,15 +87,17 @@ def gemm_traffic(N: int, D: int, dom: str):
 
 
 def stream_peaks():
-    """Measured HBM rate on this GPU for context: a 1 GiB device copy (read + write bytes),
-    best of 10, timed with events."""
+    """Measured HBM rates on this GPU for context, best of 10, timed with events: a 1 GiB
+    device copy (read + write bytes) and a read-only stream, a sum over 2 GiB (torch's
+    reduction; read bytes only)."""
     import torch
 
     n = (1 << 30) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
+    big = torch.ones(2 * n, dtype=torch.float32, device="cuda")
     res = {}
-    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 2 * 4 * n),):
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 2 * 4 * n), ("read", lambda: big.sum(), 8 * n)):
         fn()
         best = None
         for _ in range(10):
@@ -104,7 +109,7 @@ def stream_peaks():
             ms = e0.elapsed_time(e1)
             best = ms if best is None else min(best, ms)
         res[name] = round(nbytes / (best * 1e-3) / 1e9, 1)
-    del a, b
+    del a, b, big
     torch.cuda.empty_cache()
     return res
 
@@ -126,6 +131,9 @@ def parse():
     ap.add_argument("--serve-pilot", type=int, default=32, help="requests of the saturation pilot")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--serve-side-loads", default="0.5,0.95",
+                    help="further load points, as fractions of saturation ('' for none)")
+    ap.add_argument("--serve-side-requests", type=int, default=160, help="requests per further load point")
     ap.add_argument("--no-conv", action="store_true", help="skip the convolutional-dictionary fits")
     ap.add_argument("--conv-only", action="store_true", help="only the convolutional-dictionary fits (for profiling)")
     ap.add_argument("--no-dct", action="store_true", help="skip the DCT-dictionary fits")
@@ -308,7 +316,8 @@ def main():
         roof.update(traffic_read=round(traf["read"]), traffic_write=round(traf["write"]),
                     traffic_over_algorithmic=round(traf["total"] / nbytes_launch[dom], 4))
     peaks = stream_peaks()
-    roof.update(measured_copy_gbps=peaks["copy"], frac_of_measured_copy=round(ops[dom]["gbps"] / peaks["copy"], 4))
+    roof.update(measured_copy_gbps=peaks["copy"], frac_of_measured_copy=round(ops[dom]["gbps"] / peaks["copy"], 4),
+                measured_read_gbps=peaks["read"], frac_of_measured_read=round(ops[dom]["gbps"] / peaks["read"], 4))
     log(f"measured stream rates: {peaks}")
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "EM-iters/s", "n_gpus": 1, "steps": args.steps,
@@ -372,7 +381,10 @@ def conv_bench():
     bytes_app = 20.0 * D * Q + 4.0 * D
     peak = {"bf16": 2500.0, "fp32": 157.3}
     res = dict(workload=f"causal FIR dictionary: D=N={D}, {L} taps of exp(-t/{w['tau']:g}), Bernoulli({w['p']})*Exp(1) "
-                        f"spikes, sigma={w['sigma']}, K={w['K']} T={w['T']} tol={w['tol']} U={w['U']}")
+                        f"spikes, sigma={w['sigma']}, K={w['K']} T={w['T']} tol={w['tol']} U={w['U']}",
+               signal_storage="bf16 forms: taps rounded to bf16; the signals P and V travel as hi/lo bf16 pairs "
+                              "(4 bytes per value, the bytes of FP32), so the bf16 gain is the matrix rate, not "
+                              "halved signal traffic")
     z = torch.from_numpy(prob.z)
     for name, dt, refine, mstep in (("bf16_refined", "bf16", 3, "gaussian"), ("fp32", "fp32", 0, "gaussian"),
                                     ("bf16_refined_nonneg", "bf16", 3, "nonneg")):
@@ -573,52 +585,72 @@ def serving(args):
     del items
     log(f"serving pilot: {len(ids)} requests in {sat_s:.2f}s = {sat_rps:.2f} req/s")
 
-    # 2. Poisson arrivals at a fraction of saturation
-    rate = args.serve_load * sat_rps
-    arrivals = workloads.poisson_arrivals(len(descs), rate, seed=777)
-    prep = Prepared(descs)
-    srv = lib.Server(budget, max_slots=128, steps_per_tick=4)
-    ids, done = [], {}
-    nxt = prep.get()
-    k = 0
-    late = 0.0
-    t0 = time.perf_counter()
-    last_log = t0
-    while len(done) < len(descs):
-        now = time.perf_counter() - t0
-        while nxt is not None and k < len(descs) and arrivals[k] <= now:
-            late = max(late, now - arrivals[k])
-            ids.append(submit(srv, *nxt))
-            k += 1
-            nxt = prep.get() if k < len(descs) else None
-        running, pending = srv.step()
-        drain(srv, ids, done)
-        if running == 0 and pending == 0 and k < len(descs):
-            time.sleep(max(0.0, min(0.002, arrivals[k] - (time.perf_counter() - t0))))
-        if time.perf_counter() - last_log > 10:
-            last_log = time.perf_counter()
-            log(f"serving: {len(done)}/{len(descs)} done, {running} running, {pending} pending")
-    el = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    lat = np.array([inf["t_finish_ms"] - inf["t_submit_ms"] for inf in done.values()])
-    steps = sum(inf["total_cg_steps"] for inf in done.values())
-    res = dict(requests=len(descs), workload="dense Gaussian requests, D uniform in [512, 16384], N = D/4, 5% spikes, "
-                                             "sigma in {0.01, 0.05}, K=16, T=30, tol=1e-5, FP32",
-               budget_gib=args.serve_budget_gib, saturated_rps=round(sat_rps, 3), arrival_rps=round(rate, 3),
-               throughput_rps=round(len(descs) / el, 3), em_iters_per_s=round(len(descs) * SERVE_KW["T"] / el, 2),
-               p50_ms=round(float(np.percentile(lat, 50)), 2), p99_ms=round(float(np.percentile(lat, 99)), 2),
-               mean_ms=round(float(lat.mean()), 2), max_active=st["max_active"], ticks=st["ticks"],
-               cg_steps_total=int(steps), max_submit_delay_ms=round(1e3 * late, 1),
-               bytes_peak_gib=round(st["bytes_peak"] / (1 << 30), 3))
-    log(f"serving: {res}")
+    # 2. Poisson arrivals at fractions of saturation
+    def stream(load, descs, seed):
+        rate = load * sat_rps
+        arrivals = workloads.poisson_arrivals(len(descs), rate, seed=seed)
+        prep = Prepared(descs)
+        srv = lib.Server(budget, max_slots=128, steps_per_tick=4)
+        ids, done = [], {}
+        nxt = prep.get()
+        k = 0
+        late = 0.0
+        t0 = time.perf_counter()
+        last_log = t0
+        while len(done) < len(descs):
+            now = time.perf_counter() - t0
+            while nxt is not None and k < len(descs) and arrivals[k] <= now:
+                late = max(late, now - arrivals[k])
+                ids.append(submit(srv, *nxt))
+                k += 1
+                nxt = prep.get() if k < len(descs) else None
+            running, pending = srv.step()
+            drain(srv, ids, done)
+            if running == 0 and pending == 0 and k < len(descs):
+                time.sleep(max(0.0, min(0.002, arrivals[k] - (time.perf_counter() - t0))))
+            if time.perf_counter() - last_log > 10:
+                last_log = time.perf_counter()
+                log(f"serving at {load}x: {len(done)}/{len(descs)} done, {running} running, {pending} pending")
+        el = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array([inf["t_finish_ms"] - inf["t_submit_ms"] for inf in done.values()])
+        steps = sum(inf["total_cg_steps"] for inf in done.values())
+        gbps = st["dict_bytes"] / (st["tick_ms"] * 1e-3) / 1e9
+        res = dict(load=load, requests=len(descs), arrival_rps=round(rate, 3),
+                   throughput_rps=round(len(descs) / el, 3), em_iters_per_s=round(len(descs) * SERVE_KW["T"] / el, 2),
+                   p50_ms=round(float(np.percentile(lat, 50)), 2), p99_ms=round(float(np.percentile(lat, 99)), 2),
+                   mean_ms=round(float(lat.mean()), 2), max_active=st["max_active"], ticks=st["ticks"],
+                   cg_steps_total=int(steps), max_submit_delay_ms=round(1e3 * late, 1),
+                   bytes_peak_gib=round(st["bytes_peak"] / (1 << 30), 3),
+                   tick_device_s=round(st["tick_ms"] * 1e-3, 2), busy_frac=round(st["tick_ms"] * 1e-3 / el, 3),
+                   dict_gbps_over_ticks=round(gbps, 1))
+        log(f"serving at {load}x: {res}")
+        return res
+
+    main_pt = stream(args.serve_load, descs, 777)
+    side = []
+    for i, ld in enumerate(float(x) for x in args.serve_side_loads.split(",") if x.strip()):
+        side.append(stream(ld, descs[:min(args.serve_side_requests, len(descs))], 778 + i))
+    res = dict(main_pt, workload="dense Gaussian requests, D uniform in [512, 16384], N = D/4, 5% spikes, "
+                                 "sigma in {0.01, 0.05}, K=16, T=30, tol=1e-5, FP32",
+               budget_gib=args.serve_budget_gib, saturated_rps=round(sat_rps, 3))
+    res["roofline"] = dict(bound="hbm", kernel="serving tick (ks_gemm and the vector kernels)",
+                           achieved=main_pt["dict_gbps_over_ticks"], peak=HBM_PEAK_GBPS, unit="GB/s",
+                           frac=round(main_pt["dict_gbps_over_ticks"] / HBM_PEAK_GBPS, 4),
+                           note="dictionary bytes of the completed fits' CG steps (2 passes x N D x 4 each) over "
+                                "the device time of every tick, so the other kernels of a tick count against it")
+    res["load_points"] = [dict((k, p[k]) for k in ("load", "requests", "arrival_rps", "throughput_rps", "p50_ms",
+                                                   "p99_ms", "max_active", "dict_gbps_over_ticks"))
+                          for p in sorted([main_pt] + side, key=lambda p: p["load"])]
     return res
 
 
 def cpu_baseline(prob, w, st, cg_steps):
     """The FP64 oracle on a bounded sample: one E-step capped at `cg_steps` CG
     steps (tol = 0 so it runs them all), scaled to EM iterations/s with the
-    mean CG steps per EM iteration of the GPU fit on the same workload."""
+    oracle's own mean CG steps per EM iteration on this workload (from its stored
+    full fit, tests/golden/large_oracle.npz), or the GPU fit's when that is absent."""
     import numpy as np
 
     import oracle
@@ -631,13 +663,19 @@ def cpu_baseline(prob, w, st, cg_steps):
     oracle.cofem(op, prob.y, prob.beta, T=1, K=w["K"], U=cg_steps, tol=0.0, seed=2024)
     el = time.perf_counter() - t1
     per_step = el / cg_steps
-    mean_steps = st["total_cg_steps"] / max(st["T"], 1)
+    golden = os.path.join(ROOT, "tests", "golden", "large_oracle.npz")
+    if prob.N == 16384 and prob.D == 65536 and os.path.exists(golden):
+        g = np.load(golden)
+        mean_steps = float(g["cg_steps"].mean())
+        whose = f"the oracle's own mean {mean_steps:.1f} CG steps per EM iteration (its stored full fit)"
+    else:
+        mean_steps = st["total_cg_steps"] / max(st["T"], 1)
+        whose = f"the GPU fit's mean {mean_steps:.1f} CG steps per EM iteration"
     v = 1.0 / (per_step * mean_steps)
     log(f"cpu baseline: {cg_steps} CG steps in {el:.1f}s ({per_step:.3f}s/step), widening {t_conv:.1f}s")
     return dict(value=round(v, 5), unit="EM-iters/s", cores=threads, kind="oracle",
-                sample=f"one E-step of the same workload capped at {cg_steps} CG steps ({el:.1f}s), scaled by the "
-                       f"GPU fit's mean {mean_steps:.1f} CG steps per EM iteration; NumPy FP64 with {threads} BLAS "
-                       f"threads")
+                sample=f"one E-step of the same workload capped at {cg_steps} CG steps ({el:.1f}s), scaled by "
+                       f"{whose}; NumPy FP64 with {threads} BLAS threads")
 
 
 if __name__ == "__main__":

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define COFEM_ABI_VERSION 5
+#define COFEM_ABI_VERSION 6
 #define COFEM_MAX_T 512 /* longest EM run recorded in cofem_stats */
 #define COFEM_MAX_K 63  /* probes per EM iteration (one 64-bit hash word per coordinate) */
 
@@ -367,6 +367,9 @@ typedef struct cofem_server_stats {
   int64_t bytes_in_use;  /* arena bytes held by running fits */
   int64_t bytes_peak;    /* never above budget */
   int64_t budget;
+  double tick_ms;        /* device time of the ticks' kernel sequences (events around each) */
+  double dict_bytes;     /* dictionary bytes the completed fits' CG steps read by algorithm:
+                            sum over them of (CG steps) x 2 passes x N D x 4 bytes */
 } cofem_server_stats;
 
 /*

@@ -23,7 +23,7 @@ OPS = {"dense": 0, "conv": 1, "dct": 2}
 DTYPES = {"fp32": 0, "bf16": 1}
 MSTEP = {"gaussian": 0, "nonneg": 1}
 PROBE_MODES = {"hash": 0, "hadamard": 1}
-ABI_VERSION = 5  # COFEM_ABI_VERSION of include/cofem.h
+ABI_VERSION = 6  # COFEM_ABI_VERSION of include/cofem.h
 
 # every symbol include/cofem.h declares
 EXPORTS = [
@@ -90,7 +90,7 @@ class ServerStats(ctypes.Structure):
         ("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
         ("rejected", ctypes.c_int64), ("ticks", ctypes.c_int64), ("active", ctypes.c_int32),
         ("max_active", ctypes.c_int32), ("bytes_in_use", ctypes.c_int64), ("bytes_peak", ctypes.c_int64),
-        ("budget", ctypes.c_int64),
+        ("budget", ctypes.c_int64), ("tick_ms", ctypes.c_double), ("dict_bytes", ctypes.c_double),
     ]
 
 

@@ -426,6 +426,7 @@ struct cofem_server {
   int64_t next_id = 1;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  hipEvent_t ev_tick[2] = {nullptr, nullptr};  // around each tick's graph launch
   bool table_dirty = true;
   double t0 = 0;
   cofem_server_stats stats{};
@@ -491,6 +492,8 @@ void destroy_server(cofem_server* s) {
   if (s->d_phase) (void)hipFree(s->d_phase);
   if (s->d_ctr) (void)hipFree(s->d_ctr);
   if (s->h_phase) (void)hipHostFree(s->h_phase);
+  for (hipEvent_t e : s->ev_tick)
+    if (e) (void)hipEventDestroy(e);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
 }
@@ -626,6 +629,11 @@ COFEM_API cofem_status cofem_server_create(size_t hbm_budget, int32_t max_slots,
     s->h_phase = nullptr;
     return bail(COFEM_ENOMEM, "pinned allocation failed");
   }
+  for (hipEvent_t& e : s->ev_tick)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      return bail(COFEM_EDEVICE, "event creation failed");
+    }
   rebuild_table(s);
   if (hipMemcpyAsync(s->d_table, &s->h_table, sizeof(SrvTable), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
       hipStreamSynchronize(s->stream) != hipSuccess)
@@ -714,9 +722,14 @@ COFEM_API cofem_status cofem_server_step(cofem_server* s, int32_t* n_running, in
   s->stats.active = n;
   s->stats.max_active = std::max(s->stats.max_active, n);
   if (n > 0) {
+    SRV_TRY(hipEventRecord(s->ev_tick[0], s->stream));
     SRV_TRY(hipGraphLaunch(s->exec, s->stream));
+    SRV_TRY(hipEventRecord(s->ev_tick[1], s->stream));
     SRV_TRY(hipMemcpyAsync(s->h_phase, s->d_phase, sizeof(int) * n, hipMemcpyDeviceToHost, s->stream));
     SRV_TRY(hipStreamSynchronize(s->stream));
+    float tick_ms = 0.0f;
+    SRV_TRY(hipEventElapsedTime(&tick_ms, s->ev_tick[0], s->ev_tick[1]));
+    s->stats.tick_ms += tick_ms;
     s->stats.ticks++;
     for (int k = 0; k < n; ++k) {
       if (s->h_phase[k] != PH_DONE) continue;
@@ -735,6 +748,7 @@ COFEM_API cofem_status cofem_server_step(cofem_server* s, int32_t* n_running, in
       SRV_TRY(hipMemcpyAsync(&st, sd.st, sizeof(CGState), hipMemcpyDeviceToHost, s->stream));
       SRV_TRY(hipStreamSynchronize(s->stream));
       r.total_steps = st.total_steps;
+      s->stats.dict_bytes += (double)st.total_steps * 2.0 * (double)r.p.N * (double)r.p.D * sizeof(float);
       r.state = COFEM_REQ_DONE;
       r.t_finish = wall_ms() - s->t0;
       s->arena.release(r.off, r.bytes);

@@ -104,7 +104,7 @@ def test_null_arguments_are_rejected():
     assert so.cofem_set_probe_mode(None, 1) == -1
     assert so.cofem_posterior(None, None, None, None, None) == -1
     so.cofem_destroy(None)
-    assert so.cofem_abi_version() == 5
+    assert so.cofem_abi_version() == 6
 
 
 def test_server_rejects_bad_arguments_without_device_work():
