@@ -263,9 +263,9 @@ def main():
     y_d = torch.from_numpy(prob.y).cuda()
     torch.cuda.synchronize()
 
-    def run(phi_dtype, refine_last, steps, warmup, timing, var_batches=0):
+    def run(phi_dtype, refine_last, steps, warmup, timing, var_batches=0, theta="ones"):
         m = lib.CoFEM(prob.N, prob.D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024,
-                      phi_dtype=phi_dtype, refine_last=refine_last)
+                      phi_dtype=phi_dtype, refine_last=refine_last, theta=theta)
         for i in range(warmup):
             m.set_dictionary(phi_d)
             m.fit(y_d)
@@ -332,6 +332,9 @@ def main():
         "cg_steps_per_fit": st["total_cg_steps"],
         "cg_steps_per_em_iter": st["cg_steps"],
         "posterior_variance": run.var,
+        "arithmetic": "operator: bf16 (or FP32) dictionary, FP32 accumulation; CG dot products, gamma, eta, rho, pi "
+                      "and the stop test in FP64; X, R, P, Psi stored in FP32, their element-wise updates computed "
+                      "in FP64 and rounded to FP32",
     }
     if not args.no_fp32 and args.workload == "large":
         el32, st32, tim32, mu32 = run("fp32", 0, 1, 0, True)
@@ -343,6 +346,12 @@ def main():
                                (torch.linalg.vector_norm(mu.double() - mu32.double()) /
                                 torch.linalg.vector_norm(mu32.double())).item()))
         log(f"fp32 comparison fit: {out['fp32']}")
+    if args.workload == "large":
+        # the Jacobi preconditioner of Sec. III-C (theta_j = ||Phi_:j||^2) beside the default theta = 1
+        elj, stj, _, _ = run("bf16", refine, 1, 0, False, theta="jacobi")
+        out["jacobi"] = dict(em_iters_per_s=round(w["T"] / elj, 3), cg_steps=stj["total_cg_steps"],
+                             cg_steps_per_em_iter=stj["cg_steps"], theta_ones_cg_steps=st["total_cg_steps"])
+        log(f"jacobi fit: {out['jacobi']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, w, st, args.cpu_steps)
     del phi_d, y_d, prob
@@ -386,10 +395,12 @@ def conv_bench():
                               "(4 bytes per value, the bytes of FP32), so the bf16 gain is the matrix rate, not "
                               "halved signal traffic")
     z = torch.from_numpy(prob.z)
-    for name, dt, refine, mstep in (("bf16_refined", "bf16", 3, "gaussian"), ("fp32", "fp32", 0, "gaussian"),
-                                    ("bf16_refined_nonneg", "bf16", 3, "nonneg")):
+    for name, dt, refine, mstep, theta in (("bf16_refined", "bf16", 3, "gaussian", "ones"),
+                                           ("fp32", "fp32", 0, "gaussian", "ones"),
+                                           ("bf16_refined_nonneg", "bf16", 3, "nonneg", "ones"),
+                                           ("bf16_refined_jacobi", "bf16", 3, "gaussian", "jacobi")):
         m = lib.CoFEM(D, D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024, op="conv",
-                      conv_taps=L, phi_dtype=dt, refine_last=refine, mstep=mstep)
+                      conv_taps=L, phi_dtype=dt, refine_last=refine, mstep=mstep, theta=theta)
         if dt == "bf16":
             m.set_dictionary(h_d)
             m.fit(y_d)
@@ -416,6 +427,7 @@ def conv_bench():
         res[name] = dict(em_iters_per_s=round(w["T"] / el, 3), ms_per_fit=round(1e3 * el, 1),
                          cg_steps=st["total_cg_steps"], ms_per_cg_step=round(1e3 * el / st["total_cg_steps"], 4),
                          nrmse=round(nrmse, 4), passes=passes)
+        res[name]["cg_steps_per_em_iter"] = st["cg_steps"]
         log(f"conv {name}: {res[name]}")
     return res
 
