@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define COFEM_ABI_VERSION 6
+#define COFEM_ABI_VERSION 7
 #define COFEM_MAX_T 512 /* longest EM run recorded in cofem_stats */
 #define COFEM_MAX_K 63  /* probes per EM iteration (one 64-bit hash word per coordinate) */
 
@@ -286,25 +286,49 @@ typedef struct cofem_mt cofem_mt;
 
 #define COFEM_MAX_TASKS 64
 
+/* How the L E-steps of an EM iteration run (cofem_mt_create_mode). */
+#define COFEM_MT_AUTO 0    /* batched when the settings allow it, else streams */
+#define COFEM_MT_STREAMS 1 /* one context per task, each on its own stream */
+#define COFEM_MT_BATCHED 2 /* all tasks' systems together, one launch per phase */
+
 /*
  * Validate *p (the shape N x D and the settings every task shares; mstep_mode must
- * be COFEM_MSTEP_GAUSSIAN), allocate L task workspaces on the current device and
- * bind them to `stream`: task 0 runs on `stream`, every other task on a stream the
- * library creates (and destroys with the handle); the loading calls and cofem_mt_fit
- * order them after `stream` at their start and cofem_mt_fit orders `stream` after them
- * at its end, so the caller sees the fit's work on `stream` alone.  Dense, FIR and
- * subsampled-DCT dictionaries.  1 <= L <= COFEM_MAX_TASKS.
- * Errors: COFEM_EINVAL, COFEM_ENOMEM, COFEM_EDEVICE.
+ * be COFEM_MSTEP_GAUSSIAN) and allocate L task workspaces on the current device.
+ *
+ * COFEM_MT_BATCHED solves the L (K + 1) systems of an EM iteration together, as
+ * Sec. III-E.1 describes: every CG step of every task is one launch per phase (the
+ * operator's two contractions over all tasks' tiles, the vector kernels over all
+ * tasks' columns), captured as a graph of 8 CG steps; each task keeps its own stop
+ * rule (Algorithm 2 per task), and the joint M-step runs on the device once every
+ * task's E-step has ended, so the tasks advance through the EM iterations together.
+ * It takes dense FP32 dictionaries (op_kind COFEM_OP_DENSE, phi_dtype
+ * COFEM_PHI_FP32), refine_last 0 and K <= 31; all work runs on `stream`.
+ *
+ * COFEM_MT_STREAMS runs one context per task: task 0 on `stream`, every other task on
+ * a stream the library creates (and destroys with the handle); the loading calls and
+ * cofem_mt_fit order them after `stream` at their start and cofem_mt_fit orders
+ * `stream` after them at its end, so the caller sees the fit's work on `stream` alone.
+ * Dense, FIR and subsampled-DCT dictionaries, every precision form.
+ *
+ * COFEM_MT_AUTO takes the batched form when *p allows it.  1 <= L <= COFEM_MAX_TASKS.
+ * Errors: COFEM_EINVAL (bad parameters or mode, or COFEM_MT_BATCHED with settings it
+ * does not take), COFEM_ENOMEM, COFEM_EDEVICE.
  */
+cofem_status cofem_mt_create_mode(const cofem_params* p, int32_t L, int32_t mode, void* stream, cofem_mt** out);
+
+/* cofem_mt_create_mode with COFEM_MT_AUTO. */
 cofem_status cofem_mt_create(const cofem_params* p, int32_t L, void* stream, cofem_mt** out);
+
+/* 1 if the handle runs the batched form, 0 otherwise (NULL: 0). */
+int32_t cofem_mt_batched(const cofem_mt* m);
 
 /* Free the tasks and their workspaces (NULL is a no-op). */
 void cofem_mt_destroy(cofem_mt* m);
 
 /* Load task `task`'s dictionary (as cofem_set_dictionary).  Errors: COFEM_EINVAL, COFEM_EDEVICE. */
 cofem_status cofem_mt_set_dictionary(cofem_mt* m, int32_t task, const float* phi);
-/* Load task `task`'s kept DCT samples (as cofem_set_dct_samples; op_kind COFEM_OP_DCT).
- * Errors: COFEM_EINVAL, COFEM_EDEVICE. */
+/* Load task `task`'s kept DCT samples (as cofem_set_dct_samples; op_kind COFEM_OP_DCT;
+ * the streams form only).  Errors: COFEM_EINVAL, COFEM_EDEVICE. */
 cofem_status cofem_mt_set_dct_samples(cofem_mt* m, int32_t task, const int32_t* rows);
 
 /*

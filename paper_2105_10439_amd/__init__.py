@@ -23,7 +23,7 @@ OPS = {"dense": 0, "conv": 1, "dct": 2}
 DTYPES = {"fp32": 0, "bf16": 1}
 MSTEP = {"gaussian": 0, "nonneg": 1}
 PROBE_MODES = {"hash": 0, "hadamard": 1}
-ABI_VERSION = 6  # COFEM_ABI_VERSION of include/cofem.h
+ABI_VERSION = 7  # COFEM_ABI_VERSION of include/cofem.h
 
 # every symbol include/cofem.h declares
 EXPORTS = [
@@ -34,7 +34,7 @@ EXPORTS = [
     "cofem_server_create", "cofem_server_destroy", "cofem_server_submit", "cofem_server_step",
     "cofem_server_poll", "cofem_server_cancel", "cofem_server_get_stats",
     "cofem_mt_create", "cofem_mt_destroy", "cofem_mt_set_dictionary", "cofem_mt_set_dct_samples", "cofem_mt_fit",
-    "cofem_mt_posterior",
+    "cofem_mt_posterior", "cofem_mt_create_mode", "cofem_mt_batched",
 ]
 REQ_STATE = {0: "pending", 1: "running", 2: "done", -1: "unknown"}
 
@@ -129,6 +129,8 @@ def load() -> ctypes.CDLL:
         "cofem_server_get_stats": (i32, [vp, ctypes.POINTER(ServerStats)]),
         "cofem_server_cancel": (i32, [vp, i64]),
         "cofem_mt_create": (i32, [ctypes.POINTER(Params), i32, vp, ctypes.POINTER(vp)]),
+        "cofem_mt_create_mode": (i32, [ctypes.POINTER(Params), i32, i32, vp, ctypes.POINTER(vp)]),
+        "cofem_mt_batched": (i32, [vp]),
         "cofem_mt_destroy": (None, [vp]),
         "cofem_mt_set_dictionary": (i32, [vp, i32, vp]),
         "cofem_mt_set_dct_samples": (i32, [vp, i32, vp]),
@@ -291,11 +293,16 @@ def conv_apply_A_static(h, alpha, P, beta, want_pi=False, stream=None):
     return (Psi, pi) if want_pi else Psi
 
 
+MT_MODES = {"auto": 0, "streams": 1, "batched": 2}
+
+
 class MultiTask(CoFEM):
-    """Multi-task CoFEM (cofem_mt_*): L problems of one shape sharing alpha."""
+    """Multi-task CoFEM (cofem_mt_*): L problems of one shape sharing alpha.  mode: "batched"
+    (all tasks' systems together, one launch per phase), "streams" (one context per task on
+    its own stream) or "auto" (batched when the settings allow it)."""
 
     def __init__(self, L, N, D, beta, K, T, U, tol, theta="ones", stop="joint", op="dense", phi_dtype="fp32",
-                 refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30, stream=None):
+                 refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30, stream=None, mode="auto"):
         import torch
 
         lib = load()
@@ -303,10 +310,13 @@ class MultiTask(CoFEM):
                                   seed, alpha_floor)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
-        _check(lib.cofem_mt_create(ctypes.byref(self.params), int(L), ctypes.c_void_p(self.stream.cuda_stream),
-                                   ctypes.byref(h)))
+        if mode not in MT_MODES:
+            raise ValueError(f"mode must be one of {sorted(MT_MODES)}")
+        _check(lib.cofem_mt_create_mode(ctypes.byref(self.params), int(L), MT_MODES[mode],
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self.L, self.N, self.D = int(L), int(N), int(D)
+        self.batched = bool(lib.cofem_mt_batched(self._h))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

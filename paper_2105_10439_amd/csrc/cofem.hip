@@ -7,6 +7,7 @@
 // steps enqueued after the stop rule fired are no-ops on the device.
 #include "cofem.h"
 #include "kernels.h"
+#include "mt_batch.h"
 
 #include <algorithm>
 #include <chrono>
@@ -905,9 +906,12 @@ COFEM_API cofem_status cofem_get_timing(cofem_ctx* c, int32_t which, double* tot
 }
 
 // ---------------------------------------------------------------------------
-// Multi-task CoFEM: one context per task, alpha shared (the buffer of task 0).
+// Multi-task CoFEM, in one of two forms: batched (every task a slot of one alpha group
+// of the serving kernels, mt_batch.h), or one context per task on its own stream with
+// alpha shared (the buffer of task 0).
 // ---------------------------------------------------------------------------
 struct cofem_mt {
+  cofem::MtBatch* batch = nullptr;  // the batched form; the fields below are then unused
   std::vector<cofem_ctx*> tasks;
   // task 0 runs on the caller's stream, task l > 0 on streams[l - 1] (created here, default
   // priority); ev[l] orders the tasks' streams around the shared alpha
@@ -921,6 +925,8 @@ struct cofem_mt {
 namespace {
 
 void mt_free(cofem_mt* m) {
+  cofem::mtb_destroy(m->batch);
+  m->batch = nullptr;
   for (cofem_ctx* c : m->tasks) cofem_destroy(c);
   m->tasks.clear();
   for (hipStream_t s : m->streams) (void)hipStreamDestroy(s);
@@ -935,14 +941,33 @@ void mt_free(cofem_mt* m) {
 }  // namespace
 
 COFEM_API cofem_status cofem_mt_create(const cofem_params* p, int32_t L, void* stream, cofem_mt** out) {
+  return cofem_mt_create_mode(p, L, COFEM_MT_AUTO, stream, out);
+}
+
+COFEM_API cofem_status cofem_mt_create_mode(const cofem_params* p, int32_t L, int32_t mode, void* stream,
+                                           cofem_mt** out) {
   if (!out) return fail(COFEM_EINVAL, "out is NULL");
   *out = nullptr;
   if (L < 1 || L > COFEM_MAX_TASKS) return fail(COFEM_EINVAL, "L must be in [1, COFEM_MAX_TASKS]");
+  if (mode != COFEM_MT_AUTO && mode != COFEM_MT_STREAMS && mode != COFEM_MT_BATCHED)
+    return fail(COFEM_EINVAL, "bad multi-task mode");
   cofem_status rc = validate(p);
   if (rc != COFEM_OK) return rc;
   if (p->mstep_mode != COFEM_MSTEP_GAUSSIAN) return fail(COFEM_EINVAL, "multi-task fits use the Gaussian M-step");
+  const bool eligible = cofem::mtb_eligible(*p);
+  if (mode == COFEM_MT_BATCHED && !eligible)
+    return fail(COFEM_EINVAL, "the batched multi-task fit takes dense FP32 dictionaries, no refinement, K <= 31");
   cofem_mt* m = new (std::nothrow) cofem_mt();
   if (!m) return fail(COFEM_ENOMEM, "host allocation failed");
+  if (mode == COFEM_MT_BATCHED || (mode == COFEM_MT_AUTO && eligible)) {
+    rc = cofem::mtb_create(*p, L, static_cast<hipStream_t>(stream), &m->batch);
+    if (rc != COFEM_OK) {
+      delete m;
+      return rc;
+    }
+    *out = m;
+    return COFEM_OK;
+  }
   std::vector<const float*> mus(L), ss(L);
   for (int l = 0; l < L; ++l) {
     hipEvent_t e = nullptr;
@@ -997,6 +1022,8 @@ COFEM_API void cofem_mt_destroy(cofem_mt* m) {
   delete m;
 }
 
+COFEM_API int32_t cofem_mt_batched(const cofem_mt* m) { return (m && m->batch) ? 1 : 0; }
+
 // Task `task`'s stream after the caller's stream (task 0's), so that the task reads
 // caller data only once the caller's stream has produced it.
 static cofem_status mt_after_caller(cofem_mt* m, int task) {
@@ -1007,6 +1034,7 @@ static cofem_status mt_after_caller(cofem_mt* m, int task) {
 }
 
 COFEM_API cofem_status cofem_mt_set_dictionary(cofem_mt* m, int32_t task, const float* phi) {
+  if (m && m->batch) return cofem::mtb_set_dictionary(m->batch, task, phi);
   if (!m || task < 0 || task >= (int32_t)m->tasks.size()) return fail(COFEM_EINVAL, "bad task");
   cofem_status rc = mt_after_caller(m, task);
   if (rc != COFEM_OK) return rc;
@@ -1014,6 +1042,7 @@ COFEM_API cofem_status cofem_mt_set_dictionary(cofem_mt* m, int32_t task, const 
 }
 
 COFEM_API cofem_status cofem_mt_set_dct_samples(cofem_mt* m, int32_t task, const int32_t* rows) {
+  if (m && m->batch) return fail(COFEM_EINVAL, "the batched multi-task fit takes dense dictionaries");
   if (!m || task < 0 || task >= (int32_t)m->tasks.size()) return fail(COFEM_EINVAL, "bad task");
   cofem_status rc = mt_after_caller(m, task);
   if (rc != COFEM_OK) return rc;
@@ -1022,6 +1051,7 @@ COFEM_API cofem_status cofem_mt_set_dct_samples(cofem_mt* m, int32_t task, const
 
 COFEM_API cofem_status cofem_mt_fit(cofem_mt* m, const float* const* ys) {
   if (!m || !ys) return fail(COFEM_EINVAL, "NULL argument");
+  if (m->batch) return cofem::mtb_fit(m->batch, ys);
   const int L = (int)m->tasks.size();
   for (int l = 0; l < L; ++l) {
     if (!ys[l]) return fail(COFEM_EINVAL, "NULL observation");
@@ -1079,6 +1109,7 @@ COFEM_API cofem_status cofem_mt_fit(cofem_mt* m, const float* const* ys) {
 
 COFEM_API cofem_status cofem_mt_posterior(cofem_mt* m, int32_t task, float* mu, float* s, float* alpha,
                                           cofem_stats* st) {
+  if (m && m->batch) return cofem::mtb_posterior(m->batch, task, mu, s, alpha, st);
   if (!m || task < 0 || task >= (int32_t)m->tasks.size()) return fail(COFEM_EINVAL, "bad task");
   if (!m->fitted) return fail(COFEM_ESTATE, "cofem_mt_posterior before a successful cofem_mt_fit");
   cofem_ctx* c = m->tasks[task];

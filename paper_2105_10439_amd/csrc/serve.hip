@@ -1,4 +1,5 @@
-// Serving: continuous batching of independent CoFEM fits (include/cofem.h).
+// Serving: continuous batching of independent CoFEM fits (include/cofem.h), and the
+// batched multi-task fit (Sec. III-E.1) on the same kernels.
 //
 // Every admitted request owns a slot: a region of one device arena holding its
 // dictionary (row-major and transposed, FP32), its CG blocks and its state.  A
@@ -8,6 +9,12 @@
 // slots (rebuilt by the host only when slots are admitted or retired), and each
 // slot moves through its own EM iterations on the device.  The per-tile work is
 // the same code as the single-problem path (tiles.h).
+//
+// A group of slots shares one alpha (multi-task CoFEM): its members run their own
+// E-steps (own dictionary, observation, probes and stop rule), each computes its mu and
+// s when its E-step ends and then waits; once every member has finished E-step t, one
+// kernel forms the joint M-step alpha_j = L / sum_l (mu_lj^2 + s_lj) and the members
+// move to E-step t + 1 together.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +29,7 @@
 
 #include "cofem.h"
 #include "kernels.h"
+#include "mt_batch.h"
 #include "tiles.h"
 
 #define COFEM_API extern "C" __attribute__((visibility("default")))
@@ -53,7 +61,9 @@ struct SlotDev {
   float *V, *Ypart, *X, *R, *Pd, *Psi, *minv, *alpha, *b, *theta, *mu, *s;
   double *part, *pipart;
   CGState* st;
-  int* steps_log;  // CG steps of each E-step (T ints)
+  int* steps_log;       // CG steps of each E-step (T ints)
+  double* resid_log;    // ||R||_F / ||B||_F at the end of each E-step (T doubles)
+  int grp_first, grp_n;  // alpha group: slots grp_first .. grp_first + grp_n - 1 (grp_n = 0: none)
 };
 
 // Tile table of the running slots: for every kind of tile, a prefix sum of the
@@ -213,30 +223,82 @@ __global__ __launch_bounds__(VBLOCK) void ks_mstep(const SlotDev* __restrict__ s
     const int local = t - tab->em[i];
     if (sd.st->phase != PH_CG || !sd.st->done || local >= (int)((sd.D + VBLOCK - 1) / VBLOCK)) continue;
     const int tt = sd.st->t;
+    // a group member takes mu and s only (recomputed unchanged while it waits for the group)
     mstep_block(sd.c, iteration_key(sd.seed, tt), sd.D, sd.Dp, local, sd.X, sd.mu, sd.s, sd.alpha, sd.floor,
-                tt < sd.T ? 1 : 0, sd.st);
+                (tt < sd.T && sd.grp_n == 0) ? 1 : 0, sd.st);
   }
 }
 
-// One thread per slot: record the finished E-step and move to the next EM
-// iteration or to DONE; publish every listed slot's phase.
+__device__ __forceinline__ bool estep_over(const CGState* st) { return st->phase == PH_CG && st->done; }
+
+// Joint M-step of an alpha group once every member has finished the same E-step t < T:
+// alpha_j = 1 / max((1/L) sum_l (mu_lj^2 + s_lj), floor), the members summed in slot
+// order in FP64, floor events counted on the first member.  The group's first slot's
+// E-step blocks cover D.
+__global__ __launch_bounds__(VBLOCK) void ks_group_alpha(const SlotDev* __restrict__ slots,
+                                                         const SrvTable* __restrict__ tab) {
+  const int n = tab->n, total = tab->em[n];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_slot(tab->em, n, t);
+    const int si = tab->slot[i];
+    const SlotDev& sd = slots[si];
+    const int local = t - tab->em[i];
+    if (sd.grp_n == 0 || si != sd.grp_first || local >= (int)((sd.D + VBLOCK - 1) / VBLOCK)) continue;
+    bool ready = true;
+    for (int m = 0; m < sd.grp_n; ++m) {
+      const CGState* st = slots[si + m].st;
+      ready = ready && estep_over(st) && st->t == sd.st->t;
+    }
+    if (!ready || sd.st->t >= sd.T) continue;
+    const int64_t j = (int64_t)local * VBLOCK + threadIdx.x;
+    int low = 0;
+    if (j < sd.D) {
+      double acc = 0.0;
+      for (int m = 0; m < sd.grp_n; ++m) {
+        const double mu = (double)slots[si + m].mu[j];
+        acc += mu * mu + (double)slots[si + m].s[j];
+      }
+      double den = acc / (double)sd.grp_n;
+      if (den < sd.floor) {
+        den = sd.floor;
+        low = 1;
+      }
+      sd.alpha[j] = (float)(1.0 / den);
+    }
+    low = wave_sum_int(low);
+    if ((threadIdx.x & 63) == 0 && low) atomicAdd(&sd.st->clamped, low);
+  }
+}
+
+// One block, one thread per listed slot: record the finished E-step and move to the
+// next EM iteration or to DONE (a group member only once every member has finished the
+// same E-step); publish every listed slot's phase.  Every thread decides from the
+// states as they were at entry before any thread changes one.
 __global__ void ks_advance(const SlotDev* __restrict__ slots, const SrvTable* __restrict__ tab,
                            int* __restrict__ phase_out) {
-  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < tab->n; i += blockDim.x * gridDim.x) {
-    const SlotDev& sd = slots[tab->slot[i]];
-    CGState* st = sd.st;
-    if (st->phase == PH_CG && st->done) {
-      sd.steps_log[st->t - 1] = st->steps;
-      st->total_steps += st->steps;
-      if (st->t < sd.T) {
-        st->t += 1;
-        st->phase = PH_INIT;
-      } else {
-        st->phase = PH_DONE;
-      }
+  __shared__ unsigned char over[SRV_MAXSLOTS];  // by slot index
+  const int n = tab->n, i = threadIdx.x;
+  for (int k = i; k < SRV_MAXSLOTS; k += blockDim.x) over[k] = 0;
+  __syncthreads();
+  if (i < n) over[tab->slot[i]] = estep_over(slots[tab->slot[i]].st) ? 1 : 0;
+  __syncthreads();
+  if (i >= n) return;
+  const SlotDev& sd = slots[tab->slot[i]];
+  CGState* st = sd.st;
+  bool go = over[tab->slot[i]] != 0;
+  for (int m = 0; go && m < sd.grp_n; ++m) go = over[sd.grp_first + m] != 0;
+  if (go) {
+    sd.steps_log[st->t - 1] = st->steps;
+    sd.resid_log[st->t - 1] = st->delta;
+    st->total_steps += st->steps;
+    if (st->t < sd.T) {
+      st->t += 1;
+      st->phase = PH_INIT;
+    } else {
+      st->phase = PH_DONE;
     }
-    phase_out[i] = st->phase;
   }
+  phase_out[i] = st->phase;
 }
 
 // ---- admission kernels ---------------------------------------------------------
@@ -317,18 +379,19 @@ struct SlotLayout {
   int nrb1, splits1, nrb2, splits2;
   int64_t kchunk1, kchunk2;
   size_t off_phi, off_phiT, off_V, off_Yp, off_X, off_R, off_Pd, off_Psi, off_vec, off_y, off_part, off_pipart,
-      off_st, off_log, total;
+      off_st, off_log, off_rlog, total;
 };
 
-SlotLayout layout_of(const cofem_params& p) {
+// kchunk: reduction length per split of both contractions (a multiple of 256).
+SlotLayout layout_of(const cofem_params& p, int64_t kchunk = SRV_KCHUNK) {
   SlotLayout L{};
   L.Np = rup(p.N, 256);
   L.Dp = rup(p.D, 256);
   L.nrb1 = (int)(L.Np / (64 * SRV_RT));
-  L.kchunk1 = std::min<int64_t>(SRV_KCHUNK, L.Dp);
+  L.kchunk1 = std::min<int64_t>(kchunk, L.Dp);
   L.splits1 = cdivi(L.Dp, L.kchunk1);
   L.nrb2 = (int)(L.Dp / (64 * SRV_RT));
-  L.kchunk2 = std::min<int64_t>(SRV_KCHUNK, L.Np);
+  L.kchunk2 = std::min<int64_t>(kchunk, L.Np);
   L.splits2 = cdivi(L.Np, L.kchunk2);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -351,6 +414,7 @@ SlotLayout layout_of(const cofem_params& p) {
   L.off_pipart = take((size_t)(L.Dp / VPART + 1) * QMAX * sizeof(double));
   L.off_st = take(sizeof(CGState));
   L.off_log = take((size_t)p.T * sizeof(int));
+  L.off_rlog = take((size_t)p.T * sizeof(double));
   L.total = o;
   return L;
 }
@@ -455,30 +519,36 @@ cofem_status validate_request(const cofem_params* p) {
   return COFEM_OK;
 }
 
-cofem_status capture_tick(cofem_server* s) {
-  SRV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-  hipLaunchKernelGGL(ks_reset_ctr, dim3(1), dim3(128), 0, s->stream, s->d_ctr, 2 * s->steps);
-  hipLaunchKernelGGL(ks_em_init, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
-  hipLaunchKernelGGL(ks_em_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
-  for (int k = 0; k < s->steps; ++k) {
-    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, s->stream, s->d_slots, s->d_table, 1,
-                       s->d_ctr + 2 * k);
-    hipLaunchKernelGGL(ks_finish1, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
-    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, s->stream, s->d_slots, s->d_table, 2,
-                       s->d_ctr + 2 * k + 1);
-    hipLaunchKernelGGL(ks_finish2, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
-    hipLaunchKernelGGL(ks_update, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
-    hipLaunchKernelGGL(ks_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
-    hipLaunchKernelGGL(ks_direction, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
+// One tick as a graph: E-step initialisation, `steps` CG steps, M-step, the alpha groups'
+// joint M-step, EM advance.  ctr holds 2 * steps tile counters.
+cofem_status capture_tick_graph(hipStream_t st, int steps, const SlotDev* slots, const SrvTable* tab, int* ctr,
+                                int* phase, hipGraph_t* graph, hipGraphExec_t* exec) {
+  SRV_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(ks_reset_ctr, dim3(1), dim3(128), 0, st, ctr, 2 * steps);
+  hipLaunchKernelGGL(ks_em_init, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
+  hipLaunchKernelGGL(ks_em_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, st, slots, tab);
+  for (int k = 0; k < steps; ++k) {
+    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, st, slots, tab, 1, ctr + 2 * k);
+    hipLaunchKernelGGL(ks_finish1, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
+    hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, st, slots, tab, 2, ctr + 2 * k + 1);
+    hipLaunchKernelGGL(ks_finish2, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
+    hipLaunchKernelGGL(ks_update, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
+    hipLaunchKernelGGL(ks_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, st, slots, tab);
+    hipLaunchKernelGGL(ks_direction, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
   }
-  hipLaunchKernelGGL(ks_mstep, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, s->stream, s->d_slots, s->d_table);
-  hipLaunchKernelGGL(ks_advance, dim3(1), dim3(SRV_MAXSLOTS), 0, s->stream, s->d_slots, s->d_table, s->d_phase);
+  hipLaunchKernelGGL(ks_mstep, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
+  hipLaunchKernelGGL(ks_group_alpha, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
+  hipLaunchKernelGGL(ks_advance, dim3(1), dim3(SRV_MAXSLOTS), 0, st, slots, tab, phase);
   hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(s->stream, &g);
+  hipError_t e = hipStreamEndCapture(st, &g);
   if (e != hipSuccess) return sfail(COFEM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-  s->graph = g;
-  SRV_TRY(hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0));
+  *graph = g;
+  SRV_TRY(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
   return COFEM_OK;
+}
+
+cofem_status capture_tick(cofem_server* s) {
+  return capture_tick_graph(s->stream, s->steps, s->d_slots, s->d_table, s->d_ctr, s->d_phase, &s->graph, &s->exec);
 }
 
 void destroy_server(cofem_server* s) {
@@ -498,11 +568,9 @@ void destroy_server(cofem_server* s) {
   delete s;
 }
 
-// Copy the request's inputs into its slot and prepare its first E-step.
-cofem_status admit(cofem_server* s, int slot, Request& r) {
-  const cofem_params& p = r.p;
-  const SlotLayout L = layout_of(p);
-  char* base = s->arena_base + r.off;
+// The device description of a fit whose workspace (layout_of(p, kchunk)) starts at base.
+SlotDev make_slot(const cofem_params& p, char* base, int64_t kchunk = SRV_KCHUNK) {
+  const SlotLayout L = layout_of(p, kchunk);
   SlotDev sd{};
   sd.c.Q = p.K + 1;
   sd.c.Qp = SRV_QP;
@@ -528,10 +596,8 @@ cofem_status admit(cofem_server* s, int slot, Request& r) {
   sd.kchunk2 = L.kchunk2;
   sd.nbx = cdivi(L.Dp, VCHUNK);
   sd.nbn = cdivi(L.Np, VCHUNK);
-  float* phi = reinterpret_cast<float*>(base + L.off_phi);
-  float* phiT = reinterpret_cast<float*>(base + L.off_phiT);
-  sd.phi = phi;
-  sd.phiT = phiT;
+  sd.phi = reinterpret_cast<float*>(base + L.off_phi);
+  sd.phiT = reinterpret_cast<float*>(base + L.off_phiT);
   sd.V = reinterpret_cast<float*>(base + L.off_V);
   sd.Ypart = reinterpret_cast<float*>(base + L.off_Yp);
   sd.X = reinterpret_cast<float*>(base + L.off_X);
@@ -545,11 +611,25 @@ cofem_status admit(cofem_server* s, int slot, Request& r) {
   sd.theta = vec + 3 * L.Dp;
   sd.mu = vec + 4 * L.Dp;
   sd.s = vec + 5 * L.Dp;
-  float* yv = reinterpret_cast<float*>(base + L.off_y);
   sd.part = reinterpret_cast<double*>(base + L.off_part);
   sd.pipart = reinterpret_cast<double*>(base + L.off_pipart);
   sd.st = reinterpret_cast<CGState*>(base + L.off_st);
   sd.steps_log = reinterpret_cast<int*>(base + L.off_log);
+  sd.resid_log = reinterpret_cast<double*>(base + L.off_rlog);
+  sd.grp_first = 0;
+  sd.grp_n = 0;
+  return sd;
+}
+
+// Copy the request's inputs into its slot and prepare its first E-step.
+cofem_status admit(cofem_server* s, int slot, Request& r) {
+  const cofem_params& p = r.p;
+  const SlotLayout L = layout_of(p);
+  char* base = s->arena_base + r.off;
+  const SlotDev sd = make_slot(p, base);
+  float* phi = reinterpret_cast<float*>(base + L.off_phi);
+  float* phiT = reinterpret_cast<float*>(base + L.off_phiT);
+  float* yv = reinterpret_cast<float*>(base + L.off_y);
   const int64_t nd = L.Np * L.Dp;
   // zero the padded buffers the copies do not cover (V's padded rows and columns stay zero)
   hipLaunchKernelGGL(ks_zero, dim3(1024), dim3(256), 0, s->stream, phi, nd);
@@ -572,22 +652,27 @@ cofem_status admit(cofem_server* s, int slot, Request& r) {
   return COFEM_OK;
 }
 
-void rebuild_table(cofem_server* s) {
-  SrvTable& t = s->h_table;
+// Append slot i (described by sd) to the tile table.
+void table_add(SrvTable& t, int i, const SlotDev& sd) {
+  auto pad8 = [](int x) { return (x + 7) & ~7; };
+  const int k = t.n++;
+  t.slot[k] = i;
+  t.em[k + 1] = t.em[k] + pad8((int)(sd.Dp / VBLOCK));
+  t.g1[k + 1] = t.g1[k] + pad8(sd.nrb1 * sd.splits1);
+  t.g2[k + 1] = t.g2[k] + pad8(sd.nrb2 * sd.splits2);
+  t.f1[k + 1] = t.f1[k] + pad8(sd.nbn * SRV_QP);
+  t.vq[k + 1] = t.vq[k] + pad8(sd.nbx * sd.c.Q);
+}
+
+void table_clear(SrvTable& t) {
   t.n = 0;
   t.em[0] = t.g1[0] = t.g2[0] = t.f1[0] = t.vq[0] = 0;
-  auto pad8 = [](int x) { return (x + 7) & ~7; };
-  for (int i = 0; i < s->max_slots; ++i) {
-    if (s->slot_req[i] < 0) continue;
-    const SlotDev& sd = s->slot_dev[i];
-    const int k = t.n++;
-    t.slot[k] = i;
-    t.em[k + 1] = t.em[k] + pad8((int)(sd.Dp / VBLOCK));
-    t.g1[k + 1] = t.g1[k] + pad8(sd.nrb1 * sd.splits1);
-    t.g2[k + 1] = t.g2[k] + pad8(sd.nrb2 * sd.splits2);
-    t.f1[k + 1] = t.f1[k] + pad8(sd.nbn * SRV_QP);
-    t.vq[k + 1] = t.vq[k] + pad8(sd.nbx * sd.c.Q);
-  }
+}
+
+void rebuild_table(cofem_server* s) {
+  table_clear(s->h_table);
+  for (int i = 0; i < s->max_slots; ++i)
+    if (s->slot_req[i] >= 0) table_add(s->h_table, i, s->slot_dev[i]);
 }
 
 }  // namespace
@@ -823,3 +908,251 @@ COFEM_API cofem_status cofem_server_get_stats(cofem_server* s, cofem_server_stat
   *out = s->stats;
   return COFEM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Batched multi-task fit (Sec. III-E.1): the L tasks are the slots 0 .. L - 1 of one
+// alpha group, so every CG step of all L(K + 1) systems is one launch per phase
+// (two contraction launches over every task's tiles, the vector kernels over every
+// task's columns), each task keeping its own stop rule, and the joint M-step runs on
+// the device once all L E-steps of an EM iteration have ended.
+// ---------------------------------------------------------------------------
+namespace cofem {
+
+struct MtBatch {
+  hipStream_t stream = nullptr;
+  cofem_params p{};
+  int L = 0;
+  int steps = 8;           // CG steps per graph launch
+  int64_t kchunk = SRV_KCHUNK;
+  SlotLayout lay{};
+  char* arena = nullptr;   // L slot workspaces, then the shared alpha
+  float* alpha = nullptr;
+  SlotDev* d_slots = nullptr;
+  SrvTable* d_table = nullptr;
+  int* d_ctr = nullptr;
+  int* d_phase = nullptr;
+  int* d_count = nullptr;  // non-finite entries found by the last check
+  int* h_phase = nullptr;  // pinned
+  std::vector<SlotDev> sd;
+  std::vector<char> loaded;
+  std::vector<double> ms_setup;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<CGState> h_st;
+  std::vector<std::vector<int>> steps_log;
+  std::vector<std::vector<double>> resid_log;
+  double ms_fit = 0.0;
+  bool fitted = false;
+};
+
+bool mtb_eligible(const cofem_params& p) {
+  return p.op_kind == COFEM_OP_DENSE && p.phi_dtype == COFEM_PHI_FP32 && p.refine_last == 0 && p.K >= 1 &&
+         p.K <= SRV_QP - 1 && p.mstep_mode == COFEM_MSTEP_GAUSSIAN;
+}
+
+void mtb_destroy(MtBatch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->arena) (void)hipFree(b->arena);
+  if (b->d_slots) (void)hipFree(b->d_slots);
+  if (b->d_table) (void)hipFree(b->d_table);
+  if (b->d_ctr) (void)hipFree(b->d_ctr);
+  if (b->d_phase) (void)hipFree(b->d_phase);
+  if (b->d_count) (void)hipFree(b->d_count);
+  if (b->h_phase) (void)hipHostFree(b->h_phase);
+  delete b;
+}
+
+cofem_status mtb_create(const cofem_params& p, int L, hipStream_t stream, MtBatch** out) {
+  *out = nullptr;
+  if (!mtb_eligible(p))
+    return sfail(COFEM_EINVAL, "the batched multi-task fit takes dense FP32 dictionaries, no refinement, K <= 31");
+  if (L < 1 || L > SRV_MAXSLOTS) return sfail(COFEM_EINVAL, "bad task count");
+  MtBatch* b = new (std::nothrow) MtBatch();
+  if (!b) return sfail(COFEM_ENOMEM, "host allocation failed");
+  b->stream = stream;
+  b->p = p;
+  b->L = L;
+  // split the contractions finer until each launch has about two tiles per persistent
+  // block (the tasks' tiles together), down to 256-long reductions
+  auto tiles = [&](int64_t kc) {
+    const SlotLayout t = layout_of(p, kc);
+    return (int64_t)L * std::min<int64_t>((int64_t)t.nrb1 * t.splits1, (int64_t)t.nrb2 * t.splits2);
+  };
+  while (b->kchunk > 256 && tiles(b->kchunk) < 2 * SRV_GEMM_GRID) b->kchunk /= 2;
+  b->lay = layout_of(p, b->kchunk);
+  auto bail = [&](cofem_status st, const char* what) {
+    (void)hipGetLastError();
+    mtb_destroy(b);
+    return sfail(st, what);
+  };
+  const size_t per = b->lay.total;
+  if (hipMalloc((void**)&b->arena, per * L + (size_t)b->lay.Dp * sizeof(float)) != hipSuccess)
+    return bail(COFEM_ENOMEM, "task workspace allocation failed");
+  b->alpha = reinterpret_cast<float*>(b->arena + per * L);
+  if (hipMalloc((void**)&b->d_slots, sizeof(SlotDev) * SRV_MAXSLOTS) != hipSuccess ||
+      hipMalloc((void**)&b->d_table, sizeof(SrvTable)) != hipSuccess ||
+      hipMalloc((void**)&b->d_phase, sizeof(int) * SRV_MAXSLOTS) != hipSuccess ||
+      hipMalloc((void**)&b->d_ctr, sizeof(int) * 2 * b->steps) != hipSuccess ||
+      hipMalloc((void**)&b->d_count, sizeof(int)) != hipSuccess)
+    return bail(COFEM_ENOMEM, "task tables allocation failed");
+  if (hipHostMalloc((void**)&b->h_phase, sizeof(int) * SRV_MAXSLOTS, hipHostMallocDefault) != hipSuccess) {
+    b->h_phase = nullptr;
+    return bail(COFEM_ENOMEM, "pinned allocation failed");
+  }
+  SrvTable tab;
+  table_clear(tab);
+  for (int l = 0; l < L; ++l) {
+    cofem_params q = p;
+    q.seed = p.seed + (uint64_t)l;  // task l's probes
+    SlotDev sd = make_slot(q, b->arena + per * l, b->kchunk);
+    sd.alpha = b->alpha;
+    sd.grp_first = 0;
+    sd.grp_n = L;
+    b->sd.push_back(sd);
+    table_add(tab, l, sd);
+  }
+  b->loaded.assign(L, 0);
+  b->ms_setup.assign(L, 0.0);
+  if (hipMemcpyAsync(b->d_slots, b->sd.data(), sizeof(SlotDev) * L, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(b->d_table, &tab, sizeof(SrvTable), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return bail(COFEM_EDEVICE, "task table upload failed");
+  // capture on a stream of our own (the caller's may be the legacy default stream, which
+  // cannot capture); the graph is launched on the caller's stream
+  hipStream_t cap = nullptr;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+    return bail(COFEM_EDEVICE, "hipStreamCreate failed");
+  cofem_status rc = capture_tick_graph(cap, b->steps, b->d_slots, b->d_table, b->d_ctr, b->d_phase, &b->graph,
+                                       &b->exec);
+  (void)hipStreamDestroy(cap);
+  if (rc != COFEM_OK) {
+    mtb_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return COFEM_OK;
+}
+
+// Count the non-finite entries of x[0 .. n) on the stream; an error names `what`.
+static cofem_status mtb_check_finite(MtBatch* b, const float* x, int64_t n, const std::string& what) {
+  SRV_TRY(hipMemsetAsync(b->d_count, 0, sizeof(int), b->stream));
+  launch_count_nonfinite(x, n, b->d_count, b->stream);
+  int bad = 0;
+  SRV_TRY(hipMemcpyAsync(&bad, b->d_count, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  SRV_TRY(hipStreamSynchronize(b->stream));
+  if (bad > 0)
+    return sfail(COFEM_EINVAL, what + " has " + std::to_string(bad) + " non-finite entries (NaN or infinity)");
+  return COFEM_OK;
+}
+
+cofem_status mtb_set_dictionary(MtBatch* b, int task, const float* phi) {
+  if (task < 0 || task >= b->L || !phi) return sfail(COFEM_EINVAL, "bad task or NULL dictionary");
+  const double t0 = wall_ms();
+  const SlotLayout& L = b->lay;
+  const cofem_params& p = b->p;
+  char* base = b->arena + L.total * task;
+  float* ph = reinterpret_cast<float*>(base + L.off_phi);
+  float* phT = reinterpret_cast<float*>(base + L.off_phiT);
+  b->loaded[task] = 0;
+  b->fitted = false;
+  hipLaunchKernelGGL(ks_zero, dim3(1024), dim3(256), 0, b->stream, ph, L.Np * L.Dp);
+  SRV_TRY(hipMemcpy2DAsync(ph, (size_t)L.Dp * sizeof(float), phi, (size_t)p.D * sizeof(float),
+                           (size_t)p.D * sizeof(float), (size_t)p.N, hipMemcpyDeviceToDevice, b->stream));
+  cofem_status rc = mtb_check_finite(b, ph, L.Np * L.Dp, "the dictionary");
+  if (rc != COFEM_OK) return rc;
+  hipLaunchKernelGGL(ks_transpose, dim3((unsigned)(L.Dp / 64), (unsigned)(L.Np / 64)), dim3(256), 0, b->stream, ph,
+                     L.Np, L.Dp, phT);
+  hipLaunchKernelGGL(ks_theta, dim3((unsigned)cdivi(L.Dp, 256)), dim3(256), 0, b->stream, ph, L.Np, p.D, L.Dp,
+                     p.theta_mode == COFEM_THETA_JACOBI ? 1 : 0, b->sd[task].theta);
+  SRV_TRY(hipGetLastError());
+  SRV_TRY(hipStreamSynchronize(b->stream));
+  b->loaded[task] = 1;
+  b->ms_setup[task] = wall_ms() - t0;
+  return COFEM_OK;
+}
+
+cofem_status mtb_fit(MtBatch* b, const float* const* ys) {
+  const cofem_params& p = b->p;
+  const SlotLayout& L = b->lay;
+  for (int l = 0; l < b->L; ++l) {
+    if (!ys[l]) return sfail(COFEM_EINVAL, "NULL observation");
+    if (!b->loaded[l]) return sfail(COFEM_ESTATE, "cofem_mt_fit before every task has a dictionary");
+  }
+  const double t0 = wall_ms();
+  b->fitted = false;
+  for (int l = 0; l < b->L; ++l) {
+    const SlotDev& sd = b->sd[l];
+    float* yv = reinterpret_cast<float*>(b->arena + L.total * l + L.off_y);
+    hipLaunchKernelGGL(ks_zero, dim3(64), dim3(256), 0, b->stream, yv, L.Np);
+    SRV_TRY(hipMemcpyAsync(yv, ys[l], (size_t)p.N * sizeof(float), hipMemcpyDeviceToDevice, b->stream));
+    cofem_status rc = mtb_check_finite(b, yv, p.N, "ys[" + std::to_string(l) + "]");
+    if (rc != COFEM_OK) return rc;
+    hipLaunchKernelGGL(ks_zero, dim3(256), dim3(256), 0, b->stream, sd.V, (int64_t)SRV_QP * L.Np);
+    launch_rhs(sd.phiT, nullptr, L.Np, L.Np, L.Dp, yv, p.beta, sd.b, b->stream);
+    hipLaunchKernelGGL(ks_slot_start, dim3(64), dim3(256), 0, b->stream, sd.st, b->alpha, L.Dp);
+  }
+  SRV_TRY(hipGetLastError());
+  // each E-step takes at most ceil(U / steps) + 1 launches (its first starts with the
+  // E-step initialisation), and the tasks advance together
+  const int64_t limit = (int64_t)p.T * ((p.U + b->steps - 1) / b->steps + 2) + 2;
+  bool done = false;
+  for (int64_t tick = 0; tick < limit && !done; ++tick) {
+    SRV_TRY(hipGraphLaunch(b->exec, b->stream));
+    SRV_TRY(hipMemcpyAsync(b->h_phase, b->d_phase, sizeof(int) * b->L, hipMemcpyDeviceToHost, b->stream));
+    SRV_TRY(hipStreamSynchronize(b->stream));
+    done = true;
+    for (int l = 0; l < b->L; ++l) done = done && b->h_phase[l] == PH_DONE;
+  }
+  if (!done) return sfail(COFEM_EDEVICE, "batched multi-task fit did not finish within its launch bound");
+  b->h_st.assign(b->L, CGState{});
+  b->steps_log.assign(b->L, std::vector<int>(p.T));
+  b->resid_log.assign(b->L, std::vector<double>(p.T));
+  for (int l = 0; l < b->L; ++l) {
+    const SlotDev& sd = b->sd[l];
+    SRV_TRY(hipMemcpyAsync(&b->h_st[l], sd.st, sizeof(CGState), hipMemcpyDeviceToHost, b->stream));
+    SRV_TRY(hipMemcpyAsync(b->steps_log[l].data(), sd.steps_log, sizeof(int) * p.T, hipMemcpyDeviceToHost, b->stream));
+    SRV_TRY(hipMemcpyAsync(b->resid_log[l].data(), sd.resid_log, sizeof(double) * p.T, hipMemcpyDeviceToHost,
+                           b->stream));
+  }
+  SRV_TRY(hipStreamSynchronize(b->stream));
+  b->ms_fit = wall_ms() - t0;
+  b->fitted = true;
+  for (int l = 0; l < b->L; ++l) {
+    const CGState& st = b->h_st[l];
+    // the mu column can only be inactive in joint mode through a breakdown
+    if (st.active[0] == 0 && st.breakdown > 0 && p.stop_mode == COFEM_STOP_JOINT)
+      return sfail(COFEM_EBREAKDOWN, "CG breakdown in the mu column of task " + std::to_string(l));
+  }
+  return COFEM_OK;
+}
+
+cofem_status mtb_posterior(MtBatch* b, int task, float* mu, float* s, float* alpha, cofem_stats* st) {
+  if (task < 0 || task >= b->L) return sfail(COFEM_EINVAL, "bad task");
+  if (!b->fitted) return sfail(COFEM_ESTATE, "cofem_mt_posterior before a successful cofem_mt_fit");
+  const SlotDev& sd = b->sd[task];
+  const size_t bytes = (size_t)b->p.D * sizeof(float);
+  if (mu) SRV_TRY(hipMemcpyAsync(mu, sd.mu, bytes, hipMemcpyDeviceToDevice, b->stream));
+  if (s) SRV_TRY(hipMemcpyAsync(s, sd.s, bytes, hipMemcpyDeviceToDevice, b->stream));
+  if (alpha) SRV_TRY(hipMemcpyAsync(alpha, b->alpha, bytes, hipMemcpyDeviceToDevice, b->stream));
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    const CGState& h = b->h_st[task];
+    st->T = b->p.T;
+    for (int t = 0; t < b->p.T; ++t) {
+      st->cg_steps[t] = b->steps_log[task][t];
+      st->rel_resid[t] = b->resid_log[task][t];
+    }
+    st->clamped = h.clamped;
+    st->breakdown = h.breakdown;
+    st->total_cg_steps = h.total_steps;
+    st->ms_setup = b->ms_setup[task];
+    st->ms_fit = b->ms_fit;
+  }
+  SRV_TRY(hipStreamSynchronize(b->stream));
+  return COFEM_OK;
+}
+
+}  // namespace cofem

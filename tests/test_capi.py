@@ -94,6 +94,22 @@ def test_multitask_create_rejects_bad_arguments_without_device_work(L, bad):
     assert so.cofem_last_error().decode()
 
 
+@pytest.mark.parametrize("mode,bad", [(3, {}), (-1, {}), (2, dict(phi_dtype=1)), (2, dict(refine_last=2)),
+                                      (2, dict(K=32)), (2, dict(op_kind=1, conv_taps=16, N=256))])
+def test_multitask_mode_rejects_what_it_cannot_run_without_device_work(mode, bad):
+    """An unknown mode, or the batched form with settings it does not take (bf16 or refined
+    dictionaries, K > 31, a FIR dictionary), fails before any device work."""
+    so = lib.load()
+    p = lib.make_params(N=64, D=256, beta=1e4, K=8, T=5, U=10, tol=1e-6)
+    for k, v in bad.items():
+        setattr(p, k, v)
+    h = ctypes.c_void_p()
+    rc = so.cofem_mt_create_mode(ctypes.byref(p), 2, mode, None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    msg = so.cofem_last_error().decode()
+    assert ("mode" in msg) if mode not in (0, 1, 2) else ("batched" in msg)
+
+
 def test_null_arguments_are_rejected():
     so = lib.load()
     assert so.cofem_create(None, None, None) == -1
@@ -104,7 +120,8 @@ def test_null_arguments_are_rejected():
     assert so.cofem_set_probe_mode(None, 1) == -1
     assert so.cofem_posterior(None, None, None, None, None) == -1
     so.cofem_destroy(None)
-    assert so.cofem_abi_version() == 6
+    assert so.cofem_abi_version() == 7
+    assert so.cofem_mt_batched(None) == 0
 
 
 def test_server_rejects_bad_arguments_without_device_work():

@@ -2,7 +2,9 @@
 alpha, each task's E-step covariance-free with its own dictionary and probes (seed + l),
 the joint M-step alpha_j = L / sum_l (mu_lj^2 + s_lj), against the oracle's
 `cofem_multitask` at the same probes, stop rule and tolerance (FP32 bar as for single
-fits: mu within 1e-4, s within 1e-3, alpha on the support within 1e-3 in log)."""
+fits: mu within 1e-4, s within 1e-3, alpha on the support within 1e-3 in log).  Both
+forms: "batched" (all tasks' systems in one launch per phase) and "streams" (one context
+per task on its own stream)."""
 import numpy as np
 import pytest
 
@@ -27,11 +29,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+@pytest.mark.parametrize("mode", ["streams", "batched"])
 @pytest.mark.parametrize("L", [1, 3])
-def test_multitask_matches_oracle(gpu, L):
+def test_multitask_matches_oracle(gpu, L, mode):
     probs = workloads.multitask_problems(L, N=120, D=400, d=12, sigma=0.01, seed=61)
     K, T, U, tol, seed = 8, 30, 300, 1e-6, 21
-    m = gpu.MultiTask(L, 120, 400, probs[0].beta, K=K, T=T, U=U, tol=tol, seed=seed)
+    m = gpu.MultiTask(L, 120, 400, probs[0].beta, K=K, T=T, U=U, tol=tol, seed=seed, mode=mode)
+    assert m.batched == (mode == "batched")
     for l, p in enumerate(probs):
         m.set_dictionary(l, _t(p.phi))
     m.fit([_t(p.y) for p in probs])
@@ -41,13 +45,18 @@ def test_multitask_matches_oracle(gpu, L):
                                                                probs[0].beta, T=T, K=K, U=U, tol=tol, seed=seed)
     alpha = _np(out[0][2])
     sup = np.abs(mus_ref[0]) > 1e-3 * np.abs(mus_ref[0]).max()
+    key = "multitask" if mode == "streams" else "multitask_batched"
     for l in range(L):
         mu, s, a, st = out[l]
         e_mu, e_s = _rel(_np(mu), mus_ref[l]), _rel(_np(s), ss_ref[l])
-        print(f"L={L} task {l}: CG steps {st['total_cg_steps']} (oracle {sum(r[l] for r in steps_ref)})")
-        check(f"multitask_L{L}/task{l}/mu", e_mu, 1e-4)
-        check(f"multitask_L{L}/task{l}/s", e_s, 1e-3)
+        print(f"{mode} L={L} task {l}: CG steps {st['total_cg_steps']} (oracle {sum(r[l] for r in steps_ref)})")
+        check(f"{key}_L{L}/task{l}/mu", e_mu, 1e-4)
+        check(f"{key}_L{L}/task{l}/s", e_s, 1e-3)
         assert np.array_equal(_np(a), alpha)        # every task reports the shared alpha
+        # the record: one CG step count and residual ratio per E-step
+        assert st["T"] == T and sum(st["cg_steps"]) == st["total_cg_steps"]
+        assert all(1 <= n <= U for n in st["cg_steps"])
+        assert all(0.0 < r <= tol or n == U for r, n in zip(st["rel_resid"], st["cg_steps"]))
     assert np.max(np.abs(np.log(alpha[sup] / a_ref[sup]))) < 1e-3
     if L == 1:
         # one task is plain CoFEM
@@ -79,15 +88,17 @@ def test_multitask_shares_support_better_than_single_tasks(gpu):
     assert err(joint) < err(single)
 
 
-def test_multitask_concurrent_fit_is_deterministic(gpu):
-    """The tasks' E-steps run concurrently on their own streams; every task's reductions
-    are in a fixed order and the shared alpha is formed after all of them, so two fits
-    on the same inputs agree bitwise (and the caller's stream sees the finished fit)."""
+@pytest.mark.parametrize("mode", ["streams", "batched"])
+def test_multitask_concurrent_fit_is_deterministic(gpu, mode):
+    """The tasks' E-steps run concurrently (on their own streams, or as the tiles of one
+    launch per phase); every task's reductions are in a fixed order and the shared alpha
+    is formed after all of them, so two fits on the same inputs agree bitwise (and the
+    caller's stream sees the finished fit)."""
     import torch
 
     L, N, D = 3, 200, 800
     probs = workloads.multitask_problems(L, N=N, D=D, d=20, sigma=0.01, seed=63)
-    m = gpu.MultiTask(L, N, D, probs[0].beta, K=8, T=12, U=300, tol=1e-6, seed=4)
+    m = gpu.MultiTask(L, N, D, probs[0].beta, K=8, T=12, U=300, tol=1e-6, seed=4, mode=mode)
     for l, p in enumerate(probs):
         m.set_dictionary(l, _t(p.phi))
     ys = [_t(p.y) for p in probs]
@@ -162,3 +173,35 @@ def test_multitask_dct_matches_oracle(gpu):
         binds(f"multitask_dct/task{l}", _rel(mus[l], mus_t[l]), 1e-4)
         check(f"multitask_dct/task{l}/mu", _rel(_np(out[l][0]), mus[l]), bar)
         check(f"multitask_dct/task{l}/s", _rel(_np(out[l][1]), ss[l]), 10 * bar)
+
+
+def test_batched_tasks_with_different_step_counts(gpu):
+    """Tasks whose E-steps need very different numbers of CG steps (one task's dictionary
+    scaled down, which makes its systems far better conditioned) finish their solves at
+    different launches: the early ones wait for the group, the joint M-step sees every
+    task's final mu and s, and the fit matches the oracle; the record shows the different
+    counts.  tol 1e-8, where the oracle's mu moves by under 3e-7 to tol 1e-10; the bar is
+    the FP32 floor of the fit's systems (kappa up to 2.3e3 at alpha = 1)."""
+    L, N, D = 3, 250, 500
+    probs = workloads.multitask_problems(L, N=N, D=D, d=15, sigma=0.05, seed=68)
+    K, T, U, tol, seed = 8, 8, 600, 1e-8, 9
+    # the tasks share beta; task 2's dictionary scaled by 0.01 brings its A close to diag(alpha)
+    # (the oracle takes 1333, 1378 and 504 CG steps over the fit)
+    phis = [p.phi if l < 2 else 0.01 * p.phi for l, p in enumerate(probs)]
+    m = gpu.MultiTask(L, N, D, probs[0].beta, K=K, T=T, U=U, tol=tol, seed=seed, mode="batched")
+    for l in range(L):
+        m.set_dictionary(l, _t(phis[l]))
+    m.fit([_t(p.y) for p in probs])
+    out = [m.posterior(l) for l in range(L)]
+    m.close()
+    ys = [p.y for p in probs]
+    a_ref, mus, ss, steps = oracle.cofem_multitask(phis, ys, probs[0].beta, T=T, K=K, U=U, tol=tol, seed=seed)
+    _, mus_t, _, _ = oracle.cofem_multitask(phis, ys, probs[0].beta, T=T, K=K, U=U, tol=tol / 100, seed=seed)
+    totals = [out[l][3]["total_cg_steps"] for l in range(L)]
+    print(f"CG steps per task: gpu {totals}, oracle {[sum(r[l] for r in steps) for l in range(L)]}")
+    assert max(totals) >= 2 * min(totals)
+    for l in range(L):
+        bar = fp32_fit_bar(phis[l], probs[0].beta, [np.ones(D), a_ref])
+        binds(f"multitask_batched_uneven/task{l}", _rel(mus[l], mus_t[l]), bar)
+        check(f"multitask_batched_uneven/task{l}/mu", _rel(_np(out[l][0]), mus[l]), bar)
+        check(f"multitask_batched_uneven/task{l}/s", _rel(_np(out[l][1]), ss[l]), 10 * bar)
