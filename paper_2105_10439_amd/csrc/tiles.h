@@ -592,7 +592,7 @@ __device__ __forceinline__ void finish1_tile(int bx, int q, const float* __restr
   f32x4 v = *reinterpret_cast<const f32x4*>(Yp + o);
   for (int sp = 1; sp < splits; ++sp) v += *reinterpret_cast<const f32x4*>(Yp + (int64_t)sp * Qp * Np + o);
   if (V) *reinterpret_cast<f32x4*>(V + o) = v;
-  if (VH) store_split4(VH, VL, o, v, VX);
+  if (VH) store_split4<true>(VH, VL, o, v, VX);
 }
 
 // Psi = beta * sum_split Ypart + alpha Pd and the tile's partial of pi_q = sum_j Pd_jq Psi_jq
@@ -788,7 +788,7 @@ __device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, con
   for (int e = 0; e < 4; ++e) p[e] = (float)((double)mi[e] * (double)r[e] + eta * (double)p[e]);
   if constexpr (NT) __builtin_nontemporal_store(p, reinterpret_cast<f32x4*>(Pd + o));
   else *reinterpret_cast<f32x4*>(Pd + o) = p;
-  if (PdH) store_split4(PdH, PdL, o, p, PdX);
+  if (PdH) store_split4<true>(PdH, PdL, o, p, PdX);
 }
 
 }  // namespace cofem

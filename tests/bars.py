@@ -91,6 +91,10 @@ MEASURED: dict[str, float] = {
     "conv_bf16_refined/s": 1.169e-02,
     "conv_bf16_rounded/mu": 3.277e-05,
     "conv_bf16_rounded/s": 9.326e-05,
+    "conv_d65536_bf16_refined/mu": 1.159e-03,
+    "conv_d65536_bf16_refined/s": 6.360e-03,
+    "conv_d65536_fp32/mu": 2.076e-05,
+    "conv_d65536_fp32/s": 5.279e-05,
     "conv_fit/jacobi/mu": 1.836e-05,
     "conv_fit/jacobi/s": 3.333e-05,
     "conv_fit/ones/mu": 1.858e-05,
@@ -139,6 +143,14 @@ MEASURED: dict[str, float] = {
     "hadamard_fp32/s_vs_oracle": 6.407e-05,
     "large_bench_fit/nrmse": 2.267e-02,
     "large_bench_fit/true_residual": 9.621e-06,
+    "large_bf16_refined/mstep_denominator_support": 3.348e-05,
+    "large_bf16_refined/mu": 5.901e-05,
+    "large_bf16_refined/s": 1.377e-03,
+    "large_bf16_refined/s_sampled_vs_exact_solves": 5.962e-04,
+    "large_fp32/mstep_denominator_support": 2.737e-05,
+    "large_fp32/mu": 2.216e-05,
+    "large_fp32/s": 1.769e-04,
+    "large_fp32/s_sampled_vs_exact_solves": 1.423e-04,
     "large_operator/bf16": 1.906e-07,
     "large_operator/fp32": 1.223e-07,
     "medium/mu": 1.070e-06,
@@ -151,6 +163,20 @@ MEASURED: dict[str, float] = {
     "multitask_L3/task1/s": 3.134e-05,
     "multitask_L3/task2/mu": 1.105e-06,
     "multitask_L3/task2/s": 3.246e-05,
+    "multitask_batched_L1/task0/mu": 1.673e-06,
+    "multitask_batched_L1/task0/s": 6.535e-05,
+    "multitask_batched_L3/task0/mu": 9.566e-07,
+    "multitask_batched_L3/task0/s": 4.550e-05,
+    "multitask_batched_L3/task1/mu": 1.468e-06,
+    "multitask_batched_L3/task1/s": 4.517e-05,
+    "multitask_batched_L3/task2/mu": 8.601e-07,
+    "multitask_batched_L3/task2/s": 4.613e-05,
+    "multitask_batched_uneven/task0/mu": 1.476e-05,
+    "multitask_batched_uneven/task0/s": 2.217e-06,
+    "multitask_batched_uneven/task1/mu": 1.943e-05,
+    "multitask_batched_uneven/task1/s": 2.094e-06,
+    "multitask_batched_uneven/task2/mu": 2.722e-06,
+    "multitask_batched_uneven/task2/s": 6.054e-06,
     "multitask_conv_bf16/task0/mu": 4.627e-06,
     "multitask_conv_bf16/task0/s": 1.703e-05,
     "multitask_conv_bf16/task1/mu": 6.182e-06,

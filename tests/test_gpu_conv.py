@@ -215,3 +215,33 @@ def test_conv_large_bench_fit_properties(gpu, conv_large):
     check("conv_bench_fit/true_residual", res, 3 * w["tol"])
     # recovery of the Bernoulli(0.01) Exp(1) spikes (sanity, not parity; measured 16.9 %)
     check("conv_bench_fit/nrmse", nrmse, 0.18)
+
+
+# ---------------------------------------------------------------------------
+# the FIR workload's shape at D = 2^16 against the stored oracle fit
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["fp32", "bf16_refined"])
+def test_conv_d65536_fit_matches_stored_oracle(gpu, form):
+    """D = 2^16, 256 taps of exp(-t/50), Bernoulli(0.01) Exp(1) spikes, sigma = 0.05, K = 20,
+    T = 5, tol 1e-8, U = 600, probe seed 2024 (tests/golden/make_reference.py conv16): 64
+    full 1024-sample runs per column tile, two tiles (the second five columns wide), the
+    same kernels as the D = 2^20 workload.  FP32 fit: mu within 1e-4, s within 1e-3;
+    bf16 taps with the last 3 E-steps on the FP32 taps: the stated FIR bf16 bounds."""
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "conv16_oracle.npz")
+    if not os.path.exists(path):
+        pytest.fail(f"{path} is missing: python tests/golden/make_reference.py conv16")
+    g = np.load(path)
+    D, T, tol, U = int(g["D"]), int(g["T"]), float(g["tol"]), int(g["U"])
+    prob = workloads.make_workload("conv", D=D)
+    w = workloads.WORKLOADS["conv"]
+    kw = dict(phi_dtype="bf16", refine_last=3) if form == "bf16_refined" else {}
+    mu, s, alpha, st = _conv_fit(gpu, prob, w["K"], T, U, tol, int(g["seed"]), **kw)
+    steps, steps_or = st["total_cg_steps"], int(g["cg_steps"].sum())
+    print(f"conv D={D} {form}: CG steps gpu {st['cg_steps'][:T]} oracle {list(g['cg_steps'])} "
+          f"(ratio {steps / steps_or:.3f})")
+    bar_mu, bar_s = (1e-4, 1e-3) if form == "fp32" else (BF16_REFINED_FIR_MU, BF16_REFINED_FIR_S)
+    check(f"conv_d65536_{form}/mu", _rel(mu, g["mu"]), bar_mu)
+    check(f"conv_d65536_{form}/s", _rel(s, g["s"]), bar_s)
+    assert st["breakdown"] == 0 and all(np.isfinite(x).all() for x in (mu, s, alpha))

@@ -1,18 +1,30 @@
-"""GPU checks at the full size of the benchmark workload (N=16384, D=65536, K=32).
+"""GPU checks at the full size of the benchmark workload (N=16384, D=65536, K=32, T=30,
+tol 1e-5, probe seed 2024).
 
-A complete FP64 oracle fit at this size takes about an hour on the host, so:
-  * the operator is compared with the oracle on sampled output coordinates it
-    computes one by one (Psi_j = beta Phi_:j^T (Phi P) + alpha_j P_j);
-  * the benchmark's own fit (bf16 dictionary, last 3 EM iterations FP32) is
-    checked by properties that hold at any size: the true FP64 residual of its
-    mu column, and the end-to-end recovery (NRMSE) that the paper reports for
-    dense Gaussian dictionaries after 30 EM iterations (below 2 %).
+* The operator against the oracle on sampled output coordinates it computes one by
+  one (Psi_j = beta Phi_:j^T (Phi P) + alpha_j P_j).
+* Both fits of the benchmark, all-FP32 and bf16 with the last 3 EM iterations on the
+  FP32 dictionary, against the stored FP64 oracle fit of the same problem
+  (tests/golden/make_reference.py large): mu within 1e-4 (FP32) or the stated bf16
+  bound, s within 1e-3 or its bf16 bound, and the GPU/oracle ratio of CG steps.
+* diag(Sigma) independently of the E-step's solves: for 64 sampled coordinates the
+  stored golden holds c_j = A^{-1} e_j at alpha^(T) (FP64 PCG to 1e-11), hence the value
+  the diagonal estimate of Eq. (diag-estimate) takes with the last E-step's probes when
+  every solve is exact, (1/K) sum_k p_kj (c_j . p_k), and Sigma_jj itself with the spread
+  of the Rademacher estimate (Lemma 1).  The GPU's s at those coordinates is compared
+  with the first; the second bounds how far any K-probe estimate can sit from Sigma_jj.
+* The benchmark fit's true FP64 residual and recovery (properties at any size).
 The contexts are created exactly as bench.py creates them.
 """
+import os
+
 import numpy as np
 import pytest
 
 import workloads
+from bars import BF16_REFINED_MU, BF16_REFINED_S, check
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "large_oracle.npz")
 
 pytestmark = pytest.mark.gpu
 
@@ -75,8 +87,54 @@ def test_large_operator_sampled(gpu, large, dtype):
     scale = prob.beta * (np.abs(cols).T @ np.abs(V)) + np.abs(alpha[js, None] * P64[js])
     err = np.abs(got - ref) / scale
     tol = 1e-5 if dtype == "fp32" else 1e-4
-    print(f"{dtype}: max scaled error {err.max():.2e}")
-    assert err.max() < tol
+    check(f"large_operator/{dtype}", err.max(), tol)
+
+
+def _bench_fit(gpu, prob, phi_d, y_d, form):
+    w = workloads.WORKLOADS["large"]
+    kw = dict(phi_dtype="bf16", refine_last=3) if form == "bf16_refined" else dict(phi_dtype="fp32")
+    m = gpu.CoFEM(prob.N, prob.D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024, **kw)
+    m.set_dictionary(phi_d)
+    m.fit(y_d)
+    mu, s, alpha, st = m.posterior()
+    m.close()
+    return (mu.cpu().numpy().astype(np.float64), s.cpu().numpy().astype(np.float64),
+            alpha.cpu().numpy().astype(np.float64), st)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16_refined"])
+def test_large_fit_matches_stored_oracle(gpu, large, form):
+    prob, phi_d, y_d = large
+    if not os.path.exists(GOLDEN):
+        pytest.fail(f"{GOLDEN} is missing: python tests/golden/make_reference.py large")
+    g = np.load(GOLDEN)
+    assert int(g["seed"]) == 2024
+    mu, s, alpha, st = _bench_fit(gpu, prob, phi_d, y_d, form)
+    steps, steps_or = st["total_cg_steps"], int(g["cg_steps"].sum())
+    sup = np.abs(g["mu"]) > 1e-3 * np.abs(g["mu"]).max()
+    print(f"large {form}: CG steps gpu {steps} oracle {steps_or} (ratio {steps / steps_or:.3f}); "
+          f"support mu rel {_rel(mu[sup], g['mu'][sup]):.2e}, NRMSE gpu {_rel(mu, prob.z):.4f} "
+          f"oracle {_rel(g['mu'], prob.z):.4f}")
+    bar_mu, bar_s = (1e-4, 1e-3) if form == "fp32" else (BF16_REFINED_MU, BF16_REFINED_S)
+    check(f"large_{form}/mu", _rel(mu, g["mu"]), bar_mu)
+    check(f"large_{form}/s", _rel(s, g["s"]), bar_s)
+    # the last M-step's denominators on the support, 1 / alpha_j = mu_j^2 + s_j (Eq. mstep,
+    # from E-step T - 1): their error is at most that of mu^2 plus that of s
+    check(f"large_{form}/mstep_denominator_support", _rel(1.0 / alpha[sup], 1.0 / g["alpha"][sup]),
+          2 * bar_mu + bar_s)
+    check(f"large_{form}/cg_step_ratio_minus_1", abs(steps / steps_or - 1.0), 0.05)
+    # diag(Sigma) at the sampled coordinates, independent of the E-step's CG solves
+    js, s_exact, sjj = g["js"], g["s_exact_probes"], g["sigma_jj"]
+    spread = np.sqrt(g["sigma_offdiag_sq"] / 32.0)           # Lemma 1: std of the K = 32 estimate
+    check(f"large_{form}/s_sampled_vs_exact_solves", _rel(s[js], s_exact), 10 * bar_s)
+    z = (s[js] - sjj) / spread
+    print(f"large {form}: s_j - Sigma_jj over the Lemma 1 spread at 64 coordinates: max |z| "
+          f"{np.abs(z).max():.2f}, oracle's own {np.abs((g['s'][js] - sjj) / spread).max():.2f}")
+    assert np.abs(z).max() < 5
 
 
 def test_large_bench_fit_properties(gpu, large):
@@ -91,20 +149,19 @@ def test_large_bench_fit_properties(gpu, large):
     mu = mu.cpu().numpy().astype(np.float64)
     alpha = alpha.cpu().numpy().astype(np.float64)
     s = s.cpu().numpy().astype(np.float64)
-    print(f"bench fit: CG steps per EM iteration {st['cg_steps']}")
+    print(f"bench fit: CG steps per EM iteration {st['cg_steps']}", flush=True)
     assert st["used_bf16"] == [1] * (w["T"] - 3) + [0] * 3
     assert np.isfinite(mu).all() and np.isfinite(s).all() and np.isfinite(alpha).all()
     # Algorithm 1 returns alpha^(T), the alpha of the last E-step (no M-step at t = T), and
     # that E-step used the FP32 dictionary: mu solves (beta Phi^T Phi + diag(alpha)) mu = b.
     # The joint stop rule bounds the recursive residual by tol * ||B||_F (~ tol * ||b|| here);
-    # FP32 rounding lets the true residual drift above it by a modest factor.
+    # FP32 rounding lets the true residual drift from it by a small factor (measured 0.96 tol).
     b = prob.beta * _rmatmul64(prob.phi, prob.y.astype(np.float64)[:, None])[:, 0]
     Amu = prob.beta * _rmatmul64(prob.phi, _matmul64(prob.phi, mu[:, None]))[:, 0] + alpha * mu
     true_res = np.linalg.norm(b - Amu) / np.linalg.norm(b)
     nrmse = np.linalg.norm(mu - prob.z) / np.linalg.norm(prob.z)
-    print(f"true residual of mu {true_res:.2e} (tol {w['tol']:.0e}), NRMSE {100 * nrmse:.2f}%")
-    assert true_res < 100 * w["tol"]
+    check("large_bench_fit/true_residual", true_res, 3 * w["tol"])
     # end-to-end recovery (sanity, not parity).  The paper reports below 2 % after 30 EM
     # iterations for its dense Gaussian setting (Uniform(-2, 2) spikes); this workload's
-    # N(0, 1) spikes include amplitudes near the noise floor, so the bound is looser.
-    assert nrmse < 0.05
+    # N(0, 1) spikes include amplitudes near the noise floor (measured 2.27 %).
+    check("large_bench_fit/nrmse", nrmse, 0.025)

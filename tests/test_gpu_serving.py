@@ -188,3 +188,15 @@ def test_submit_rejects_non_finite_observation(gpu):
     assert e.value.status == -1 and "y[7]" in str(e.value)
     assert srv.stats()["rejected"] == 1
     srv.close()
+
+
+def test_stats_count_dictionary_bytes_and_tick_time(gpu):
+    """The serving roofline's inputs: dict_bytes is the algorithmic dictionary traffic of the
+    completed fits (each CG step reads the N x D FP32 dictionary twice) and tick_ms the device
+    time of the ticks."""
+    probs = [_req(D, 90 + i) for i, D in enumerate([600, 1000, 1400])]
+    kw = dict(K=8, T=4, U=200, tol=1e-5, seed=23)
+    res, st = _run(gpu, probs, kw, budget=GiB, max_slots=4)
+    expect = sum(r[3]["total_cg_steps"] * 2.0 * p.N * p.D * 4 for r, p in zip(res, probs))
+    assert st["dict_bytes"] == expect
+    assert st["tick_ms"] > 0.0 and st["ticks"] > 0
