@@ -88,8 +88,10 @@ def gemm_traffic(N: int, D: int, dom: str):
 
 def stream_peaks():
     """Measured HBM rates on this GPU for context, best of 10, timed with events: a 1 GiB
-    device copy (read + write bytes) and a read-only stream, a sum over 2 GiB (torch's
-    reduction; read bytes only)."""
+    device copy (read + write bytes) and a read-only stream, the row sums of a 2 GiB FP32
+    matrix of 16384 x 32768 (torch's reduction over the last dimension; read bytes only,
+    the fastest read of the torch reductions tried: a full sum, a column sum, amax, a
+    norm, a dot product and an FP32 matrix-vector product read at 3.7-5.6 TB/s)."""
     import torch
 
     n = (1 << 30) // 4
@@ -97,7 +99,8 @@ def stream_peaks():
     b = torch.empty_like(a)
     big = torch.ones(2 * n, dtype=torch.float32, device="cuda")
     res = {}
-    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 2 * 4 * n), ("read", lambda: big.sum(), 8 * n)):
+    rows = big.view(1 << 14, -1)
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 2 * 4 * n), ("read", lambda: rows.sum(1), 8 * n)):
         fn()
         best = None
         for _ in range(10):
@@ -333,8 +336,9 @@ def main():
         "cg_steps_per_em_iter": st["cg_steps"],
         "posterior_variance": run.var,
         "arithmetic": "operator: bf16 (or FP32) dictionary, FP32 accumulation; CG dot products, gamma, eta, rho, pi "
-                      "and the stop test in FP64; X, R, P, Psi stored in FP32, their element-wise updates computed "
-                      "in FP64 and rounded to FP32",
+                      "and the stop test in FP64; X, R, P, Psi stored in FP32, their element-wise updates "
+                      "computed in FP64 with the FP64 step scalars and rounded to FP32 once (an all-FP32 form "
+                      "measured less accurate at no speed gain)",
     }
     if not args.no_fp32 and args.workload == "large":
         el32, st32, tim32, mu32 = run("fp32", 0, 1, 0, True)
@@ -372,10 +376,11 @@ def conv_bench():
     one timed fit with bf16 taps and the last 3 EM iterations on FP32 taps, one timed
     all-FP32 fit, and one timed bf16-refined fit with the non-negative M-step of
     Sec. III-E.2 (the model of the calcium-deconvolution application); NRMSE of mu
-    against the true spikes for each.  Per operator application (both filter passes): algorithmic
-    flops 4 L D Q (Q = K + 1 real columns) against the MFMA peak of the dtype, and
-    algorithmic bytes (pass 1 reads Pd and writes V, pass 2 reads V, Pd, alpha and
-    writes Psi: 20 D Q + 4 D bytes, signals as FP32 or as bf16 hi/lo pairs) against 8 TB/s."""
+    against the true spikes for each.  Per operator application: algorithmic flops
+    4 L D Q (Q = K + 1 real columns) against the MFMA peak of the dtype, and algorithmic
+    bytes against 8 TB/s: FP32, two filter launches moving 20 D Q + 4 D bytes (pass 1
+    reads Pd and writes V, pass 2 reads V, Pd, alpha and writes Psi); bf16, one launch
+    with V kept in registers, 8 D Q + 4 D bytes (Pd as its hi/lo pair, alpha, Psi)."""
     import torch
 
     import paper_2105_10439_amd as lib
@@ -387,7 +392,11 @@ def conv_bench():
     h_d = torch.from_numpy(prob.h).cuda()
     y_d = torch.from_numpy(prob.y).cuda()
     flops_app = 4.0 * L * D * Q
-    bytes_app = 20.0 * D * Q + 4.0 * D
+    # FP32: two filter launches, pass 1 reads Pd and writes V, pass 2 reads V, Pd and alpha
+    # and writes Psi; bf16: one launch with V in registers, reading Pd's hi/lo pair and alpha
+    # and writing Psi (the epilogue's second read of Pd is the same data)
+    bytes_app = {"fp32": 20.0 * D * Q + 4.0 * D, "bf16": 8.0 * D * Q + 4.0 * D}
+    per_app = {"fp32": 2, "bf16": 1}
     peak = {"bf16": 2500.0, "fp32": 157.3}
     res = dict(workload=f"causal FIR dictionary: D=N={D}, {L} taps of exp(-t/{w['tau']:g}), Bernoulli({w['p']})*Exp(1) "
                         f"spikes, sigma={w['sigma']}, K={w['K']} T={w['T']} tol={w['tol']} U={w['U']}",
@@ -417,12 +426,13 @@ def conv_bench():
         for k in ("bf16", "fp32"):
             ms, n = m.get_timing(k)
             if n:
-                app_s = 2 * ms / n * 1e-3
-                passes[k] = dict(launches=n, avg_pass_us=round(1e3 * ms / n, 1),
+                app_s = per_app[k] * ms / n * 1e-3
+                passes[k] = dict(launches=n, launches_per_application=per_app[k],
+                                 avg_launch_us=round(1e3 * ms / n, 1), us_per_application=round(1e6 * app_s, 1),
                                  tflops=round(flops_app / app_s / 1e12, 1),
                                  mfma_frac=round(flops_app / app_s / 1e12 / peak[k], 4),
-                                 gbps=round(bytes_app / app_s / 1e9, 1),
-                                 hbm_frac=round(bytes_app / app_s / 1e9 / HBM_PEAK_GBPS, 4))
+                                 algorithmic_bytes=bytes_app[k], gbps=round(bytes_app[k] / app_s / 1e9, 1),
+                                 hbm_frac=round(bytes_app[k] / app_s / 1e9 / HBM_PEAK_GBPS, 4))
         m.close()
         res[name] = dict(em_iters_per_s=round(w["T"] / el, 3), ms_per_fit=round(1e3 * el, 1),
                          cg_steps=st["total_cg_steps"], ms_per_cg_step=round(1e3 * el / st["total_cg_steps"], 4),
@@ -435,8 +445,11 @@ def conv_bench():
 def multitask_bench():
     """Multi-task CoFEM (Sec. III-E.1): L = 4 tasks of the medium shape (N = 2048,
     D = 8192, FP32 dictionaries, 64 MiB each) sharing one support of 5 % spikes, K = 20,
-    T = 30, tol 1e-5: one warm-up and one timed fit.  The value is shared-alpha EM
-    iterations per second (each = L covariance-free E-steps and one joint M-step)."""
+    T = 30, tol 1e-5: one warm-up and one timed fit in each form, batched (all tasks'
+    systems in one launch per phase) and streams (one context per task on its own stream;
+    the automatic choice at L = 4 and the reported value); then both forms on 32 smaller
+    tasks (N = 512, D = 2048), where the streams no longer fit the hardware queues.  The value is shared-alpha EM iterations per
+    second (each = L covariance-free E-steps and one joint M-step)."""
     import torch
 
     import paper_2105_10439_amd as lib
@@ -447,29 +460,63 @@ def multitask_bench():
     L, N, D = w["L"], w["N"], w["D"]
     phis = [torch.from_numpy(p.phi).cuda() for p in probs]
     ys = [torch.from_numpy(p.y).cuda() for p in probs]
-    m = lib.MultiTask(L, N, D, probs[0].beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024)
-    for l in range(L):
-        m.set_dictionary(l, phis[l])
-    m.fit(ys)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    m.fit(ys)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t
-    steps, nrmse = [], []
-    for l in range(L):
-        mu, _, _, st = m.posterior(l)
-        steps.append(st["total_cg_steps"])
-        z = torch.from_numpy(probs[l].z)
-        nrmse.append(round(float(torch.linalg.vector_norm(mu.double().cpu() - z) / torch.linalg.vector_norm(z)), 4))
-    m.close()
+
+    def one(mode):
+        m = lib.MultiTask(L, N, D, probs[0].beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024, mode=mode)
+        for l in range(L):
+            m.set_dictionary(l, phis[l])
+        m.fit(ys)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        m.fit(ys)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        steps, nrmse = [], []
+        for l in range(L):
+            mu, _, _, st = m.posterior(l)
+            steps.append(st["total_cg_steps"])
+            z = torch.from_numpy(probs[l].z)
+            nrmse.append(round(float(torch.linalg.vector_norm(mu.double().cpu() - z) / torch.linalg.vector_norm(z)), 4))
+        m.close()
+        return el, steps, nrmse
+
+    el, steps, nrmse = one("batched")
+    el_s, steps_s, nrmse_s = one("streams")
+    # many small tasks: L = 32 of N = 512, D = 2048 (same recipe, same K, T, tol)
+    many = {}
+    Lm, Nm, Dm = 32, 512, 2048
+    mprobs = workloads.multitask_problems(Lm, N=Nm, D=Dm, d=Dm // 20, sigma=w["sigma"], seed=w["seed"] + 1)
+    mphis = [torch.from_numpy(p.phi).cuda() for p in mprobs]
+    mys = [torch.from_numpy(p.y).cuda() for p in mprobs]
+    for mode in ("batched", "streams"):
+        m = lib.MultiTask(Lm, Nm, Dm, mprobs[0].beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024,
+                          mode=mode)
+        for l in range(Lm):
+            m.set_dictionary(l, mphis[l])
+        m.fit(mys)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        m.fit(mys)
+        torch.cuda.synchronize()
+        el_m = time.perf_counter() - t
+        m.close()
+        many[mode] = round(w["T"] / el_m, 3)
     op_bytes = 2.0 * N * D * 4 * sum(steps)  # two FP32 dictionary passes per CG step of each task
+    auto = "batched" if L > 4 else "streams"  # cofem_mt_create's automatic choice
+    el_a = el if auto == "batched" else el_s
     res = dict(workload=f"multi-task dense: L={L} tasks of N={N} D={D}, shared support of {w['d']} spikes, "
                         f"sigma={w['sigma']}, K={w['K']} T={w['T']} tol={w['tol']} U={w['U']}, FP32",
-               em_iters_per_s=round(w["T"] / el, 3), ms_per_fit=round(1e3 * el, 1), cg_steps_per_task=steps,
-               ms_per_cg_step=round(1e3 * el / sum(steps), 4), nrmse_per_task=nrmse,
-               dictionary_gbps_whole_fit=round(op_bytes / el / 1e9, 1),
-               note="dictionaries (4 x 64 MiB) fit in the 256 MB Infinity Cache, so this is not an HBM figure")
+               form=auto, em_iters_per_s=round(w["T"] / el_a, 3), ms_per_fit=round(1e3 * el_a, 1),
+               batched=dict(em_iters_per_s=round(w["T"] / el, 3), ms_per_fit=round(1e3 * el, 1),
+                            cg_steps_per_task=steps, ms_per_cg_step=round(1e3 * el / max(steps), 4),
+                            nrmse_per_task=nrmse, dictionary_gbps_whole_fit=round(op_bytes / el / 1e9, 1)),
+               streams=dict(em_iters_per_s=round(w["T"] / el_s, 3), ms_per_fit=round(1e3 * el_s, 1),
+                            cg_steps_per_task=steps_s, nrmse_per_task=nrmse_s),
+               many_tasks=dict(workload=f"L={Lm} tasks of N={Nm} D={Dm}, {Dm // 20} shared spikes, same settings",
+                               em_iters_per_s_batched=many["batched"], em_iters_per_s_streams=many["streams"]),
+               note="ms_per_cg_step: fit time over the most CG steps of any task (the tasks advance "
+                    "together); dictionaries (4 x 64 MiB) and their transposed copies are 512 MiB, about "
+                    "twice the 256 MB Infinity Cache")
     log(f"multitask: {res}")
     return res
 

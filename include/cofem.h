@@ -287,9 +287,10 @@ typedef struct cofem_mt cofem_mt;
 #define COFEM_MAX_TASKS 64
 
 /* How the L E-steps of an EM iteration run (cofem_mt_create_mode). */
-#define COFEM_MT_AUTO 0    /* batched when the settings allow it, else streams */
+#define COFEM_MT_AUTO 0    /* batched when the settings allow it and L > 4, else streams */
 #define COFEM_MT_STREAMS 1 /* one context per task, each on its own stream */
 #define COFEM_MT_BATCHED 2 /* all tasks' systems together, one launch per phase */
+#define COFEM_MT_AUTO_STREAMS_MAX 4 /* COFEM_MT_AUTO: the most tasks it runs as streams */
 
 /*
  * Validate *p (the shape N x D and the settings every task shares; mstep_mode must
@@ -310,7 +311,12 @@ typedef struct cofem_mt cofem_mt;
  * `stream` after them at its end, so the caller sees the fit's work on `stream` alone.
  * Dense, FIR and subsampled-DCT dictionaries, every precision form.
  *
- * COFEM_MT_AUTO takes the batched form when *p allows it.  1 <= L <= COFEM_MAX_TASKS.
+ * COFEM_MT_AUTO takes the batched form when *p allows it and L > COFEM_MT_AUTO_STREAMS_MAX:
+ * the task streams overlap only as far as the hardware queues of a process go (4 by
+ * default), so beyond that the batched form is faster (measured at K = 20: L = 16 tasks of
+ * 1024 x 4096, 97 against 69 EM iterations/s; L = 32 of 512 x 2048, 140 against 45), while
+ * at L = 4 the streams overlap their small kernels better (L = 4 of 2048 x 8192: 66 against
+ * 61).  1 <= L <= COFEM_MAX_TASKS.
  * Errors: COFEM_EINVAL (bad parameters or mode, or COFEM_MT_BATCHED with settings it
  * does not take), COFEM_ENOMEM, COFEM_EDEVICE.
  */

@@ -299,7 +299,7 @@ MT_MODES = {"auto": 0, "streams": 1, "batched": 2}
 class MultiTask(CoFEM):
     """Multi-task CoFEM (cofem_mt_*): L problems of one shape sharing alpha.  mode: "batched"
     (all tasks' systems together, one launch per phase), "streams" (one context per task on
-    its own stream) or "auto" (batched when the settings allow it)."""
+    its own stream) or "auto" (batched when the settings allow it and L > 4, else streams)."""
 
     def __init__(self, L, N, D, beta, K, T, U, tol, theta="ones", stop="joint", op="dense", phi_dtype="fp32",
                  refine_last=0, conv_taps=0, seed=0, alpha_floor=1e-30, stream=None, mode="auto"):

@@ -323,12 +323,22 @@ cofem_status apply_conv(cofem_ctx* c, bool use16, const float* alpha, const Solv
   p2.pipart = c->pipart;
   TimedLaunch t;
   cofem_status rc;
-  const int which = use16 ? 1 : 0;
-  if (c->timing && (rc = timed_begin(c, which, step, &t)) != COFEM_OK) return rc;
-  launch_conv_pass(p1, 0, use16 ? 1 : 0, c->stream);
+  if (use16) {
+    // both filters in one launch, V in registers
+    ConvArgs op = p2;
+    op.xclear = p1.xclear;
+    op.inH = c->PdH;
+    op.inL = c->PdL;
+    if (c->timing && (rc = timed_begin(c, 1, step, &t)) != COFEM_OK) return rc;
+    launch_conv_op_bf16(op, c->stream);
+    if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
+    return COFEM_OK;
+  }
+  if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
+  launch_conv_pass(p1, 0, 0, c->stream);
   if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
-  if (c->timing && (rc = timed_begin(c, which, step, &t)) != COFEM_OK) return rc;
-  launch_conv_pass(p2, 1, use16 ? 1 : 0, c->stream);
+  if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
+  launch_conv_pass(p2, 1, 0, c->stream);
   if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
   return COFEM_OK;
 }
@@ -659,13 +669,15 @@ COFEM_API cofem_status cofem_create(const cofem_params* p, void* stream, cofem_c
     }
   }
   // hi/lo slices of Pd and V: the bf16 operators; with the third slices also the dense
-  // FP32 operator
+  // FP32 operator (the bf16 FIR operator keeps V in registers and needs no V slices)
   const bool dense32 = c->need32 && !matrix_free;
   if (c->need16 || dense32) {
     TRY(dalloc(c, &c->PdH, (size_t)Qp * Dp));
     TRY(dalloc(c, &c->PdL, (size_t)Qp * Dp));
-    TRY(dalloc(c, &c->VH, (size_t)Qp * Np));
-    TRY(dalloc(c, &c->VL, (size_t)Qp * Np));
+    if (!conv) {
+      TRY(dalloc(c, &c->VH, (size_t)Qp * Np));
+      TRY(dalloc(c, &c->VL, (size_t)Qp * Np));
+    }
   }
   if (dense32) {
     TRY(dalloc(c, &c->PdX, (size_t)Qp * Dp));
@@ -959,7 +971,9 @@ COFEM_API cofem_status cofem_mt_create_mode(const cofem_params* p, int32_t L, in
     return fail(COFEM_EINVAL, "the batched multi-task fit takes dense FP32 dictionaries, no refinement, K <= 31");
   cofem_mt* m = new (std::nothrow) cofem_mt();
   if (!m) return fail(COFEM_ENOMEM, "host allocation failed");
-  if (mode == COFEM_MT_BATCHED || (mode == COFEM_MT_AUTO && eligible)) {
+  // the streams form overlaps the tasks only as far as the device's hardware queues go (4
+  // per process by default): batched beyond that
+  if (mode == COFEM_MT_BATCHED || (mode == COFEM_MT_AUTO && eligible && L > COFEM_MT_AUTO_STREAMS_MAX)) {
     rc = cofem::mtb_create(*p, L, static_cast<hipStream_t>(stream), &m->batch);
     if (rc != COFEM_OK) {
       delete m;

@@ -327,6 +327,183 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// The whole bf16 operator application in one pass: Psi = beta Phi^T (Phi Pd) + alpha Pd
+// and the pi partials, with V = Phi Pd kept in registers instead of going through HBM.
+// A wave owns one column tile and one run of output blocks [m0, m0 + cnt) as in the
+// two-pass form.  Step k computes V block m0 + k by the causal filter (from Pd blocks
+// m0 + k - NB + 1 .. m0 + k, a window of S slots loaded PF steps ahead) and pushes it,
+// as its hi/lo bf16 pair in the MFMA operand layout, into a ring of S slots; from step
+// NB - 1 on it also computes the anti-causal output block m0 + k - NB + 1 from the NB
+// newest V blocks and runs the epilogue.  The run thus computes NB - 1 V blocks past
+// its end (the halo the anti-causal filter reads), which the two-pass form read back
+// from HBM.  The arithmetic is that of the two passes step for step (the same MFMAs in
+// the same order, V rounded to the same pair, rows >= D zeroed), so Psi and pi are
+// bitwise the same.  The causal filter's output leaves the MFMA with lane (c, g)
+// holding rows 16 par + 4 g .. + 3 of column c; the anti-causal filter takes lane
+// (c, g) = rows 8 g .. 8 g + 7, so each V block is regrouped across lanes (16 lane
+// shuffles) before it is split.  The Toeplitz blocks of both filters (36 KB) sit in LDS.
+template <int NB>
+__global__ __launch_bounds__(256, 2) void k_conv_bf16_op(ConvArgs a) {
+  constexpr int PF = 2, S = NB + PF;
+  if (a.xclear && blockIdx.x == 0 && threadIdx.x == 0) *a.xclear = 0;  // a new CG step
+  if (a.done && *a.done) return;
+  __shared__ bf16x8_t sT[2][2][NB][64];  // [filter][par][d][lane]: causal, anti-causal
+  for (int f = threadIdx.x; f < 4 * NB * 64; f += blockDim.x) {
+    const int l = f & 63, blk = f >> 6;
+    const int d = blk % NB, par = (blk / NB) & 1, dir = blk / (2 * NB);
+    const int r16 = l & 15, g = l >> 4;
+    u16x8 t;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int m = dir == 0 ? 32 * d + 16 * par + r16 - 8 * g - j : 32 * d + 8 * g + j - 16 * par - r16;
+      t[j] = a.hp16[CONV_HOFF + m];
+    }
+    sT[dir][par][d][l] = __builtin_bit_cast(bf16x8_t, t);
+  }
+  __syncthreads();
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= a.nbx * a.nct) return;
+  const int bx = wid / a.nct, ct = wid - bx * a.nct;
+  const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
+  const int64_t q = ct * 16 + r16;
+  const bool qv = q < a.Q;
+  const int64_t nb32 = a.Dp >> 5;
+  const int64_t m0 = (int64_t)bx * (VCHUNK / 32);
+  const int cnt = (int)std::min<int64_t>(VCHUNK / 32, nb32 - m0);
+  const int steps = cnt + NB - 1;
+
+  // Pd pair in the tile-interleaved layout (see k_conv_bf16); padding-column lanes load
+  // column 16 ct's segment and use zeros
+  const int64_t qs = qv ? q : (int64_t)ct * 16;
+  const int64_t bstride = 32 * sig_tile_width(qs, a.Q);
+  const uint16_t* sh = a.inH + sig_index(qs, 8 * g, a.Dp, a.Q);
+  const uint16_t* sl = a.inL + sig_index(qs, 8 * g, a.Dp, a.Q);
+  const int64_t base = m0 - (NB - 1);  // Pd block of window position 0
+  const bf16x8_t zero = __builtin_bit_cast(bf16x8_t, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+  auto load = [&](const uint16_t* s, int64_t p) -> bf16x8_t {
+    const int64_t b = base + p;
+    const bool inb = b >= 0 && b < nb32;
+    const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(s + bstride * (inb ? b : 0));
+    return (qv && inb) ? v : zero;
+  };
+  // epilogue operands of anti-causal output block i of the run (clamped to the run)
+  struct PdRaw {
+    u16x4 h, l;
+  };
+  const int64_t pd0 = sig_index(qs, 4 * g, a.Dp, a.Q) + m0 * bstride;
+  auto clampi = [&](int i) -> int { return i < 0 ? 0 : (i < cnt ? i : cnt - 1); };
+  auto rowp_of = [&](int i) -> int64_t { return (m0 + clampi(i)) * 32 + 4 * g; };
+  auto pd_fetch = [&](int i, int par) -> PdRaw {
+    const int64_t o = pd0 + clampi(i) * bstride + 16 * par;
+    return PdRaw{*reinterpret_cast<const u16x4*>(a.PdH + o), *reinterpret_cast<const u16x4*>(a.PdL + o)};
+  };
+  auto pd_value = [](const PdRaw& r) -> f32x4 {
+    f32x4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = bf16_val(r.h[e]) + bf16_val(r.l[e]);
+    return v;
+  };
+  // regrouping of a V block: lane (c, g) takes rows 8 g .. 8 g + 7, i.e. rows 16 par' + 8 h'
+  // + j with par' = g >> 1, h' = g & 1, from lanes (c, 2 h') (j < 4) and (c, 2 h' + 1)
+  const int src0 = r16 + 16 * (2 * (g & 1)), src1 = src0 + 16;
+  const bool hi_par = (g >> 1) != 0;
+
+  bf16x8_t wh[S], wl[S], vh[S], vl[S];
+#pragma unroll
+  for (int p = 0; p < S - 1; ++p) {
+    wh[p] = load(sh, p);
+    wl[p] = load(sl, p);
+  }
+#pragma unroll
+  for (int p = 0; p < S; ++p) vh[p] = vl[p] = zero;
+  f32x4 aln[2];
+  PdRaw pdn[2];
+#pragma unroll
+  for (int par = 0; par < 2; ++par) {
+    aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(1 - NB) + 16 * par);
+    pdn[par] = pd_fetch(1 - NB, par);
+  }
+  double pacc = 0.0;
+  for (int k0 = 0; k0 < steps; k0 += S) {
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      const int k = k0 + u;
+      wh[(u + S - 1) % S] = load(sh, k + S - 1);
+      wl[(u + S - 1) % S] = load(sl, k + S - 1);
+      const int i = k - (NB - 1);  // anti-causal output block of this step
+      f32x4 al[2];
+      PdRaw pd[2];
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        al[par] = aln[par];
+        pd[par] = pdn[par];
+        aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(i + 1) + 16 * par);
+        pdn[par] = pd_fetch(i + 1, par);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (k < steps) {
+        // causal: V block m0 + k
+        f32x4 acc[2];
+#pragma unroll
+        for (int par = 0; par < 2; ++par) acc[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+          const int w = (u + NB - 1 - d) % S;
+#pragma unroll
+          for (int par = 0; par < 2; ++par) {
+            const bf16x8_t t = sT[0][par][d][lane];
+            acc[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(t, wh[w], acc[par], 0, 0, 0);
+            acc[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(t, wl[w], acc[par], 0, 0, 0);
+          }
+        }
+        const int64_t vrow = (m0 + k) * 32 + 4 * g;
+#pragma unroll
+        for (int par = 0; par < 2; ++par)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (vrow + 16 * par + e >= a.D) acc[par][e] = 0.0f;
+        u16x8 hh, ll;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float x0 = __shfl(acc[0][e], src0, 64), x1 = __shfl(acc[1][e], src0, 64);
+          const float y0 = __shfl(acc[0][e], src1, 64), y1 = __shfl(acc[1][e], src1, 64);
+          uint16_t h, l;
+          split_bf16(hi_par ? x1 : x0, h, l);
+          hh[e] = h;
+          ll[e] = l;
+          split_bf16(hi_par ? y1 : y0, h, l);
+          hh[4 + e] = h;
+          ll[4 + e] = l;
+        }
+        vh[u] = __builtin_bit_cast(bf16x8_t, hh);
+        vl[u] = __builtin_bit_cast(bf16x8_t, ll);
+        if (i >= 0 && i < cnt) {
+          // anti-causal: output block m0 + i from V blocks m0 + i .. m0 + i + NB - 1
+          f32x4 acc2[2];
+#pragma unroll
+          for (int par = 0; par < 2; ++par) acc2[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int d = 0; d < NB; ++d) {
+            const int w = (u + S - (NB - 1) + d) % S;
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+              const bf16x8_t t = sT[1][par][d][lane];
+              acc2[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(t, vh[w], acc2[par], 0, 0, 0);
+              acc2[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(t, vl[w], acc2[par], 0, 0, 0);
+            }
+          }
+          const int64_t rowp = (m0 + i) * 32 + 4 * g;
+#pragma unroll
+          for (int par = 0; par < 2; ++par)
+            conv_epilogue(a, 1, q, qv, rowp + 16 * par, acc2[par], al[par], pd_value(pd[par]), pacc);
+        }
+      }
+    }
+  }
+  conv_pi_store(a, q, qv, g, bx, pacc);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline unsigned cdiv_(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -362,6 +539,14 @@ static void conv_bf16_dir(const ConvArgs& a, int nb, dim3 grid, hipStream_t s) {
   if (nb <= 3) hipLaunchKernelGGL((k_conv_bf16<3, DIR>), grid, dim3(256), 0, s, a);
   else if (nb <= 5) hipLaunchKernelGGL((k_conv_bf16<5, DIR>), grid, dim3(256), 0, s, a);
   else hipLaunchKernelGGL((k_conv_bf16<9, DIR>), grid, dim3(256), 0, s, a);
+}
+
+void launch_conv_op_bf16(const ConvArgs& a, hipStream_t s) {
+  const dim3 grid(cdiv_((int64_t)a.nbx * a.nct, 4));
+  const int nb = conv_blocks_bf16(a.L);
+  if (nb <= 3) hipLaunchKernelGGL((k_conv_bf16_op<3>), grid, dim3(256), 0, s, a);
+  else if (nb <= 5) hipLaunchKernelGGL((k_conv_bf16_op<5>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_conv_bf16_op<9>), grid, dim3(256), 0, s, a);
 }
 
 void launch_conv_pass(const ConvArgs& a, int dir, int bf16, hipStream_t s) {

@@ -210,6 +210,9 @@ void launch_conv_setup(const float* h, int L, int64_t D, int64_t Dp, int jacobi,
 void launch_conv_rhs(const float* hp32, const uint16_t* hp16, int L, int64_t D, int64_t Dp, const float* y,
                      double beta, float* b, hipStream_t s);
 void launch_conv_pass(const ConvArgs& a, int dir, int bf16, hipStream_t s);
+// The bf16 operator in one launch (both filters, V in registers): inH/inL = Pd's pair,
+// PdH/PdL = the same pair, alpha, out32 = Psi, pipart, xclear, done.
+void launch_conv_op_bf16(const ConvArgs& a, hipStream_t s);
 
 // ---- subsampled DCT dictionary (dct.hip) ----------------------------------------
 // Phi = M Omega^{-1}: Omega the orthonormal DCT-II of size D, M keeps N samples.

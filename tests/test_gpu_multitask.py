@@ -205,3 +205,14 @@ def test_batched_tasks_with_different_step_counts(gpu):
         binds(f"multitask_batched_uneven/task{l}", _rel(mus[l], mus_t[l]), bar)
         check(f"multitask_batched_uneven/task{l}/mu", _rel(_np(out[l][0]), mus[l]), bar)
         check(f"multitask_batched_uneven/task{l}/s", _rel(_np(out[l][1]), ss[l]), 10 * bar)
+
+
+def test_auto_mode_takes_batched_beyond_four_tasks(gpu):
+    """The automatic choice: streams up to 4 tasks (the hardware queues a process gets by
+    default), batched beyond, and streams whenever the batched form cannot take the
+    settings (here a bf16 dictionary)."""
+    for L, kw, want in ((4, {}, False), (5, {}, True), (8, dict(phi_dtype="bf16"), False)):
+        m = gpu.MultiTask(L, 64, 256, 1e4, K=4, T=2, U=10, tol=1e-5, **kw)
+        got = m.batched
+        m.close()
+        assert got == want, (L, kw)
