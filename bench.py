@@ -185,8 +185,8 @@ def pmc_probe():
 
 def pmc_probe_conv():
     """As pmc_probe, for the FIR dictionary: the 1 GiB copy, then three applications of the
-    bf16 operator at D = 2^20, 256 taps, K = 20 (one causal and one anti-causal filter pass
-    each)."""
+    bf16 operator at D = 2^20, 256 taps, K = 20 (one k_conv_bf16_op launch each, both filters
+    with V in registers)."""
     import numpy as np
     import torch
 
@@ -394,7 +394,7 @@ def conv_bench():
     flops_app = 4.0 * L * D * Q
     # FP32: two filter launches, pass 1 reads Pd and writes V, pass 2 reads V, Pd and alpha
     # and writes Psi; bf16: one launch with V in registers, reading Pd's hi/lo pair and alpha
-    # and writing Psi (the epilogue's second read of Pd is the same data)
+    # and writing Psi (the epilogue takes Pd from the causal filter's window)
     bytes_app = {"fp32": 20.0 * D * Q + 4.0 * D, "bf16": 8.0 * D * Q + 4.0 * D}
     per_app = {"fp32": 2, "bf16": 1}
     peak = {"bf16": 2500.0, "fp32": 157.3}

@@ -286,6 +286,8 @@ cofem_status apply_dct(cofem_ctx* c, const float* alpha, const SolveCfg& sc, int
   return COFEM_OK;
 }
 
+// The FIR operator: bf16, both filters in one launch with V kept in registers; FP32,
+// the two filter passes with V through memory (conv.hip).
 cofem_status apply_conv(cofem_ctx* c, bool use16, const float* alpha, const SolveCfg& sc, int step) {
   ConvArgs a{};
   a.hp32 = c->hp32;
@@ -298,47 +300,30 @@ cofem_status apply_conv(cofem_ctx* c, bool use16, const float* alpha, const Solv
   a.nbx = (int)((c->Dp + 1023) / 1024);
   a.beta = sc.beta;
   a.done = &c->st->done;
-  ConvArgs p1 = a, p2 = a;
-  if (use16) {
-    p1.xclear = &c->st->xpend;
-    p1.inH = c->PdH;
-    p1.inL = c->PdL;
-    p1.outH = c->VH;
-    p1.outL = c->VL;
-    p2.inH = c->VH;
-    p2.inL = c->VL;
-  } else {
-    p1.in32 = c->Pd;
-    p1.out32 = c->V;
-    p2.in32 = c->V;
-  }
-  p2.out32 = c->Psi;
-  p2.alpha = alpha;
-  if (use16) {  // the bf16 form carries Pd as its hi/lo pair
-    p2.PdH = c->PdH;
-    p2.PdL = c->PdL;
-  } else {
-    p2.Pd = c->Pd;
-  }
-  p2.pipart = c->pipart;
+  a.out32 = c->Psi;
+  a.alpha = alpha;
+  a.pipart = c->pipart;
   TimedLaunch t;
   cofem_status rc;
-  if (use16) {
-    // both filters in one launch, V in registers
-    ConvArgs op = p2;
-    op.xclear = p1.xclear;
-    op.inH = c->PdH;
-    op.inL = c->PdL;
+  if (use16) {  // the bf16 form carries Pd as its hi/lo pair
+    a.xclear = &c->st->xpend;
+    a.inH = c->PdH;
+    a.inL = c->PdL;
     if (c->timing && (rc = timed_begin(c, 1, step, &t)) != COFEM_OK) return rc;
-    launch_conv_op_bf16(op, c->stream);
+    launch_conv_op_bf16(a, c->stream);
     if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
     return COFEM_OK;
   }
+  ConvArgs p1 = a;
+  p1.in32 = c->Pd;
+  p1.out32 = c->V;
+  a.in32 = c->V;
+  a.Pd = c->Pd;
   if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
-  launch_conv_pass(p1, 0, 0, c->stream);
+  launch_conv_pass(p1, 0, c->stream);
   if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
   if (c->timing && (rc = timed_begin(c, 0, step, &t)) != COFEM_OK) return rc;
-  launch_conv_pass(p2, 1, 0, c->stream);
+  launch_conv_pass(a, 1, c->stream);
   if (c->timing && (rc = timed_end(c, &t)) != COFEM_OK) return rc;
   return COFEM_OK;
 }

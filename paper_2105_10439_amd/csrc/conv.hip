@@ -9,14 +9,16 @@
 // the 16 x 16 Toeplitz block T_d[r][c] = h[16 d + r - c] (zero outside [0, L)),
 // d = 0 .. NB-1 with NB = floor((L + 14) / 16) + 1 (17 for L = 256, so the
 // blocks carry 6 % more multiply-adds than the taps).  A wave owns one 16-column
-// tile of right-hand sides and a run of VCHUNK output samples: the NB Toeplitz
-// blocks sit in VGPRs in the MFMA operand layout for the whole run, and the
-// input blocks pass through a sliding window of NB VGPR slots, so each input
-// sample is loaded once per run and used NB times.  The anti-causal filter is
-// the same with T_d^T and the window running forward.  The second pass fuses
-// the rest of the operator application: Psi = beta (.) + alpha Pd and the FP64
-// partials of pi_q = sum_j Pd_jq Psi_jq, one per (column, VCHUNK run), in the
-// layout the CG update kernel reduces.
+// tile of right-hand sides and a run of VCHUNK output samples, and the input
+// blocks pass through a sliding window of VGPR slots, so each input sample is
+// loaded once per run and used NB times.  The anti-causal filter is the same with
+// T_d^T and the window running forward, and it carries the rest of the operator
+// application: Psi = beta (.) + alpha Pd and the FP64 partials of
+// pi_q = sum_j Pd_jq Psi_jq, one per (column, VCHUNK run), in the layout the CG
+// update kernel reduces.  FP32 form: two passes (k_conv_f32), V through memory, the
+// Toeplitz blocks in VGPRs for the whole run.  bf16 form: one launch per application
+// (k_conv_bf16_op), V = Phi Pd kept in registers, the Toeplitz blocks of both filters
+// in LDS.
 //
 // FP32 form: v_mfma_f32_16x16x4_f32, taps and signals in FP32.
 // bf16 form: v_mfma_f32_16x16x32_bf16 with the taps rounded to bfloat16 once (the
@@ -35,7 +37,6 @@
 namespace cofem {
 
 typedef __attribute__((ext_vector_type(8))) unsigned short u16x8;
-typedef __attribute__((ext_vector_type(4))) unsigned short u16x4;
 
 // Padded taps: hp[CONV_HOFF + m] = h[m] for 0 <= m < L, zero for the rest of the
 // CONV_HPAD entries (every index the Toeplitz blocks touch stays inside).
@@ -202,130 +203,6 @@ __global__ __launch_bounds__(256) void k_conv_f32(ConvArgs a) {
   if (DIR == 1) conv_pi_store(a, q, qv, g, bx, pacc);
 }
 
-template <int NB, int DIR>
-__global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
-  constexpr int PF = DIR == 1 ? 2 : 3, S = NB + PF;  // the anti-causal pass also holds its epilogue operands
-  if (DIR == 0 && a.xclear && blockIdx.x == 0 && threadIdx.x == 0) *a.xclear = 0;  // a new CG step
-  if (a.done && *a.done) return;
-  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wid >= a.nbx * a.nct) return;
-  const int bx = wid / a.nct, ct = wid - bx * a.nct;
-  const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
-  const int64_t q = ct * 16 + r16;
-  const bool qv = q < a.Q;
-  const int64_t nb32 = a.Dp >> 5;
-  const int64_t m0 = (int64_t)bx * (VCHUNK / 32);
-  const int cnt = (int)std::min<int64_t>(VCHUNK / 32, nb32 - m0);
-
-  // Toeplitz blocks: lane (r16, g) holds T^(par)_d[r16][8 g .. 8 g + 8).
-  bf16x8_t A[2][NB];
-#pragma unroll
-  for (int par = 0; par < 2; ++par)
-#pragma unroll
-    for (int d = 0; d < NB; ++d) {
-      u16x8 t;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int m = DIR == 0 ? 32 * d + 16 * par + r16 - 8 * g - j : 32 * d + 8 * g + j - 16 * par - r16;
-        t[j] = a.hp16[CONV_HOFF + m];
-      }
-      A[par][d] = __builtin_bit_cast(bf16x8_t, t);
-    }
-
-  // signal slices in the tile-interleaved layout: block b of this tile is 32 w contiguous
-  // elements for the tile's w real columns, lane (r16, g) at 32 r16 + 8 g; lanes of padding
-  // columns load column 16 ct's segment and use zeros
-  const int64_t qs = qv ? q : (int64_t)ct * 16;
-  const int64_t bstride = 32 * sig_tile_width(qs, a.Q);
-  const uint16_t* sh = a.inH + sig_index(qs, 8 * g, a.Dp, a.Q);
-  const uint16_t* sl = a.inL + sig_index(qs, 8 * g, a.Dp, a.Q);
-  const int64_t base = DIR == 0 ? m0 - (NB - 1) : m0;
-  const bf16x8_t zero = __builtin_bit_cast(bf16x8_t, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-  auto load = [&](const uint16_t* s, int64_t b) -> bf16x8_t {
-    const bool inb = b >= 0 && b < nb32;
-    const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(s + bstride * (inb ? b : 0));
-    return (qv && inb) ? v : zero;
-  };
-  auto rowp_of = [&](int i) -> int64_t { return (m0 + std::min(i, cnt - 1)) * 32 + 4 * g; };
-  // the epilogue's Pd: its hi/lo pair (the value the filter passes used) for rows
-  // 32 (m0 + i) + 16 par + 4 g .. + 3 of column qs, at block stride bstride like the
-  // signal; fetched as raw halves and summed at use
-  struct PdRaw {
-    u16x4 h, l;
-  };
-  const int64_t pd0 = DIR == 1 ? sig_index(qs, 4 * g, a.Dp, a.Q) + m0 * bstride : 0;
-  auto pd_fetch = [&](int i, int par) -> PdRaw {
-    const int64_t o = pd0 + std::min(i, cnt - 1) * bstride + 16 * par;
-    return PdRaw{*reinterpret_cast<const u16x4*>(a.PdH + o), *reinterpret_cast<const u16x4*>(a.PdL + o)};
-  };
-  auto pd_value = [](const PdRaw& r) -> f32x4 {
-    f32x4 v;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = bf16_val(r.h[e]) + bf16_val(r.l[e]);
-    return v;
-  };
-
-  bf16x8_t wh[S], wl[S];
-#pragma unroll
-  for (int p = 0; p < S - 1; ++p) {
-    wh[p] = load(sh, base + p);
-    wl[p] = load(sl, base + p);
-  }
-  // epilogue operands (anti-causal pass), fetched one iteration ahead
-  f32x4 aln[2];
-  PdRaw pdn[2];
-#pragma unroll
-  for (int par = 0; par < 2; ++par) {
-    aln[par] = f32x4{0.f, 0.f, 0.f, 0.f};
-    pdn[par] = PdRaw{u16x4{0, 0, 0, 0}, u16x4{0, 0, 0, 0}};
-    if (DIR == 1) {
-      aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(0) + 16 * par);
-      pdn[par] = pd_fetch(0, par);
-    }
-  }
-  double pacc = 0.0;
-  for (int i0 = 0; i0 < cnt; i0 += S) {
-#pragma unroll
-    for (int u = 0; u < S; ++u) {
-      const int i = i0 + u;
-      wh[(u + S - 1) % S] = load(sh, base + i + S - 1);
-      wl[(u + S - 1) % S] = load(sl, base + i + S - 1);
-      f32x4 al[2];
-      PdRaw pd[2];
-#pragma unroll
-      for (int par = 0; par < 2; ++par) {
-        al[par] = aln[par];
-        pd[par] = pdn[par];
-        if (DIR == 1) {
-          aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(i + 1) + 16 * par);
-          pdn[par] = pd_fetch(i + 1, par);
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      if (i < cnt) {
-        // hi and lo products accumulate together, as in the dense bf16 contraction
-        f32x4 acc[2];
-#pragma unroll
-        for (int par = 0; par < 2; ++par) acc[par] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int d = 0; d < NB; ++d) {
-          const int w = DIR == 0 ? (u + NB - 1 - d) % S : (u + d) % S;
-#pragma unroll
-          for (int par = 0; par < 2; ++par) {
-            acc[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wh[w], acc[par], 0, 0, 0);
-            acc[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[par][d], wl[w], acc[par], 0, 0, 0);
-          }
-        }
-        const int64_t rowp = (m0 + i) * 32 + 4 * g;  // row of par 0; par 1 is 16 further
-#pragma unroll
-        for (int par = 0; par < 2; ++par)
-          conv_epilogue(a, DIR, q, qv, rowp + 16 * par, acc[par], al[par], pd_value(pd[par]), pacc);
-      }
-    }
-  }
-  if (DIR == 1) conv_pi_store(a, q, qv, g, bx, pacc);
-}
-
 // ---------------------------------------------------------------------------
 // The whole bf16 operator application in one pass: Psi = beta Phi^T (Phi Pd) + alpha Pd
 // and the pi partials, with V = Phi Pd kept in registers instead of going through HBM.
@@ -341,7 +218,9 @@ __global__ __launch_bounds__(256) void k_conv_bf16(ConvArgs a) {
 // bitwise the same.  The causal filter's output leaves the MFMA with lane (c, g)
 // holding rows 16 par + 4 g .. + 3 of column c; the anti-causal filter takes lane
 // (c, g) = rows 8 g .. 8 g + 7, so each V block is regrouped across lanes (16 lane
-// shuffles) before it is split.  The Toeplitz blocks of both filters (36 KB) sit in LDS.
+// shuffles) before it is split.  The epilogue's Pd block is the oldest block of the
+// causal filter's window at that step, so it is regrouped from there the other way
+// instead of read again.  The Toeplitz blocks of both filters (36 KB) sit in LDS.
 template <int NB>
 __global__ __launch_bounds__(256, 2) void k_conv_bf16_op(ConvArgs a) {
   constexpr int PF = 2, S = NB + PF;
@@ -372,8 +251,9 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16_op(ConvArgs a) {
   const int cnt = (int)std::min<int64_t>(VCHUNK / 32, nb32 - m0);
   const int steps = cnt + NB - 1;
 
-  // Pd pair in the tile-interleaved layout (see k_conv_bf16); padding-column lanes load
-  // column 16 ct's segment and use zeros
+  // Pd pair in the tile-interleaved layout of sig_index: block b of this tile is 32 w
+  // contiguous elements for the tile's w real columns, lane (r16, g) at 32 r16 + 8 g;
+  // padding-column lanes load column 16 ct's segment and use zeros
   const int64_t qs = qv ? q : (int64_t)ct * 16;
   const int64_t bstride = 32 * sig_tile_width(qs, a.Q);
   const uint16_t* sh = a.inH + sig_index(qs, 8 * g, a.Dp, a.Q);
@@ -386,27 +266,19 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16_op(ConvArgs a) {
     const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(s + bstride * (inb ? b : 0));
     return (qv && inb) ? v : zero;
   };
-  // epilogue operands of anti-causal output block i of the run (clamped to the run)
-  struct PdRaw {
-    u16x4 h, l;
-  };
-  const int64_t pd0 = sig_index(qs, 4 * g, a.Dp, a.Q) + m0 * bstride;
+  // alpha at the rows of anti-causal output block i of the run (clamped to the run)
   auto clampi = [&](int i) -> int { return i < 0 ? 0 : (i < cnt ? i : cnt - 1); };
   auto rowp_of = [&](int i) -> int64_t { return (m0 + clampi(i)) * 32 + 4 * g; };
-  auto pd_fetch = [&](int i, int par) -> PdRaw {
-    const int64_t o = pd0 + clampi(i) * bstride + 16 * par;
-    return PdRaw{*reinterpret_cast<const u16x4*>(a.PdH + o), *reinterpret_cast<const u16x4*>(a.PdL + o)};
-  };
-  auto pd_value = [](const PdRaw& r) -> f32x4 {
-    f32x4 v;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = bf16_val(r.h[e]) + bf16_val(r.l[e]);
-    return v;
-  };
   // regrouping of a V block: lane (c, g) takes rows 8 g .. 8 g + 7, i.e. rows 16 par' + 8 h'
   // + j with par' = g >> 1, h' = g & 1, from lanes (c, 2 h') (j < 4) and (c, 2 h' + 1)
   const int src0 = r16 + 16 * (2 * (g & 1)), src1 = src0 + 16;
   const bool hi_par = (g >> 1) != 0;
+  // the epilogue's Pd: the anti-causal output block of step k is window position k, so it
+  // comes from the window (the value hi + lo the filters used) regrouped the other way:
+  // lane (c, g) takes rows 16 par + 4 g + e from lane (c, 2 par + (g >> 1)), element
+  // 4 (g & 1) + e
+  const int pdsrc = r16 + 16 * (g >> 1);
+  const bool pd_hi = (g & 1) != 0;
 
   bf16x8_t wh[S], wl[S], vh[S], vl[S];
 #pragma unroll
@@ -417,12 +289,8 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16_op(ConvArgs a) {
 #pragma unroll
   for (int p = 0; p < S; ++p) vh[p] = vl[p] = zero;
   f32x4 aln[2];
-  PdRaw pdn[2];
 #pragma unroll
-  for (int par = 0; par < 2; ++par) {
-    aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(1 - NB) + 16 * par);
-    pdn[par] = pd_fetch(1 - NB, par);
-  }
+  for (int par = 0; par < 2; ++par) aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(1 - NB) + 16 * par);
   double pacc = 0.0;
   for (int k0 = 0; k0 < steps; k0 += S) {
 #pragma unroll
@@ -432,13 +300,10 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16_op(ConvArgs a) {
       wl[(u + S - 1) % S] = load(sl, k + S - 1);
       const int i = k - (NB - 1);  // anti-causal output block of this step
       f32x4 al[2];
-      PdRaw pd[2];
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
         al[par] = aln[par];
-        pd[par] = pdn[par];
         aln[par] = *reinterpret_cast<const f32x4*>(a.alpha + rowp_of(i + 1) + 16 * par);
-        pdn[par] = pd_fetch(i + 1, par);
       }
       __builtin_amdgcn_sched_barrier(0);
       if (k < steps) {
@@ -492,10 +357,23 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16_op(ConvArgs a) {
               acc2[par] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(t, vl[w], acc2[par], 0, 0, 0);
             }
           }
+          float x[8];
+          {
+            const u16x8 ph = __builtin_bit_cast(u16x8, wh[u]), pl = __builtin_bit_cast(u16x8, wl[u]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) x[j] = bf16_val(ph[j]) + bf16_val(pl[j]);
+          }
           const int64_t rowp = (m0 + i) * 32 + 4 * g;
 #pragma unroll
-          for (int par = 0; par < 2; ++par)
-            conv_epilogue(a, 1, q, qv, rowp + 16 * par, acc2[par], al[par], pd_value(pd[par]), pacc);
+          for (int par = 0; par < 2; ++par) {
+            f32x4 pd;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float lo = __shfl(x[e], pdsrc + 32 * par, 64), hi = __shfl(x[4 + e], pdsrc + 32 * par, 64);
+              pd[e] = pd_hi ? hi : lo;
+            }
+            conv_epilogue(a, 1, q, qv, rowp + 16 * par, acc2[par], al[par], pd, pacc);
+          }
         }
       }
     }
@@ -534,13 +412,6 @@ static void conv_f32_dir(const ConvArgs& a, int nb, dim3 grid, hipStream_t s) {
   else hipLaunchKernelGGL((k_conv_f32<17, DIR>), grid, dim3(256), 0, s, a);
 }
 
-template <int DIR>
-static void conv_bf16_dir(const ConvArgs& a, int nb, dim3 grid, hipStream_t s) {
-  if (nb <= 3) hipLaunchKernelGGL((k_conv_bf16<3, DIR>), grid, dim3(256), 0, s, a);
-  else if (nb <= 5) hipLaunchKernelGGL((k_conv_bf16<5, DIR>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_conv_bf16<9, DIR>), grid, dim3(256), 0, s, a);
-}
-
 void launch_conv_op_bf16(const ConvArgs& a, hipStream_t s) {
   const dim3 grid(cdiv_((int64_t)a.nbx * a.nct, 4));
   const int nb = conv_blocks_bf16(a.L);
@@ -549,17 +420,11 @@ void launch_conv_op_bf16(const ConvArgs& a, hipStream_t s) {
   else hipLaunchKernelGGL((k_conv_bf16_op<9>), grid, dim3(256), 0, s, a);
 }
 
-void launch_conv_pass(const ConvArgs& a, int dir, int bf16, hipStream_t s) {
+void launch_conv_pass(const ConvArgs& a, int dir, hipStream_t s) {
   const dim3 grid(cdiv_((int64_t)a.nbx * a.nct, 4));
-  if (bf16) {
-    const int nb = conv_blocks_bf16(a.L);
-    if (dir == 0) conv_bf16_dir<0>(a, nb, grid, s);
-    else conv_bf16_dir<1>(a, nb, grid, s);
-  } else {
-    const int nb = conv_blocks_f32(a.L);
-    if (dir == 0) conv_f32_dir<0>(a, nb, grid, s);
-    else conv_f32_dir<1>(a, nb, grid, s);
-  }
+  const int nb = conv_blocks_f32(a.L);
+  if (dir == 0) conv_f32_dir<0>(a, nb, grid, s);
+  else conv_f32_dir<1>(a, nb, grid, s);
 }
 
 }  // namespace cofem

@@ -209,9 +209,11 @@ void launch_conv_setup(const float* h, int L, int64_t D, int64_t Dp, int jacobi,
 // b = beta Phi^T y with the FP32 taps (hp16 null) or the bfloat16 taps.
 void launch_conv_rhs(const float* hp32, const uint16_t* hp16, int L, int64_t D, int64_t Dp, const float* y,
                      double beta, float* b, hipStream_t s);
-void launch_conv_pass(const ConvArgs& a, int dir, int bf16, hipStream_t s);
+// One FP32 filter pass: dir 0, V = Phi Pd (in32 = Pd, out32 = V); dir 1, Psi = beta Phi^T V
+// + alpha Pd and the pi partials (in32 = V, Pd, alpha, out32 = Psi, pipart).
+void launch_conv_pass(const ConvArgs& a, int dir, hipStream_t s);
 // The bf16 operator in one launch (both filters, V in registers): inH/inL = Pd's pair,
-// PdH/PdL = the same pair, alpha, out32 = Psi, pipart, xclear, done.
+// alpha, out32 = Psi, pipart, xclear, done.
 void launch_conv_op_bf16(const ConvArgs& a, hipStream_t s);
 
 // ---- subsampled DCT dictionary (dct.hip) ----------------------------------------

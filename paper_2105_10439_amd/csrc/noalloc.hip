@@ -138,8 +138,8 @@ COFEM_API cofem_status cofem_conv_apply_A_static(const float* h, int32_t L, int6
   p2.alpha = alpha_p;
   p2.Pd = Pd;
   p2.pipart = pipart;
-  launch_conv_pass(p1, 0, 0, s);
-  launch_conv_pass(p2, 1, 0, s);
+  launch_conv_pass(p1, 0, s);
+  launch_conv_pass(p2, 1, s);
   launch_unpack_block(PsiP, ncols, D, l.Dp, Psi, s);
   if (pi) launch_reduce_pi(ncols, l.Dp, pipart, pi, s);
   const hipError_t e = hipGetLastError();
