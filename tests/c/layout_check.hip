@@ -5,10 +5,15 @@
 //      last tile, only w = min(16, Q - 16 (q / 16)) columns wide, takes no padding);
 //   2. the filter kernels' signal loads, a lane's base sig_index(q, 8 g) plus 32 w per
 //      32-sample block, land where sig_index puts sample 32 b + 8 g;
-//   3. the anti-causal epilogue's reads of P's pair, sig_index(q, 4 g) plus 32 w m plus
-//      16 par, land where sig_index puts sample 32 m + 16 par + 4 g;
-//   4. a full 16-column tile is laid out as per tile, per 32-sample block, 16 columns of
-//      32 samples.
+//   3. a full 16-column tile is laid out as per tile, per 32-sample block, 16 columns of
+//      32 samples;
+// and, independent of Q, the two lane regroupings of the one-launch bf16 operator within a
+// 32-sample block (operand lane g holds rows 8 g .. 8 g + 7; output lane g of half par
+// holds rows 16 par + 4 g .. + 3):
+//   4. V, output to operand: operand lane g' element j takes output lane 2 (g' & 1) + (j >> 2)
+//      of half g' >> 1, element j & 3;
+//   5. the epilogue's Pd, operand to output: output lane g of half par element e takes
+//      operand lane 2 par + (g >> 1), element 4 (g & 1) + e.
 // Exit status 0 and "layout ok" on success; the first mismatch is printed otherwise.
 #include <cstdio>
 #include <vector>
@@ -42,13 +47,22 @@ int main() {
           for (int64_t b = 0; b < (Dp >> 5); ++b) {
             if (sig_index(q, 8 * g, Dp, Q) + 32 * w * b != sig_index(q, 32 * b + 8 * g, Dp, Q))
               return fail("signal load stride", Q, Dp, q, 32 * b + 8 * g);
-            for (int64_t par = 0; par < 2; ++par)
-              if (sig_index(q, 4 * g, Dp, Q) + 32 * w * b + 16 * par != sig_index(q, 32 * b + 16 * par + 4 * g, Dp, Q))
-                return fail("epilogue P pair", Q, Dp, q, 32 * b + 16 * par + 4 * g);
           }
       }
     }
   }
+  // the regroupings: rows of a 32-sample block
+  auto operand_row = [](int g, int j) { return 8 * g + j; };
+  auto output_row = [](int par, int g, int e) { return 16 * par + 4 * g + e; };
+  for (int gp = 0; gp < 4; ++gp)
+    for (int j = 0; j < 8; ++j)
+      if (output_row(gp >> 1, 2 * (gp & 1) + (j >> 2), j & 3) != operand_row(gp, j))
+        return fail("V regrouping", 0, 32, gp, j);
+  for (int par = 0; par < 2; ++par)
+    for (int g = 0; g < 4; ++g)
+      for (int e = 0; e < 4; ++e)
+        if (operand_row(2 * par + (g >> 1), 4 * (g & 1) + e) != output_row(par, g, e))
+          return fail("epilogue Pd regrouping", par, 32, g, e);
   std::printf("layout ok\n");
   return 0;
 }
