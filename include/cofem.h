@@ -425,9 +425,12 @@ cofem_status cofem_server_submit(cofem_server* s, const cofem_params* p, const f
                                  int64_t* id);
 
 /*
- * One scheduling tick: admit what fits, run one tick of every running fit, collect
- * finished fits.  Blocks until the tick's device work is done.  n_running and
- * n_pending (may be NULL) receive the counts after the tick.
+ * One scheduling tick: admit what fits, launch one tick of every running fit, then
+ * collect the fits that the previous tick finished.  Ticks are pipelined: the call
+ * returns while the tick it launched may still run (it waits for the previous one), so
+ * a finished fit becomes DONE one call after the tick that finished it; a call with
+ * nothing running collects the last tick.  n_running and n_pending (may be NULL)
+ * receive the counts after the call.
  */
 cofem_status cofem_server_step(cofem_server* s, int32_t* n_running, int32_t* n_pending);
 

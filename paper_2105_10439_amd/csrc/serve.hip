@@ -481,7 +481,21 @@ struct cofem_server {
   SrvTable* d_table = nullptr;
   int* d_phase = nullptr;
   int* d_ctr = nullptr;  // tile counters: two per CG step of a tick
-  int* h_phase = nullptr;  // pinned
+  // Ticks are pipelined: a step launches the next tick and then reads the previous one's
+  // phases, so the host's work overlaps a running tick.  Per tick buffer b: the phases
+  // (pinned), the events around the graph and after the phase copy, and the table
+  // positions' slots and requests at launch.
+  int* h_phase[2] = {nullptr, nullptr};
+  SrvTable* h_table_up[2] = {nullptr, nullptr};  // pinned staging of the table uploads
+  int table_buf = 0;
+  struct Tick {
+    int n = 0;
+    int slot[SRV_MAXSLOTS];
+    int64_t rid[SRV_MAXSLOTS];
+  } tick[2];
+  int tick_buf = 0;       // buffer of the next launch
+  int tick_pending = -1;  // buffer of the launched tick whose phases are not read yet
+  hipEvent_t ev_ph[2] = {nullptr, nullptr};
   SrvTable h_table{};
   std::vector<SlotDev> slot_dev;
   std::vector<int64_t> slot_req;  // request id per slot, -1 = free
@@ -490,7 +504,7 @@ struct cofem_server {
   int64_t next_id = 1;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  hipEvent_t ev_tick[2] = {nullptr, nullptr};  // around each tick's graph launch
+  hipEvent_t ev_tick[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // around each tick's graph
   bool table_dirty = true;
   double t0 = 0;
   cofem_server_stats stats{};
@@ -561,9 +575,13 @@ void destroy_server(cofem_server* s) {
   if (s->d_table) (void)hipFree(s->d_table);
   if (s->d_phase) (void)hipFree(s->d_phase);
   if (s->d_ctr) (void)hipFree(s->d_ctr);
-  if (s->h_phase) (void)hipHostFree(s->h_phase);
-  for (hipEvent_t e : s->ev_tick)
-    if (e) (void)hipEventDestroy(e);
+  for (int b = 0; b < 2; ++b) {
+    if (s->h_phase[b]) (void)hipHostFree(s->h_phase[b]);
+    if (s->h_table_up[b]) (void)hipHostFree(s->h_table_up[b]);
+    for (hipEvent_t e : s->ev_tick[b])
+      if (e) (void)hipEventDestroy(e);
+    if (s->ev_ph[b]) (void)hipEventDestroy(s->ev_ph[b]);
+  }
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
 }
@@ -710,15 +728,25 @@ COFEM_API cofem_status cofem_server_create(size_t hbm_budget, int32_t max_slots,
       hipMalloc((void**)&s->d_phase, sizeof(int) * SRV_MAXSLOTS) != hipSuccess ||
       hipMalloc((void**)&s->d_ctr, sizeof(int) * 2 * 64) != hipSuccess)  // steps_per_tick <= 64
     return bail(COFEM_ENOMEM, "server tables allocation failed");
-  if (hipHostMalloc((void**)&s->h_phase, sizeof(int) * SRV_MAXSLOTS, hipHostMallocDefault) != hipSuccess) {
-    s->h_phase = nullptr;
-    return bail(COFEM_ENOMEM, "pinned allocation failed");
-  }
-  for (hipEvent_t& e : s->ev_tick)
-    if (hipEventCreate(&e) != hipSuccess) {
-      e = nullptr;
+  for (int b = 0; b < 2; ++b) {
+    if (hipHostMalloc((void**)&s->h_phase[b], sizeof(int) * SRV_MAXSLOTS, hipHostMallocDefault) != hipSuccess) {
+      s->h_phase[b] = nullptr;
+      return bail(COFEM_ENOMEM, "pinned allocation failed");
+    }
+    if (hipHostMalloc((void**)&s->h_table_up[b], sizeof(SrvTable), hipHostMallocDefault) != hipSuccess) {
+      s->h_table_up[b] = nullptr;
+      return bail(COFEM_ENOMEM, "pinned allocation failed");
+    }
+    for (hipEvent_t& e : s->ev_tick[b])
+      if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+        return bail(COFEM_EDEVICE, "event creation failed");
+      }
+    if (hipEventCreateWithFlags(&s->ev_ph[b], hipEventDisableTiming) != hipSuccess) {
+      s->ev_ph[b] = nullptr;
       return bail(COFEM_EDEVICE, "event creation failed");
     }
+  }
   rebuild_table(s);
   if (hipMemcpyAsync(s->d_table, &s->h_table, sizeof(SrvTable), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
       hipStreamSynchronize(s->stream) != hipSuccess)
@@ -768,9 +796,56 @@ COFEM_API cofem_status cofem_server_submit(cofem_server* s, const cofem_params* 
   return COFEM_OK;
 }
 
+namespace {
+
+// Read the phases of the launched tick in buffer b (waiting for it) and retire the
+// requests it finished.  A slot whose request changed since the launch (cancelled, then
+// perhaps re-admitted) is skipped.
+cofem_status harvest_tick(cofem_server* s, int b) {
+  SRV_TRY(hipEventSynchronize(s->ev_ph[b]));
+  float tick_ms = 0.0f;
+  SRV_TRY(hipEventElapsedTime(&tick_ms, s->ev_tick[b][0], s->ev_tick[b][1]));
+  s->stats.tick_ms += tick_ms;
+  s->stats.ticks++;
+  const cofem_server::Tick& t = s->tick[b];
+  for (int k = 0; k < t.n; ++k) {
+    if (s->h_phase[b][k] != PH_DONE) continue;
+    const int slot = t.slot[k];
+    const int64_t rid = t.rid[k];
+    if (s->slot_req[slot] != rid) continue;
+    Request& r = s->reqs[rid];
+    const SlotDev& sd = s->slot_dev[slot];
+    r.mu.resize((size_t)r.p.D);
+    r.s.resize((size_t)r.p.D);
+    r.alpha.resize((size_t)r.p.D);
+    const size_t bytes = (size_t)r.p.D * sizeof(float);
+    CGState st;
+    // a finished slot is left alone by every kernel, so its results are final; the copies
+    // queue behind the tick launched since, which this waits for
+    SRV_TRY(hipMemcpyAsync(r.mu.data(), sd.mu, bytes, hipMemcpyDeviceToHost, s->stream));
+    SRV_TRY(hipMemcpyAsync(r.s.data(), sd.s, bytes, hipMemcpyDeviceToHost, s->stream));
+    SRV_TRY(hipMemcpyAsync(r.alpha.data(), sd.alpha, bytes, hipMemcpyDeviceToHost, s->stream));
+    SRV_TRY(hipMemcpyAsync(&st, sd.st, sizeof(CGState), hipMemcpyDeviceToHost, s->stream));
+    SRV_TRY(hipStreamSynchronize(s->stream));
+    r.total_steps = st.total_steps;
+    s->stats.dict_bytes += (double)st.total_steps * 2.0 * (double)r.p.N * (double)r.p.D * sizeof(float);
+    r.state = COFEM_REQ_DONE;
+    r.t_finish = wall_ms() - s->t0;
+    s->arena.release(r.off, r.bytes);
+    s->stats.bytes_in_use -= (int64_t)r.bytes;
+    s->slot_req[slot] = -1;
+    s->stats.completed++;
+    s->table_dirty = true;
+  }
+  return COFEM_OK;
+}
+
+}  // namespace
+
 COFEM_API cofem_status cofem_server_step(cofem_server* s, int32_t* n_running, int32_t* n_pending) {
   if (!s) return sfail(COFEM_EINVAL, "NULL server");
-  // admission, first in first out
+  // admission, first in first out (each admission waits for the stream: the copies of the
+  // caller's host buffers must be done when it returns)
   while (!s->pending.empty()) {
     int slot = -1;
     for (int i = 0; i < s->max_slots; ++i)
@@ -800,48 +875,40 @@ COFEM_API cofem_status cofem_server_step(cofem_server* s, int32_t* n_running, in
   }
   if (s->table_dirty) {
     rebuild_table(s);
-    SRV_TRY(hipMemcpyAsync(s->d_table, &s->h_table, sizeof(SrvTable), hipMemcpyHostToDevice, s->stream));
+    // staged in pinned memory: the upload runs behind the tick in flight, and the staging
+    // buffer is not written again before that tick's phases have been read
+    SrvTable* up = s->h_table_up[s->table_buf];
+    s->table_buf ^= 1;
+    std::memcpy(up, &s->h_table, sizeof(SrvTable));
+    SRV_TRY(hipMemcpyAsync(s->d_table, up, sizeof(SrvTable), hipMemcpyHostToDevice, s->stream));
     s->table_dirty = false;
   }
   const int n = s->h_table.n;
   s->stats.active = n;
   s->stats.max_active = std::max(s->stats.max_active, n);
+  int launched = -1;
   if (n > 0) {
-    SRV_TRY(hipEventRecord(s->ev_tick[0], s->stream));
+    const int b = s->tick_buf;
+    s->tick_buf ^= 1;
+    SRV_TRY(hipEventRecord(s->ev_tick[b][0], s->stream));
     SRV_TRY(hipGraphLaunch(s->exec, s->stream));
-    SRV_TRY(hipEventRecord(s->ev_tick[1], s->stream));
-    SRV_TRY(hipMemcpyAsync(s->h_phase, s->d_phase, sizeof(int) * n, hipMemcpyDeviceToHost, s->stream));
-    SRV_TRY(hipStreamSynchronize(s->stream));
-    float tick_ms = 0.0f;
-    SRV_TRY(hipEventElapsedTime(&tick_ms, s->ev_tick[0], s->ev_tick[1]));
-    s->stats.tick_ms += tick_ms;
-    s->stats.ticks++;
+    SRV_TRY(hipEventRecord(s->ev_tick[b][1], s->stream));
+    SRV_TRY(hipMemcpyAsync(s->h_phase[b], s->d_phase, sizeof(int) * n, hipMemcpyDeviceToHost, s->stream));
+    SRV_TRY(hipEventRecord(s->ev_ph[b], s->stream));
+    cofem_server::Tick& t = s->tick[b];
+    t.n = n;
     for (int k = 0; k < n; ++k) {
-      if (s->h_phase[k] != PH_DONE) continue;
-      const int slot = s->h_table.slot[k];
-      const int64_t rid = s->slot_req[slot];
-      Request& r = s->reqs[rid];
-      const SlotDev& sd = s->slot_dev[slot];
-      r.mu.resize((size_t)r.p.D);
-      r.s.resize((size_t)r.p.D);
-      r.alpha.resize((size_t)r.p.D);
-      const size_t bytes = (size_t)r.p.D * sizeof(float);
-      CGState st;
-      SRV_TRY(hipMemcpyAsync(r.mu.data(), sd.mu, bytes, hipMemcpyDeviceToHost, s->stream));
-      SRV_TRY(hipMemcpyAsync(r.s.data(), sd.s, bytes, hipMemcpyDeviceToHost, s->stream));
-      SRV_TRY(hipMemcpyAsync(r.alpha.data(), sd.alpha, bytes, hipMemcpyDeviceToHost, s->stream));
-      SRV_TRY(hipMemcpyAsync(&st, sd.st, sizeof(CGState), hipMemcpyDeviceToHost, s->stream));
-      SRV_TRY(hipStreamSynchronize(s->stream));
-      r.total_steps = st.total_steps;
-      s->stats.dict_bytes += (double)st.total_steps * 2.0 * (double)r.p.N * (double)r.p.D * sizeof(float);
-      r.state = COFEM_REQ_DONE;
-      r.t_finish = wall_ms() - s->t0;
-      s->arena.release(r.off, r.bytes);
-      s->stats.bytes_in_use -= (int64_t)r.bytes;
-      s->slot_req[slot] = -1;
-      s->stats.completed++;
-      s->table_dirty = true;
+      t.slot[k] = s->h_table.slot[k];
+      t.rid[k] = s->slot_req[t.slot[k]];
     }
+    launched = b;
+  }
+  // the tick launched by the previous step (this one's, when the server went idle)
+  const int prev = s->tick_pending;
+  s->tick_pending = launched;
+  if (prev >= 0) {
+    cofem_status rc = harvest_tick(s, prev);
+    if (rc != COFEM_OK) return rc;
   }
   int running = 0;
   for (int i = 0; i < s->max_slots; ++i) running += s->slot_req[i] >= 0;
@@ -891,9 +958,10 @@ COFEM_API cofem_status cofem_server_cancel(cofem_server* s, int64_t id) {
   if (r.state == COFEM_REQ_PENDING) {
     s->pending.erase(std::find(s->pending.begin(), s->pending.end(), id));
   } else if (r.state == COFEM_REQ_RUNNING) {
-    // every cofem_server_step ends with the server's stream drained, so no kernel of this
-    // request is in flight: its slot and arena bytes can be handed back at once (the next
-    // tick's table leaves the slot out, and a later admission re-initialises it)
+    // its slot and arena bytes are handed back at once: a tick still in flight may run
+    // this request's tiles, but everything that reuses the bytes (a later admission's
+    // copies and kernels, the next table) is queued behind that tick on the server's
+    // stream, and the tick's phases are not read for a slot whose request changed
     s->arena.release(r.off, r.bytes);
     s->stats.bytes_in_use -= (int64_t)r.bytes;
     s->slot_req[r.slot] = -1;
@@ -932,7 +1000,8 @@ struct MtBatch {
   int* d_ctr = nullptr;
   int* d_phase = nullptr;
   int* d_count = nullptr;  // non-finite entries found by the last check
-  int* h_phase = nullptr;  // pinned
+  int* h_phase[2] = {nullptr, nullptr};  // pinned, one per launch in flight
+  hipEvent_t ev_ph[2] = {nullptr, nullptr};
   std::vector<SlotDev> sd;
   std::vector<char> loaded;
   std::vector<double> ms_setup;
@@ -961,7 +1030,10 @@ void mtb_destroy(MtBatch* b) {
   if (b->d_ctr) (void)hipFree(b->d_ctr);
   if (b->d_phase) (void)hipFree(b->d_phase);
   if (b->d_count) (void)hipFree(b->d_count);
-  if (b->h_phase) (void)hipHostFree(b->h_phase);
+  for (int i = 0; i < 2; ++i) {
+    if (b->h_phase[i]) (void)hipHostFree(b->h_phase[i]);
+    if (b->ev_ph[i]) (void)hipEventDestroy(b->ev_ph[i]);
+  }
   delete b;
 }
 
@@ -998,9 +1070,15 @@ cofem_status mtb_create(const cofem_params& p, int L, hipStream_t stream, MtBatc
       hipMalloc((void**)&b->d_ctr, sizeof(int) * 2 * b->steps) != hipSuccess ||
       hipMalloc((void**)&b->d_count, sizeof(int)) != hipSuccess)
     return bail(COFEM_ENOMEM, "task tables allocation failed");
-  if (hipHostMalloc((void**)&b->h_phase, sizeof(int) * SRV_MAXSLOTS, hipHostMallocDefault) != hipSuccess) {
-    b->h_phase = nullptr;
-    return bail(COFEM_ENOMEM, "pinned allocation failed");
+  for (int i = 0; i < 2; ++i) {
+    if (hipHostMalloc((void**)&b->h_phase[i], sizeof(int) * SRV_MAXSLOTS, hipHostMallocDefault) != hipSuccess) {
+      b->h_phase[i] = nullptr;
+      return bail(COFEM_ENOMEM, "pinned allocation failed");
+    }
+    if (hipEventCreateWithFlags(&b->ev_ph[i], hipEventDisableTiming) != hipSuccess) {
+      b->ev_ph[i] = nullptr;
+      return bail(COFEM_EDEVICE, "event creation failed");
+    }
   }
   SrvTable tab;
   table_clear(tab);
@@ -1098,13 +1176,25 @@ cofem_status mtb_fit(MtBatch* b, const float* const* ys) {
   // each E-step takes at most ceil(U / steps) + 1 launches (its first starts with the
   // E-step initialisation), and the tasks advance together
   const int64_t limit = (int64_t)p.T * ((p.U + b->steps - 1) / b->steps + 2) + 2;
+  // pipelined: launch k + 1 is queued before the phases of launch k are read, so the
+  // device never waits for the host; the launch queued after the last one that mattered
+  // finds every task DONE and does nothing (every kernel skips a finished slot)
+  auto launch = [&](int64_t k) -> cofem_status {
+    const int i = (int)(k & 1);
+    SRV_TRY(hipGraphLaunch(b->exec, b->stream));
+    SRV_TRY(hipMemcpyAsync(b->h_phase[i], b->d_phase, sizeof(int) * b->L, hipMemcpyDeviceToHost, b->stream));
+    SRV_TRY(hipEventRecord(b->ev_ph[i], b->stream));
+    return COFEM_OK;
+  };
+  cofem_status lrc = launch(0);
+  if (lrc != COFEM_OK) return lrc;
   bool done = false;
   for (int64_t tick = 0; tick < limit && !done; ++tick) {
-    SRV_TRY(hipGraphLaunch(b->exec, b->stream));
-    SRV_TRY(hipMemcpyAsync(b->h_phase, b->d_phase, sizeof(int) * b->L, hipMemcpyDeviceToHost, b->stream));
-    SRV_TRY(hipStreamSynchronize(b->stream));
+    if (tick + 1 < limit && (lrc = launch(tick + 1)) != COFEM_OK) return lrc;
+    const int i = (int)(tick & 1);
+    SRV_TRY(hipEventSynchronize(b->ev_ph[i]));
     done = true;
-    for (int l = 0; l < b->L; ++l) done = done && b->h_phase[l] == PH_DONE;
+    for (int l = 0; l < b->L; ++l) done = done && b->h_phase[i][l] == PH_DONE;
   }
   if (!done) return sfail(COFEM_EDEVICE, "batched multi-task fit did not finish within its launch bound");
   b->h_st.assign(b->L, CGState{});
