@@ -400,9 +400,10 @@ def conv_bench():
     peak = {"bf16": 2500.0, "fp32": 157.3}
     res = dict(workload=f"causal FIR dictionary: D=N={D}, {L} taps of exp(-t/{w['tau']:g}), Bernoulli({w['p']})*Exp(1) "
                         f"spikes, sigma={w['sigma']}, K={w['K']} T={w['T']} tol={w['tol']} U={w['U']}",
-               signal_storage="bf16 forms: taps rounded to bf16; the signals P and V travel as hi/lo bf16 pairs "
-                              "(4 bytes per value, the bytes of FP32), so the bf16 gain is the matrix rate, not "
-                              "halved signal traffic")
+               signal_storage="bf16 forms: taps rounded to bf16; the direction P travels as its hi/lo bf16 "
+                              "pair (4 bytes per value, the bytes of FP32) and V = Phi P stays in registers in "
+                              "the one-launch operator, so the bf16 gain is the matrix rate and the V round trip, "
+                              "not halved signal bytes (a 2-byte signal form measured no net gain in emulation)")
     z = torch.from_numpy(prob.z)
     for name, dt, refine, mstep, theta in (("bf16_refined", "bf16", 3, "gaussian", "ones"),
                                            ("fp32", "fp32", 0, "gaussian", "ones"),
