@@ -437,9 +437,11 @@ cofem_status estep_chunk_launches(cofem_ctx* c, bool use16, const float* alpha) 
     if (rc != COFEM_OK) return rc;
     // FIR dictionary, bf16 form: X += gamma P moves from the update to the direction kernel
     const bool xdir = sc.sigblk && sl.H;
-    launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream, xdir);
+    const bool fused = cg_direction_fuses_scalars(sc, sl.H);
+    launch_cg_update(sc, c->Dp, c->minv, c->X, c->R, c->Pd, c->Psi, c->pipart, c->part, c->st, c->stream, xdir,
+                     !fused);
     launch_cg_direction(sc, c->Dp, c->minv, c->R, c->Pd, sl.H, sl.L, c->st, c->stream, sl.X,
-                        xdir ? c->X : nullptr);
+                        xdir ? c->X : nullptr, c->part);
   }
   return COFEM_OK;
 }

@@ -38,6 +38,7 @@ struct CGState {
   int total_steps;      // serving: CG steps over the fit
   int xpend;            // this step's update ran and left X += gamma P to the direction kernel
   int nonfinite;        // non-finite entries found in the last checked input (y, Phi or taps)
+  double rho_prev[QMAX];  // rho_q as the update used it for gamma (the old rho of the direction)
 };
 
 struct SolveCfg {
@@ -142,19 +143,26 @@ void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, double* pi, hipSt
 
 // ---- CG vector updates (Algorithm 2 after the operator) -----------------------
 // gamma_q = rho_q / pi_q (pi reduced from pipart), X += Pd gamma, R -= Psi gamma, partials
-// of ||R_q||^2 and rho'_q = sum R minv R into part; then one block applies the stop rule
-// and computes eta (two launches; three when a first block reduces the pi partials).
+// of ||R_q||^2 and rho'_q = sum R minv R into part; then (scalars) one block applies the stop
+// rule and computes eta (a first block reduces the pi partials when a column has many).
 // xdir: X += gamma Pd is left to launch_cg_direction (FIR dictionary, bf16 form: its direction
 // kernel reads Pd anyway; pass 1 of the filter clears the state's flag each step).
+// scalars = false leaves the scalar reductions to launch_cg_direction (when
+// cg_direction_fuses_scalars), which then runs them in its own launch.
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
                       const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s,
-                      bool xdir = false);
+                      bool xdir = false, bool scalars = true);
+// Whether launch_cg_direction runs the CG scalars too: for column-major directions (every
+// form except the FIR dictionary's bf16 one).
+bool cg_direction_fuses_scalars(const SolveCfg& c, const uint16_t* PdH);
 // Pd = minv R + eta Pd (FP32, and bf16 hi/lo if PdH != null, and the third slice if PdX != null).
 // With X (only with c.sigblk and PdH: the update's xdir form), first X += gamma Pd when the
-// step's update ran, also on the step whose update met the stop rule.
+// step's update ran, also on the step whose update met the stop rule.  When
+// cg_direction_fuses_scalars, the same launch first reduces the update's partials `part`
+// (the CG scalars, and eta per column; part is then required).
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
-                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX = nullptr,
-                         float* X = nullptr);
+                         uint16_t* PdH, uint16_t* PdL, CGState* st, hipStream_t s, uint16_t* PdX = nullptr,
+                         float* X = nullptr, const double* part = nullptr);
 
 // Multi-task M-step over L tasks' mu and s (device arrays of L device pointers).
 void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int64_t D, float* alpha, double floor,

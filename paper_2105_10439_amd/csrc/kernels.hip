@@ -200,13 +200,38 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(SolveCfg c, int nbx, const 
   cg_scalars_block(c, nbx, part, st);
 }
 
+// The CG scalars and the direction update in one launch (column-major directions).  Every
+// block reduces its own column's rho' partials, in the order of cg_scalars_block, for
+// eta_q = rho'_q / rho_q, with rho_q from rho_prev (recorded by the update with gamma, so
+// block (0, 0) can write the new rho while the others still run); block (0, 0) also runs
+// cg_scalars_block, the state's norms, stop rule, step count and done flag.  A block that
+// starts after this step's stop rule has fired may skip its tile: the direction is not
+// used again in the E-step.  Results are those of the separate scalars and direction
+// kernels, bit for bit.
 template <bool NT>
-__global__ __launch_bounds__(VBLOCK) void k_cg_direction(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
-                                                         const float* __restrict__ R, float* __restrict__ Pd,
-                                                         uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
-                                                         uint16_t* __restrict__ PdX, const CGState* __restrict__ st) {
+__global__ __launch_bounds__(VBLOCK) void k_cg_scalars_direction(SolveCfg c, int nbx, const double* __restrict__ part,
+                                                                 int64_t Dp, const float* __restrict__ minv,
+                                                                 const float* __restrict__ R, float* __restrict__ Pd,
+                                                                 uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
+                                                                 uint16_t* __restrict__ PdX, CGState* __restrict__ st) {
   if (st->done) return;
-  cg_direction_tile<NT>(blockIdx.x, blockIdx.y, Dp, minv, R, Pd, PdH, PdL, st, PdX);
+  const int q = blockIdx.y;
+  __shared__ double s_eta;
+  if (threadIdx.x < 64) {
+    const double2* pq = reinterpret_cast<const double2*>(part + (int64_t)q * nbx * 2);
+    double b = 0.0;
+#pragma unroll 8
+    for (int i = threadIdx.x; i < nbx; i += 64) b += pq[i].y;
+    b = wave_sum(b);
+    if (threadIdx.x == 0) {
+      const double old = st->rho_prev[q];
+      s_eta = (old != 0.0) ? b / old : 0.0;
+    }
+  }
+  __syncthreads();
+  const double eta = s_eta;
+  if (blockIdx.x == 0 && blockIdx.y == 0) cg_scalars_block(c, nbx, part, st);
+  cg_direction_tile_eta<NT>(blockIdx.x, q, Dp, eta, minv, R, Pd, PdH, PdL, PdX);
 }
 
 // The direction update with the bf16 slices in the tile-interleaved layout (the FIR
@@ -498,7 +523,8 @@ void launch_finish_pass2(const SolveCfg& c, const float* Ypart, int splits, int6
 constexpr int GAMMA_PRE_MIN_CHUNKS = 128;
 
 void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X, float* R, const float* Pd,
-                      const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s, bool xdir) {
+                      const float* Psi, const double* pipart, double* part, CGState* st, hipStream_t s, bool xdir,
+                      bool scalars) {
   const unsigned nbx = cdiv(Dp, VCHUNK);
   const dim3 grid(nbx, (unsigned)c.Q);
   const bool pre = nbx > (unsigned)GAMMA_PRE_MIN_CHUNKS;
@@ -507,15 +533,17 @@ void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X
              : pre  ? (c.nt_store ? k_cg_update<true, true, true> : k_cg_update<true, false, true>)
                     : (c.nt_store ? k_cg_update<false, true, true> : k_cg_update<false, false, true>);
   hipLaunchKernelGGL(kern, grid, dim3(VBLOCK), 0, s, c, Dp, minv, X, R, Pd, Psi, pipart, part, st);
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(1024), 0, s, c, (int)nbx, (const double*)part, st);
+  if (scalars) hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(1024), 0, s, c, (int)nbx, (const double*)part, st);
 }
+bool cg_direction_fuses_scalars(const SolveCfg& c, const uint16_t* PdH) { return !(c.sigblk && PdH); }
 
 void launch_reduce_pi(int Q, int64_t Dp, const double* pipart, double* pi, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_pi, dim3(1), dim3(VBLOCK), 0, s, Q, (int)cdiv(Dp, VCHUNK), pipart, pi);
 }
 
 void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const float* R, float* Pd,
-                         uint16_t* PdH, uint16_t* PdL, const CGState* st, hipStream_t s, uint16_t* PdX, float* X) {
+                         uint16_t* PdH, uint16_t* PdL, CGState* st, hipStream_t s, uint16_t* PdX, float* X,
+                         const double* part) {
   // FP32 P non-temporally only when the operator reads the slices instead
   const bool nt = c.nt_store && PdH;
   if (c.sigblk && PdH) {
@@ -525,8 +553,10 @@ void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const
                        R, Pd, PdH, PdL, X, st);
     return;
   }
-  hipLaunchKernelGGL(nt ? k_cg_direction<true> : k_cg_direction<false>, dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q),
-                     dim3(VBLOCK), 0, s, c, Dp, minv, R, Pd, PdH, PdL, PdX, st);
+  // column-major directions: the CG scalars run in the same launch
+  hipLaunchKernelGGL(nt ? k_cg_scalars_direction<true> : k_cg_scalars_direction<false>,
+                     dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q), dim3(VBLOCK), 0, s, c, (int)cdiv(Dp, VCHUNK), part, Dp,
+                     minv, R, Pd, PdH, PdL, PdX, st);
 }
 
 void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int64_t D, float* alpha, double floor,

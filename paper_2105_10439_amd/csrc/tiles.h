@@ -633,6 +633,7 @@ __device__ __forceinline__ double column_gamma(int q, int nbx, const double* __r
   if (record && (threadIdx.x & 63) == 0) {
     st->pi[q] = pi;
     st->gamma[q] = gam;
+    st->rho_prev[q] = rho;
     if (act && !(pi > 0.0) && rho != 0.0) {  // breakdown: freeze the column
       st->active[q] = 0;
       atomicAdd(&st->breakdown, 1);
@@ -773,13 +774,12 @@ __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, con
 // when PdX is not null; column-major slices: the interleaved layout of the FIR dictionary
 // has a kernel of its own).  NT: P stored non-temporally (the slices are what the operator reads).
 template <bool NT = false>
-__device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, const float* __restrict__ minv,
-                                                  const float* __restrict__ R, float* __restrict__ Pd,
-                                                  uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
-                                                  const CGState* __restrict__ st, uint16_t* __restrict__ PdX = nullptr) {
+__device__ __forceinline__ void cg_direction_tile_eta(int bx, int q, int64_t Dp, double eta,
+                                                      const float* __restrict__ minv, const float* __restrict__ R,
+                                                      float* __restrict__ Pd, uint16_t* __restrict__ PdH,
+                                                      uint16_t* __restrict__ PdL, uint16_t* __restrict__ PdX) {
   const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
   if (j >= Dp) return;
-  const double eta = st->eta[q];
   const int64_t o = (int64_t)q * Dp + j;
   const f32x4 mi = *reinterpret_cast<const f32x4*>(minv + j);
   const f32x4 r = *reinterpret_cast<const f32x4*>(R + o);
@@ -789,6 +789,13 @@ __device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, con
   if constexpr (NT) __builtin_nontemporal_store(p, reinterpret_cast<f32x4*>(Pd + o));
   else *reinterpret_cast<f32x4*>(Pd + o) = p;
   if (PdH) store_split4<true>(PdH, PdL, o, p, PdX);
+}
+template <bool NT = false>
+__device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, const float* __restrict__ minv,
+                                                  const float* __restrict__ R, float* __restrict__ Pd,
+                                                  uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
+                                                  const CGState* __restrict__ st, uint16_t* __restrict__ PdX = nullptr) {
+  cg_direction_tile_eta<NT>(bx, q, Dp, st->eta[q], minv, R, Pd, PdH, PdL, PdX);
 }
 
 }  // namespace cofem
