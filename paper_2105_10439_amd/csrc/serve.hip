@@ -193,25 +193,36 @@ __global__ __launch_bounds__(VBLOCK) void ks_update(const SlotDev* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(VBLOCK) void ks_scalars(const SlotDev* __restrict__ slots,
-                                                     const SrvTable* __restrict__ tab) {
-  for (int i = blockIdx.x; i < tab->n; i += gridDim.x) {
-    const SlotDev& sd = slots[tab->slot[i]];
-    if (!in_cg(sd)) continue;
-    cg_scalars_block(sd.c, sd.nbx, sd.part, sd.st);
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(VBLOCK) void ks_direction(const SlotDev* __restrict__ slots,
-                                                       const SrvTable* __restrict__ tab) {
+// The CG scalars and the direction of every running slot in one launch (as the
+// single-problem k_cg_scalars_direction): a tile reduces its column's rho' partials for
+// eta with the old rho from rho_prev, and the slot's first tile also runs the slot's
+// scalars (norms, stop rule, step count, done).
+__global__ __launch_bounds__(VBLOCK) void ks_scalars_direction(const SlotDev* __restrict__ slots,
+                                                               const SrvTable* __restrict__ tab) {
+  __shared__ double s_eta;
   const int n = tab->n, total = tab->vq[n];
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     const int i = find_slot(tab->vq, n, t);
     const SlotDev& sd = slots[tab->slot[i]];
     const int local = t - tab->vq[i];
     if (!in_cg(sd) || local >= sd.nbx * sd.c.Q) continue;
-    cg_direction_tile(local % sd.nbx, local / sd.nbx, sd.Dp, sd.minv, sd.R, sd.Pd, nullptr, nullptr, sd.st);
+    const int bx = local % sd.nbx, q = local / sd.nbx;
+    if (threadIdx.x < 64) {
+      const double2* pq = reinterpret_cast<const double2*>(sd.part + (int64_t)q * sd.nbx * 2);
+      double b = 0.0;
+#pragma unroll 8
+      for (int k = threadIdx.x; k < sd.nbx; k += 64) b += pq[k].y;
+      b = wave_sum(b);
+      if (threadIdx.x == 0) {
+        const double old = sd.st->rho_prev[q];
+        s_eta = (old != 0.0) ? b / old : 0.0;
+      }
+    }
+    __syncthreads();
+    const double eta = s_eta;
+    if (local == 0) cg_scalars_block(sd.c, sd.nbx, sd.part, sd.st);
+    cg_direction_tile_eta(bx, q, sd.Dp, eta, sd.minv, sd.R, sd.Pd, nullptr, nullptr, nullptr);
+    __syncthreads();  // s_eta and the scalars' shared arrays are reused by the next tile
   }
 }
 
@@ -547,8 +558,7 @@ cofem_status capture_tick_graph(hipStream_t st, int steps, const SlotDev* slots,
     hipLaunchKernelGGL(ks_gemm, dim3(SRV_GEMM_GRID), dim3(64 * GEMM_WAVES), 0, st, slots, tab, 2, ctr + 2 * k + 1);
     hipLaunchKernelGGL(ks_finish2, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
     hipLaunchKernelGGL(ks_update, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
-    hipLaunchKernelGGL(ks_scalars, dim3(SRV_MAXSLOTS), dim3(VBLOCK), 0, st, slots, tab);
-    hipLaunchKernelGGL(ks_direction, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
+    hipLaunchKernelGGL(ks_scalars_direction, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
   }
   hipLaunchKernelGGL(ks_mstep, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
   hipLaunchKernelGGL(ks_group_alpha, dim3(SRV_VEC_GRID), dim3(VBLOCK), 0, st, slots, tab);
