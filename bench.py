@@ -150,6 +150,9 @@ def parse():
     ap.add_argument("--pmc-probe-conv", action="store_true",
                     help="only run a 1 GiB copy and three bf16 FIR operator applications at D=2^20 "
                          "(for rocprofv3 --pmc)")
+    ap.add_argument("--pmc-probe-dct", action="store_true",
+                    help="only run ten DCT operator applications at D=2^15 and one fit with eager launches "
+                         "(for rocprofv3 --pmc)")
     return ap.parse_args()
 
 
@@ -214,6 +217,34 @@ def pmc_probe_conv():
     log("pmc probe (FIR) done")
 
 
+def pmc_probe_dct():
+    """The DCT workload's kernels for the wave-state counters: ten applications of the split
+    operator (three launches each) at D = 2^15, Q = 21, then one fit with per-launch events, so
+    that its CG steps run as eager launches (the counters see every dispatch)."""
+    import numpy as np
+    import torch
+
+    import paper_2105_10439_amd as lib
+    import workloads
+
+    torch.cuda.set_device(0)
+    w = workloads.WORKLOADS["dct"]
+    prob = workloads.make_workload("dct")
+    m = lib.CoFEM(prob.N, prob.D, prob.beta, K=w["K"], T=w["T"], U=w["U"], tol=w["tol"], seed=2024, op="dct")
+    m.set_dictionary(torch.from_numpy(prob.rows).cuda())
+    rng = np.random.default_rng(0)
+    P = torch.from_numpy(rng.standard_normal((w["K"] + 1, prob.D)).astype(np.float32)).cuda()
+    al = torch.ones(prob.D, dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        m.apply_A(al, P)
+    torch.cuda.synchronize()
+    m.set_timing(True)
+    m.fit(torch.from_numpy(prob.y).cuda())
+    torch.cuda.synchronize()
+    m.close()
+    log("pmc probe (DCT) done")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -224,6 +255,9 @@ def main():
         return
     if args.pmc_probe_conv:
         pmc_probe_conv()
+        return
+    if args.pmc_probe_dct:
+        pmc_probe_dct()
         return
     if args.serve_only:
         import torch

@@ -530,7 +530,6 @@ __global__ __launch_bounds__(SP_NT) void k_dct_split1(DctArgs a) {
   __shared__ float2 twS[S];
   __shared__ float2 ex[16 * SS::CS];
   __shared__ float2 xs[SP_RC * XS];
-  if (a.done && *a.done) return;
   int q, g;
   sp_tile(SS::G, q, g);
   const float* __restrict__ p = a.in + (int64_t)q * a.Dp;
@@ -551,6 +550,7 @@ __global__ __launch_bounds__(SP_NT) void k_dct_split1(DctArgs a) {
     }
   }
   sp_tables<LOG2L>(wt, twS, a);
+  if (a.done && *a.done) return;  // a step enqueued after the stop rule fired (tested once the loads are out)
   lds_barrier();
 #pragma unroll
   for (int i = 0; i <= IPT; ++i) {
@@ -599,7 +599,6 @@ __global__ __launch_bounds__(SP_NT) void k_dct_split2(DctArgs a) {
   __shared__ float2 twS[S];
   __shared__ float2 ex[16 * SS::CS];
   __shared__ float2 ex2[S * SP_RC];
-  if (a.done && *a.done) return;
   int q, g;
   sp_tile(SS::G, q, g);
   const int row = threadIdx.x % SP_RC, grp = threadIdx.x / SP_RC;
@@ -614,6 +613,7 @@ __global__ __launch_bounds__(SP_NT) void k_dct_split2(DctArgs a) {
 #pragma unroll
   for (int d = 0; d < R2; ++d) m[d] = a.mzt[r * S + grp + 16 * d];
   sp_tables<LOG2L>(wt, twS, a);
+  if (a.done && *a.done) return;
   lds_barrier();
   if (grp < R2) sp_half1<LOG2L>(v, row, grp, ex, twS);
   lds_barrier();
@@ -653,7 +653,6 @@ __global__ __launch_bounds__(SP_NT) void k_dct_split3(DctArgs a) {
   __shared__ float2 ex[16 * SS::CS];
   __shared__ float2 ex2[S * SP_RC];
   __shared__ double red[SP_NT / 64];
-  if (a.done && *a.done) return;
   int q, g;
   sp_tile(G, q, g);
   const int row = threadIdx.x % SP_RC, grp = threadIdx.x / SP_RC;
@@ -677,6 +676,7 @@ __global__ __launch_bounds__(SP_NT) void k_dct_split3(DctArgs a) {
     adk[d] = a.alpha[j];
   }
   sp_tables<LOG2L>(wt, twS, a);
+  if (a.done && *a.done) return;
   lds_barrier();
   if (grp < R2) sp_half1<LOG2L>(v, row, grp, ex, twS);
   lds_barrier();

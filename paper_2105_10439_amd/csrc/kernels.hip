@@ -184,8 +184,8 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_update(SolveCfg c, int64_t Dp, co
                                                       const float* __restrict__ Pd, const float* __restrict__ Psi,
                                                       const double* __restrict__ pipart, double* __restrict__ part,
                                                       CGState* __restrict__ st) {
-  if (st->done) return;
-  cg_update_tile<PRE, NT, XU>(c, blockIdx.x, blockIdx.y, gridDim.x, Dp, minv, X, R, Pd, Psi, pipart, part, st);
+  cg_update_tile<PRE, NT, XU>(c, blockIdx.x, blockIdx.y, gridDim.x, Dp, minv, X, R, Pd, Psi, pipart, part, st,
+                              &st->done);
 }
 
 __global__ __launch_bounds__(1024) void k_cg_gamma(SolveCfg c, int nbx, const double* __restrict__ pipart,
@@ -206,32 +206,39 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(SolveCfg c, int nbx, const 
 // block (0, 0) can write the new rho while the others still run); block (0, 0) also runs
 // cg_scalars_block, the state's norms, stop rule, step count and done flag.  A block that
 // starts after this step's stop rule has fired may skip its tile: the direction is not
-// used again in the E-step.  Results are those of the separate scalars and direction
-// kernels, bit for bit.
+// used again in the E-step.  Every global load of a block (its tile, the partials, the
+// state's entries) goes out before the done flag is tested and before any reduction, so
+// the launch waits for memory once.  Results are those of the separate scalars and
+// direction kernels, bit for bit.
 template <bool NT>
 __global__ __launch_bounds__(VBLOCK) void k_cg_scalars_direction(SolveCfg c, int nbx, const double* __restrict__ part,
                                                                  int64_t Dp, const float* __restrict__ minv,
                                                                  const float* __restrict__ R, float* __restrict__ Pd,
                                                                  uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
                                                                  uint16_t* __restrict__ PdX, CGState* __restrict__ st) {
-  if (st->done) return;
   const int q = blockIdx.y;
-  __shared__ double s_eta;
+  // every load goes out before the done flag is tested: the tile (in flight during eta's
+  // reduction), the column's rho' partials and the old rho
+  const DirTile dt = cg_direction_load(blockIdx.x, q, Dp, minv, R, Pd);
+  const bool scal = blockIdx.x == 0 && blockIdx.y == 0;
+  ScalarsIn si;
+  if (scal) si = cg_scalars_load(c, nbx, part, st);
+  double old = 0.0, b = 0.0;
   if (threadIdx.x < 64) {
+    old = st->rho_prev[q];
     const double2* pq = reinterpret_cast<const double2*>(part + (int64_t)q * nbx * 2);
-    double b = 0.0;
 #pragma unroll 8
     for (int i = threadIdx.x; i < nbx; i += 64) b += pq[i].y;
+  }
+  if (st->done) return;
+  __shared__ double s_eta;
+  if (threadIdx.x < 64) {
     b = wave_sum(b);
-    if (threadIdx.x == 0) {
-      const double old = st->rho_prev[q];
-      s_eta = (old != 0.0) ? b / old : 0.0;
-    }
+    if (threadIdx.x == 0) s_eta = (old != 0.0) ? b / old : 0.0;
   }
   __syncthreads();
-  const double eta = s_eta;
-  if (blockIdx.x == 0 && blockIdx.y == 0) cg_scalars_block(c, nbx, part, st);
-  cg_direction_tile_eta<NT>(blockIdx.x, q, Dp, eta, minv, R, Pd, PdH, PdL, PdX);
+  cg_direction_store<NT>(dt, blockIdx.x, q, Dp, s_eta, Pd, PdH, PdL, PdX);
+  if (scal) cg_scalars_finish(c, nbx, part, st, si);
 }
 
 // The direction update with the bf16 slices in the tile-interleaved layout (the FIR

@@ -624,22 +624,47 @@ __device__ __forceinline__ void finish2_tile(const SolveCfg& c, int bx, int q, i
 // gamma_q = rho_q / pi_q from the column's nbx pi partials, summed in a fixed order; a
 // column with pi_q <= 0 and rho_q != 0 breaks down and is frozen.  Lane 0 of the calling
 // wave gets the result; with `record` it also writes pi, gamma and the breakdown flag.
-__device__ __forceinline__ double column_gamma(int q, int nbx, const double* __restrict__ pipart,
-                                               CGState* __restrict__ st, bool record) {
-  const double pi = wave_sum_strided(pipart + (int64_t)q * nbx, nbx, 1);
-  const double rho = st->rho[q];
-  const int act = st->active[q];
-  const double gam = (act && pi > 0.0) ? rho / pi : 0.0;
+// Two halves, so that a kernel can have the inputs in flight while it does other work:
+// rho_q, the active flag and, with at most one partial per lane (nbx <= 64), the lane's
+// partial (the sum keeps the order of wave_sum_strided).
+struct GammaIn {
+  double rho, pp;
+  int act;
+};
+__device__ __forceinline__ GammaIn column_gamma_load(int q, int nbx, const double* __restrict__ pipart,
+                                                     const CGState* __restrict__ st) {
+  GammaIn g;
+  g.rho = st->rho[q];
+  g.act = st->active[q];
+  const int ln = threadIdx.x & 63;
+  g.pp = (nbx <= 64 && ln < nbx) ? pipart[(int64_t)q * nbx + ln] : 0.0;
+  return g;
+}
+__device__ __forceinline__ double column_gamma_finish(int q, int nbx, const double* __restrict__ pipart,
+                                                      CGState* __restrict__ st, bool record, const GammaIn& g) {
+  double pi;
+  if (nbx <= 64) {
+    double a = 0.0;
+    if ((int)(threadIdx.x & 63) < nbx) a += g.pp;
+    pi = wave_sum(a);
+  } else {
+    pi = wave_sum_strided(pipart + (int64_t)q * nbx, nbx, 1);
+  }
+  const double gam = (g.act && pi > 0.0) ? g.rho / pi : 0.0;
   if (record && (threadIdx.x & 63) == 0) {
     st->pi[q] = pi;
     st->gamma[q] = gam;
-    st->rho_prev[q] = rho;
-    if (act && !(pi > 0.0) && rho != 0.0) {  // breakdown: freeze the column
+    st->rho_prev[q] = g.rho;
+    if (g.act && !(pi > 0.0) && g.rho != 0.0) {  // breakdown: freeze the column
       st->active[q] = 0;
       atomicAdd(&st->breakdown, 1);
     }
   }
   return gam;
+}
+__device__ __forceinline__ double column_gamma(int q, int nbx, const double* __restrict__ pipart,
+                                               CGState* __restrict__ st, bool record) {
+  return column_gamma_finish(q, nbx, pipart, st, record, column_gamma_load(q, nbx, pipart, st));
 }
 
 // One block, one wave per column: gamma_q for all columns into the state, for problems
@@ -662,8 +687,10 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
                                                const float* __restrict__ minv, float* __restrict__ X,
                                                float* __restrict__ R, const float* __restrict__ Pd,
                                                const float* __restrict__ Psi, const double* __restrict__ pipart,
-                                               double* __restrict__ part, CGState* __restrict__ st) {
-  // the block's loads go out before gamma's reduction, which they do not depend on
+                                               double* __restrict__ part, CGState* __restrict__ st,
+                                               const int* __restrict__ done = nullptr) {
+  // the block's loads go out before gamma's reduction, which they do not depend on, and
+  // before the done flag (when given) is tested
   const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
   const bool in = j < Dp;
   const int64_t o = (int64_t)q * Dp + j;
@@ -677,6 +704,9 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
     r = *reinterpret_cast<const f32x4*>(R + o);
     ps = *reinterpret_cast<const f32x4*>(Psi + o);
   }
+  GammaIn gin;
+  if (!PRE && threadIdx.x < 64) gin = column_gamma_load(q, nbx, pipart, st);
+  if (done && *done) return;
   if (!XU && bx == 0 && q == 0 && threadIdx.x == 0) st->xpend = 1;
   double gam;
   if (PRE) {
@@ -684,7 +714,7 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
   } else {
     __shared__ double s_gam;
     if (threadIdx.x < 64) {
-      const double g = column_gamma(q, nbx, pipart, st, bx == 0);
+      const double g = column_gamma_finish(q, nbx, pipart, st, bx == 0, gin);
       if (threadIdx.x == 0) s_gam = g;
     }
     __syncthreads();
@@ -716,41 +746,103 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
 
 // One block: ||R_q||^2 and rho'_q from the partials (one wave per column, any block
 // size), the stop rule of Algorithm 2 (joint Frobenius ratio, or per-column freezing),
-// steps, eta_q = rho'_q / rho_q.
-__device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, const double* __restrict__ part,
-                                                 CGState* __restrict__ st) {
+// steps, eta_q = rho'_q / rho_q.  Two halves, so that the block's global loads go out
+// before the work that precedes the reductions (the block is on the critical path of
+// its launch): the state's entries and, with at most one partial per lane and column,
+// the partials of the wave's first 8 columns; the additions keep the order of the
+// one-column loop.
+struct ScalarsIn {
+  double2 v[8];
+  double bn2, old, bnorm2;
+  int act, steps;
+};
+__device__ __forceinline__ ScalarsIn cg_scalars_load(const SolveCfg& c, int nbx, const double* __restrict__ part,
+                                                     const CGState* __restrict__ st) {
+  ScalarsIn in;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int q = threadIdx.x;
+  in.act = 0;
+  in.bn2 = in.old = in.bnorm2 = 0.0;
+  in.steps = 0;
+  if (q < c.Q) {
+    in.act = st->active[q];
+    in.bn2 = st->bn2[q];
+    in.old = st->rho[q];
+  }
+  if (threadIdx.x == 0) {
+    in.bnorm2 = st->bnorm2;
+    in.steps = st->steps;
+  }
+  if (nbx <= 64) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int qk = wv + k * nw;
+      if (qk < c.Q && ln < nbx) in.v[k] = reinterpret_cast<const double2*>(part + (int64_t)qk * nbx * 2)[ln];
+    }
+  }
+  return in;
+}
+__device__ __forceinline__ void cg_scalars_finish(const SolveCfg& c, int nbx, const double* __restrict__ part,
+                                                  CGState* __restrict__ st, const ScalarsIn& in) {
   __shared__ double s_rr[QMAX], s_rw[QMAX];
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int q = wv; q < c.Q; q += nw) {
-    const double2* pq = reinterpret_cast<const double2*>(part + (int64_t)q * nbx * 2);
-    double a = 0.0, b = 0.0;
-#pragma unroll 8
-    for (int i = ln; i < nbx; i += 64) {  // loads issued together, additions in order
-      const double2 v = pq[i];
-      a += v.x;
-      b += v.y;
+  const int q = threadIdx.x;
+  if (nbx <= 64) {
+    for (int q0 = wv; q0 < c.Q; q0 += 8 * nw) {
+      double2 v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int qk = q0 + k * nw;
+        if (q0 == wv) v[k] = in.v[k];
+        else if (qk < c.Q && ln < nbx) v[k] = reinterpret_cast<const double2*>(part + (int64_t)qk * nbx * 2)[ln];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int qk = q0 + k * nw;
+        if (qk >= c.Q) break;  // wave-uniform
+        double a = 0.0, b = 0.0;
+        if (ln < nbx) {
+          a += v[k].x;
+          b += v[k].y;
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (ln == 0) {
+          s_rr[qk] = a;
+          s_rw[qk] = b;
+        }
+      }
     }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (ln == 0) {
-      s_rr[q] = a;
-      s_rw[q] = b;
+  } else {
+    for (int qk = wv; qk < c.Q; qk += nw) {
+      const double2* pq = reinterpret_cast<const double2*>(part + (int64_t)qk * nbx * 2);
+      double a = 0.0, b = 0.0;
+#pragma unroll 8
+      for (int i = ln; i < nbx; i += 64) {  // loads issued together, additions in order
+        const double2 v = pq[i];
+        a += v.x;
+        b += v.y;
+      }
+      a = wave_sum(a);
+      b = wave_sum(b);
+      if (ln == 0) {
+        s_rr[qk] = a;
+        s_rw[qk] = b;
+      }
     }
   }
   __syncthreads();
   // per column, one thread each: the column stop test (column mode), ||R_q||^2, eta and rho
   __shared__ int s_act[QMAX];
-  const int q = threadIdx.x;
   if (q < c.Q) {
-    int act = st->active[q];
-    if (c.stop_mode != 0 && act && sqrt(s_rr[q] / st->bn2[q]) <= c.tol) {
+    int act = in.act;
+    if (c.stop_mode != 0 && act && sqrt(s_rr[q] / in.bn2) <= c.tol) {
       act = 0;
       st->active[q] = 0;
     }
     s_act[q] = act;
     st->rn2[q] = s_rr[q];
-    const double old = st->rho[q];
-    st->eta[q] = (old != 0.0) ? s_rw[q] / old : 0.0;
+    st->eta[q] = (in.old != 0.0) ? s_rw[q] / in.old : 0.0;
     st->rho[q] = s_rw[q];
   }
   __syncthreads();
@@ -761,34 +853,60 @@ __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, con
     rsum += s_rr[k];
     nact += s_act[k];
   }
-  const double delta = sqrt(rsum / st->bnorm2);
+  const double delta = sqrt(rsum / in.bnorm2);
   st->delta = delta;
-  const int steps = st->steps + 1;
+  const int steps = in.steps + 1;
   st->steps = steps;
   int done = (c.stop_mode == 0) ? (delta <= c.tol) : (nact == 0);
   if (steps >= c.U) done = 1;
   st->done = done;
 }
+__device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, const double* __restrict__ part,
+                                                 CGState* __restrict__ st) {
+  cg_scalars_finish(c, nbx, part, st, cg_scalars_load(c, nbx, part, st));
+}
 
 // P = M^-1 R + eta P (FP32, and bf16 hi/lo when PdH is not null, and the third slice
 // when PdX is not null; column-major slices: the interleaved layout of the FIR dictionary
-// has a kernel of its own).  NT: P stored non-temporally (the slices are what the operator reads).
+// has a kernel of its own).  Two halves, so that a kernel can issue the tile's loads
+// before it reduces eta, on which they do not depend.  NT: P stored non-temporally (the
+// slices are what the operator reads).
+struct DirTile {
+  f32x4 mi, r, p;
+  bool in;
+};
+__device__ __forceinline__ DirTile cg_direction_load(int bx, int q, int64_t Dp, const float* __restrict__ minv,
+                                                     const float* __restrict__ R, const float* __restrict__ Pd) {
+  DirTile d;
+  const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
+  d.in = j < Dp;
+  if (d.in) {
+    const int64_t o = (int64_t)q * Dp + j;
+    d.mi = *reinterpret_cast<const f32x4*>(minv + j);
+    d.r = *reinterpret_cast<const f32x4*>(R + o);
+    d.p = *reinterpret_cast<const f32x4*>(Pd + o);
+  }
+  return d;
+}
+template <bool NT = false>
+__device__ __forceinline__ void cg_direction_store(const DirTile& d, int bx, int q, int64_t Dp, double eta,
+                                                   float* __restrict__ Pd, uint16_t* __restrict__ PdH,
+                                                   uint16_t* __restrict__ PdL, uint16_t* __restrict__ PdX) {
+  if (!d.in) return;
+  const int64_t o = (int64_t)q * Dp + (int64_t)bx * VCHUNK + 4 * threadIdx.x;
+  f32x4 p;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) p[e] = (float)((double)d.mi[e] * (double)d.r[e] + eta * (double)d.p[e]);
+  if constexpr (NT) __builtin_nontemporal_store(p, reinterpret_cast<f32x4*>(Pd + o));
+  else *reinterpret_cast<f32x4*>(Pd + o) = p;
+  if (PdH) store_split4<true>(PdH, PdL, o, p, PdX);
+}
 template <bool NT = false>
 __device__ __forceinline__ void cg_direction_tile_eta(int bx, int q, int64_t Dp, double eta,
                                                       const float* __restrict__ minv, const float* __restrict__ R,
                                                       float* __restrict__ Pd, uint16_t* __restrict__ PdH,
                                                       uint16_t* __restrict__ PdL, uint16_t* __restrict__ PdX) {
-  const int64_t j = (int64_t)bx * VCHUNK + 4 * threadIdx.x;
-  if (j >= Dp) return;
-  const int64_t o = (int64_t)q * Dp + j;
-  const f32x4 mi = *reinterpret_cast<const f32x4*>(minv + j);
-  const f32x4 r = *reinterpret_cast<const f32x4*>(R + o);
-  f32x4 p = *reinterpret_cast<const f32x4*>(Pd + o);
-#pragma unroll
-  for (int e = 0; e < 4; ++e) p[e] = (float)((double)mi[e] * (double)r[e] + eta * (double)p[e]);
-  if constexpr (NT) __builtin_nontemporal_store(p, reinterpret_cast<f32x4*>(Pd + o));
-  else *reinterpret_cast<f32x4*>(Pd + o) = p;
-  if (PdH) store_split4<true>(PdH, PdL, o, p, PdX);
+  cg_direction_store<NT>(cg_direction_load(bx, q, Dp, minv, R, Pd), bx, q, Dp, eta, Pd, PdH, PdL, PdX);
 }
 template <bool NT = false>
 __device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, const float* __restrict__ minv,
