@@ -113,7 +113,9 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, int dir, int64_
       ps[e] = (float)(a.beta * (double)v[e] + (double)al[e] * (double)pd[e]);
       pacc += (double)pd[e] * (double)ps[e];
     }
-    if (qv) *reinterpret_cast<f32x4*>(a.out32 + o) = ps;
+    // non-temporal: Psi (Q x D FP32, 88 MB at D = 2^20) is read once, by the update launch,
+    // long after these lines would have left the L2
+    if (qv) __builtin_nontemporal_store(ps, reinterpret_cast<f32x4*>(a.out32 + o));
   }
 }
 

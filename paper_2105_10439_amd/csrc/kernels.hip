@@ -206,10 +206,10 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(SolveCfg c, int nbx, const 
 // block (0, 0) can write the new rho while the others still run); block (0, 0) also runs
 // cg_scalars_block, the state's norms, stop rule, step count and done flag.  A block that
 // starts after this step's stop rule has fired may skip its tile: the direction is not
-// used again in the E-step.  Every global load of a block (its tile, the partials, the
-// state's entries) goes out before the done flag is tested and before any reduction, so
-// the launch waits for memory once.  Results are those of the separate scalars and
-// direction kernels, bit for bit.
+// used again in the E-step.  A block's tile, its column's partials and the old rho go out
+// before the done flag is tested and before the reduction, so the launch waits for memory
+// once (block (0, 0) runs the scalars after its tile).  Results are those of the separate
+// scalars and direction kernels, bit for bit.
 template <bool NT>
 __global__ __launch_bounds__(VBLOCK) void k_cg_scalars_direction(SolveCfg c, int nbx, const double* __restrict__ part,
                                                                  int64_t Dp, const float* __restrict__ minv,
@@ -220,9 +220,6 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_scalars_direction(SolveCfg c, int
   // every load goes out before the done flag is tested: the tile (in flight during eta's
   // reduction), the column's rho' partials and the old rho
   const DirTile dt = cg_direction_load(blockIdx.x, q, Dp, minv, R, Pd);
-  const bool scal = blockIdx.x == 0 && blockIdx.y == 0;
-  ScalarsIn si;
-  if (scal) si = cg_scalars_load(c, nbx, part, st);
   double old = 0.0, b = 0.0;
   if (threadIdx.x < 64) {
     old = st->rho_prev[q];
@@ -238,7 +235,7 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_scalars_direction(SolveCfg c, int
   }
   __syncthreads();
   cg_direction_store<NT>(dt, blockIdx.x, q, Dp, s_eta, Pd, PdH, PdL, PdX);
-  if (scal) cg_scalars_finish(c, nbx, part, st, si);
+  if (blockIdx.x == 0 && blockIdx.y == 0) cg_scalars_block(c, nbx, part, st);
 }
 
 // The direction update with the bf16 slices in the tile-interleaved layout (the FIR
@@ -250,6 +247,8 @@ typedef __attribute__((ext_vector_type(4))) unsigned short u16x4v;
 // XD (the bf16 form, whose direction is its hi/lo pair: the FP32 Pd is neither read nor
 // written): also X += gamma P (the update left it here) when the step's update ran
 // (xpend), before the done test, so the step that meets the stop rule still moves X.
+// NT: X, P and its slices stored non-temporally (the operator streams them back long
+// after these lines would have left the L2).
 template <bool NT, bool XD>
 __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t Dp, const float* __restrict__ minv,
                                                              const float* __restrict__ R, float* __restrict__ Pd,
@@ -297,7 +296,7 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_direction_sig(SolveCfg c, int64_t
       if constexpr (NT) __builtin_nontemporal_store(p[k], reinterpret_cast<f32x4*>(Pd + o));
       else *reinterpret_cast<f32x4*>(Pd + o) = p[k];
     }
-    store_split4(PdH, PdL, sig_index(q, j, Dp, c.Q), p[k]);
+    store_split4<NT>(PdH, PdL, sig_index(q, j, Dp, c.Q), p[k]);
   }
 }
 

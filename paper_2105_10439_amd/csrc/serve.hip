@@ -208,8 +208,6 @@ __global__ __launch_bounds__(VBLOCK) void ks_scalars_direction(const SlotDev* __
     if (!in_cg(sd) || local >= sd.nbx * sd.c.Q) continue;
     const int bx = local % sd.nbx, q = local / sd.nbx;
     const DirTile dt = cg_direction_load(bx, q, sd.Dp, sd.minv, sd.R, sd.Pd);  // in flight during eta's reduction
-    ScalarsIn si;
-    if (local == 0) si = cg_scalars_load(sd.c, sd.nbx, sd.part, sd.st);
     if (threadIdx.x < 64) {
       const double old = sd.st->rho_prev[q];  // loaded with the partials, not after them
       const double2* pq = reinterpret_cast<const double2*>(sd.part + (int64_t)q * sd.nbx * 2);
@@ -221,7 +219,7 @@ __global__ __launch_bounds__(VBLOCK) void ks_scalars_direction(const SlotDev* __
     }
     __syncthreads();
     cg_direction_store(dt, bx, q, sd.Dp, s_eta, sd.Pd, nullptr, nullptr, nullptr);
-    if (local == 0) cg_scalars_finish(sd.c, sd.nbx, sd.part, sd.st, si);
+    if (local == 0) cg_scalars_block(sd.c, sd.nbx, sd.part, sd.st);
     __syncthreads();  // s_eta and the scalars' shared arrays are reused by the next tile
   }
 }

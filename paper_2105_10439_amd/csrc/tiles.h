@@ -682,7 +682,7 @@ __device__ __forceinline__ void cg_gamma_block(const SolveCfg& c, int nbx, const
 // all tiles get the same value (the tile of chunk 0 records it).
 // XU = false (the FIR dictionary's bf16 form): X is left to the direction kernel, which
 // reads P anyway; block (0, 0) flags it in the state (xpend).
-template <bool PRE, bool NT = false, bool XU = true>  // NT: X stored non-temporally
+template <bool PRE, bool NT = false, bool XU = true>  // NT: X (and for PRE, R) stored non-temporally
 __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q, int nbx, int64_t Dp,
                                                const float* __restrict__ minv, float* __restrict__ X,
                                                float* __restrict__ R, const float* __restrict__ Pd,
@@ -734,7 +734,11 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
       if constexpr (NT) __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(X + o));
       else *reinterpret_cast<f32x4*>(X + o) = x;
     }
-    *reinterpret_cast<f32x4*>(R + o) = r;
+    // R too once the columns are long enough for gamma to come precomputed (over 128
+    // chunks): the vectors then far exceed the L2s, and a plain store leaves dirty lines
+    // that the end of the launch writes back
+    if constexpr (NT && PRE) __builtin_nontemporal_store(r, reinterpret_cast<f32x4*>(R + o));
+    else *reinterpret_cast<f32x4*>(R + o) = r;
   }
   rr = block_sum(rr);
   rw = block_sum(rw);
@@ -746,58 +750,39 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
 
 // One block: ||R_q||^2 and rho'_q from the partials (one wave per column, any block
 // size), the stop rule of Algorithm 2 (joint Frobenius ratio, or per-column freezing),
-// steps, eta_q = rho'_q / rho_q.  Two halves, so that the block's global loads go out
-// before the work that precedes the reductions (the block is on the critical path of
-// its launch): the state's entries and, with at most one partial per lane and column,
-// the partials of the wave's first 8 columns; the additions keep the order of the
-// one-column loop.
-struct ScalarsIn {
-  double2 v[8];
-  double bn2, old, bnorm2;
-  int act, steps;
-};
-__device__ __forceinline__ ScalarsIn cg_scalars_load(const SolveCfg& c, int nbx, const double* __restrict__ part,
-                                                     const CGState* __restrict__ st) {
-  ScalarsIn in;
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
-  const int q = threadIdx.x;
-  in.act = 0;
-  in.bn2 = in.old = in.bnorm2 = 0.0;
-  in.steps = 0;
-  if (q < c.Q) {
-    in.act = st->active[q];
-    in.bn2 = st->bn2[q];
-    in.old = st->rho[q];
-  }
-  if (threadIdx.x == 0) {
-    in.bnorm2 = st->bnorm2;
-    in.steps = st->steps;
-  }
-  if (nbx <= 64) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int qk = wv + k * nw;
-      if (qk < c.Q && ln < nbx) in.v[k] = reinterpret_cast<const double2*>(part + (int64_t)qk * nbx * 2)[ln];
-    }
-  }
-  return in;
-}
-__device__ __forceinline__ void cg_scalars_finish(const SolveCfg& c, int nbx, const double* __restrict__ part,
-                                                  CGState* __restrict__ st, const ScalarsIn& in) {
+// steps, eta_q = rho'_q / rho_q.  The block is on the critical path of its launch, so its
+// global loads go out early: the state's entries first, then, with at most one partial
+// per lane and column, the partials of SCB_BATCH of the wave's columns at once (the
+// additions keep the order of the one-column loop; a larger batch costs the launch's
+// other blocks occupancy).
+constexpr int SCB_BATCH = 6;
+__device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, const double* __restrict__ part,
+                                                 CGState* __restrict__ st) {
   __shared__ double s_rr[QMAX], s_rw[QMAX];
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
   const int q = threadIdx.x;
+  int act = 0;
+  double bn2 = 0.0, old = 0.0, bnorm2 = 0.0;
+  int steps = 0;
+  if (q < c.Q) {
+    act = st->active[q];
+    bn2 = st->bn2[q];
+    old = st->rho[q];
+  }
+  if (threadIdx.x == 0) {
+    bnorm2 = st->bnorm2;
+    steps = st->steps;
+  }
   if (nbx <= 64) {
-    for (int q0 = wv; q0 < c.Q; q0 += 8 * nw) {
-      double2 v[8];
+    for (int q0 = wv; q0 < c.Q; q0 += SCB_BATCH * nw) {
+      double2 v[SCB_BATCH];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < SCB_BATCH; ++k) {
         const int qk = q0 + k * nw;
-        if (q0 == wv) v[k] = in.v[k];
-        else if (qk < c.Q && ln < nbx) v[k] = reinterpret_cast<const double2*>(part + (int64_t)qk * nbx * 2)[ln];
+        if (qk < c.Q && ln < nbx) v[k] = reinterpret_cast<const double2*>(part + (int64_t)qk * nbx * 2)[ln];
       }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < SCB_BATCH; ++k) {
         const int qk = q0 + k * nw;
         if (qk >= c.Q) break;  // wave-uniform
         double a = 0.0, b = 0.0;
@@ -835,14 +820,13 @@ __device__ __forceinline__ void cg_scalars_finish(const SolveCfg& c, int nbx, co
   // per column, one thread each: the column stop test (column mode), ||R_q||^2, eta and rho
   __shared__ int s_act[QMAX];
   if (q < c.Q) {
-    int act = in.act;
-    if (c.stop_mode != 0 && act && sqrt(s_rr[q] / in.bn2) <= c.tol) {
+    if (c.stop_mode != 0 && act && sqrt(s_rr[q] / bn2) <= c.tol) {
       act = 0;
       st->active[q] = 0;
     }
     s_act[q] = act;
     st->rn2[q] = s_rr[q];
-    st->eta[q] = (in.old != 0.0) ? s_rw[q] / in.old : 0.0;
+    st->eta[q] = (old != 0.0) ? s_rw[q] / old : 0.0;
     st->rho[q] = s_rw[q];
   }
   __syncthreads();
@@ -853,17 +837,13 @@ __device__ __forceinline__ void cg_scalars_finish(const SolveCfg& c, int nbx, co
     rsum += s_rr[k];
     nact += s_act[k];
   }
-  const double delta = sqrt(rsum / in.bnorm2);
+  const double delta = sqrt(rsum / bnorm2);
   st->delta = delta;
-  const int steps = in.steps + 1;
+  steps += 1;
   st->steps = steps;
   int done = (c.stop_mode == 0) ? (delta <= c.tol) : (nact == 0);
   if (steps >= c.U) done = 1;
   st->done = done;
-}
-__device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, const double* __restrict__ part,
-                                                 CGState* __restrict__ st) {
-  cg_scalars_finish(c, nbx, part, st, cg_scalars_load(c, nbx, part, st));
 }
 
 // P = M^-1 R + eta P (FP32, and bf16 hi/lo when PdH is not null, and the third slice
