@@ -200,25 +200,29 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(SolveCfg c, int nbx, const 
   cg_scalars_block(c, nbx, part, st);
 }
 
-// The CG scalars and the direction update in one launch (column-major directions).  Every
-// block reduces its own column's rho' partials, in the order of cg_scalars_block, for
+// The CG scalars and the direction update in one launch (column-major directions).  Row 0
+// of the grid is the scalars: its block (0, 0) runs cg_scalars_block (the state's norms,
+// stop rule, step count, done flag, new rho), dispatched first and beside the direction
+// tiles rather than after one of them.  Rows 1 .. Q are the direction tiles: every block
+// reduces its own column's rho' partials, in the order of cg_scalars_block, for
 // eta_q = rho'_q / rho_q, with rho_q from rho_prev (recorded by the update with gamma, so
-// block (0, 0) can write the new rho while the others still run); block (0, 0) also runs
-// cg_scalars_block, the state's norms, stop rule, step count and done flag.  A block that
-// starts after this step's stop rule has fired may skip its tile: the direction is not
-// used again in the E-step.  A block's tile, its column's partials and the old rho go out
-// before the done flag is tested and before the reduction, so the launch waits for memory
-// once (block (0, 0) runs the scalars after its tile).  Results are those of the separate
-// scalars and direction kernels, bit for bit.
+// the scalars may write the new rho while the tiles run).  A tile that starts after this
+// step's stop rule has fired may skip its work: the direction is not used again in the
+// E-step.  A tile's loads (its slice of R, Pd and M^-1, its column's partials, the old rho)
+// go out before the done flag is tested and before the reduction, so the launch waits for
+// memory once.  Results are those of the separate scalars and direction kernels, bit for
+// bit.
 template <bool NT>
 __global__ __launch_bounds__(VBLOCK) void k_cg_scalars_direction(SolveCfg c, int nbx, const double* __restrict__ part,
                                                                  int64_t Dp, const float* __restrict__ minv,
                                                                  const float* __restrict__ R, float* __restrict__ Pd,
                                                                  uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
                                                                  uint16_t* __restrict__ PdX, CGState* __restrict__ st) {
-  const int q = blockIdx.y;
-  // every load goes out before the done flag is tested: the tile (in flight during eta's
-  // reduction), the column's rho' partials and the old rho
+  if (blockIdx.y == 0) {
+    if (blockIdx.x == 0 && !st->done) cg_scalars_block(c, nbx, part, st);
+    return;
+  }
+  const int q = blockIdx.y - 1;
   const DirTile dt = cg_direction_load(blockIdx.x, q, Dp, minv, R, Pd);
   double old = 0.0, b = 0.0;
   if (threadIdx.x < 64) {
@@ -235,7 +239,6 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_scalars_direction(SolveCfg c, int
   }
   __syncthreads();
   cg_direction_store<NT>(dt, blockIdx.x, q, Dp, s_eta, Pd, PdH, PdL, PdX);
-  if (blockIdx.x == 0 && blockIdx.y == 0) cg_scalars_block(c, nbx, part, st);
 }
 
 // The direction update with the bf16 slices in the tile-interleaved layout (the FIR
@@ -561,8 +564,8 @@ void launch_cg_direction(const SolveCfg& c, int64_t Dp, const float* minv, const
   }
   // column-major directions: the CG scalars run in the same launch
   hipLaunchKernelGGL(nt ? k_cg_scalars_direction<true> : k_cg_scalars_direction<false>,
-                     dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q), dim3(VBLOCK), 0, s, c, (int)cdiv(Dp, VCHUNK), part, Dp,
-                     minv, R, Pd, PdH, PdL, PdX, st);
+                     dim3(cdiv(Dp, VCHUNK), (unsigned)c.Q + 1), dim3(VBLOCK), 0, s, c, (int)cdiv(Dp, VCHUNK), part,
+                     Dp, minv, R, Pd, PdH, PdL, PdX, st);
 }
 
 void launch_mt_mstep(const float* const* mus, const float* const* ss, int L, int64_t D, float* alpha, double floor,
