@@ -112,11 +112,13 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // Sum of p[i * stride] over i < n by one wave, in a fixed order (all lanes get it).  The
-// unrolled loop issues a lane's loads together; the additions keep their order.
+// unrolled loop issues UNR of a lane's loads together (registers permitting, 16 take
+// 1024 values in one round trip); the additions keep their order whatever UNR.
+template <int UNR = 8>
 __device__ __forceinline__ double wave_sum_strided(const double* p, int n, int stride) {
   const int lane = threadIdx.x & 63;
   double a = 0.0;
-#pragma unroll 8
+#pragma unroll UNR
   for (int i = lane; i < n; i += 64) a += p[(int64_t)i * stride];
   return wave_sum(a);
 }

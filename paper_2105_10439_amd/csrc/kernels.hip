@@ -188,16 +188,22 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_update(SolveCfg c, int64_t Dp, co
                               &st->done);
 }
 
-__global__ __launch_bounds__(1024) void k_cg_gamma(SolveCfg c, int nbx, const double* __restrict__ pipart,
-                                                   CGState* __restrict__ st) {
+// gamma_q for all columns into the state, for problems with many pi partials per column
+// (the update tiles then read gamma instead of each re-reducing the partials): one
+// single-wave block per column, 16 of a lane's loads in flight at once.
+__global__ __launch_bounds__(64) void k_cg_gamma(SolveCfg c, int nbx, const double* __restrict__ pipart,
+                                                 CGState* __restrict__ st) {
   if (st->done) return;
-  cg_gamma_block(c, nbx, pipart, st);
+  column_gamma<16>(blockIdx.x, nbx, pipart, st, true);
 }
 
+// The CG scalars as a launch of their own (before the FIR dictionary's interleaved-slice
+// direction kernel): one block, 16 of a lane's loads in flight at once (one block per
+// launch, so its registers cost no occupancy).
 __global__ __launch_bounds__(1024) void k_cg_scalars(SolveCfg c, int nbx, const double* __restrict__ part,
                                                      CGState* __restrict__ st) {
   if (st->done) return;
-  cg_scalars_block(c, nbx, part, st);
+  cg_scalars_block<16>(c, nbx, part, st);
 }
 
 // The CG scalars and the direction update in one launch (column-major directions).  Row 0
@@ -537,7 +543,7 @@ void launch_cg_update(const SolveCfg& c, int64_t Dp, const float* minv, float* X
   const unsigned nbx = cdiv(Dp, VCHUNK);
   const dim3 grid(nbx, (unsigned)c.Q);
   const bool pre = nbx > (unsigned)GAMMA_PRE_MIN_CHUNKS;
-  if (pre) hipLaunchKernelGGL(k_cg_gamma, dim3(1), dim3(1024), 0, s, c, (int)nbx, pipart, st);
+  if (pre) hipLaunchKernelGGL(k_cg_gamma, dim3((unsigned)c.Q), dim3(64), 0, s, c, (int)nbx, pipart, st);
   auto kern = xdir ? (pre ? k_cg_update<true, true, false> : k_cg_update<false, true, false>)
              : pre  ? (c.nt_store ? k_cg_update<true, true, true> : k_cg_update<true, false, true>)
                     : (c.nt_store ? k_cg_update<false, true, true> : k_cg_update<false, false, true>);

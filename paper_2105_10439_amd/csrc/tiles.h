@@ -640,6 +640,7 @@ __device__ __forceinline__ GammaIn column_gamma_load(int q, int nbx, const doubl
   g.pp = (nbx <= 64 && ln < nbx) ? pipart[(int64_t)q * nbx + ln] : 0.0;
   return g;
 }
+template <int UNR = 8>
 __device__ __forceinline__ double column_gamma_finish(int q, int nbx, const double* __restrict__ pipart,
                                                       CGState* __restrict__ st, bool record, const GammaIn& g) {
   double pi;
@@ -648,7 +649,7 @@ __device__ __forceinline__ double column_gamma_finish(int q, int nbx, const doub
     if ((int)(threadIdx.x & 63) < nbx) a += g.pp;
     pi = wave_sum(a);
   } else {
-    pi = wave_sum_strided(pipart + (int64_t)q * nbx, nbx, 1);
+    pi = wave_sum_strided<UNR>(pipart + (int64_t)q * nbx, nbx, 1);
   }
   const double gam = (g.act && pi > 0.0) ? g.rho / pi : 0.0;
   if (record && (threadIdx.x & 63) == 0) {
@@ -662,23 +663,15 @@ __device__ __forceinline__ double column_gamma_finish(int q, int nbx, const doub
   }
   return gam;
 }
+template <int UNR = 8>
 __device__ __forceinline__ double column_gamma(int q, int nbx, const double* __restrict__ pipart,
                                                CGState* __restrict__ st, bool record) {
-  return column_gamma_finish(q, nbx, pipart, st, record, column_gamma_load(q, nbx, pipart, st));
-}
-
-// One block, one wave per column: gamma_q for all columns into the state, for problems
-// with many pi partials per column (the update tiles then read gamma instead of each
-// re-reducing the partials).
-__device__ __forceinline__ void cg_gamma_block(const SolveCfg& c, int nbx, const double* __restrict__ pipart,
-                                               CGState* __restrict__ st) {
-  const int nw = blockDim.x >> 6;
-  for (int q = threadIdx.x >> 6; q < c.Q; q += nw) column_gamma(q, nbx, pipart, st, true);
+  return column_gamma_finish<UNR>(q, nbx, pipart, st, record, column_gamma_load(q, nbx, pipart, st));
 }
 
 // X += gamma Pd, R -= gamma Psi; partials of ||R_q||^2 and rho'_q = sum R (M^-1 R) at
 // part[(q * nbx + bx) * 2 + {0, 1}].  gamma_q comes from the state (PRE, after
-// cg_gamma_block) or is reduced here by every tile of the column, in the same order, so
+// k_cg_gamma) or is reduced here by every tile of the column, in the same order, so
 // all tiles get the same value (the tile of chunk 0 records it).
 // XU = false (the FIR dictionary's bf16 form): X is left to the direction kernel, which
 // reads P anyway; block (0, 0) flags it in the state (xpend).
@@ -756,6 +749,7 @@ __device__ __forceinline__ void cg_update_tile(const SolveCfg& c, int bx, int q,
 // additions keep the order of the one-column loop; a larger batch costs the launch's
 // other blocks occupancy).
 constexpr int SCB_BATCH = 6;
+template <int UNR = 8>
 __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, const double* __restrict__ part,
                                                  CGState* __restrict__ st) {
   __shared__ double s_rr[QMAX], s_rw[QMAX];
@@ -802,7 +796,7 @@ __device__ __forceinline__ void cg_scalars_block(const SolveCfg& c, int nbx, con
     for (int qk = wv; qk < c.Q; qk += nw) {
       const double2* pq = reinterpret_cast<const double2*>(part + (int64_t)qk * nbx * 2);
       double a = 0.0, b = 0.0;
-#pragma unroll 8
+#pragma unroll UNR
       for (int i = ln; i < nbx; i += 64) {  // loads issued together, additions in order
         const double2 v = pq[i];
         a += v.x;
