@@ -216,8 +216,9 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(SolveCfg c, int nbx, const 
 // step's stop rule has fired may skip its work: the direction is not used again in the
 // E-step.  A tile's loads (its slice of R, Pd and M^-1, its column's partials, the old rho)
 // go out before the done flag is tested and before the reduction, so the launch waits for
-// memory once.  Results are those of the separate scalars and direction kernels, bit for
-// bit.
+// memory once; the flag is read once per block (the scalars block may write it meanwhile),
+// so a block's waves agree.  Results are those of the separate scalars and direction
+// kernels, bit for bit.
 template <bool NT>
 __global__ __launch_bounds__(VBLOCK) void k_cg_scalars_direction(SolveCfg c, int nbx, const double* __restrict__ part,
                                                                  int64_t Dp, const float* __restrict__ minv,
@@ -231,19 +232,26 @@ __global__ __launch_bounds__(VBLOCK) void k_cg_scalars_direction(SolveCfg c, int
   const int q = blockIdx.y - 1;
   const DirTile dt = cg_direction_load(blockIdx.x, q, Dp, minv, R, Pd);
   double old = 0.0, b = 0.0;
+  int dn = 0;
   if (threadIdx.x < 64) {
+    dn = st->done;
     old = st->rho_prev[q];
     const double2* pq = reinterpret_cast<const double2*>(part + (int64_t)q * nbx * 2);
 #pragma unroll 8
     for (int i = threadIdx.x; i < nbx; i += 64) b += pq[i].y;
   }
-  if (st->done) return;
+  // the scalars block may set done during this launch: one reading for the whole block
   __shared__ double s_eta;
+  __shared__ int s_done;
   if (threadIdx.x < 64) {
     b = wave_sum(b);
-    if (threadIdx.x == 0) s_eta = (old != 0.0) ? b / old : 0.0;
+    if (threadIdx.x == 0) {
+      s_done = dn;
+      s_eta = (old != 0.0) ? b / old : 0.0;
+    }
   }
   __syncthreads();
+  if (s_done) return;
   cg_direction_store<NT>(dt, blockIdx.x, q, Dp, s_eta, Pd, PdH, PdL, PdX);
 }
 

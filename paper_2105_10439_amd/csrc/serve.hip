@@ -200,12 +200,19 @@ __global__ __launch_bounds__(VBLOCK) void ks_update(const SlotDev* __restrict__ 
 __global__ __launch_bounds__(VBLOCK) void ks_scalars_direction(const SlotDev* __restrict__ slots,
                                                                const SrvTable* __restrict__ tab) {
   __shared__ double s_eta;
+  __shared__ int s_run;
   const int n = tab->n, total = tab->vq[n];
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     const int i = find_slot(tab->vq, n, t);
     const SlotDev& sd = slots[tab->slot[i]];
     const int local = t - tab->vq[i];
-    if (!in_cg(sd) || local >= sd.nbx * sd.c.Q) continue;
+    // the slot's first tile sets done during this launch: one reading of the flag for the
+    // whole block, so its waves agree on which tiles they run (and so on their barriers)
+    if (threadIdx.x == 0) s_run = in_cg(sd) && local < sd.nbx * sd.c.Q;
+    __syncthreads();
+    const int run = s_run;
+    __syncthreads();  // s_run is written again for the next tile
+    if (!run) continue;
     const int bx = local % sd.nbx, q = local / sd.nbx;
     const DirTile dt = cg_direction_load(bx, q, sd.Dp, sd.minv, sd.R, sd.Pd);  // in flight during eta's reduction
     if (threadIdx.x < 64) {
