@@ -875,19 +875,5 @@ __device__ __forceinline__ void cg_direction_store(const DirTile& d, int bx, int
   else *reinterpret_cast<f32x4*>(Pd + o) = p;
   if (PdH) store_split4<true>(PdH, PdL, o, p, PdX);
 }
-template <bool NT = false>
-__device__ __forceinline__ void cg_direction_tile_eta(int bx, int q, int64_t Dp, double eta,
-                                                      const float* __restrict__ minv, const float* __restrict__ R,
-                                                      float* __restrict__ Pd, uint16_t* __restrict__ PdH,
-                                                      uint16_t* __restrict__ PdL, uint16_t* __restrict__ PdX) {
-  cg_direction_store<NT>(cg_direction_load(bx, q, Dp, minv, R, Pd), bx, q, Dp, eta, Pd, PdH, PdL, PdX);
-}
-template <bool NT = false>
-__device__ __forceinline__ void cg_direction_tile(int bx, int q, int64_t Dp, const float* __restrict__ minv,
-                                                  const float* __restrict__ R, float* __restrict__ Pd,
-                                                  uint16_t* __restrict__ PdH, uint16_t* __restrict__ PdL,
-                                                  const CGState* __restrict__ st, uint16_t* __restrict__ PdX = nullptr) {
-  cg_direction_tile_eta<NT>(bx, q, Dp, st->eta[q], minv, R, Pd, PdH, PdL, PdX);
-}
 
 }  // namespace cofem
